@@ -1,0 +1,533 @@
+"""Plain FP64 CPU oracle of the RMRT-LB scheme (arXiv:2206.00366).
+
+TEST INFRASTRUCTURE ONLY -- imported by tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product path.
+
+Everything is dense and literal: the transformation matrix M is built from its
+definition (raw moments, Sec. V eq. 5-2), inverted numerically, the relaxation
+matrix S is assembled as a full q x q matrix (eq. 5-1, 5-8), and the
+equilibrium, source and auxiliary distributions are evaluated in velocity space
+from the general rectangular equilibrium g_eq(A, B, M) (eq. 3-3, 3-4).  One
+time step is eq. 2-2-3 followed by propagation (eq. 2-2, second line).
+
+Arrays: populations have shape (q, N) with N = nx*ny*nz nodes in x-fastest
+order (node index = x + nx*(y + ny*z)); all arithmetic is float64.
+
+Readings of the paper where it is silent or garbled (kept in one place so the
+GPU side can take the same ones; numbering as in the design notes):
+  A1  the printed rD3Q27 x-z edge velocities (eq. 3-2b, j = 11..14) repeat two
+      vectors; they are read as (c1,0,c3), (-c1,0,c3), (-c1,0,-c3), (c1,0,-c3),
+      the pattern of the x-y and y-z edges.
+  A2  c_s^2 <= 0 selects min_a c_a^2 / 3.
+  A3  rD3Q27 omega_19 defaults to r1 r2 r3 / 8 with r_a = c_s^2 / c_a^2.
+  A4  3D raw-moment rows: all monomials with exponents in {0,1,2} (rD3Q27), or
+      those with at most two non-zero exponents (rD3Q19).
+  A5  rates of order >= 3 default to s_nu (NSE) and 1 (NCDE).
+  A6  s_0, S_1 and the blocks below the diagonal are 1, 1 and 0 for the NSE.
+  A7  dt = 1 unless given.
+  A8  the e_alpha of the source distribution (eq. NSEFeq) is 1.
+  A9  M_2G uses form (a) of eq. M2GComput with the full S_2 block.
+  A10 boundaries: halfway bounce-back at wall faces and solid nodes.
+  A11 nu_b < 0 selects 2 nu / d (eq. 4-27-1 with a = 0, Remark V of Sec. IV).
+  A14 NCDE: D = phi I, beta = 1, K = D(phi) I with D(phi) = D0 (1 + D2 phi^2),
+      B = phi u_adv with constant u_adv, C = phi u_adv u_adv.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# --------------------------------------------------------------------------
+# Lattices: integer unit offsets e_j; c_j = e_j (.) (dx_a / dt)  (Sec. III)
+# --------------------------------------------------------------------------
+
+# rD2Q9, eq. 3-1 (column order as printed)
+_E_Q9 = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+
+# rD3Q27, eq. 3-2a/b/c; j = 11..14 follow reading A1
+_E_Q27 = [
+    (0, 0, 0),
+    (1, 0, 0), (0, 1, 0), (0, 0, 1), (-1, 0, 0), (0, -1, 0), (0, 0, -1),
+    (1, 1, 0), (-1, 1, 0), (-1, -1, 0), (1, -1, 0),
+    (1, 0, 1), (-1, 0, 1), (-1, 0, -1), (1, 0, -1),
+    (0, 1, 1), (0, -1, 1), (0, -1, -1), (0, 1, -1),
+    (1, 1, 1), (1, 1, -1), (1, -1, 1), (-1, 1, 1),
+    (-1, -1, -1), (-1, -1, 1), (-1, 1, -1), (1, -1, -1),
+]
+
+WALL_XM, WALL_XP, WALL_YM, WALL_YP, WALL_ZM, WALL_ZP = 1, 2, 4, 8, 16, 32
+
+
+def unit_offsets(lattice: str) -> np.ndarray:
+    """Integer offsets e_j, shape (q, d). rD3Q19 = first 19 of rD3Q27 (Sec. III)."""
+    if lattice == "Q9":
+        return np.array(_E_Q9, dtype=np.int64)
+    if lattice == "Q27":
+        return np.array(_E_Q27, dtype=np.int64)
+    if lattice == "Q19":
+        return np.array(_E_Q27[:19], dtype=np.int64)
+    raise ValueError(lattice)
+
+
+def opposite(E: np.ndarray) -> np.ndarray:
+    """opp[j] = index k with e_k = -e_j (brute force search)."""
+    q = E.shape[0]
+    opp = np.empty(q, dtype=np.int64)
+    for j in range(q):
+        hits = [k for k in range(q) if np.all(E[k] == -E[j])]
+        assert len(hits) == 1
+        opp[j] = hits[0]
+    return opp
+
+
+def weights(lattice: str, c: np.ndarray, cs2: float, w_corner: float | None = None) -> np.ndarray:
+    """Weights of eq. 3-3-5 (rD2Q9) and eq. 3-3-8 (rD3Q27; rD3Q19 has omega_19 = 0)."""
+    c = np.asarray(c, dtype=np.float64)
+    r = cs2 / c**2
+    if lattice == "Q9":
+        w5 = r[0] * r[1] / 4.0
+        w1 = r[0] / 2.0 - 2.0 * w5
+        w2 = r[1] / 2.0 - 2.0 * w5
+        w = np.array([0.0, w1, w2, w1, w2, w5, w5, w5, w5])
+    else:
+        if lattice == "Q19":
+            w19 = 0.0
+        else:
+            w19 = r[0] * r[1] * r[2] / 8.0 if (w_corner is None or w_corner < 0) else float(w_corner)
+        w7 = r[0] * r[1] / 4.0 - 2.0 * w19
+        w11 = r[0] * r[2] / 4.0 - 2.0 * w19
+        w15 = r[1] * r[2] / 4.0 - 2.0 * w19
+        w1 = r[0] / 2.0 - 2.0 * (w7 + w11) - 4.0 * w19
+        w2 = r[1] / 2.0 - 2.0 * (w7 + w15) - 4.0 * w19
+        w3 = r[2] / 2.0 - 2.0 * (w11 + w15) - 4.0 * w19
+        w = [0.0, w1, w2, w3, w1, w2, w3] + [w7] * 4 + [w11] * 4 + [w15] * 4
+        if lattice == "Q27":
+            w += [w19] * 8
+        w = np.array(w)
+    w[0] = 1.0 - w[1:].sum()
+    return w
+
+
+def moment_exponents(lattice: str) -> list[tuple[int, ...]]:
+    """Raw-moment rows c_x^a c_y^b (c_z^p), exponents in {0,1,2} (eq. 5-2).
+
+    rD2Q9 rows follow the printed factorisation M = D M~ (eq. Md2q9); 3D rows
+    follow reading A4 (by total degree, diagonal second moments first)."""
+    if lattice == "Q9":
+        return [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (1, 1), (1, 2), (2, 1), (2, 2)]
+    rows = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1),
+            (2, 0, 0), (0, 2, 0), (0, 0, 2), (1, 1, 0), (1, 0, 1), (0, 1, 1),
+            (2, 1, 0), (2, 0, 1), (1, 2, 0), (0, 2, 1), (1, 0, 2), (0, 1, 2), (1, 1, 1),
+            (2, 2, 0), (2, 0, 2), (0, 2, 2), (2, 1, 1), (1, 2, 1), (1, 1, 2),
+            (2, 2, 1), (2, 1, 2), (1, 2, 2), (2, 2, 2)]
+    if lattice == "Q19":
+        rows = [r for r in rows if sum(1 for k in r if k > 0) <= 2]
+    return rows
+
+
+def moment_matrix(C: np.ndarray, exps) -> np.ndarray:
+    """M[i, j] = prod_a C[j, a] ** exps[i][a]  (eq. 5-2)."""
+    q = C.shape[0]
+    M = np.ones((len(exps), q))
+    for i, ex in enumerate(exps):
+        for a, k in enumerate(ex):
+            M[i] *= C[:, a] ** k
+    return M
+
+
+def g_eq(C, w, c, cs2, A, B, Mt):
+    """General rectangular equilibrium, eq. 3-3 with eq. 3-4 and c_sa = c_s.
+
+    A: (N,), B: (d, N), Mt: (d, d, N) symmetric.  Returns (q, N).
+    g_j = w_j (A + c~_j . B + Q~_j : M),  c~ = c_j / cs2,
+    Q~_aa = Q_aa / (cs2 (c_a^2 - cs2)),  Q~_ab = Q_ab / (2 cs2^2) (a != b),
+    Q_j = c_j c_j - cs2 I.
+    """
+    q, d = C.shape
+    c = np.asarray(c, dtype=np.float64)
+    Q = np.einsum("ja,jb->jab", C, C) - cs2 * np.eye(d)[None]
+    Qt = np.empty_like(Q)
+    for a in range(d):
+        for b in range(d):
+            if a == b:
+                Qt[:, a, a] = Q[:, a, a] / (cs2 * (c[a] ** 2 - cs2))
+            else:
+                Qt[:, a, b] = Q[:, a, b] / (2.0 * cs2 * cs2)
+    ct = C / cs2
+    return w[:, None] * (A[None, :] + ct @ B + np.einsum("jab,abn->jn", Qt, Mt))
+
+
+# --------------------------------------------------------------------------
+# Relaxation rates and the second-order block (Sec. IV eq. 4-27 .. 4-31, Sec. V eq. 5-8)
+# --------------------------------------------------------------------------
+
+def nse_rates(c, cs2, nu, nu_b, d, dt=1.0):
+    """Solve eq. 4-31 for the rates: s_ab (off-diagonal), s_s,a and s_b,a."""
+    c = np.asarray(c, dtype=np.float64)
+    s_ab = 1.0 / (0.5 + nu / (cs2 * dt))
+    s_s = 1.0 / (0.5 + 2.0 * nu / ((c**2 - cs2) * dt))
+    s_b = 1.0 / (0.5 + d * nu_b / ((c**2 - cs2) * dt))
+    return s_ab, s_s, s_b
+
+
+def S2_inverse_block(c, cs2, s_s, s_b, d):
+    """S_2^(1) = diag(1/s_s) + a b^T / d of eq. 4-27-1."""
+    c = np.asarray(c, dtype=np.float64)
+    a = (1.0 / s_b - 1.0 / s_s) * (c**2 - cs2)
+    b = 1.0 / (c**2 - cs2)
+    return np.diag(1.0 / s_s) + np.outer(a, b) / d
+
+
+def S2_sherman_morrison(c, cs2, s_s, s_b, d):
+    """Closed-form inverse of eq. 5-8-1: A - A a~ b^T A / (1 + b^T A a~)."""
+    c = np.asarray(c, dtype=np.float64)
+    A = np.diag(s_s)
+    a = (1.0 / s_b - 1.0 / s_s) * (c**2 - cs2)
+    abar = a / d
+    b = 1.0 / (c**2 - cs2)
+    return A - (A @ np.outer(abar, b) @ A) / (1.0 + b @ A @ abar)
+
+
+# --------------------------------------------------------------------------
+# Model
+# --------------------------------------------------------------------------
+
+DEFAULTS = dict(lattice="Q9", equation="NSE", n=(8, 8, 1), dx=(1.0, 1.0, 1.0), dt=1.0,
+                cs2=-1.0, nu=0.1, nu_b=-1.0, s_hi=-1.0, w_corner=-1.0,
+                D0=0.0, D2=0.0, adv=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0),
+                source=0.0, rho0=1.0, wall_faces=0)
+
+
+class Model:
+    """Dense FP64 RMRT-LB model for one rectangular domain."""
+
+    def __init__(self, params: dict, solid: np.ndarray | None = None):
+        p = dict(DEFAULTS)
+        p.update(params)
+        self.p = p
+        self.lattice = p["lattice"]
+        self.nse = p["equation"] == "NSE"
+        E = unit_offsets(self.lattice)
+        self.E = E
+        self.q, self.d = E.shape
+        nx, ny, nz = (int(v) for v in p["n"])
+        if self.d == 2:
+            assert nz == 1
+        self.shape = (nx, ny, nz)
+        self.N = nx * ny * nz
+        self.dt = float(p["dt"])
+        c = np.array(p["dx"][: self.d], dtype=np.float64) / self.dt          # c_a = dx_a / dt
+        self.c = c
+        cs2 = float(p["cs2"])
+        if cs2 <= 0:
+            cs2 = float(np.min(c**2)) / 3.0                                    # A2
+        self.cs2 = cs2
+        self.C = E * c[None, :]
+        self.opp = opposite(E)
+        self.w = weights(self.lattice, c, cs2, p["w_corner"])
+        self.exps = moment_exponents(self.lattice)
+        self.M = moment_matrix(self.C, self.exps)
+        self.Minv = np.linalg.inv(self.M)
+        self.order = np.array([sum(e) for e in self.exps])
+        self.rho0 = float(p["rho0"])
+        self.force = np.array(p["force"][: self.d], dtype=np.float64)
+        self.source = float(p["source"])
+        self.adv = np.array(p["adv"][: self.d], dtype=np.float64)
+        d, q = self.d, self.q
+        row = {e: i for i, e in enumerate(self.exps)}
+        unit = [tuple(1 if k == a else 0 for k in range(d)) for a in range(d)]
+        self.row0 = row[tuple([0] * d)]
+        self.rows1 = [row[unit[a]] for a in range(d)]
+        self.rows2d = [row[tuple(2 * v for v in unit[a])] for a in range(d)]
+        self.pairs = [(a, b) for a in range(d) for b in range(a + 1, d)]
+        self.rows2o = [row[tuple(unit[a][k] + unit[b][k] for k in range(d))] for a, b in self.pairs]
+
+        S = np.zeros((q, q))
+        if self.nse:
+            nu = float(p["nu"])
+            nu_b = float(p["nu_b"])
+            if nu_b < 0:
+                nu_b = 2.0 * nu / d                                            # A11
+            self.nu, self.nu_b = nu, nu_b
+            s_ab, s_s, s_b = nse_rates(c, cs2, nu, nu_b, d, self.dt)
+            self.s_ab, self.s_s, self.s_b = s_ab, s_s, s_b
+            self.S2inv1 = S2_inverse_block(c, cs2, s_s, s_b, d)
+            self.Sbar21 = np.linalg.inv(self.S2inv1)                           # eq. 5-8-1 (numeric)
+            s_hi = float(p["s_hi"])
+            if s_hi <= 0:
+                s_hi = s_ab                                                    # A5
+            self.s_hi = s_hi
+            for i in range(q):
+                if self.order[i] == 0 or self.order[i] == 1:
+                    S[i, i] = 1.0                                              # A6
+                elif self.order[i] >= 3:
+                    S[i, i] = s_hi
+            for a in range(d):
+                for b in range(d):
+                    S[self.rows2d[a], self.rows2d[b]] = self.Sbar21[a, b]
+            for r in self.rows2o:
+                S[r, r] = s_ab
+        else:
+            s_hi = float(p["s_hi"])
+            if s_hi <= 0:
+                s_hi = 1.0                                                     # A5 / A14
+            self.s_hi = s_hi
+            for i in range(q):
+                if self.order[i] == 0:
+                    S[i, i] = 1.0
+                elif self.order[i] >= 2:
+                    S[i, i] = s_hi
+            # order-1 rows carry the local rate s_1(phi), added per node
+        self.S = S
+        self.P1 = np.zeros((q, q))
+        for r in self.rows1:
+            self.P1[r, r] = 1.0
+        self._build_streaming(solid)
+
+    # ---------------------------------------------------------------- geometry
+    def _build_streaming(self, solid):
+        nx, ny, nz = self.shape
+        walls = int(self.p["wall_faces"])
+        if solid is None:
+            solid = np.zeros(self.N, dtype=bool)
+        self.solid = np.asarray(solid, dtype=bool).reshape(self.N)
+        self.fluid = ~self.solid
+        idx = np.arange(self.N)
+        x = idx % nx
+        y = (idx // nx) % ny
+        z = idx // (nx * ny)
+        self.xyz = (x, y, z)
+        E3 = np.zeros((self.q, 3), dtype=np.int64)
+        E3[:, : self.d] = self.E
+        self.target = np.empty((self.q, self.N), dtype=np.int64)
+        self.bounce = np.zeros((self.q, self.N), dtype=bool)
+        dims = (nx, ny, nz)
+        for j in range(self.q):
+            t = [x + E3[j, 0], y + E3[j, 1], z + E3[j, 2]]
+            out_wall = np.zeros(self.N, dtype=bool)
+            for a in range(3):
+                lo = t[a] < 0
+                hi = t[a] >= dims[a]
+                if walls & (1 << (2 * a)):
+                    out_wall |= lo
+                if walls & (1 << (2 * a + 1)):
+                    out_wall |= hi
+                t[a] = np.mod(t[a], dims[a])
+            lin = t[0] + nx * (t[1] + ny * t[2])
+            self.target[j] = lin
+            self.bounce[j] = out_wall | self.solid[lin]
+
+    # -------------------------------------------------------------- equilibria
+    def macroscopic(self, fbar):
+        """rho (or phi) and u from fbar, eq. 2-4-1 / eq. 2-4-2."""
+        if self.nse:
+            rho = fbar.sum(axis=0) + self.dt * self.source / 2.0
+            u = (self.C.T @ fbar + self.dt * self.force[:, None] / 2.0) / rho[None, :]
+            return rho, u
+        phi = fbar.sum(axis=0) + self.dt * self.source / 2.0
+        return phi, np.repeat(self.adv[:, None], fbar.shape[1], axis=1)
+
+    def s1_ncde(self, phi):
+        """Local first-order rate from eq. 4-10 with beta = 1, K = D(phi) I."""
+        D = self.p["D0"] * (1.0 + self.p["D2"] * phi**2)
+        return 1.0 / (0.5 + D / (self.cs2 * self.dt))
+
+    def distributions(self, fbar):
+        """f_eq, F and G of the node states in fbar (eq. NSEfeq/NSEFeq/NSEGeq or eq. 4-14/4-14-1)."""
+        d, n = self.d, fbar.shape[1]
+        I = np.eye(d)[:, :, None]
+        if self.nse:
+            rho, u = self.macroscopic(fbar)
+            feq = g_eq(self.C, self.w, self.c, self.cs2, rho, rho[None] * u,
+                       rho[None, None] * np.einsum("an,bn->abn", u, u))
+            Sb, Fb = self.source, self.force
+            F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, Sb),
+                     np.repeat(Fb[:, None], n, axis=1), -self.cs2 * Sb * np.repeat(I, n, axis=2))
+            T = (np.einsum("an,b->abn", u, Fb) + np.einsum("a,bn->abn", Fb, u)
+                 + self.cs2 * Sb * np.repeat(I, n, axis=2))
+            M2G = self._apply_I_minus_half_S2(T)
+            G = g_eq(self.C, self.w, self.c, self.cs2, np.zeros(n), np.zeros((d, n)), M2G)
+            return feq, F, G, None
+        phi, u = self.macroscopic(fbar)
+        B = phi[None] * u
+        feq = g_eq(self.C, self.w, self.c, self.cs2, phi, B,
+                   phi[None, None] * np.einsum("an,bn->abn", u, u))
+        S = self.source
+        F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, S), np.zeros((d, n)), np.zeros((d, d, n)))
+        s1 = self.s1_ncde(phi)
+        M1G = (1.0 - s1[None] / 2.0) * u * S                                   # eq. 4-11, B' = u_adv
+        G = g_eq(self.C, self.w, self.c, self.cs2, np.zeros(n), M1G, np.zeros((d, d, n)))
+        return feq, F, G, s1
+
+    def _second_order_vec(self, T):
+        """Symmetric tensor -> vector over the second-order rows (diagonal then off-diagonal)."""
+        return [T[a, a] for a in range(self.d)] + [T[a, b] for a, b in self.pairs]
+
+    def _apply_I_minus_half_S2(self, T):
+        """(I - S_2/2) acting on the second-order moment rows (eq. M2GComput a)."""
+        rows = self.rows2d + self.rows2o
+        S22 = self.S[np.ix_(rows, rows)]
+        v = np.array(self._second_order_vec(T))
+        v2 = v - 0.5 * np.einsum("ij,jn->in", S22, v)
+        out = np.zeros_like(T)
+        for a in range(self.d):
+            out[a, a] = v2[a]
+        for k, (a, b) in enumerate(self.pairs):
+            out[a, b] = v2[self.d + k]
+            out[b, a] = v2[self.d + k]
+        return out
+
+    def apply_S(self, x, s1=None):
+        """S x with S the block relaxation matrix; NCDE adds s_1(phi) on the first-order rows."""
+        y = self.S @ x
+        if s1 is not None:
+            y = y + s1[None, :] * (self.P1 @ x)
+        return y
+
+    # --------------------------------------------------------------- collision
+    def collide(self, fbar):
+        """Post-collision fbar* in moment space, eq. 2-2-3 (before propagation)."""
+        feq, F, G, s1 = self.distributions(fbar)
+        m = self.M @ fbar
+        meq = self.M @ feq
+        mF = self.M @ F
+        mG = self.M @ G
+        mstar = m - self.apply_S(m - meq, s1) + self.dt * (mG + mF - 0.5 * self.apply_S(mF, s1))
+        return np.linalg.solve(self.M, mstar)
+
+    def collide_velocity_space(self, fbar):
+        """Same collision written in velocity space with Lambda = M^-1 S M (eq. 2-3, eq. 5-1)."""
+        feq, F, G, s1 = self.distributions(fbar)
+
+        def Lam(x):
+            return self.Minv @ self.apply_S(self.M @ x, s1)
+
+        return fbar - Lam(fbar - feq) + self.dt * (G + F - 0.5 * Lam(F))
+
+    # ------------------------------------------------------------- propagation
+    def stream(self, fstar, fprev):
+        """Propagation (eq. 2-2) with halfway bounce-back (reading A10).
+
+        Fluid nodes push fstar_j to x + e_j; a population whose target is a
+        wall or a solid node returns to its own node in direction opp(j).
+        Solid nodes keep their previous content."""
+        out = fprev.copy()
+        fl = self.fluid
+        for j in range(self.q):
+            go = fl & ~self.bounce[j]
+            out[j, self.target[j, go]] = fstar[j, go]
+            back = fl & self.bounce[j]
+            out[self.opp[j], back] = fstar[j, back]
+        return out
+
+    def step(self, fbar, nsteps=1):
+        for _ in range(nsteps):
+            fstar = fbar.copy()
+            fstar[:, self.fluid] = self.collide(fbar[:, self.fluid])
+            fbar = self.stream(fstar, fbar)
+        return fbar
+
+    # ---------------------------------------------------------- initialisation
+    def init(self, rho, u, with_fne=False):
+        """fbar(t=0) = f_eq(rho, u) - dt F / 2 [+ f_ne from eq. fne].
+
+        rho (or phi): (N,); u: (d, N) (ignored for the NCDE, which uses u_adv)."""
+        n = self.N
+        d = self.d
+        rho = np.asarray(rho, dtype=np.float64).reshape(n)
+        I = np.eye(d)[:, :, None]
+        if self.nse:
+            u = np.asarray(u, dtype=np.float64).reshape(d, n)
+            Mt = rho[None, None] * np.einsum("an,bn->abn", u, u)
+            if with_fne:
+                Mt = Mt + self.m2_ne(rho, u)
+            feq = g_eq(self.C, self.w, self.c, self.cs2, rho, rho[None] * u, Mt)
+            Sb, Fb = self.source, self.force
+            F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, Sb),
+                     np.repeat(Fb[:, None], n, axis=1), -self.cs2 * Sb * np.repeat(I, n, axis=2))
+        else:
+            u = np.repeat(self.adv[:, None], n, axis=1)
+            feq = g_eq(self.C, self.w, self.c, self.cs2, rho, rho[None] * u,
+                       rho[None, None] * np.einsum("an,bn->abn", u, u))
+            F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, self.source),
+                     np.zeros((d, n)), np.zeros((d, d, n)))
+        return feq - 0.5 * self.dt * F
+
+    def velocity_gradient(self, u):
+        """grad[a, b] = d u_a / d x_b; central differences, one-sided next to walls/solids."""
+        d, n = self.d, self.N
+        nx, ny, nz = self.shape
+        walls = int(self.p["wall_faces"])
+        x, y, z = self.xyz
+        coords = [x, y, z]
+        dims = (nx, ny, nz)
+        g = np.zeros((d, d, n))
+        for b in range(d):
+            nbr = []
+            for s in (+1, -1):
+                t = [x.copy(), y.copy(), z.copy()]
+                t[b] = coords[b] + s
+                ok = np.ones(n, dtype=bool)
+                if s < 0 and (walls & (1 << (2 * b))):
+                    ok &= t[b] >= 0
+                if s > 0 and (walls & (1 << (2 * b + 1))):
+                    ok &= t[b] < dims[b]
+                t[b] = np.mod(t[b], dims[b])
+                lin = t[0] + nx * (t[1] + ny * t[2])
+                ok &= self.fluid[lin]
+                nbr.append((lin, ok))
+            (lp, okp), (lm, okm) = nbr
+            h = self.c[b] * self.dt
+            for a in range(d):
+                both = okp & okm
+                g[a, b, both] = (u[a, lp[both]] - u[a, lm[both]]) / (2 * h)
+                po = okp & ~okm
+                g[a, b, po] = (u[a, lp[po]] - u[a, po]) / h
+                mo = okm & ~okp
+                g[a, b, mo] = (u[a, mo] - u[a, lm[mo]]) / h
+        return g
+
+    def m2_ne(self, rho, u):
+        """m_2^ne = -(I - S_2/2)^-1 tau - dt/2 (u F + F u + cs2 S I)  (eq. 4-34, eq. 4-28)."""
+        d, n = self.d, self.N
+        g = self.velocity_gradient(u)
+        div = np.einsum("aan->n", g)
+        I = np.eye(d)[:, :, None]
+        tau = (rho[None, None] * self.nu * (g + g.transpose(1, 0, 2) - (2.0 / d) * div[None, None] * I)
+               + rho[None, None] * self.nu_b * div[None, None] * I)
+        rows = self.rows2d + self.rows2o
+        S22 = self.S[np.ix_(rows, rows)]
+        K = np.linalg.inv(np.eye(len(rows)) - 0.5 * S22)
+        v = np.einsum("ij,jn->in", K, np.array(self._second_order_vec(tau)))
+        out = np.zeros((d, d, n))
+        for a in range(d):
+            out[a, a] = -v[a]
+        for k, (a, b) in enumerate(self.pairs):
+            out[a, b] = -v[d + k]
+            out[b, a] = -v[d + k]
+        Fb, Sb = self.force, self.source
+        out -= 0.5 * self.dt * (np.einsum("an,b->abn", u, Fb) + np.einsum("a,bn->abn", Fb, u)
+                                + self.cs2 * Sb * I)
+        return out
+
+
+# --------------------------------------------------------------------------
+# Closed-form solutions used to pin the oracle (exact solutions of the PDEs the
+# scheme recovers: eq. NSE, eq. 4-15)
+# --------------------------------------------------------------------------
+
+def gaussian_hill(xp, yp, t, sigma0, D, xc, yc, adv, Lx, Ly, images=2):
+    """2D advected Gaussian with constant diffusivity on a periodic box (peak 1 at t = 0)."""
+    s2 = sigma0**2 + 2.0 * D * t
+    amp = sigma0**2 / s2
+    out = np.zeros_like(xp, dtype=np.float64)
+    for i in range(-images, images + 1):
+        for k in range(-images, images + 1):
+            dx = xp - (xc + adv[0] * t) - i * Lx
+            dy = yp - (yc + adv[1] * t) - k * Ly
+            out += amp * np.exp(-(dx**2 + dy**2) / (2.0 * s2))
+    return out
+
+
+def poiseuille(yc, H, g, nu):
+    """Plane channel profile u(y) = g y (H - y) / (2 nu)."""
+    return g * yc * (H - yc) / (2.0 * nu)
