@@ -1,0 +1,236 @@
+/*
+ * rmrt.h -- C ABI of the MI355X (gfx950) rectangular multiple-relaxation-time
+ * lattice Boltzmann library (RMRT-LB of Chai, Yuan & Shi, arXiv:2206.00366).
+ *
+ * One call of rmrt_step advances every node by the evolution equation in its
+ * moment-space form (Sec. V eq. 2-2-3, with fbar = f - dt F / 2 of Sec. II
+ * eq. 2-3): raw moments m = M fbar (eq. 5-2), relaxation with the block
+ * relaxation matrix S whose second-order block comes from the shear and bulk
+ * viscosities (Sec. IV eq. 4-27, 4-31; Sec. V eq. 5-8), back-transform
+ * M^-1 (eq. 5-4), then propagation f(x + c_j dt) (Sec. II eq. 2-2).
+ *
+ * Conventions shared by every entry point
+ *   - Lattice units: c_a = dx_a / dt.  Nodes are indexed x-fastest:
+ *     node = x + nx * (y + ny * z); 2D problems use nz = 1.
+ *   - Population buffers are structure-of-arrays: slot j of node i lives at
+ *     element j * N + i (N = nx*ny*nz), j in the paper's velocity order
+ *     (rD2Q9 eq. 3-1, rD3Q27 eq. 3-2; rD3Q19 = first 19 of rD3Q27).
+ *   - Stored values are deviations from the rest equilibrium:
+ *       RMRT_F64    : double  d_j = fbar_j - w_j rho0
+ *       RMRT_F32DEV : float   d_j = fbar_j - w_j rho0
+ *       RMRT_F16DEV : _Float16 h_j = (fbar_j - w_j rho0) / w_j  (round to nearest even)
+ *     (rho0 is the reference density of the NSE, or the reference phi of the
+ *     NCDE, usually 0.)
+ *   - Every device pointer is caller-owned device memory borrowed for the
+ *     lifetime of the context; the library owns only the context, its device
+ *     parameter block, reduction scratch and any captured graph.
+ *   - Every call is ordered on the caller's hipStream_t (passed as void*;
+ *     NULL = the default stream).  Only rmrt_reduce and rmrt_residual
+ *     synchronise that stream, to return their FP64 results to the host.
+ *   - Every function returns RMRT_OK (0) or a negative RMRT_E* code; a
+ *     thread-local message is available from rmrt_last_error().  Nothing
+ *     throws across the ABI.
+ */
+#ifndef RMRT_H
+#define RMRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define RMRT_OK 0
+#define RMRT_EINVAL (-1)        /* invalid argument or parameter set            */
+#define RMRT_EUNSUPPORTED (-2)  /* valid but not built (e.g. Q9 with nz > 1)    */
+#define RMRT_EHIP (-3)          /* a HIP runtime call failed                    */
+#define RMRT_ENONFINITE (-4)    /* a reduction found NaN or Inf                 */
+#define RMRT_ENOMEM (-5)        /* host or device allocation failed             */
+
+/* ---- enumerations ---- */
+enum { RMRT_Q9 = 0, RMRT_Q19 = 1, RMRT_Q27 = 2 };                  /* rD2Q9, rD3Q19, rD3Q27 */
+enum { RMRT_NSE = 0, RMRT_NCDE = 1 };                              /* Sec. IV B / IV A      */
+enum { RMRT_F64 = 0, RMRT_F32DEV = 1, RMRT_F16DEV = 2 };           /* population storage    */
+enum { RMRT_AB = 0, RMRT_AA = 1 };                                 /* two-lattice / in-place */
+enum { RMRT_OUT_F64 = 0, RMRT_OUT_F32 = 1 };                       /* macroscopic outputs   */
+
+/* wall_faces bits: 1 = halfway bounce-back wall on that face, 0 = periodic */
+#define RMRT_WALL_XM 1u
+#define RMRT_WALL_XP 2u
+#define RMRT_WALL_YM 4u
+#define RMRT_WALL_YP 8u
+#define RMRT_WALL_ZM 16u
+#define RMRT_WALL_ZP 32u
+
+/*
+ * Parameters of one rectangular domain.  Zero or negative values of the
+ * "default" fields select the documented defaults.
+ *
+ *   lattice, equation, storage, pattern : enumerations above
+ *   n[3]      nodes per axis (n[2] = 1 for rD2Q9)
+ *   dx[3]     grid spacings dx_a; dt time step (<= 0 -> 1)          (Sec. III)
+ *   cs2       sound speed squared c_s^2 (<= 0 -> min_a c_a^2 / 3); must satisfy
+ *             0 < c_s^2 / c_a^2 < 1 (eq. 3-3-3 / eq. 3-3-8 bounds)
+ *   nu, nu_b  kinematic shear and bulk viscosity (NSE; nu_b < 0 -> 2 nu / d,
+ *             which makes the second-order block diagonal, Remark V of Sec. IV)
+ *   s_hi      rate of every moment of order >= 3 (NSE, <= 0 -> s_nu) or >= 2
+ *             (NCDE, <= 0 -> 1); these rates do not enter the recovered PDE
+ *   w_corner  rD3Q27 omega_19 (< 0 -> r1 r2 r3 / 8, r_a = c_s^2 / c_a^2)
+ *   D0, D2    NCDE diffusivity D(phi) = D0 (1 + D2 phi^2); K = D(phi) I
+ *             through the local first-order rate (eq. 4-10, beta = 1)
+ *   adv[3]    NCDE constant advection velocity: B = phi adv (eq. NCDE)
+ *   force[3]  NSE body-force density Fbar (eq. NSE), constant in space
+ *   source    NSE mass source Sbar, or NCDE source S, constant in space
+ *   rho0      reference density (NSE) or reference phi (NCDE) of the stored
+ *             deviations
+ *   wall_faces RMRT_WALL_* bits (halfway bounce-back); other faces periodic
+ *   check_every if > 0, rmrt_step runs an FP64 mass check every that many
+ *             steps and returns RMRT_ENONFINITE when it is not finite
+ */
+typedef struct rmrt_params {
+  int lattice, equation, storage, pattern;
+  int n[3];
+  double dx[3];
+  double dt;
+  double cs2;
+  double nu, nu_b, s_hi;
+  double w_corner;
+  double D0, D2;
+  double adv[3];
+  double force[3];
+  double source;
+  double rho0;
+  unsigned wall_faces;
+  int check_every;
+} rmrt_params;
+
+/* Values the library derives from a parameter set (host only, no GPU). */
+typedef struct rmrt_derived {
+  int q, d;
+  double c[3], cs2;
+  double w[27];           /* weights, paper order (eq. 3-3-5, eq. 3-3-8)          */
+  double s_nu, s_s[3], s_b[3], s_hi;  /* rates from eq. 4-31                      */
+  double Sbar2[3][3];     /* second-order diagonal block, eq. 5-8-1                */
+  double nu_b;
+} rmrt_derived;
+
+typedef struct rmrt_ctx rmrt_ctx;
+typedef struct rmrt_batch rmrt_batch;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* rmrt_last_error(void);
+
+/* Library version string. */
+const char* rmrt_version(void);
+
+/*
+ * Validate a parameter set and fill *out with the derived lattice weights and
+ * relaxation rates (Sec. III eq. 3-3-5 / 3-3-8; Sec. IV eq. 4-31; Sec. V
+ * eq. 5-8-1).  Host only.  Returns RMRT_EINVAL for: an unknown enumeration,
+ * n < 1, rD2Q9 with n[2] != 1, dx <= 0, c_s^2 >= c_a^2 on any axis, a negative
+ * weight, nu <= 0 or nu_b <= 0 (NSE), D0 <= 0 (NCDE) or a rate outside (0, 2).
+ */
+int rmrt_derive(const rmrt_params* p, rmrt_derived* out);
+
+/* Bytes of one population buffer for p (q * N * element size). Host only. */
+int rmrt_population_bytes(const rmrt_params* p, size_t* bytes);
+
+/*
+ * Create a context for one domain and write the initial populations.
+ *   f0, f1  device population buffers (rmrt_population_bytes each); f1 must be
+ *           NULL for RMRT_AA and non-NULL for RMRT_AB
+ *   solid   device uint8 mask of N nodes (1 = solid, bounce-back), or NULL
+ *   rho     device double[N]: initial rho (NSE) or phi (NCDE)
+ *   u       device double[d*N] SoA initial velocity (NSE; ignored by the NCDE)
+ *   with_fne 1 adds the non-equilibrium part g_eq(0, 0, m_2^ne) built from the
+ *           central-difference velocity gradient (Sec. IV eq. fne, eq. 4-34)
+ * The initial state is fbar = f_eq(rho, u) - dt F / 2 [+ f_ne] (eq. NSEfeq,
+ * eq. NSEFeq, eq. 2-3).  Asynchronous on stream.
+ */
+int rmrt_init(rmrt_ctx** out, const rmrt_params* p, void* f0, void* f1, const uint8_t* solid,
+              const double* rho, const double* u, int with_fne, void* stream);
+
+/* Re-initialise the populations of an existing context (same meaning as in rmrt_init). */
+int rmrt_set_fields(rmrt_ctx* ctx, const double* rho, const double* u, int with_fne, void* stream);
+
+/*
+ * Advance nsteps >= 0 time steps (eq. 2-2-3 then propagation with halfway
+ * bounce-back).  nsteps > 1 replays a HIP graph of nsteps launches that is
+ * captured on first use and cached per (nsteps, parity).
+ */
+int rmrt_step(rmrt_ctx* ctx, int nsteps, void* stream);
+
+/*
+ * Macroscopic fields of the current state (eq. 2-4-1 / eq. 2-4-2):
+ * rho (or phi) into rho_out[N]; u into u_out[d*N] SoA (may be NULL).
+ * out_dtype RMRT_OUT_F64 or RMRT_OUT_F32.  Solid nodes are written as rho0, 0.
+ */
+int rmrt_moments(rmrt_ctx* ctx, void* rho_out, void* u_out, int out_dtype, void* stream);
+
+/* Decode the current state into full populations fbar_j (double, q*N, natural layout). */
+int rmrt_populations(rmrt_ctx* ctx, double* f_out, void* stream);
+
+/*
+ * FP64 sums over fluid nodes: out[0] = sum rho (or phi), out[1..3] = sum rho u
+ * (eq. 2-4-2; the mass and momentum that eq. 4-18-1 conserves).  Synchronises
+ * stream.  Returns RMRT_ENONFINITE if any sum is NaN or Inf.
+ */
+int rmrt_reduce(rmrt_ctx* ctx, double out[4], void* stream);
+
+/*
+ * Steady-state residual r = ||u^n - u^prev||_2 / ||u^n||_2 (FP64, fluid nodes)
+ * against the velocity stored by the previous call on this context; the first
+ * call stores u and returns r = +inf.  Synchronises stream.
+ */
+int rmrt_residual(rmrt_ctx* ctx, double* r, void* stream);
+
+/* Number of steps taken since init (the AA pattern's parity is its low bit). */
+int rmrt_steps_taken(const rmrt_ctx* ctx, long long* steps);
+
+/* Release the context (does not free the caller's buffers). */
+int rmrt_free(rmrt_ctx* ctx);
+
+/*
+ * Batched persistent stepping of nd independent domains that share lattice,
+ * equation, storage, pattern and forcing on/off, but not sizes, spacings,
+ * viscosities or walls.  One persistent kernel per step processes a static
+ * list of (domain, node-range) tiles; rmrt_batch_step replays a HIP graph of
+ * nsteps such launches.
+ *   params  array of nd parameter sets
+ *   f0, f1  arrays of nd device population buffers (f1 NULL for RMRT_AA)
+ *   solid   array of nd device masks or NULL (the array or any entry)
+ * Populations are initialised to rest (rho = rho0, u = 0 plus -dt F / 2).
+ */
+int rmrt_batch_create(rmrt_batch** out, int nd, const rmrt_params* params, void* const* f0,
+                      void* const* f1, const uint8_t* const* solid, void* stream);
+
+/* Borrow the context of domain d (for rmrt_set_fields/moments/reduce/residual/populations;
+ * rmrt_step on it returns RMRT_EINVAL).  Owned by the batch. */
+int rmrt_batch_domain(rmrt_batch* b, int d, rmrt_ctx** out);
+
+/*
+ * Time every tile configuration of the built-in candidate list over `steps`
+ * steps each (HIP events on stream), keep the fastest and return its index in
+ * *chosen (may be NULL).  The timing runs advance the state; call
+ * rmrt_set_fields afterwards when the initial state matters.
+ */
+int rmrt_batch_autotune(rmrt_batch* b, int steps, void* stream, int* chosen);
+
+/* Select tile configuration `cfg` (0 .. rmrt_batch_num_configs()-1) explicitly. */
+int rmrt_batch_set_config(rmrt_batch* b, int cfg);
+int rmrt_batch_num_configs(void);
+/* Describe configuration cfg: threads per block, nodes per tile, blocks per CU. */
+int rmrt_batch_config_info(int cfg, int* threads, int* tile_nodes, int* blocks_per_cu);
+
+/* Advance every domain nsteps steps (graph replay of persistent launches). */
+int rmrt_batch_step(rmrt_batch* b, int nsteps, void* stream);
+
+int rmrt_batch_free(rmrt_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RMRT_H */

@@ -1,0 +1,322 @@
+// Device-side building blocks of the RMRT-LB step for gfx950.
+//
+// The collision works on raw moments (Sec. V eq. 5-2) of the stored
+// deviations d_j = fbar_j - w_j rho0.  Because every lattice here is a subset
+// of the 3^d tensor-product velocity set, M = D M~ (eq. Md2q9) factorises per
+// axis: with the three populations (f-, f0, f+) of one lattice line,
+//     (f- + f0 + f+,  f+ - f-,  f+ + f-)
+// are the exponent-0/1/2 entries of M~ f, and the inverse is
+//     f0 = mu0 - mu2,  f+- = (mu2 +- mu1) / 2.
+// The kernel keeps the moments in that integer-matrix ("scaled") basis; the
+// diagonal D is folded into host-side coefficient tables.  rD3Q19 runs the
+// 27-slot transform with the 8 corner populations and the 8 moments with three
+// non-zero exponents fixed at zero (those monomials vanish on rD3Q19, so the
+// embedded inverse returns zero corners).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "lbm_params.hpp"
+
+namespace rmrt {
+
+// ----------------------------------------------------------------------------
+// Lattices (paper velocity order; rD3Q27 edges j = 11..14 per the repaired
+// x-z block of eq. 3-2b)
+// ----------------------------------------------------------------------------
+constexpr int kE27[27][3] = {
+    {0, 0, 0},   {1, 0, 0},   {0, 1, 0},  {0, 0, 1},   {-1, 0, 0},  {0, -1, 0}, {0, 0, -1},
+    {1, 1, 0},   {-1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {1, 0, 1},   {-1, 0, 1}, {-1, 0, -1},
+    {1, 0, -1},  {0, 1, 1},   {0, -1, 1}, {0, -1, -1}, {0, 1, -1},  {1, 1, 1},  {1, 1, -1},
+    {1, -1, 1},  {-1, 1, 1},  {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {1, -1, -1}};
+constexpr int kE9[9][3] = {{0, 0, 0}, {1, 0, 0},  {0, 1, 0},   {-1, 0, 0}, {0, -1, 0},
+                           {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+
+template <int L>
+struct Lat {
+  static constexpr int D = (L == LAT_Q9) ? 2 : 3;
+  static constexpr int Q = (L == LAT_Q9) ? 9 : (L == LAT_Q19 ? 19 : 27);
+  static constexpr int NS = (L == LAT_Q9) ? 9 : 27;  // tensor slots
+  static constexpr int e(int j, int a) { return (L == LAT_Q9) ? kE9[j][a] : kE27[j][a]; }
+  static constexpr int slot(int j) {
+    return (e(j, 0) + 1) + 3 * (e(j, 1) + 1) + (D == 3 ? 9 * (e(j, 2) + 1) : 0);
+  }
+  static constexpr int opp(int j) {
+    for (int k = 0; k < Q; ++k)
+      if (e(k, 0) == -e(j, 0) && e(k, 1) == -e(j, 1) && e(k, 2) == -e(j, 2)) return k;
+    return -1;
+  }
+  // moment slot with three non-zero exponents: not a moment of rD3Q19
+  static constexpr bool dropped(int n) {
+    return L == LAT_Q19 && (n % 3) != 0 && ((n / 3) % 3) != 0 && (n / 9) != 0;
+  }
+  // population slot not present in the lattice (rD3Q19 corners)
+  static constexpr bool absent(int s) {
+    return L == LAT_Q19 && (s % 3) != 1 && ((s / 3) % 3) != 1 && (s / 9) != 1;
+  }
+};
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Storage: decode/encode of the stored deviations
+// ----------------------------------------------------------------------------
+template <int ST>
+struct Store;
+template <>
+struct Store<ST_F64> {
+  using S = double;
+  using T = double;
+  template <int J>
+  __device__ static __forceinline__ T dec(S v, const Coef<T>&) { return v; }
+  template <int J>
+  __device__ static __forceinline__ S enc(T v, const Coef<T>&) { return v; }
+};
+template <>
+struct Store<ST_F32> {
+  using S = float;
+  using T = float;
+  template <int J>
+  __device__ static __forceinline__ T dec(S v, const Coef<T>&) { return v; }
+  template <int J>
+  __device__ static __forceinline__ S enc(T v, const Coef<T>&) { return v; }
+};
+template <>
+struct Store<ST_F16> {
+  using S = _Float16;
+  using T = float;
+  // h_j = d_j / w_j keeps every slot well inside the normal half range
+  template <int J>
+  __device__ static __forceinline__ T dec(S v, const Coef<T>& C) { return (float)v * C.w[J]; }
+  template <int J>
+  __device__ static __forceinline__ S enc(T v, const Coef<T>& C) { return (_Float16)(v * C.iw[J]); }
+};
+
+template <typename T>
+__device__ __forceinline__ const Coef<T>& coef(const DomainDev& D);
+template <>
+__device__ __forceinline__ const Coef<double>& coef<double>(const DomainDev& D) { return D.cd; }
+template <>
+__device__ __forceinline__ const Coef<float>& coef<float>(const DomainDev& D) { return D.cf; }
+
+// ----------------------------------------------------------------------------
+// Per-axis factorised transforms on 3^D tensor slots
+// ----------------------------------------------------------------------------
+template <int D, typename T, int NS>
+__device__ __forceinline__ void moments_fwd(T (&t)[NS]) {
+  static_for<0, D>([&](auto ax_) {
+    constexpr int ax = decltype(ax_)::value;
+    constexpr int st = ax == 0 ? 1 : (ax == 1 ? 3 : 9);
+    static_for<0, NS>([&](auto b_) {
+      constexpr int b = decltype(b_)::value;
+      if constexpr ((b / st) % 3 == 0) {
+        const T m = t[b], z = t[b + st], p = t[b + 2 * st];
+        const T s = m + p;
+        t[b] = s + z;
+        t[b + st] = p - m;
+        t[b + 2 * st] = s;
+      }
+    });
+  });
+}
+
+template <int D, typename T, int NS>
+__device__ __forceinline__ void moments_inv(T (&t)[NS]) {
+  static_for<0, D>([&](auto ax_) {
+    constexpr int ax = decltype(ax_)::value;
+    constexpr int st = ax == 0 ? 1 : (ax == 1 ? 3 : 9);
+    static_for<0, NS>([&](auto b_) {
+      constexpr int b = decltype(b_)::value;
+      if constexpr ((b / st) % 3 == 0) {
+        const T m0 = t[b], m1 = t[b + st], m2 = t[b + 2 * st];
+        t[b] = T(0.5) * (m2 - m1);
+        t[b + st] = m0 - m2;
+        t[b + 2 * st] = T(0.5) * (m2 + m1);
+      }
+    });
+  });
+}
+
+// Scaled raw moment n of g_eq(A, B, M) (eq. 3-3): only the terms that the
+// lattice parity leaves non-zero are emitted.  Md = (Mxx, Myy, Mzz),
+// Mo = (Mxy, Mxz, Myz).
+template <int L, int n, typename T>
+__device__ __forceinline__ T gmom(const Coef<T>& C, T A, const T (&B)[3], const T (&Md)[3],
+                                  const T (&Mo)[3]) {
+  constexpr int a = n % 3, b = (n / 3) % 3, p = n / 9;
+  constexpr int nodd = (a & 1) + (b & 1) + (p & 1);
+  if constexpr (Lat<L>::dropped(n)) {
+    return T(0);
+  } else if constexpr (nodd == 0) {
+    T r = A * C.E0[n];
+    r += Md[0] * C.E2[n][0];
+    r += Md[1] * C.E2[n][1];
+    if constexpr (Lat<L>::D == 3) r += Md[2] * C.E2[n][2];
+    return r;
+  } else if constexpr (nodd == 1) {
+    constexpr int ax = (a & 1) ? 0 : ((b & 1) ? 1 : 2);
+    return B[ax] * C.E1[n];
+  } else if constexpr (nodd == 2) {
+    constexpr int pr = (p & 1) == 0 ? 0 : ((a & 1) ? 1 : 2);  // xy, xz, yz
+    return Mo[pr] * C.E3[n];
+  } else {
+    return T(0);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Collision of one node in deviation variables (eq. 2-2-3):
+//   m* = m - S (m - m_eq') + (m_G + m_F),  m_eq' = m_eq - m_F / 2,
+// with m_eq' = g_eq(rho - Sbar/2, rho u - Fbar/2, rho u u + cs2 Sbar I / 2)
+// and m_G + m_F = g_eq(Sbar, Fbar, M_2G - cs2 Sbar I) for the NSE
+// (eq. NSEfeq, NSEFeq, NSEGeq, M2GComput a), or
+// m_eq' = g_eq(phi - S/2, phi u, phi u u), m_G + m_F = g_eq(S, M_1G, 0) with
+// M_1G = (1 - s1/2) u S for the NCDE (eq. 4-14, 4-14-1, 4-11).
+// t[] holds the deviation populations in tensor slots on entry and the
+// post-collision deviations on exit.  Returns nothing; macroscopic values are
+// recomputed by the moments kernel when needed.
+// ----------------------------------------------------------------------------
+template <int L, int EQ, bool FORCE, typename T, int NS>
+__device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C) {
+  constexpr int D = Lat<L>::D;
+  moments_fwd<D>(t);
+
+  // slots of the first and second moments
+  constexpr int sx = 1, sy = 3, sz = 9;
+  constexpr int sxx = 2, syy = 6, szz = 18;
+  const T drho = t[0];
+  T m1[3];
+  m1[0] = C.c[0] * t[sx];
+  m1[1] = C.c[1] * t[sy];
+  m1[2] = (D == 3) ? C.c[2] * t[sz] : T(0);
+
+  T eA, eB[3], eMd[3], eMo[3];
+  T sA = T(0), sB[3] = {T(0), T(0), T(0)}, sMd[3] = {T(0), T(0), T(0)}, sMo[3] = {T(0), T(0), T(0)};
+  T s1 = T(0);
+  if constexpr (EQ == EQ_NSE) {
+    const T rho = C.rho0 + drho + C.half_source;                       // eq. 2-4-2
+    const T jx = m1[0] + C.half_force[0], jy = m1[1] + C.half_force[1],
+            jz = m1[2] + C.half_force[2];
+    const T ir = T(1) / rho;
+    const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    eA = drho;
+    eB[0] = m1[0];
+    eB[1] = m1[1];
+    eB[2] = m1[2];
+    eMd[0] = jx * ux;
+    eMd[1] = jy * uy;
+    eMd[2] = jz * uz;
+    eMo[0] = jx * uy;
+    eMo[1] = jx * uz;
+    eMo[2] = jy * uz;
+    if constexpr (FORCE) {
+      const T hs = C.half_cs2_source;
+      eMd[0] += hs;
+      eMd[1] += hs;
+      eMd[2] += hs;
+      // M_2G = (I - S2/2)(u F + F u + cs2 Sbar I)   (eq. M2GComput a)
+      const T Txx = T(2) * ux * C.force[0] + C.cs2_source;
+      const T Tyy = T(2) * uy * C.force[1] + C.cs2_source;
+      const T Tzz = T(2) * uz * C.force[2] + C.cs2_source;
+      sA = C.source;
+      sB[0] = C.force[0];
+      sB[1] = C.force[1];
+      sB[2] = C.force[2];
+      sMd[0] = C.IhS[0][0] * Txx + C.IhS[0][1] * Tyy + C.IhS[0][2] * Tzz - C.cs2_source;
+      sMd[1] = C.IhS[1][0] * Txx + C.IhS[1][1] * Tyy + C.IhS[1][2] * Tzz - C.cs2_source;
+      sMd[2] = C.IhS[2][0] * Txx + C.IhS[2][1] * Tyy + C.IhS[2][2] * Tzz - C.cs2_source;
+      sMo[0] = C.ihs_off[0] * (ux * C.force[1] + uy * C.force[0]);
+      sMo[1] = C.ihs_off[1] * (ux * C.force[2] + uz * C.force[0]);
+      sMo[2] = C.ihs_off[2] * (uy * C.force[2] + uz * C.force[1]);
+    }
+  } else {
+    const T phi = C.rho0 + drho + C.half_source;                       // eq. 2-4-1
+    const T Dphi = C.D0 * (T(1) + C.D2 * phi * phi);
+    s1 = T(1) / (T(0.5) + Dphi * C.inv_cs2_dt);                        // eq. 4-10
+    eA = drho;
+    eB[0] = phi * C.adv[0];
+    eB[1] = phi * C.adv[1];
+    eB[2] = phi * C.adv[2];
+    eMd[0] = eB[0] * C.adv[0];
+    eMd[1] = eB[1] * C.adv[1];
+    eMd[2] = eB[2] * C.adv[2];
+    eMo[0] = eB[0] * C.adv[1];
+    eMo[1] = eB[0] * C.adv[2];
+    eMo[2] = eB[1] * C.adv[2];
+    if constexpr (FORCE) {
+      const T g = (T(1) - T(0.5) * s1) * C.source;                      // eq. 4-11
+      sA = C.source;
+      sB[0] = g * C.adv[0];
+      sB[1] = g * C.adv[1];
+      sB[2] = g * C.adv[2];
+    }
+  }
+
+  if constexpr (EQ == EQ_NSE) {
+    // second-order diagonal block: full (D x D) relaxation matrix, scaled basis
+    T nd[3];
+    nd[0] = t[sxx] - gmom<L, sxx>(C, eA, eB, eMd, eMo);
+    nd[1] = t[syy] - gmom<L, syy>(C, eA, eB, eMd, eMo);
+    if constexpr (D == 3) nd[2] = t[szz] - gmom<L, szz>(C, eA, eB, eMd, eMo);
+    T rx = C.Sd[0][0] * nd[0] + C.Sd[0][1] * nd[1];
+    T ry = C.Sd[1][0] * nd[0] + C.Sd[1][1] * nd[1];
+    T rz = T(0);
+    if constexpr (D == 3) {
+      rx += C.Sd[0][2] * nd[2];
+      ry += C.Sd[1][2] * nd[2];
+      rz = C.Sd[2][0] * nd[0] + C.Sd[2][1] * nd[1] + C.Sd[2][2] * nd[2];
+    }
+    t[sxx] -= rx;
+    t[syy] -= ry;
+    if constexpr (D == 3) t[szz] -= rz;
+  }
+
+  static_for<0, NS>([&](auto n_) {
+    constexpr int n = decltype(n_)::value;
+    constexpr int a = n % 3, b = (n / 3) % 3, p = n / 9;
+    constexpr int ord = a + b + p;
+    constexpr bool diag2 = (n == sxx || n == syy || n == szz);
+    if constexpr (Lat<L>::dropped(n)) {
+      t[n] = T(0);
+    } else {
+      T src = T(0);
+      if constexpr (FORCE) src = gmom<L, n>(C, sA, sB, sMd, sMo);
+      if constexpr (ord == 0) {
+        t[n] += src;                                   // conserved (eq. 4-18-1)
+      } else if constexpr (ord == 1) {
+        if constexpr (EQ == EQ_NSE) {
+          t[n] += src;                                 // conserved; rate irrelevant
+        } else {
+          const T eq = gmom<L, n>(C, eA, eB, eMd, eMo);
+          t[n] = t[n] - s1 * (t[n] - eq) + src;
+        }
+      } else if constexpr (EQ == EQ_NSE && diag2) {
+        t[n] += src;                                   // relaxed above
+      } else {
+        T rate;
+        if constexpr (EQ == EQ_NSE && ord == 2) {
+          constexpr int pr = (p == 0) ? 0 : ((a == 1) ? 1 : 2);
+          rate = C.s_off[pr];
+        } else {
+          rate = C.s_hi;
+        }
+        const T eq = gmom<L, n>(C, eA, eB, eMd, eMo);
+        t[n] = t[n] - rate * (t[n] - eq) + src;
+      }
+    }
+  });
+
+  moments_inv<D>(t);
+}
+
+}  // namespace rmrt

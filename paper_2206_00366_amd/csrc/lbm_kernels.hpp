@@ -1,0 +1,619 @@
+// Kernels of the RMRT-LB step and its companions (init, macroscopic fields,
+// FP64 reductions), templated over lattice, storage, equation, forcing,
+// boundary handling and memory pattern.  Explicitly instantiated per
+// (lattice, storage) in lbm_q*.hip.
+//
+// Memory patterns (stored state "natural" = slot j of node x holds f_j(x)):
+//   PH_AB       read own slots of buffer `in`, write f*_j to slot j of x + e_j
+//               in buffer `out` (push), or to slot opp(j) of x when x + e_j
+//               is a wall or solid (halfway bounce-back).
+//   PH_AA_EVEN  in place: read own slots, write f*_j to own slot opp(j).
+//               Leaves the "swapped" state: f_j(x) sits in slot opp(j) of
+//               x - e_j (or slot j of x when x - e_j bounces).
+//   PH_AA_ODD   in place: read the swapped state, write like PH_AB.
+// Every thread reads and writes the same address set in the AA patterns, so
+// the in-place update has no races.
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace rmrt {
+
+#define RMRT_WALL_XM 1u
+#define RMRT_WALL_XP 2u
+#define RMRT_WALL_YM 4u
+#define RMRT_WALL_YP 8u
+#define RMRT_WALL_ZM 16u
+#define RMRT_WALL_ZP 32u
+
+// exact n / d for n < 2^32 with m = floor(2^32 / d) (0xffffffff for d = 1)
+__device__ __forceinline__ uint32_t fast_div(uint32_t n, uint32_t d, uint32_t m, uint32_t& r) {
+  uint32_t q = __umulhi(n, m);
+  uint32_t rr = n - q * d;
+  if (rr >= d) {
+    q += 1;
+    rr -= d;
+  }
+  r = rr;
+  return q;
+}
+
+// Geometry of one node: neighbour offsets with periodic wrap and wall flags.
+template <int D>
+struct Geo {
+  int32_t ox[3], oy[3], oz[3];
+  bool lo[3], hi[3];
+  __device__ __forceinline__ void make(const DomainDev& Dm, uint32_t idx) {
+    uint32_t x, y, z, r;
+    const uint32_t q1 = fast_div(idx, Dm.nx, Dm.mnx, r);
+    x = r;
+    if constexpr (D == 2) {
+      y = q1;
+      z = 0;
+    } else {
+      z = fast_div(idx, Dm.nxny, Dm.mnxny, r);
+      y = q1 - z * Dm.ny;
+    }
+    const int32_t nx = (int32_t)Dm.nx, ny = (int32_t)Dm.ny, nz = (int32_t)Dm.nz;
+    const int32_t nxny = (int32_t)Dm.nxny;
+    ox[0] = (x == 0) ? nx - 1 : -1;
+    ox[1] = 0;
+    ox[2] = (x == Dm.nx - 1) ? 1 - nx : 1;
+    oy[0] = (y == 0) ? (ny - 1) * nx : -nx;
+    oy[1] = 0;
+    oy[2] = (y == Dm.ny - 1) ? -(ny - 1) * nx : nx;
+    if constexpr (D == 3) {
+      oz[0] = (z == 0) ? (nz - 1) * nxny : -nxny;
+      oz[2] = (z == Dm.nz - 1) ? -(nz - 1) * nxny : nxny;
+    } else {
+      oz[0] = 0;
+      oz[2] = 0;
+    }
+    oz[1] = 0;
+    const uint32_t w = Dm.walls;
+    lo[0] = (x == 0) && (w & RMRT_WALL_XM);
+    hi[0] = (x == Dm.nx - 1) && (w & RMRT_WALL_XP);
+    lo[1] = (y == 0) && (w & RMRT_WALL_YM);
+    hi[1] = (y == Dm.ny - 1) && (w & RMRT_WALL_YP);
+    lo[2] = (D == 3) && (z == 0) && (w & RMRT_WALL_ZM);
+    hi[2] = (D == 3) && (z == Dm.nz - 1) && (w & RMRT_WALL_ZP);
+  }
+  template <int L, int J>
+  __device__ __forceinline__ int32_t off() const {
+    constexpr int ex = Lat<L>::e(J, 0), ey = Lat<L>::e(J, 1), ez = Lat<L>::e(J, 2);
+    return ox[ex + 1] + oy[ey + 1] + oz[ez + 1];
+  }
+  // does the link from this node along e_J hit a wall face or a solid node?
+  template <int L, int J>
+  __device__ __forceinline__ bool bounce(const DomainDev& Dm, uint32_t idx) const {
+    constexpr int ex = Lat<L>::e(J, 0), ey = Lat<L>::e(J, 1), ez = Lat<L>::e(J, 2);
+    if constexpr (ex == 0 && ey == 0 && ez == 0) return false;
+    bool b = false;
+    if constexpr (ex < 0) b = b || lo[0];
+    if constexpr (ex > 0) b = b || hi[0];
+    if constexpr (ey < 0) b = b || lo[1];
+    if constexpr (ey > 0) b = b || hi[1];
+    if constexpr (ez < 0) b = b || lo[2];
+    if constexpr (ez > 0) b = b || hi[2];
+    if (Dm.has_solid) b = b || (Dm.solid[idx + (uint32_t)off<L, J>()] != 0);
+    return b;
+  }
+};
+
+// Element offset (in S units, from the buffer start) of the slot read for
+// population j of node idx, in the natural (own) or swapped layout.
+template <int L, int BC, bool SWAPPED, int J, int D>
+__device__ __forceinline__ size_t read_elem(const DomainDev& Dm, const Geo<D>& g, uint32_t idx) {
+  const size_t N = Dm.N;
+  if constexpr (!SWAPPED) {
+    return (size_t)J * N + idx;
+  } else {
+    constexpr int O = Lat<L>::opp(J);
+    if constexpr (BC == 1) {
+      if (g.template bounce<L, O>(Dm, idx)) return (size_t)J * N + idx;
+    }
+    return (size_t)O * N + (uint32_t)(idx + (uint32_t)g.template off<L, O>());
+  }
+}
+
+// ----------------------------------------------------------------------------
+// The fused collide-and-stream kernel.  Work is a list of tiles (contiguous
+// node ranges of a domain); a null tile list means one domain split into
+// tiles of `tile_nodes` nodes with one tile per workgroup.
+// ----------------------------------------------------------------------------
+template <int L, int ST, int EQ, bool FORCE, int BC, int PH>
+__device__ __forceinline__ void step_node(const DomainDev& Dm, const Coef<typename Store<ST>::T>& C,
+                                          typename Store<ST>::S* fin, typename Store<ST>::S* fout,
+                                          uint32_t idx) {
+  using SS = Store<ST>;
+  using S = typename SS::S;
+  using T = typename SS::T;
+  constexpr int Q = Lat<L>::Q, NS = Lat<L>::NS, D = Lat<L>::D;
+  if constexpr (BC == 1) {
+    if (Dm.has_solid && Dm.solid[idx]) return;
+  }
+  Geo<D> g;
+  if constexpr (PH != PH_AA_EVEN) g.make(Dm, idx);
+  const uint32_t N = Dm.N;
+  T t[NS];
+  static_for<0, NS>([&](auto s_) {
+    constexpr int s = decltype(s_)::value;
+    if constexpr (Lat<L>::absent(s)) t[s] = T(0);
+  });
+  // gather
+  static_for<0, Q>([&](auto j_) {
+    constexpr int J = decltype(j_)::value;
+    S v;
+    if constexpr (PH == PH_AA_ODD) {
+      v = fin[read_elem<L, BC, true, J>(Dm, g, idx)];
+    } else {
+      const S* __restrict__ pj = fin + (size_t)J * N;
+      v = pj[idx];
+    }
+    t[Lat<L>::slot(J)] = SS::template dec<J>(v, C);
+  });
+
+  collide<L, EQ, FORCE>(t, C);
+
+  // scatter
+  static_for<0, Q>([&](auto j_) {
+    constexpr int J = decltype(j_)::value;
+    constexpr int O = Lat<L>::opp(J);
+    const S v = SS::template enc<J>(t[Lat<L>::slot(J)], C);
+    if constexpr (PH == PH_AA_EVEN) {
+      S* __restrict__ po = fout + (size_t)O * N;
+      po[idx] = v;
+    } else if constexpr (BC == 0) {
+      S* __restrict__ pj = fout + (size_t)J * N;
+      pj[(uint32_t)(idx + (uint32_t)g.template off<L, J>())] = v;
+    } else {
+      const bool b = g.template bounce<L, J>(Dm, idx);
+      const size_t e = b ? (size_t)O * N + idx
+                         : (size_t)J * N + (uint32_t)(idx + (uint32_t)g.template off<L, J>());
+      fout[e] = v;
+    }
+  });
+}
+
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
+  // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+  // contiguous range of tiles so neighbouring tiles share its L2
+  const uint32_t xcd = b & 7u, local = b >> 3;
+  const uint32_t per = G >> 3, rem = G & 7u;
+  return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
+template <int L, int ST, int EQ, bool FORCE, int BC, int PH>
+__global__ void __launch_bounds__(256)
+    k_step(const DomainDev* __restrict__ doms, const Tile* __restrict__ tiles, uint32_t ntiles,
+           uint32_t tile_nodes, uint32_t parity) {
+  using SS = Store<ST>;
+  using S = typename SS::S;
+  using T = typename SS::T;
+  for (uint32_t tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+    uint32_t dom, start, count;
+    if (tiles != nullptr) {
+      const Tile tl = tiles[tt];
+      dom = tl.dom;
+      start = tl.start;
+      count = tl.count;
+    } else {
+      const uint32_t t = (gridDim.x == ntiles) ? xcd_remap(tt, ntiles) : tt;
+      dom = 0;
+      start = t * tile_nodes;
+      const uint32_t N = doms[0].N;
+      count = (N - start < tile_nodes) ? N - start : tile_nodes;
+    }
+    const DomainDev& Dm = doms[dom];
+    const Coef<T>& C = coef<T>(Dm);
+    S* fa = (S*)Dm.fa;
+    S* fb = (S*)Dm.fb;
+    S* fin;
+    S* fout;
+    if constexpr (PH == PH_AB) {
+      fin = parity ? fb : fa;
+      fout = parity ? fa : fb;
+    } else {
+      fin = fa;
+      fout = fa;
+    }
+    for (uint32_t i = threadIdx.x; i < count; i += blockDim.x)
+      step_node<L, ST, EQ, FORCE, BC, PH>(Dm, C, fin, fout, start + i);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Decoding helpers for the companion kernels (FP64)
+// ----------------------------------------------------------------------------
+template <int ST, int J>
+__device__ __forceinline__ double dec64(typename Store<ST>::S v, const Coef<double>& C) {
+  if constexpr (ST == ST_F16)
+    return (double)(float)v * C.w[J];
+  else
+    return (double)v;
+}
+template <int ST, int J>
+__device__ __forceinline__ typename Store<ST>::S enc64(double v, const Coef<double>& C) {
+  using S = typename Store<ST>::S;
+  if constexpr (ST == ST_F16)
+    return (S)(float)(v * C.iw[J]);
+  else
+    return (S)v;
+}
+
+// current population buffer of a domain after `parity` steps
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::S* current_buffer(const DomainDev& Dm, uint32_t parity,
+                                                                 bool ab) {
+  using S = typename Store<ST>::S;
+  return (ab && parity) ? (S*)Dm.fb : (S*)Dm.fa;
+}
+
+// Gather the deviations d_j of node idx (paper order, FP64).
+template <int L, int ST, int BC, bool SWAPPED>
+__device__ __forceinline__ void gather64(const DomainDev& Dm, const typename Store<ST>::S* f,
+                                         uint32_t idx, double (&d)[Lat<L>::Q]) {
+  constexpr int D = Lat<L>::D;
+  Geo<D> g;
+  if constexpr (SWAPPED) g.make(Dm, idx);
+  static_for<0, Lat<L>::Q>([&](auto j_) {
+    constexpr int J = decltype(j_)::value;
+    d[J] = dec64<ST, J>(f[read_elem<L, BC, SWAPPED, J>(Dm, g, idx)], Dm.cd);
+  });
+}
+
+// rho' = sum d_j and the first moment sum c_j d_j of node idx
+template <int L>
+__device__ __forceinline__ void first_moments(const DomainDev& Dm, const double (&d)[Lat<L>::Q],
+                                              double& drho, double (&m1)[3]) {
+  drho = 0.0;
+  m1[0] = m1[1] = m1[2] = 0.0;
+  static_for<0, Lat<L>::Q>([&](auto j_) {
+    constexpr int J = decltype(j_)::value;
+    drho += d[J];
+    if constexpr (Lat<L>::e(J, 0) != 0) m1[0] += (double)Lat<L>::e(J, 0) * d[J];
+    if constexpr (Lat<L>::e(J, 1) != 0) m1[1] += (double)Lat<L>::e(J, 1) * d[J];
+    if constexpr (Lat<L>::e(J, 2) != 0) m1[2] += (double)Lat<L>::e(J, 2) * d[J];
+  });
+  m1[0] *= Dm.cd.c[0];
+  m1[1] *= Dm.cd.c[1];
+  m1[2] *= Dm.cd.c[2];
+}
+
+// rho (or phi) and u of node idx (eq. 2-4-1 / eq. 2-4-2)
+template <int L, int ST, int EQ, int BC, bool SWAPPED>
+__device__ __forceinline__ void macro_node(const DomainDev& Dm, const typename Store<ST>::S* f,
+                                           uint32_t idx, double& rho, double (&u)[3],
+                                           double& drho_out) {
+  double d[Lat<L>::Q];
+  gather64<L, ST, BC, SWAPPED>(Dm, f, idx, d);
+  double drho, m1[3];
+  first_moments<L>(Dm, d, drho, m1);
+  const Coef<double>& C = Dm.cd;
+  rho = C.rho0 + drho + C.half_source;
+  drho_out = drho + C.half_source;
+  if constexpr (EQ == EQ_NSE) {
+    const double ir = 1.0 / rho;
+    u[0] = (m1[0] + C.half_force[0]) * ir;
+    u[1] = (m1[1] + C.half_force[1]) * ir;
+    u[2] = (m1[2] + C.half_force[2]) * ir;
+  } else {
+    u[0] = C.adv[0];
+    u[1] = C.adv[1];
+    u[2] = C.adv[2];
+  }
+}
+
+template <int L, int ST, int EQ, int BC, bool SWAPPED>
+__global__ void __launch_bounds__(256)
+    k_moments(const DomainDev* __restrict__ doms, uint32_t dom, uint32_t parity, int ab, void* rho_out,
+              void* u_out, int out_f32) {
+  const DomainDev& Dm = doms[dom];
+  const auto* f = current_buffer<ST>(Dm, parity, ab);
+  constexpr int D = Lat<L>::D;
+  const uint32_t N = Dm.N;
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+    double rho, u[3], drho;
+    if (BC == 1 && Dm.has_solid && Dm.solid[idx]) {
+      rho = Dm.cd.rho0;
+      u[0] = u[1] = u[2] = 0.0;
+    } else {
+      macro_node<L, ST, EQ, BC, SWAPPED>(Dm, f, idx, rho, u, drho);
+    }
+    if (out_f32) {
+      ((float*)rho_out)[idx] = (float)rho;
+      if (u_out)
+        for (int a = 0; a < D; ++a) ((float*)u_out)[(size_t)a * N + idx] = (float)u[a];
+    } else {
+      ((double*)rho_out)[idx] = rho;
+      if (u_out)
+        for (int a = 0; a < D; ++a) ((double*)u_out)[(size_t)a * N + idx] = u[a];
+    }
+  }
+}
+
+template <int L, int ST, int BC, bool SWAPPED>
+__global__ void __launch_bounds__(256)
+    k_populations(const DomainDev* __restrict__ doms, uint32_t dom, uint32_t parity, int ab,
+                  double* out) {
+  const DomainDev& Dm = doms[dom];
+  const auto* f = current_buffer<ST>(Dm, parity, ab);
+  const uint32_t N = Dm.N;
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+    if (BC == 1 && Dm.has_solid && Dm.solid[idx]) {
+      for (int j = 0; j < Lat<L>::Q; ++j) out[(size_t)j * N + idx] = 0.0;
+      continue;
+    }
+    double d[Lat<L>::Q];
+    gather64<L, ST, BC, SWAPPED>(Dm, f, idx, d);
+    static_for<0, Lat<L>::Q>([&](auto j_) {
+      constexpr int J = decltype(j_)::value;
+      out[(size_t)J * N + idx] = Dm.cd.w[J] * Dm.cd.rho0 + d[J];
+    });
+  }
+}
+
+// ---- block reduction of K doubles ----
+template <int K>
+__device__ __forceinline__ void block_reduce_store(double (&v)[K], double* out) {
+  __shared__ double sh[K][8];
+  for (int k = 0; k < K; ++k) {
+    double x = v[k];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    v[k] = x;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int k = 0; k < K; ++k) sh[k][wid] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += sh[k][w];
+      out[(size_t)blockIdx.x * K + k] = s;
+    }
+  }
+}
+
+// partial sums per workgroup: [sum rho', sum j_x, j_y, j_z, fluid node count]
+template <int L, int ST, int EQ, int BC, bool SWAPPED>
+__global__ void __launch_bounds__(256)
+    k_reduce(const DomainDev* __restrict__ doms, uint32_t dom, uint32_t parity, int ab,
+             double* partials) {
+  const DomainDev& Dm = doms[dom];
+  const auto* f = current_buffer<ST>(Dm, parity, ab);
+  const uint32_t N = Dm.N;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+    if (BC == 1 && Dm.has_solid && Dm.solid[idx]) continue;
+    double d[Lat<L>::Q];
+    gather64<L, ST, BC, SWAPPED>(Dm, f, idx, d);
+    double drho, m1[3];
+    first_moments<L>(Dm, d, drho, m1);
+    acc[0] += drho + Dm.cd.half_source;
+    if constexpr (EQ == EQ_NSE) {
+      acc[1] += m1[0] + Dm.cd.half_force[0];
+      acc[2] += m1[1] + Dm.cd.half_force[1];
+      acc[3] += m1[2] + Dm.cd.half_force[2];
+    }
+    acc[4] += 1.0;
+  }
+  block_reduce_store<5>(acc, partials);
+}
+
+// steady residual partials: [sum |u - u_prev|^2, sum |u|^2]; stores u into prev
+// (NCDE: phi instead of u)
+template <int L, int ST, int EQ, int BC, bool SWAPPED>
+__global__ void __launch_bounds__(256)
+    k_residual(const DomainDev* __restrict__ doms, uint32_t dom, uint32_t parity, int ab, double* prev,
+               int have_prev, double* partials) {
+  const DomainDev& Dm = doms[dom];
+  const auto* f = current_buffer<ST>(Dm, parity, ab);
+  const uint32_t N = Dm.N;
+  constexpr int K = (EQ == EQ_NSE) ? Lat<L>::D : 1;
+  double acc[2] = {0, 0};
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+    if (BC == 1 && Dm.has_solid && Dm.solid[idx]) continue;
+    double rho, u[3], drho;
+    macro_node<L, ST, EQ, BC, SWAPPED>(Dm, f, idx, rho, u, drho);
+    double v[3] = {u[0], u[1], u[2]};
+    if constexpr (EQ != EQ_NSE) v[0] = rho;
+    for (int a = 0; a < K; ++a) {
+      const double old = prev[(size_t)a * N + idx];
+      if (have_prev) acc[0] += (v[a] - old) * (v[a] - old);
+      acc[1] += v[a] * v[a];
+      prev[(size_t)a * N + idx] = v[a];
+    }
+  }
+  block_reduce_store<2>(acc, partials);
+}
+
+// sums nb x K partials in a fixed order (deterministic)
+template <int K>
+__global__ void k_reduce_final(const double* __restrict__ partials, uint32_t nb, double* out) {
+  __shared__ double sh[K][256];
+  double v[K];
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x)
+    for (int k = 0; k < K; ++k) v[k] += partials[(size_t)b * K + k];
+  for (int k = 0; k < K; ++k) sh[k][threadIdx.x] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (uint32_t t = 0; t < blockDim.x; ++t) s += sh[k][t];
+      out[k] = s;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Initialisation: fbar = g_eq(A, B, M) in velocity space (eq. 3-3) with
+//   NSE : A = rho - rho0 - Sbar/2, B = rho u - Fbar/2,
+//         M = rho u u + cs2 Sbar I / 2 [+ m_2^ne of eq. 4-34]
+//   NCDE: A = phi - phi0 - S/2,    B = phi adv,  M = phi adv adv
+// written in the natural layout, or through the swapped addressing when the
+// state is expected after an odd number of AA steps.
+// ----------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void velocity_gradient(const DomainDev& Dm, const double* u, uint32_t idx,
+                                                  const Geo<D>& g, double (&G)[3][3]) {
+  const uint32_t N = Dm.N;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) G[a][b] = 0.0;
+  for (int b = 0; b < D; ++b) {
+    const int32_t op = (b == 0) ? g.ox[2] : (b == 1 ? g.oy[2] : g.oz[2]);
+    const int32_t om = (b == 0) ? g.ox[0] : (b == 1 ? g.oy[0] : g.oz[0]);
+    const uint32_t ip = idx + (uint32_t)op, im = idx + (uint32_t)om;
+    bool okp = !g.hi[b], okm = !g.lo[b];
+    if (Dm.has_solid) {
+      okp = okp && !Dm.solid[ip];
+      okm = okm && !Dm.solid[im];
+    }
+    const double h = Dm.cd.c[b] * Dm.cd.dt;
+    for (int a = 0; a < D; ++a) {
+      const double* ua = u + (size_t)a * N;
+      if (okp && okm)
+        G[a][b] = (ua[ip] - ua[im]) / (2.0 * h);
+      else if (okp)
+        G[a][b] = (ua[ip] - ua[idx]) / h;
+      else if (okm)
+        G[a][b] = (ua[idx] - ua[im]) / h;
+    }
+  }
+}
+
+template <int L, int ST, int EQ, bool SWAPPED>
+__global__ void __launch_bounds__(256)
+    k_init(const DomainDev* __restrict__ doms, uint32_t dom, uint32_t parity, int ab,
+           const double* __restrict__ rho_in, const double* __restrict__ u_in, int with_fne) {
+  using S = typename Store<ST>::S;
+  constexpr int D = Lat<L>::D;
+  const DomainDev& Dm = doms[dom];
+  const Coef<double>& C = Dm.cd;
+  S* f = current_buffer<ST>(Dm, parity, ab);
+  const uint32_t N = Dm.N;
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+    Geo<D> g;
+    g.make(Dm, idx);
+    const double r = rho_in ? rho_in[idx] : C.rho0;
+    double A, B[3] = {0, 0, 0}, M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    if constexpr (EQ == EQ_NSE) {
+      double u[3] = {0, 0, 0};
+      if (u_in)
+        for (int a = 0; a < D; ++a) u[a] = u_in[(size_t)a * N + idx];
+      A = r - C.rho0 - C.half_source;
+      for (int a = 0; a < 3; ++a) B[a] = r * u[a] - C.half_force[a];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) M[a][b] = r * u[a] * u[b] + (a == b ? C.half_cs2_source : 0.0);
+      if (with_fne && u_in && !(Dm.has_solid && Dm.solid[idx])) {
+        // m_2^ne = -(I - S2/2)^-1 tau - dt/2 (u F + F u + cs2 Sbar I)   (eq. 4-34)
+        double G[3][3];
+        velocity_gradient<D>(Dm, u_in, idx, g, G);
+        double div = 0.0;
+        for (int a = 0; a < D; ++a) div += G[a][a];
+        double tau[3][3];
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b)
+            tau[a][b] = r * Dm.ic.nu * (G[a][b] + G[b][a] - (a == b ? 2.0 / D * div : 0.0)) +
+                        (a == b ? r * Dm.ic.nu_b * div : 0.0);
+        double mne[3][3];
+        for (int a = 0; a < 3; ++a) {
+          double s = 0.0;
+          for (int b = 0; b < 3; ++b) s += Dm.ic.Kd[a][b] * tau[b][b];
+          mne[a][a] = -s;
+        }
+        mne[0][1] = mne[1][0] = -Dm.ic.k_off[0] * tau[0][1];
+        mne[0][2] = mne[2][0] = -Dm.ic.k_off[1] * tau[0][2];
+        mne[1][2] = mne[2][1] = -Dm.ic.k_off[2] * tau[1][2];
+        // (C.half_force and C.half_cs2_source already carry the factor dt / 2)
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b)
+            M[a][b] += mne[a][b] - (u[a] * C.half_force[b] + C.half_force[a] * u[b] +
+                                    (a == b ? C.half_cs2_source : 0.0));
+      }
+    } else {
+      A = r - C.rho0 - C.half_source;
+      for (int a = 0; a < 3; ++a) B[a] = r * C.adv[a];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) M[a][b] = r * C.adv[a] * C.adv[b];
+    }
+    // g_eq_j = w_j (A + c_j.B / cs2 + sum_a M_aa (c_ja^2 - cs2) / (cs2 (c_a^2 - cs2))
+    //               + sum_{a<b} M_ab c_ja c_jb / cs2^2)
+    const double ics2 = C.inv_cs2;
+    double qa[3], qo[3];
+    for (int a = 0; a < 3; ++a) qa[a] = 1.0 / (C.c[a] * C.c[a] - C.cs2);
+    qo[0] = C.c[0] * C.c[1] * ics2 * ics2;
+    qo[1] = C.c[0] * C.c[2] * ics2 * ics2;
+    qo[2] = C.c[1] * C.c[2] * ics2 * ics2;
+    static_for<0, Lat<L>::Q>([&](auto j_) {
+      constexpr int J = decltype(j_)::value;
+      constexpr int ex = Lat<L>::e(J, 0), ey = Lat<L>::e(J, 1), ez = Lat<L>::e(J, 2);
+      double v = A + ics2 * (ex * C.c[0] * B[0] + ey * C.c[1] * B[1] + ez * C.c[2] * B[2]);
+      const int e[3] = {ex, ey, ez};
+      for (int a = 0; a < D; ++a) {
+        const double cja2 = e[a] * e[a] * C.c[a] * C.c[a];
+        v += M[a][a] * (cja2 - C.cs2) * ics2 * qa[a];
+      }
+      v += M[0][1] * (ex * ey) * qo[0];
+      if constexpr (D == 3) {
+        v += M[0][2] * (ex * ez) * qo[1];
+        v += M[1][2] * (ey * ez) * qo[2];
+      }
+      v *= C.w[J];
+      size_t e_out;
+      if constexpr (SWAPPED) {
+        // f_J(x) lives in slot opp(J) of x - e_J, or slot J of x if that link bounces
+        constexpr int O = Lat<L>::opp(J);
+        bool b = false;
+        b = g.template bounce<L, O>(Dm, idx);
+        e_out = b ? (size_t)J * N + idx : (size_t)O * N + (uint32_t)(idx + (uint32_t)g.template off<L, O>());
+      } else {
+        e_out = (size_t)J * N + idx;
+      }
+      if (!(Dm.has_solid && Dm.solid[idx])) f[e_out] = enc64<ST, J>(v, C);
+    });
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Host-side launch descriptors (defined per lattice/storage translation unit)
+// ----------------------------------------------------------------------------
+struct StepLaunch {
+  const DomainDev* doms;
+  const Tile* tiles;
+  uint32_t ntiles, tile_nodes, parity;
+  int eq, force, bc, phase;
+  unsigned grid, block;
+  hipStream_t stream;
+};
+struct AuxLaunch {
+  const DomainDev* doms;
+  uint32_t dom, parity;
+  int ab, eq, bc, swapped;
+  unsigned grid, block;
+  hipStream_t stream;
+  // kind-specific
+  void* out0;
+  void* out1;
+  const double* in0;
+  const double* in1;
+  int flag;
+};
+
+template <int L, int ST>
+hipError_t launch_step(const StepLaunch& a);
+template <int L, int ST>
+hipError_t launch_init(const AuxLaunch& a);
+template <int L, int ST>
+hipError_t launch_moments(const AuxLaunch& a);
+template <int L, int ST>
+hipError_t launch_populations(const AuxLaunch& a);
+template <int L, int ST>
+hipError_t launch_reduce(const AuxLaunch& a);
+template <int L, int ST>
+hipError_t launch_residual(const AuxLaunch& a);
+hipError_t launch_reduce_final(const double* partials, uint32_t nb, double* out, int K, hipStream_t s);
+
+}  // namespace rmrt

@@ -1,0 +1,122 @@
+// Host launchers: map runtime enumerations onto kernel template instances.
+#pragma once
+
+#include "lbm_kernels.hpp"
+
+namespace rmrt {
+
+template <int L, int ST, int EQ, bool F, int BC, int PH>
+hipError_t do_step(const StepLaunch& a) {
+  hipLaunchKernelGGL((k_step<L, ST, EQ, F, BC, PH>), dim3(a.grid), dim3(a.block), 0, a.stream, a.doms,
+                     a.tiles, a.ntiles, a.tile_nodes, a.parity);
+  return hipGetLastError();
+}
+template <int L, int ST, int EQ, bool F, int BC>
+hipError_t step_ph(const StepLaunch& a) {
+  switch (a.phase) {
+    case PH_AB: return do_step<L, ST, EQ, F, BC, PH_AB>(a);
+    case PH_AA_EVEN: return do_step<L, ST, EQ, F, BC, PH_AA_EVEN>(a);
+    case PH_AA_ODD: return do_step<L, ST, EQ, F, BC, PH_AA_ODD>(a);
+  }
+  return hipErrorInvalidValue;
+}
+template <int L, int ST, int EQ, bool F>
+hipError_t step_bc(const StepLaunch& a) {
+  return a.bc ? step_ph<L, ST, EQ, F, 1>(a) : step_ph<L, ST, EQ, F, 0>(a);
+}
+template <int L, int ST, int EQ>
+hipError_t step_f(const StepLaunch& a) {
+  return a.force ? step_bc<L, ST, EQ, true>(a) : step_bc<L, ST, EQ, false>(a);
+}
+template <int L, int ST>
+hipError_t launch_step(const StepLaunch& a) {
+  return a.eq == EQ_NCDE ? step_f<L, ST, EQ_NCDE>(a) : step_f<L, ST, EQ_NSE>(a);
+}
+
+// ---- companions: dispatch over (eq, bc, swapped) ----
+#define RMRT_AUX_DISPATCH(KCALL)                                       \
+  if (a.eq == EQ_NSE) {                                                \
+    if (a.bc) {                                                        \
+      if (a.swapped) { KCALL(EQ_NSE, 1, true); } else { KCALL(EQ_NSE, 1, false); } \
+    } else {                                                           \
+      if (a.swapped) { KCALL(EQ_NSE, 0, true); } else { KCALL(EQ_NSE, 0, false); } \
+    }                                                                  \
+  } else {                                                             \
+    if (a.bc) {                                                        \
+      if (a.swapped) { KCALL(EQ_NCDE, 1, true); } else { KCALL(EQ_NCDE, 1, false); } \
+    } else {                                                           \
+      if (a.swapped) { KCALL(EQ_NCDE, 0, true); } else { KCALL(EQ_NCDE, 0, false); } \
+    }                                                                  \
+  }                                                                    \
+  return hipGetLastError();
+
+template <int L, int ST>
+hipError_t launch_moments(const AuxLaunch& a) {
+#define K_MOM(EQ, BC, SW)                                                                          \
+  hipLaunchKernelGGL((k_moments<L, ST, EQ, BC, SW>), dim3(a.grid), dim3(a.block), 0, a.stream, a.doms, \
+                     a.dom, a.parity, a.ab, a.out0, a.out1, a.flag)
+  RMRT_AUX_DISPATCH(K_MOM)
+#undef K_MOM
+}
+
+template <int L, int ST>
+hipError_t launch_reduce(const AuxLaunch& a) {
+#define K_RED(EQ, BC, SW)                                                                         \
+  hipLaunchKernelGGL((k_reduce<L, ST, EQ, BC, SW>), dim3(a.grid), dim3(a.block), 0, a.stream, a.doms, \
+                     a.dom, a.parity, a.ab, (double*)a.out0)
+  RMRT_AUX_DISPATCH(K_RED)
+#undef K_RED
+}
+
+template <int L, int ST>
+hipError_t launch_residual(const AuxLaunch& a) {
+#define K_RES(EQ, BC, SW)                                                                           \
+  hipLaunchKernelGGL((k_residual<L, ST, EQ, BC, SW>), dim3(a.grid), dim3(a.block), 0, a.stream, a.doms, \
+                     a.dom, a.parity, a.ab, (double*)a.out1, a.flag, (double*)a.out0)
+  RMRT_AUX_DISPATCH(K_RES)
+#undef K_RES
+}
+
+template <int L, int ST>
+hipError_t launch_populations(const AuxLaunch& a) {
+  if (a.bc) {
+    if (a.swapped)
+      hipLaunchKernelGGL((k_populations<L, ST, 1, true>), dim3(a.grid), dim3(a.block), 0, a.stream,
+                         a.doms, a.dom, a.parity, a.ab, (double*)a.out0);
+    else
+      hipLaunchKernelGGL((k_populations<L, ST, 1, false>), dim3(a.grid), dim3(a.block), 0, a.stream,
+                         a.doms, a.dom, a.parity, a.ab, (double*)a.out0);
+  } else {
+    if (a.swapped)
+      hipLaunchKernelGGL((k_populations<L, ST, 0, true>), dim3(a.grid), dim3(a.block), 0, a.stream,
+                         a.doms, a.dom, a.parity, a.ab, (double*)a.out0);
+    else
+      hipLaunchKernelGGL((k_populations<L, ST, 0, false>), dim3(a.grid), dim3(a.block), 0, a.stream,
+                         a.doms, a.dom, a.parity, a.ab, (double*)a.out0);
+  }
+  return hipGetLastError();
+}
+
+template <int L, int ST>
+hipError_t launch_init(const AuxLaunch& a) {
+#define K_INIT(EQ, SW)                                                                          \
+  hipLaunchKernelGGL((k_init<L, ST, EQ, SW>), dim3(a.grid), dim3(a.block), 0, a.stream, a.doms, \
+                     a.dom, a.parity, a.ab, a.in0, a.in1, a.flag)
+  if (a.eq == EQ_NSE) {
+    if (a.swapped) { K_INIT(EQ_NSE, true); } else { K_INIT(EQ_NSE, false); }
+  } else {
+    if (a.swapped) { K_INIT(EQ_NCDE, true); } else { K_INIT(EQ_NCDE, false); }
+  }
+#undef K_INIT
+  return hipGetLastError();
+}
+
+#define RMRT_INSTANTIATE(L, ST)                                 \
+  template hipError_t launch_step<L, ST>(const StepLaunch&);    \
+  template hipError_t launch_init<L, ST>(const AuxLaunch&);     \
+  template hipError_t launch_moments<L, ST>(const AuxLaunch&);  \
+  template hipError_t launch_populations<L, ST>(const AuxLaunch&); \
+  template hipError_t launch_reduce<L, ST>(const AuxLaunch&);   \
+  template hipError_t launch_residual<L, ST>(const AuxLaunch&);
+
+}  // namespace rmrt

@@ -1,0 +1,62 @@
+// Parameter block shared by the host code and the kernels of this library
+// (one record per domain, resident in device memory, read with scalar loads).
+#pragma once
+
+#include <stdint.h>
+
+namespace rmrt {
+
+enum { LAT_Q9 = 0, LAT_Q19 = 1, LAT_Q27 = 2 };
+enum { EQ_NSE = 0, EQ_NCDE = 1 };
+enum { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2 };
+enum { PH_AB = 0, PH_AA_EVEN = 1, PH_AA_ODD = 2 };
+
+// Coefficients in the working precision T.  Tables indexed by a tensor slot n
+// (n = a + 3 b + 9 p for the raw moment c_x^a c_y^b c_z^p) are in the scaled
+// basis m~ = D^-1 m of the integer factor M~.
+template <typename T>
+struct Coef {
+  T rho0, cs2, inv_cs2, dt;
+  T c[3];
+  T w[27], iw[27];          // weights in paper order and their reciprocals
+  // scaled raw moment n of g_eq(A, B, M):
+  //   A E0[n] + B_odd E1[n] + sum_a M_aa E2[n][a] + M_pair E3[n]
+  T E0[27], E1[27], E2[27][3], E3[27];
+  T Sd[3][3];               // scaled second-order diagonal block: Sbar_ab c_b^2 / c_a^2
+  T s_off[3];               // rates of the xy, xz, yz second moments
+  T s_hi;                   // rate of the higher moments
+  T IhS[3][3];              // I - Sbar/2 (unscaled), for M_2G
+  T ihs_off[3];             // 1 - s_off/2
+  T force[3], half_force[3];
+  T source, half_source, cs2_source, half_cs2_source;
+  T adv[3], D0, D2, inv_cs2_dt;
+};
+
+// Initialisation-only quantities (always FP64).
+struct InitCoef {
+  double Kd[3][3];   // (I - Sbar/2)^-1 on the diagonal second moments
+  double k_off[3];   // 1 / (1 - s_off/2)
+  double nu, nu_b;
+};
+
+struct DomainDev {
+  Coef<double> cd;
+  Coef<float> cf;
+  InitCoef ic;
+  uint32_t nx, ny, nz, N;
+  uint32_t nxny;
+  uint32_t mnx, mnxny;      // floor(2^32 / divisor) (0xffffffff for divisor 1)
+  uint32_t walls;           // RMRT_WALL_* bits
+  uint32_t has_solid;
+  uint32_t lattice, equation, storage;
+  void* fa;                 // population buffer 0
+  void* fb;                 // population buffer 1 (two-lattice pattern)
+  const uint8_t* solid;     // 1 byte per node or null
+};
+
+// One unit of persistent-kernel work: nodes [start, start + count) of a domain.
+struct Tile {
+  uint32_t dom, start, count, pad;
+};
+
+}  // namespace rmrt

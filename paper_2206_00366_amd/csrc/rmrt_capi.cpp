@@ -1,0 +1,1010 @@
+// Host side of the C ABI declared in include/rmrt.h: parameter derivation and
+// validation, coefficient tables, contexts, graph-captured stepping, FP64
+// reductions and the batched persistent path with its autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/rmrt.h"
+#include "lbm_kernels.hpp"
+
+using namespace rmrt;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                            \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return fail(RMRT_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Lattice and parameter derivation (Sec. III, Sec. IV, Sec. V)
+// ---------------------------------------------------------------------------
+struct Derived {
+  int lattice, q, d;
+  double c[3], cs2, dt, r[3];
+  double w[27];
+  double nu, nu_b, s_nu, s_s[3], s_b[3], s_hi;
+  double Sbar[3][3];  // second-order diagonal block (eq. 5-8-1)
+  double D0, D2;
+  int e[27][3];
+};
+
+int lattice_q(int lat) { return lat == RMRT_Q9 ? 9 : (lat == RMRT_Q19 ? 19 : 27); }
+
+int derive(const rmrt_params* p, Derived& v) {
+  if (!p) return fail(RMRT_EINVAL, "params is NULL");
+  if (p->lattice < RMRT_Q9 || p->lattice > RMRT_Q27) return fail(RMRT_EINVAL, "unknown lattice %d", p->lattice);
+  if (p->equation != RMRT_NSE && p->equation != RMRT_NCDE)
+    return fail(RMRT_EINVAL, "unknown equation %d", p->equation);
+  if (p->storage < RMRT_F64 || p->storage > RMRT_F16DEV) return fail(RMRT_EINVAL, "unknown storage %d", p->storage);
+  if (p->pattern != RMRT_AB && p->pattern != RMRT_AA) return fail(RMRT_EINVAL, "unknown pattern %d", p->pattern);
+  v.lattice = p->lattice;
+  v.q = lattice_q(p->lattice);
+  v.d = p->lattice == RMRT_Q9 ? 2 : 3;
+  for (int a = 0; a < 3; ++a)
+    if (p->n[a] < 1) return fail(RMRT_EINVAL, "n[%d] = %d < 1", a, p->n[a]);
+  if (v.d == 2 && p->n[2] != 1) return fail(RMRT_EINVAL, "rD2Q9 needs n[2] == 1");
+  const double N = (double)p->n[0] * p->n[1] * p->n[2];
+  if (N * v.q >= 4294967295.0) return fail(RMRT_EUNSUPPORTED, "q * N must be below 2^32");
+  v.dt = p->dt > 0 ? p->dt : 1.0;
+  for (int a = 0; a < 3; ++a) {
+    double dx = (a < v.d) ? p->dx[a] : 1.0;
+    if (!(dx > 0)) return fail(RMRT_EINVAL, "dx[%d] must be > 0", a);
+    v.c[a] = dx / v.dt;  // c_a = dx_a / dt (Sec. III)
+  }
+  double cmin2 = v.c[0] * v.c[0];
+  for (int a = 1; a < v.d; ++a) cmin2 = std::min(cmin2, v.c[a] * v.c[a]);
+  v.cs2 = p->cs2 > 0 ? p->cs2 : cmin2 / 3.0;
+  for (int a = 0; a < 3; ++a) {
+    v.r[a] = v.cs2 / (v.c[a] * v.c[a]);
+    if (a < v.d && !(v.r[a] > 0 && v.r[a] < 1))
+      return fail(RMRT_EINVAL, "need 0 < cs2 / c_%d^2 < 1 (got %g)", a, v.r[a]);
+  }
+  for (int j = 0; j < 27; ++j)
+    for (int a = 0; a < 3; ++a) v.e[j][a] = (p->lattice == RMRT_Q9) ? (j < 9 ? kE9[j][a] : 0) : kE27[j][a];
+  // weights: eq. 3-3-5 (rD2Q9), eq. 3-3-8 (rD3Q27; omega_19 = 0 gives rD3Q19)
+  std::fill(v.w, v.w + 27, 0.0);
+  const double* r = v.r;
+  if (p->lattice == RMRT_Q9) {
+    const double w5 = r[0] * r[1] / 4.0;
+    const double w1 = r[0] / 2.0 - 2.0 * w5, w2 = r[1] / 2.0 - 2.0 * w5;
+    const double ws[9] = {0, w1, w2, w1, w2, w5, w5, w5, w5};
+    for (int j = 1; j < 9; ++j) v.w[j] = ws[j];
+  } else {
+    double w19 = 0.0;
+    if (p->lattice == RMRT_Q27) w19 = p->w_corner >= 0 ? p->w_corner : r[0] * r[1] * r[2] / 8.0;
+    const double w7 = r[0] * r[1] / 4.0 - 2.0 * w19;
+    const double w11 = r[0] * r[2] / 4.0 - 2.0 * w19;
+    const double w15 = r[1] * r[2] / 4.0 - 2.0 * w19;
+    const double w1 = r[0] / 2.0 - 2.0 * (w7 + w11) - 4.0 * w19;
+    const double w2 = r[1] / 2.0 - 2.0 * (w7 + w15) - 4.0 * w19;
+    const double w3 = r[2] / 2.0 - 2.0 * (w11 + w15) - 4.0 * w19;
+    const double base[7] = {0, w1, w2, w3, w1, w2, w3};
+    for (int j = 1; j < 7; ++j) v.w[j] = base[j];
+    for (int j = 7; j < 11; ++j) v.w[j] = w7;
+    for (int j = 11; j < 15; ++j) v.w[j] = w11;
+    for (int j = 15; j < 19; ++j) v.w[j] = w15;
+    for (int j = 19; j < v.q; ++j) v.w[j] = w19;
+  }
+  double sum = 0;
+  for (int j = 1; j < v.q; ++j) sum += v.w[j];
+  v.w[0] = 1.0 - sum;
+  for (int j = 0; j < v.q; ++j)
+    if (!(v.w[j] >= 0)) return fail(RMRT_EINVAL, "weight w_%d = %g is negative", j, v.w[j]);
+
+  v.D0 = p->D0;
+  v.D2 = p->D2;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) v.Sbar[a][b] = 0.0;
+  if (p->equation == RMRT_NSE) {
+    v.nu = p->nu;
+    if (!(v.nu > 0)) return fail(RMRT_EINVAL, "nu must be > 0");
+    v.nu_b = p->nu_b < 0 ? 2.0 * v.nu / v.d : p->nu_b;
+    if (!(v.nu_b > 0)) return fail(RMRT_EINVAL, "nu_b must be > 0");
+    // eq. 4-31 solved for the rates
+    v.s_nu = 1.0 / (0.5 + v.nu / (v.cs2 * v.dt));
+    double a[3], b[3], Adiag[3];
+    for (int k = 0; k < v.d; ++k) {
+      const double g = v.c[k] * v.c[k] - v.cs2;
+      v.s_s[k] = 1.0 / (0.5 + 2.0 * v.nu / (g * v.dt));
+      v.s_b[k] = 1.0 / (0.5 + v.d * v.nu_b / (g * v.dt));
+      a[k] = (1.0 / v.s_b[k] - 1.0 / v.s_s[k]) * g;
+      b[k] = 1.0 / g;
+      Adiag[k] = v.s_s[k];
+    }
+    // Sherman-Morrison form of the inverse of diag(1/s_s) + a b^T / d (eq. 5-8-1)
+    double bAa = 0.0;
+    for (int k = 0; k < v.d; ++k) bAa += b[k] * Adiag[k] * a[k] / v.d;
+    for (int i = 0; i < v.d; ++i)
+      for (int k = 0; k < v.d; ++k)
+        v.Sbar[i][k] = (i == k ? Adiag[i] : 0.0) - Adiag[i] * (a[i] / v.d) * b[k] * Adiag[k] / (1.0 + bAa);
+    v.s_hi = p->s_hi > 0 ? p->s_hi : v.s_nu;
+    if (!(v.s_nu > 0 && v.s_nu < 2)) return fail(RMRT_EINVAL, "s_nu = %g outside (0, 2)", v.s_nu);
+    for (int k = 0; k < v.d; ++k)
+      if (!(v.s_s[k] > 0 && v.s_s[k] < 2 && v.s_b[k] > 0 && v.s_b[k] < 2))
+        return fail(RMRT_EINVAL, "second-order rates outside (0, 2)");
+  } else {
+    v.nu = v.nu_b = 0.0;
+    if (!(p->D0 > 0)) return fail(RMRT_EINVAL, "D0 must be > 0 for the NCDE");
+    if (p->D2 < 0) return fail(RMRT_EINVAL, "D2 must be >= 0");
+    v.s_nu = 1.0;
+    v.s_hi = p->s_hi > 0 ? p->s_hi : 1.0;
+    for (int k = 0; k < 3; ++k) v.s_s[k] = v.s_b[k] = 1.0;
+  }
+  if (!(v.s_hi > 0 && v.s_hi < 2)) return fail(RMRT_EINVAL, "s_hi = %g outside (0, 2)", v.s_hi);
+  return RMRT_OK;
+}
+
+// L(k) = sum_j w_j prod_a c_ja^k_a (brute force over the lattice)
+double lattice_sum(const Derived& v, const int k[3]) {
+  double s = 0.0;
+  for (int j = 0; j < v.q; ++j) {
+    double t = v.w[j];
+    for (int a = 0; a < 3; ++a)
+      for (int i = 0; i < k[a]; ++i) t *= v.e[j][a] * v.c[a];
+    s += t;
+  }
+  return s;
+}
+
+void invert3(const double A[3][3], double B[3][3], int d) {
+  // Gauss-Jordan on the leading d x d block; remaining diagonal set to 1
+  double M[3][6];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 6; ++j) M[i][j] = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) M[i][j] = (i < d && j < d) ? A[i][j] : (i == j ? 1.0 : 0.0);
+    M[i][3 + i] = 1.0;
+  }
+  for (int c = 0; c < 3; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 3; ++r)
+      if (std::fabs(M[r][c]) > std::fabs(M[piv][c])) piv = r;
+    for (int j = 0; j < 6; ++j) std::swap(M[c][j], M[piv][j]);
+    const double inv = 1.0 / M[c][c];
+    for (int j = 0; j < 6; ++j) M[c][j] *= inv;
+    for (int r = 0; r < 3; ++r)
+      if (r != c) {
+        const double f = M[r][c];
+        for (int j = 0; j < 6; ++j) M[r][j] -= f * M[c][j];
+      }
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) B[i][j] = M[i][3 + j];
+}
+
+template <typename T>
+void fill_coef(const rmrt_params* p, const Derived& v, Coef<T>& C) {
+  std::memset(&C, 0, sizeof(C));
+  const double dt = v.dt;
+  C.rho0 = (T)p->rho0;
+  C.cs2 = (T)v.cs2;
+  C.inv_cs2 = (T)(1.0 / v.cs2);
+  C.dt = (T)dt;
+  for (int a = 0; a < 3; ++a) C.c[a] = (T)v.c[a];
+  for (int j = 0; j < 27; ++j) {
+    C.w[j] = (T)v.w[j];
+    C.iw[j] = v.w[j] > 0 ? (T)(1.0 / v.w[j]) : (T)0;
+  }
+  // scaled raw-moment tables of g_eq (eq. 3-3, 3-4) for every tensor slot
+  const int d = v.d;
+  const double cs2 = v.cs2;
+  const int nslots = d == 2 ? 9 : 27;
+  for (int n = 0; n < nslots; ++n) {
+    const int ex[3] = {n % 3, (n / 3) % 3, n / 9};
+    double scale = 1.0;
+    for (int a = 0; a < 3; ++a)
+      for (int i = 0; i < ex[a]; ++i) scale *= v.c[a];
+    int odd[3], nodd = 0;
+    for (int a = 0; a < 3; ++a)
+      if (ex[a] & 1) odd[nodd++] = a;
+    if (nodd == 0) {
+      C.E0[n] = (T)(lattice_sum(v, ex) / scale);
+      const double L0 = lattice_sum(v, ex);
+      for (int a = 0; a < d; ++a) {
+        int k[3] = {ex[0], ex[1], ex[2]};
+        k[a] += 2;
+        const double g = v.c[a] * v.c[a] - cs2;
+        C.E2[n][a] = (T)((lattice_sum(v, k) - cs2 * L0) / (cs2 * g * scale));
+      }
+    } else if (nodd == 1) {
+      int k[3] = {ex[0], ex[1], ex[2]};
+      k[odd[0]] += 1;
+      C.E1[n] = (T)(lattice_sum(v, k) / (cs2 * scale));
+    } else if (nodd == 2) {
+      int k[3] = {ex[0], ex[1], ex[2]};
+      k[odd[0]] += 1;
+      k[odd[1]] += 1;
+      C.E3[n] = (T)(lattice_sum(v, k) / (cs2 * cs2 * scale));
+    }
+  }
+  // relaxation: scaled diagonal block, off-diagonal and higher rates
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      C.Sd[a][b] = (a < d && b < d) ? (T)(v.Sbar[a][b] * v.c[b] * v.c[b] / (v.c[a] * v.c[a])) : (T)0;
+      C.IhS[a][b] = (T)((a == b ? 1.0 : 0.0) - ((a < d && b < d) ? 0.5 * v.Sbar[a][b] : 0.0));
+    }
+  for (int k = 0; k < 3; ++k) {
+    C.s_off[k] = (T)v.s_nu;
+    C.ihs_off[k] = (T)(1.0 - 0.5 * v.s_nu);
+  }
+  C.s_hi = (T)v.s_hi;
+  // source terms carry the factor dt (m* gets dt (m_G + (I - S/2) m_F))
+  for (int a = 0; a < 3; ++a) {
+    const double F = (a < d) ? p->force[a] : 0.0;
+    C.force[a] = (T)(dt * F);
+    C.half_force[a] = (T)(0.5 * dt * F);
+    C.adv[a] = (T)((a < d) ? p->adv[a] : 0.0);
+  }
+  C.source = (T)(dt * p->source);
+  C.half_source = (T)(0.5 * dt * p->source);
+  C.cs2_source = (T)(dt * cs2 * p->source);
+  C.half_cs2_source = (T)(0.5 * dt * cs2 * p->source);
+  C.D0 = (T)p->D0;
+  C.D2 = (T)p->D2;
+  C.inv_cs2_dt = (T)(1.0 / (cs2 * dt));
+}
+
+uint32_t magic(uint32_t d) { return d <= 1 ? 0xffffffffu : (uint32_t)(0x100000000ull / d); }
+
+void fill_domain(const rmrt_params* p, const Derived& v, DomainDev& D, void* fa, void* fb, const uint8_t* solid) {
+  std::memset(&D, 0, sizeof(D));
+  fill_coef<double>(p, v, D.cd);
+  fill_coef<float>(p, v, D.cf);
+  double IhS[3][3], K[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) IhS[a][b] = (a == b ? 1.0 : 0.0) - 0.5 * v.Sbar[a][b];
+  invert3(IhS, K, v.d);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) D.ic.Kd[a][b] = (a < v.d && b < v.d) ? K[a][b] : 0.0;
+  for (int k = 0; k < 3; ++k) D.ic.k_off[k] = 1.0 / (1.0 - 0.5 * v.s_nu);
+  D.ic.nu = v.nu;
+  D.ic.nu_b = v.nu_b;
+  D.nx = p->n[0];
+  D.ny = p->n[1];
+  D.nz = p->n[2];
+  D.nxny = D.nx * D.ny;
+  D.N = D.nxny * D.nz;
+  D.mnx = magic(D.nx);
+  D.mnxny = magic(D.nxny);
+  D.walls = p->wall_faces & 63u;
+  if (v.d == 2) D.walls &= 15u;
+  D.has_solid = solid != nullptr;
+  D.lattice = p->lattice;
+  D.equation = p->equation;
+  D.storage = p->storage;
+  D.fa = fa;
+  D.fb = fb;
+  D.solid = solid;
+}
+
+bool has_force(const rmrt_params* p) {
+  if (p->source != 0.0) return true;
+  if (p->equation == RMRT_NSE)
+    for (int a = 0; a < 3; ++a)
+      if (p->force[a] != 0.0) return true;
+  return false;
+}
+
+size_t elem_size(int storage) { return storage == RMRT_F64 ? 8 : (storage == RMRT_F32DEV ? 4 : 2); }
+
+// ---------------------------------------------------------------------------
+// Dispatch onto the per-(lattice, storage) instantiations
+// ---------------------------------------------------------------------------
+template <template <int, int> class>
+struct Unused {};
+
+#define RMRT_DISPATCH(FN, lat, st, arg)                                               \
+  do {                                                                                \
+    switch ((lat) * 3 + (st)) {                                                       \
+      case 0: return FN<LAT_Q9, ST_F64>(arg);                                         \
+      case 1: return FN<LAT_Q9, ST_F32>(arg);                                         \
+      case 2: return FN<LAT_Q9, ST_F16>(arg);                                         \
+      case 3: return FN<LAT_Q19, ST_F64>(arg);                                        \
+      case 4: return FN<LAT_Q19, ST_F32>(arg);                                        \
+      case 5: return FN<LAT_Q19, ST_F16>(arg);                                        \
+      case 6: return FN<LAT_Q27, ST_F64>(arg);                                        \
+      case 7: return FN<LAT_Q27, ST_F32>(arg);                                        \
+      case 8: return FN<LAT_Q27, ST_F16>(arg);                                        \
+    }                                                                                 \
+    return hipErrorInvalidValue;                                                      \
+  } while (0)
+
+hipError_t dispatch_step(int lat, int st, const StepLaunch& a) { RMRT_DISPATCH(launch_step, lat, st, a); }
+hipError_t dispatch_init(int lat, int st, const AuxLaunch& a) { RMRT_DISPATCH(launch_init, lat, st, a); }
+hipError_t dispatch_moments(int lat, int st, const AuxLaunch& a) { RMRT_DISPATCH(launch_moments, lat, st, a); }
+hipError_t dispatch_populations(int lat, int st, const AuxLaunch& a) {
+  RMRT_DISPATCH(launch_populations, lat, st, a);
+}
+hipError_t dispatch_reduce(int lat, int st, const AuxLaunch& a) { RMRT_DISPATCH(launch_reduce, lat, st, a); }
+hipError_t dispatch_residual(int lat, int st, const AuxLaunch& a) { RMRT_DISPATCH(launch_residual, lat, st, a); }
+
+constexpr unsigned kAuxBlock = 256;
+constexpr unsigned kMaxAuxGrid = 2048;
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Contexts
+// ---------------------------------------------------------------------------
+struct rmrt_ctx {
+  rmrt_params p;
+  Derived v;
+  DomainDev hdom;
+  DomainDev* ddoms = nullptr;  // device array holding this domain at index dom
+  uint32_t dom = 0;
+  bool owns_ddoms = false;
+  rmrt_batch* batch = nullptr;
+  long long steps = 0;
+  double* partials = nullptr;  // kMaxAuxGrid x 5
+  double* dres = nullptr;      // 8 doubles
+  double* hres = nullptr;      // pinned, 8 doubles
+  double* uprev = nullptr;
+  bool have_prev = false;
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  hipStream_t cap = nullptr;   // capture stream
+};
+
+namespace {
+
+unsigned aux_grid(uint32_t N) {
+  unsigned g = (N + kAuxBlock - 1) / kAuxBlock;
+  return std::max(1u, std::min(g, kMaxAuxGrid));
+}
+
+AuxLaunch aux_of(const rmrt_ctx* c, hipStream_t s) {
+  AuxLaunch a;
+  std::memset(&a, 0, sizeof(a));
+  a.doms = c->ddoms;
+  a.dom = c->dom;
+  a.parity = (uint32_t)(c->steps & 1);
+  a.ab = c->p.pattern == RMRT_AB;
+  a.eq = c->p.equation;
+  a.bc = (c->hdom.walls != 0 || c->hdom.has_solid) ? 1 : 0;
+  a.swapped = (c->p.pattern == RMRT_AA) && (c->steps & 1);
+  a.grid = aux_grid(c->hdom.N);
+  a.block = kAuxBlock;
+  a.stream = s;
+  return a;
+}
+
+int ctx_alloc_scratch(rmrt_ctx* c) {
+  HIP_TRY(hipMalloc(&c->partials, sizeof(double) * kMaxAuxGrid * 5));
+  HIP_TRY(hipMalloc(&c->dres, sizeof(double) * 8));
+  HIP_TRY(hipHostMalloc(&c->hres, sizeof(double) * 8, hipHostMallocDefault));
+  return RMRT_OK;
+}
+
+void ctx_release(rmrt_ctx* c) {
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  if (c->cap) hipStreamDestroy(c->cap);
+  if (c->partials) hipFree(c->partials);
+  if (c->dres) hipFree(c->dres);
+  if (c->hres) hipHostFree(c->hres);
+  if (c->uprev) hipFree(c->uprev);
+  if (c->owns_ddoms && c->ddoms) hipFree(c->ddoms);
+}
+
+int launch_init_fields(rmrt_ctx* c, const double* rho, const double* u, int with_fne, hipStream_t s) {
+  if (with_fne && c->p.equation != RMRT_NSE) return fail(RMRT_EUNSUPPORTED, "with_fne is NSE only");
+  AuxLaunch a = aux_of(c, s);
+  a.in0 = rho;
+  a.in1 = u;
+  a.flag = with_fne;
+  hipError_t e = dispatch_init(c->p.lattice, c->p.storage, a);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "init launch failed: %s", hipGetErrorString(e));
+  c->have_prev = false;
+  return RMRT_OK;
+}
+
+int launch_one_step(rmrt_ctx* c, long long step_index, hipStream_t s) {
+  StepLaunch a;
+  std::memset(&a, 0, sizeof(a));
+  a.doms = c->ddoms + c->dom;
+  a.tiles = nullptr;
+  a.tile_nodes = 256;
+  a.ntiles = (c->hdom.N + a.tile_nodes - 1) / a.tile_nodes;
+  a.parity = (uint32_t)(step_index & 1);
+  a.eq = c->p.equation;
+  a.force = has_force(&c->p);
+  a.bc = (c->hdom.walls != 0 || c->hdom.has_solid) ? 1 : 0;
+  a.phase = c->p.pattern == RMRT_AB ? PH_AB : ((step_index & 1) ? PH_AA_ODD : PH_AA_EVEN);
+  a.grid = a.ntiles;
+  a.block = 256;
+  a.stream = s;
+  hipError_t e = dispatch_step(c->p.lattice, c->p.storage, a);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "step launch failed: %s", hipGetErrorString(e));
+  return RMRT_OK;
+}
+
+constexpr int kGraphChunk = 256;
+
+// steps n launches as a cached graph keyed by (n, parity of the first step)
+int run_graph(rmrt_ctx* c, int n, hipStream_t s) {
+  const auto key = std::make_pair(n, (int)(c->steps & 1));
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    int rc = RMRT_OK;
+    for (int i = 0; i < n && rc == RMRT_OK; ++i) rc = launch_one_step(c, c->steps + i, c->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap, &g);
+    if (rc != RMRT_OK) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(RMRT_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(RMRT_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    if (c->graphs.size() >= 16) {
+      for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+      c->graphs.clear();
+    }
+    it = c->graphs.emplace(key, ge).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, s));
+  c->steps += n;
+  return RMRT_OK;
+}
+
+int step_impl(rmrt_ctx* c, int nsteps, hipStream_t s) {
+  if (nsteps == 1) {
+    int rc = launch_one_step(c, c->steps, s);
+    if (rc == RMRT_OK) c->steps += 1;
+    return rc;
+  }
+  int left = nsteps;
+  while (left >= kGraphChunk) {
+    int rc = run_graph(c, kGraphChunk, s);
+    if (rc != RMRT_OK) return rc;
+    left -= kGraphChunk;
+  }
+  if (left > 1) return run_graph(c, left, s);
+  if (left == 1) {
+    int rc = launch_one_step(c, c->steps, s);
+    if (rc == RMRT_OK) c->steps += 1;
+    return rc;
+  }
+  return RMRT_OK;
+}
+
+int reduce_impl(rmrt_ctx* c, double out[4], hipStream_t s) {
+  AuxLaunch a = aux_of(c, s);
+  a.out0 = c->partials;
+  hipError_t e = dispatch_reduce(c->p.lattice, c->p.storage, a);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "reduce launch: %s", hipGetErrorString(e));
+  e = launch_reduce_final(c->partials, a.grid, c->dres, 5, s);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "reduce final: %s", hipGetErrorString(e));
+  HIP_TRY(hipMemcpyAsync(c->hres, c->dres, sizeof(double) * 5, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out[0] = c->hres[4] * c->p.rho0 + c->hres[0];
+  out[1] = c->hres[1];
+  out[2] = c->hres[2];
+  out[3] = c->hres[3];
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(out[k])) return fail(RMRT_ENONFINITE, "non-finite reduction result");
+  return RMRT_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* rmrt_last_error(void) { return g_last_error.c_str(); }
+
+const char* rmrt_version(void) { return "rmrt 0.1 (gfx950)"; }
+
+int rmrt_derive(const rmrt_params* p, rmrt_derived* out) {
+  Derived v;
+  int rc = derive(p, v);
+  if (rc != RMRT_OK) return rc;
+  if (!out) return fail(RMRT_EINVAL, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  out->q = v.q;
+  out->d = v.d;
+  for (int a = 0; a < 3; ++a) out->c[a] = v.c[a];
+  out->cs2 = v.cs2;
+  for (int j = 0; j < 27; ++j) out->w[j] = v.w[j];
+  out->s_nu = v.s_nu;
+  for (int a = 0; a < 3; ++a) {
+    out->s_s[a] = v.s_s[a];
+    out->s_b[a] = v.s_b[a];
+    for (int b = 0; b < 3; ++b) out->Sbar2[a][b] = v.Sbar[a][b];
+  }
+  out->s_hi = v.s_hi;
+  out->nu_b = v.nu_b;
+  return RMRT_OK;
+}
+
+int rmrt_population_bytes(const rmrt_params* p, size_t* bytes) {
+  Derived v;
+  int rc = derive(p, v);
+  if (rc != RMRT_OK) return rc;
+  if (!bytes) return fail(RMRT_EINVAL, "bytes is NULL");
+  *bytes = (size_t)v.q * p->n[0] * p->n[1] * p->n[2] * elem_size(p->storage);
+  return RMRT_OK;
+}
+
+static int ctx_create(rmrt_ctx** out, const rmrt_params* p, void* f0, void* f1, const uint8_t* solid,
+                      DomainDev* ddoms, uint32_t dom) {
+  if (!out) return fail(RMRT_EINVAL, "out is NULL");
+  *out = nullptr;
+  Derived v;
+  int rc = derive(p, v);
+  if (rc != RMRT_OK) return rc;
+  if (!f0) return fail(RMRT_EINVAL, "f0 is NULL");
+  if (p->pattern == RMRT_AB && !f1) return fail(RMRT_EINVAL, "RMRT_AB needs f1");
+  if (p->pattern == RMRT_AA && f1) return fail(RMRT_EINVAL, "RMRT_AA takes f1 = NULL");
+  rmrt_ctx* c = new (std::nothrow) rmrt_ctx();
+  if (!c) return fail(RMRT_ENOMEM, "out of host memory");
+  c->p = *p;
+  c->v = v;
+  fill_domain(p, v, c->hdom, f0, f1, solid);
+  if (ddoms) {
+    c->ddoms = ddoms;
+    c->dom = dom;
+    c->owns_ddoms = false;
+  } else {
+    hipError_t e = hipMalloc(&c->ddoms, sizeof(DomainDev));
+    if (e != hipSuccess) {
+      delete c;
+      return fail(RMRT_EHIP, "hipMalloc(param block): %s", hipGetErrorString(e));
+    }
+    c->owns_ddoms = true;
+    c->dom = 0;
+  }
+  rc = ctx_alloc_scratch(c);
+  if (rc != RMRT_OK) {
+    ctx_release(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return RMRT_OK;
+}
+
+int rmrt_init(rmrt_ctx** out, const rmrt_params* p, void* f0, void* f1, const uint8_t* solid,
+              const double* rho, const double* u, int with_fne, void* stream) {
+  rmrt_ctx* c = nullptr;
+  int rc = ctx_create(&c, p, f0, f1, solid, nullptr, 0);
+  if (rc != RMRT_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(c->ddoms, &c->hdom, sizeof(DomainDev), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    ctx_release(c);
+    delete c;
+    return fail(RMRT_EHIP, "param upload: %s", hipGetErrorString(e));
+  }
+  if (!rho) {
+    ctx_release(c);
+    delete c;
+    return fail(RMRT_EINVAL, "rho is NULL");
+  }
+  rc = launch_init_fields(c, rho, u, with_fne, s);
+  if (rc != RMRT_OK) {
+    ctx_release(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return RMRT_OK;
+}
+
+int rmrt_set_fields(rmrt_ctx* c, const double* rho, const double* u, int with_fne, void* stream) {
+  if (!c) return fail(RMRT_EINVAL, "ctx is NULL");
+  if (!rho) return fail(RMRT_EINVAL, "rho is NULL");
+  if (!c->batch) c->steps = 0;  // a standalone context restarts at an even step
+  return launch_init_fields(c, rho, u, with_fne, (hipStream_t)stream);
+}
+
+int rmrt_step(rmrt_ctx* c, int nsteps, void* stream) {
+  if (!c) return fail(RMRT_EINVAL, "ctx is NULL");
+  if (c->batch) return fail(RMRT_EINVAL, "domain belongs to a batch: use rmrt_batch_step");
+  if (nsteps < 0) return fail(RMRT_EINVAL, "nsteps < 0");
+  hipStream_t s = (hipStream_t)stream;
+  if (c->p.check_every > 0) {
+    int left = nsteps;
+    while (left > 0) {
+      const int k = std::min(left, c->p.check_every);
+      int rc = step_impl(c, k, s);
+      if (rc != RMRT_OK) return rc;
+      left -= k;
+      double r[4];
+      rc = reduce_impl(c, r, s);
+      if (rc != RMRT_OK) return rc;
+    }
+    return RMRT_OK;
+  }
+  return step_impl(c, nsteps, s);
+}
+
+int rmrt_moments(rmrt_ctx* c, void* rho_out, void* u_out, int out_dtype, void* stream) {
+  if (!c || !rho_out) return fail(RMRT_EINVAL, "ctx or rho_out is NULL");
+  if (out_dtype != RMRT_OUT_F64 && out_dtype != RMRT_OUT_F32) return fail(RMRT_EINVAL, "bad out_dtype");
+  AuxLaunch a = aux_of(c, (hipStream_t)stream);
+  a.out0 = rho_out;
+  a.out1 = u_out;
+  a.flag = out_dtype == RMRT_OUT_F32;
+  hipError_t e = dispatch_moments(c->p.lattice, c->p.storage, a);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "moments launch: %s", hipGetErrorString(e));
+  return RMRT_OK;
+}
+
+int rmrt_populations(rmrt_ctx* c, double* f_out, void* stream) {
+  if (!c || !f_out) return fail(RMRT_EINVAL, "ctx or f_out is NULL");
+  AuxLaunch a = aux_of(c, (hipStream_t)stream);
+  a.out0 = f_out;
+  hipError_t e = dispatch_populations(c->p.lattice, c->p.storage, a);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "populations launch: %s", hipGetErrorString(e));
+  return RMRT_OK;
+}
+
+int rmrt_reduce(rmrt_ctx* c, double out[4], void* stream) {
+  if (!c || !out) return fail(RMRT_EINVAL, "ctx or out is NULL");
+  return reduce_impl(c, out, (hipStream_t)stream);
+}
+
+int rmrt_residual(rmrt_ctx* c, double* r, void* stream) {
+  if (!c || !r) return fail(RMRT_EINVAL, "ctx or r is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const int K = c->p.equation == RMRT_NSE ? c->v.d : 1;
+  if (!c->uprev) HIP_TRY(hipMalloc(&c->uprev, sizeof(double) * (size_t)K * c->hdom.N));
+  AuxLaunch a = aux_of(c, s);
+  a.out0 = c->partials;
+  a.out1 = c->uprev;
+  a.flag = c->have_prev ? 1 : 0;
+  hipError_t e = dispatch_residual(c->p.lattice, c->p.storage, a);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "residual launch: %s", hipGetErrorString(e));
+  e = launch_reduce_final(c->partials, a.grid, c->dres, 2, s);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "residual final: %s", hipGetErrorString(e));
+  HIP_TRY(hipMemcpyAsync(c->hres, c->dres, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const bool first = !c->have_prev;
+  c->have_prev = true;
+  if (!std::isfinite(c->hres[0]) || !std::isfinite(c->hres[1]))
+    return fail(RMRT_ENONFINITE, "non-finite residual");
+  if (first) {
+    *r = INFINITY;
+  } else {
+    *r = c->hres[1] > 0 ? std::sqrt(c->hres[0] / c->hres[1]) : (c->hres[0] > 0 ? INFINITY : 0.0);
+  }
+  return RMRT_OK;
+}
+
+int rmrt_steps_taken(const rmrt_ctx* c, long long* steps) {
+  if (!c || !steps) return fail(RMRT_EINVAL, "NULL argument");
+  *steps = c->steps;
+  return RMRT_OK;
+}
+
+int rmrt_free(rmrt_ctx* c) {
+  if (!c) return RMRT_OK;
+  if (c->batch) return fail(RMRT_EINVAL, "domain belongs to a batch: use rmrt_batch_free");
+  ctx_release(c);
+  delete c;
+  return RMRT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched persistent stepping
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TileConfig {
+  int threads, tile_nodes, blocks_per_cu;  // blocks_per_cu <= 0: one workgroup per tile
+};
+const TileConfig kConfigs[] = {
+    {256, 256, 0},  {256, 1024, 8}, {256, 2048, 8}, {256, 4096, 8},
+    {512, 2048, 4}, {512, 8192, 4}, {128, 512, 16}, {256, 1024, 4},
+};
+constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
+
+}  // namespace
+
+struct rmrt_batch {
+  int nd = 0;
+  std::vector<rmrt_ctx*> ctxs;
+  DomainDev* ddoms = nullptr;
+  Tile* dtiles = nullptr;
+  uint32_t ntiles = 0;
+  int cfg = 1;
+  int cus = 256;
+  long long steps = 0;
+  int lattice = 0, storage = 0, equation = 0, pattern = 0, force = 0, bc = 0;
+  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+  hipStream_t cap = nullptr;
+};
+
+namespace {
+
+int batch_build_tiles(rmrt_batch* b, int cfg, hipStream_t s) {
+  const TileConfig& tc = kConfigs[cfg];
+  std::vector<Tile> tiles;
+  for (int d = 0; d < b->nd; ++d) {
+    const uint32_t N = b->ctxs[d]->hdom.N;
+    for (uint32_t st = 0; st < N; st += (uint32_t)tc.tile_nodes) {
+      Tile t;
+      t.dom = (uint32_t)d;
+      t.start = st;
+      t.count = std::min<uint32_t>((uint32_t)tc.tile_nodes, N - st);
+      t.pad = 0;
+      tiles.push_back(t);
+    }
+  }
+  if (b->dtiles) {
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipFree(b->dtiles));
+    b->dtiles = nullptr;
+  }
+  HIP_TRY(hipMalloc(&b->dtiles, sizeof(Tile) * tiles.size()));
+  HIP_TRY(hipMemcpyAsync(b->dtiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  b->ntiles = (uint32_t)tiles.size();
+  b->cfg = cfg;
+  for (auto& kv : b->graphs) hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+  return RMRT_OK;
+}
+
+int batch_launch(rmrt_batch* b, long long step_index, hipStream_t s) {
+  const TileConfig& tc = kConfigs[b->cfg];
+  StepLaunch a;
+  std::memset(&a, 0, sizeof(a));
+  a.doms = b->ddoms;
+  a.tiles = b->dtiles;
+  a.ntiles = b->ntiles;
+  a.tile_nodes = (uint32_t)tc.tile_nodes;
+  a.parity = (uint32_t)(step_index & 1);
+  a.eq = b->equation;
+  a.force = b->force;
+  a.bc = b->bc;
+  a.phase = b->pattern == RMRT_AB ? PH_AB : ((step_index & 1) ? PH_AA_ODD : PH_AA_EVEN);
+  const uint32_t persistent = tc.blocks_per_cu > 0 ? (uint32_t)(b->cus * tc.blocks_per_cu) : b->ntiles;
+  a.grid = std::min(b->ntiles, persistent);
+  a.block = (unsigned)tc.threads;
+  a.stream = s;
+  hipError_t e = dispatch_step(b->lattice, b->storage, a);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "batch step launch: %s", hipGetErrorString(e));
+  return RMRT_OK;
+}
+
+void batch_advance(rmrt_batch* b, int n) {
+  b->steps += n;
+  for (auto* c : b->ctxs) c->steps = b->steps;
+}
+
+int batch_graph(rmrt_batch* b, int n, hipStream_t s) {
+  const auto key = std::make_tuple(n, (int)(b->steps & 1), b->cfg);
+  auto it = b->graphs.find(key);
+  if (it == b->graphs.end()) {
+    if (!b->cap) HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    int rc = RMRT_OK;
+    for (int i = 0; i < n && rc == RMRT_OK; ++i) rc = batch_launch(b, b->steps + i, b->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (rc != RMRT_OK) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(RMRT_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(RMRT_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    if (b->graphs.size() >= 16) {
+      for (auto& kv : b->graphs) hipGraphExecDestroy(kv.second);
+      b->graphs.clear();
+    }
+    it = b->graphs.emplace(key, ge).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, s));
+  batch_advance(b, n);
+  return RMRT_OK;
+}
+
+int batch_step_impl(rmrt_batch* b, int nsteps, hipStream_t s) {
+  int left = nsteps;
+  while (left >= kGraphChunk) {
+    int rc = batch_graph(b, kGraphChunk, s);
+    if (rc != RMRT_OK) return rc;
+    left -= kGraphChunk;
+  }
+  if (left > 1) return batch_graph(b, left, s);
+  if (left == 1) {
+    int rc = batch_launch(b, b->steps, s);
+    if (rc == RMRT_OK) batch_advance(b, 1);
+    return rc;
+  }
+  return RMRT_OK;
+}
+
+void batch_release(rmrt_batch* b) {
+  for (auto& kv : b->graphs) hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+  if (b->cap) hipStreamDestroy(b->cap);
+  for (auto* c : b->ctxs) {
+    if (!c) continue;
+    c->batch = nullptr;
+    ctx_release(c);
+    delete c;
+  }
+  b->ctxs.clear();
+  if (b->dtiles) hipFree(b->dtiles);
+  if (b->ddoms) hipFree(b->ddoms);
+}
+
+}  // namespace
+
+extern "C" {
+
+int rmrt_batch_num_configs(void) { return kNumConfigs; }
+
+int rmrt_batch_config_info(int cfg, int* threads, int* tile_nodes, int* blocks_per_cu) {
+  if (cfg < 0 || cfg >= kNumConfigs) return fail(RMRT_EINVAL, "config %d out of range", cfg);
+  if (threads) *threads = kConfigs[cfg].threads;
+  if (tile_nodes) *tile_nodes = kConfigs[cfg].tile_nodes;
+  if (blocks_per_cu) *blocks_per_cu = kConfigs[cfg].blocks_per_cu;
+  return RMRT_OK;
+}
+
+int rmrt_batch_create(rmrt_batch** out, int nd, const rmrt_params* params, void* const* f0, void* const* f1,
+                      const uint8_t* const* solid, void* stream) {
+  if (!out) return fail(RMRT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nd < 1 || !params || !f0) return fail(RMRT_EINVAL, "need nd >= 1, params and f0");
+  const rmrt_params& p0 = params[0];
+  for (int d = 1; d < nd; ++d) {
+    const rmrt_params& p = params[d];
+    if (p.lattice != p0.lattice || p.equation != p0.equation || p.storage != p0.storage ||
+        p.pattern != p0.pattern)
+      return fail(RMRT_EINVAL, "domain %d differs in lattice/equation/storage/pattern", d);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  rmrt_batch* b = new (std::nothrow) rmrt_batch();
+  if (!b) return fail(RMRT_ENOMEM, "out of host memory");
+  b->nd = nd;
+  b->lattice = p0.lattice;
+  b->storage = p0.storage;
+  b->equation = p0.equation;
+  b->pattern = p0.pattern;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    b->cus = prop.multiProcessorCount;
+  hipError_t e = hipMalloc(&b->ddoms, sizeof(DomainDev) * nd);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(RMRT_EHIP, "hipMalloc(param blocks): %s", hipGetErrorString(e));
+  }
+  std::vector<DomainDev> host(nd);
+  for (int d = 0; d < nd; ++d) {
+    rmrt_ctx* c = nullptr;
+    const uint8_t* sd = solid ? solid[d] : nullptr;
+    int rc = ctx_create(&c, &params[d], f0[d], f1 ? f1[d] : nullptr, sd, b->ddoms, (uint32_t)d);
+    if (rc != RMRT_OK) {
+      batch_release(b);
+      delete b;
+      return rc;
+    }
+    c->batch = b;
+    b->ctxs.push_back(c);
+    host[d] = c->hdom;
+    b->force |= has_force(&params[d]) ? 1 : 0;
+    b->bc |= (c->hdom.walls != 0 || c->hdom.has_solid) ? 1 : 0;
+  }
+  e = hipMemcpyAsync(b->ddoms, host.data(), sizeof(DomainDev) * nd, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    batch_release(b);
+    delete b;
+    return fail(RMRT_EHIP, "param upload: %s", hipGetErrorString(e));
+  }
+  int rc = batch_build_tiles(b, 1, s);
+  for (int d = 0; d < nd && rc == RMRT_OK; ++d) rc = launch_init_fields(b->ctxs[d], nullptr, nullptr, 0, s);
+  if (rc != RMRT_OK) {
+    batch_release(b);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return RMRT_OK;
+}
+
+int rmrt_batch_domain(rmrt_batch* b, int d, rmrt_ctx** out) {
+  if (!b || !out || d < 0 || d >= b->nd) return fail(RMRT_EINVAL, "bad batch/domain index");
+  *out = b->ctxs[d];
+  return RMRT_OK;
+}
+
+int rmrt_batch_set_config(rmrt_batch* b, int cfg) {
+  if (!b) return fail(RMRT_EINVAL, "batch is NULL");
+  if (cfg < 0 || cfg >= kNumConfigs) return fail(RMRT_EINVAL, "config %d out of range", cfg);
+  return batch_build_tiles(b, cfg, nullptr);
+}
+
+int rmrt_batch_step(rmrt_batch* b, int nsteps, void* stream) {
+  if (!b) return fail(RMRT_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(RMRT_EINVAL, "nsteps < 0");
+  return batch_step_impl(b, nsteps, (hipStream_t)stream);
+}
+
+int rmrt_batch_autotune(rmrt_batch* b, int steps, void* stream, int* chosen) {
+  if (!b) return fail(RMRT_EINVAL, "batch is NULL");
+  if (steps < 1) return fail(RMRT_EINVAL, "steps must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int best = -1;
+  float best_ms = 1e30f;
+  for (int cfg = 0; cfg < kNumConfigs; ++cfg) {
+    int rc = batch_build_tiles(b, cfg, s);
+    if (rc == RMRT_OK) rc = batch_step_impl(b, 2, s);  // warm-up (and graph capture)
+    if (rc == RMRT_OK) rc = batch_step_impl(b, steps, s);  // captures the timed graph
+    if (rc != RMRT_OK) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return rc;
+    }
+    HIP_TRY(hipEventRecord(e0, s));
+    rc = batch_step_impl(b, steps, s);
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    if (rc != RMRT_OK) return rc;
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = cfg;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  int rc = batch_build_tiles(b, best, s);
+  if (rc != RMRT_OK) return rc;
+  if (chosen) *chosen = best;
+  return RMRT_OK;
+}
+
+int rmrt_batch_free(rmrt_batch* b) {
+  if (!b) return RMRT_OK;
+  batch_release(b);
+  delete b;
+  return RMRT_OK;
+}
+
+}  // extern "C"

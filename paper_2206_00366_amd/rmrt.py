@@ -1,0 +1,301 @@
+"""ctypes binding of librmrt.so (argument marshalling only).
+
+Every step of the method runs inside the library's HIP kernels; this module
+only converts Python values to the C structures of include/rmrt.h, passes
+device pointers of torch tensors and the current HIP stream, and turns error
+codes into exceptions.  It raises ImportError when the library is not built:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librmrt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2206_00366_amd.build` first")
+
+_lib = C.CDLL(LIB_PATH)
+
+# ---- constants (include/rmrt.h) ----
+OK, EINVAL, EUNSUPPORTED, EHIP, ENONFINITE, ENOMEM = 0, -1, -2, -3, -4, -5
+Q9, Q19, Q27 = 0, 1, 2
+NSE, NCDE = 0, 1
+F64, F32DEV, F16DEV = 0, 1, 2
+AB, AA = 0, 1
+OUT_F64, OUT_F32 = 0, 1
+WALL_XM, WALL_XP, WALL_YM, WALL_YP, WALL_ZM, WALL_ZP = 1, 2, 4, 8, 16, 32
+
+LATTICES = {"Q9": Q9, "Q19": Q19, "Q27": Q27}
+EQUATIONS = {"NSE": NSE, "NCDE": NCDE}
+STORAGES = {"f64": F64, "f32dev": F32DEV, "f16dev": F16DEV}
+PATTERNS = {"AB": AB, "AA": AA}
+Q_OF = {Q9: 9, Q19: 19, Q27: 27}
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_int), ("equation", C.c_int), ("storage", C.c_int), ("pattern", C.c_int),
+        ("n", C.c_int * 3), ("dx", C.c_double * 3), ("dt", C.c_double), ("cs2", C.c_double),
+        ("nu", C.c_double), ("nu_b", C.c_double), ("s_hi", C.c_double), ("w_corner", C.c_double),
+        ("D0", C.c_double), ("D2", C.c_double), ("adv", C.c_double * 3), ("force", C.c_double * 3),
+        ("source", C.c_double), ("rho0", C.c_double), ("wall_faces", C.c_uint), ("check_every", C.c_int),
+    ]
+
+
+class Derived(C.Structure):
+    _fields_ = [
+        ("q", C.c_int), ("d", C.c_int), ("c", C.c_double * 3), ("cs2", C.c_double),
+        ("w", C.c_double * 27), ("s_nu", C.c_double), ("s_s", C.c_double * 3), ("s_b", C.c_double * 3),
+        ("s_hi", C.c_double), ("Sbar2", (C.c_double * 3) * 3), ("nu_b", C.c_double),
+    ]
+
+
+_vp = C.c_void_p
+_sig = {
+    "rmrt_last_error": (C.c_char_p, []),
+    "rmrt_version": (C.c_char_p, []),
+    "rmrt_derive": (C.c_int, [C.POINTER(Params), C.POINTER(Derived)]),
+    "rmrt_population_bytes": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_size_t)]),
+    "rmrt_init": (C.c_int, [C.POINTER(_vp), C.POINTER(Params), _vp, _vp, _vp, _vp, _vp, C.c_int, _vp]),
+    "rmrt_set_fields": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
+    "rmrt_step": (C.c_int, [_vp, C.c_int, _vp]),
+    "rmrt_moments": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
+    "rmrt_populations": (C.c_int, [_vp, _vp, _vp]),
+    "rmrt_reduce": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
+    "rmrt_residual": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
+    "rmrt_steps_taken": (C.c_int, [_vp, C.POINTER(C.c_longlong)]),
+    "rmrt_free": (C.c_int, [_vp]),
+    "rmrt_batch_create": (C.c_int, [C.POINTER(_vp), C.c_int, C.POINTER(Params), C.POINTER(_vp),
+                                     C.POINTER(_vp), C.POINTER(_vp), _vp]),
+    "rmrt_batch_domain": (C.c_int, [_vp, C.c_int, C.POINTER(_vp)]),
+    "rmrt_batch_autotune": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(C.c_int)]),
+    "rmrt_batch_set_config": (C.c_int, [_vp, C.c_int]),
+    "rmrt_batch_num_configs": (C.c_int, []),
+    "rmrt_batch_config_info": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "rmrt_batch_step": (C.c_int, [_vp, C.c_int, _vp]),
+    "rmrt_batch_free": (C.c_int, [_vp]),
+}
+for _name, (_res, _args) in _sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class RMRTError(RuntimeError):
+    def __init__(self, code, where):
+        msg = _lib.rmrt_last_error().decode()
+        super().__init__(f"{where} returned {code}: {msg}")
+        self.code = code
+
+
+def _check(code, where):
+    if code != OK:
+        raise RMRTError(code, where)
+
+
+def lib():
+    return _lib
+
+
+def version() -> str:
+    return _lib.rmrt_version().decode()
+
+
+def make_params(lattice="Q9", equation="NSE", storage="f64", pattern="AB", n=(8, 8, 1),
+                dx=(1.0, 1.0, 1.0), dt=1.0, cs2=-1.0, nu=0.1, nu_b=-1.0, s_hi=-1.0, w_corner=-1.0,
+                D0=0.0, D2=0.0, adv=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0), source=0.0, rho0=1.0,
+                wall_faces=0, check_every=0, **_ignored) -> Params:
+    def pad3(v, fill):
+        v = list(v) + [fill] * 3
+        return v[:3]
+
+    p = Params()
+    p.lattice = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
+    p.equation = EQUATIONS[equation] if isinstance(equation, str) else int(equation)
+    p.storage = STORAGES[storage] if isinstance(storage, str) else int(storage)
+    p.pattern = PATTERNS[pattern] if isinstance(pattern, str) else int(pattern)
+    p.n[:] = [int(v) for v in pad3(n, 1)]
+    p.dx[:] = [float(v) for v in pad3(dx, 1.0)]
+    p.dt, p.cs2, p.nu, p.nu_b, p.s_hi, p.w_corner = float(dt), float(cs2), float(nu), float(nu_b), float(s_hi), float(w_corner)
+    p.D0, p.D2 = float(D0), float(D2)
+    p.adv[:] = [float(v) for v in pad3(adv, 0.0)]
+    p.force[:] = [float(v) for v in pad3(force, 0.0)]
+    p.source, p.rho0 = float(source), float(rho0)
+    p.wall_faces = int(wall_faces)
+    p.check_every = int(check_every)
+    return p
+
+
+def derive(params: Params) -> Derived:
+    out = Derived()
+    _check(_lib.rmrt_derive(C.byref(params), C.byref(out)), "rmrt_derive")
+    return out
+
+
+def population_bytes(params: Params) -> int:
+    b = C.c_size_t()
+    _check(_lib.rmrt_population_bytes(C.byref(params), C.byref(b)), "rmrt_population_bytes")
+    return b.value
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_STORE_DTYPES = {F64: "float64", F32DEV: "float32", F16DEV: "float16"}
+
+
+class Domain:
+    """One domain: owns torch tensors for its buffers and an rmrt_ctx."""
+
+    def __init__(self, params: Params, rho, u=None, solid=None, with_fne=False, device="cuda"):
+        import torch
+        self.params = params
+        self.q = Q_OF[params.lattice]
+        self.d = 2 if params.lattice == Q9 else 3
+        self.N = params.n[0] * params.n[1] * params.n[2]
+        dt = getattr(torch, _STORE_DTYPES[params.storage])
+        self.f0 = torch.empty(self.q * self.N, dtype=dt, device=device)
+        self.f1 = torch.empty_like(self.f0) if params.pattern == AB else None
+        self.solid = None if solid is None else torch.as_tensor(solid, dtype=torch.uint8, device=device).contiguous()
+        rho = torch.as_tensor(rho, dtype=torch.float64, device=device).contiguous()
+        u = None if u is None else torch.as_tensor(u, dtype=torch.float64, device=device).contiguous()
+        self._ctx = C.c_void_p()
+        _check(_lib.rmrt_init(C.byref(self._ctx), C.byref(params), _ptr(self.f0), _ptr(self.f1),
+                              _ptr(self.solid), _ptr(rho), _ptr(u), int(with_fne), _stream()), "rmrt_init")
+        self._keep = (rho, u)
+
+    @classmethod
+    def _borrow(cls, ctx, params, f0, f1, solid):
+        self = cls.__new__(cls)
+        self.params = params
+        self.q = Q_OF[params.lattice]
+        self.d = 2 if params.lattice == Q9 else 3
+        self.N = params.n[0] * params.n[1] * params.n[2]
+        self.f0, self.f1, self.solid = f0, f1, solid
+        self._ctx = ctx
+        self._borrowed = True
+        return self
+
+    def set_fields(self, rho, u=None, with_fne=False):
+        import torch
+        rho = torch.as_tensor(rho, dtype=torch.float64, device=self.f0.device).contiguous()
+        u = None if u is None else torch.as_tensor(u, dtype=torch.float64, device=self.f0.device).contiguous()
+        _check(_lib.rmrt_set_fields(self._ctx, _ptr(rho), _ptr(u), int(with_fne), _stream()), "rmrt_set_fields")
+        self._keep = (rho, u)
+
+    def step(self, n=1):
+        _check(_lib.rmrt_step(self._ctx, int(n), _stream()), "rmrt_step")
+
+    def moments(self, out_dtype=OUT_F64, with_u=True):
+        import torch
+        dt = torch.float64 if out_dtype == OUT_F64 else torch.float32
+        rho = torch.empty(self.N, dtype=dt, device=self.f0.device)
+        u = torch.empty(self.d * self.N, dtype=dt, device=self.f0.device) if with_u else None
+        _check(_lib.rmrt_moments(self._ctx, _ptr(rho), _ptr(u), int(out_dtype), _stream()), "rmrt_moments")
+        return rho, (u.view(self.d, self.N) if u is not None else None)
+
+    def populations(self):
+        import torch
+        out = torch.empty(self.q * self.N, dtype=torch.float64, device=self.f0.device)
+        _check(_lib.rmrt_populations(self._ctx, _ptr(out), _stream()), "rmrt_populations")
+        return out.view(self.q, self.N)
+
+    def reduce(self):
+        out = (C.c_double * 4)()
+        _check(_lib.rmrt_reduce(self._ctx, out, _stream()), "rmrt_reduce")
+        return list(out)
+
+    def residual(self):
+        r = C.c_double()
+        _check(_lib.rmrt_residual(self._ctx, C.byref(r), _stream()), "rmrt_residual")
+        return r.value
+
+    def steps_taken(self):
+        s = C.c_longlong()
+        _check(_lib.rmrt_steps_taken(self._ctx, C.byref(s)), "rmrt_steps_taken")
+        return s.value
+
+    def close(self):
+        if getattr(self, "_borrowed", False):
+            return
+        if self._ctx:
+            _lib.rmrt_free(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many domains stepped by one persistent kernel per step (graph replay)."""
+
+    def __init__(self, params_list, solids=None, device="cuda"):
+        import torch
+        nd = len(params_list)
+        self.params = list(params_list)
+        arr = (Params * nd)(*self.params)
+        self.f0, self.f1, self.solids = [], [], []
+        for k, p in enumerate(self.params):
+            q = Q_OF[p.lattice]
+            N = p.n[0] * p.n[1] * p.n[2]
+            dt = getattr(torch, _STORE_DTYPES[p.storage])
+            self.f0.append(torch.empty(q * N, dtype=dt, device=device))
+            self.f1.append(torch.empty_like(self.f0[-1]) if p.pattern == AB else None)
+            s = None if solids is None or solids[k] is None else torch.as_tensor(
+                solids[k], dtype=torch.uint8, device=device).contiguous()
+            self.solids.append(s)
+        f0 = (C.c_void_p * nd)(*[t.data_ptr() for t in self.f0])
+        f1 = (C.c_void_p * nd)(*[t.data_ptr() for t in self.f1]) if self.params[0].pattern == AB else None
+        sol = (C.c_void_p * nd)(*[0 if s is None else s.data_ptr() for s in self.solids])
+        self._b = C.c_void_p()
+        _check(_lib.rmrt_batch_create(C.byref(self._b), nd, arr, f0, f1, sol, _stream()), "rmrt_batch_create")
+        self.domains = []
+        for k in range(nd):
+            ctx = C.c_void_p()
+            _check(_lib.rmrt_batch_domain(self._b, k, C.byref(ctx)), "rmrt_batch_domain")
+            self.domains.append(Domain._borrow(ctx, self.params[k], self.f0[k], self.f1[k], self.solids[k]))
+
+    def step(self, n=1):
+        _check(_lib.rmrt_batch_step(self._b, int(n), _stream()), "rmrt_batch_step")
+
+    def autotune(self, steps=10):
+        ch = C.c_int()
+        _check(_lib.rmrt_batch_autotune(self._b, int(steps), _stream(), C.byref(ch)), "rmrt_batch_autotune")
+        return ch.value
+
+    def set_config(self, cfg):
+        _check(_lib.rmrt_batch_set_config(self._b, int(cfg)), "rmrt_batch_set_config")
+
+    @staticmethod
+    def configs():
+        out = []
+        for k in range(_lib.rmrt_batch_num_configs()):
+            t, n, b = C.c_int(), C.c_int(), C.c_int()
+            _check(_lib.rmrt_batch_config_info(k, C.byref(t), C.byref(n), C.byref(b)), "rmrt_batch_config_info")
+            out.append((t.value, n.value, b.value))
+        return out
+
+    def close(self):
+        if self._b:
+            _lib.rmrt_batch_free(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function that include/rmrt.h declares, and its parameter derivation
+(weights, rates, second-order block) agrees with the independent oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import rmrt_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rmrt.h")
+
+rmrt = pytest.importorskip("paper_2206_00366_amd.rmrt", reason="librmrt.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rmrt_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    names = declared_functions()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(rmrt.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding covers the same set
+    assert set(names) == set(rmrt.EXPORTED)
+
+
+CASES = [
+    dict(lattice="Q9", n=(8, 8, 1), dx=(1.0, 0.5, 1.0), nu=0.02, nu_b=0.05),
+    dict(lattice="Q9", n=(8, 8, 1), dx=(1.0, 2.0, 1.0), nu=0.1),
+    dict(lattice="Q19", n=(4, 4, 4), dx=(1.0, 1.0, 2.0), nu=0.005),
+    dict(lattice="Q19", n=(4, 4, 4), dx=(1.0, 0.5, 2.0), nu=0.03, nu_b=0.2),
+    dict(lattice="Q27", n=(4, 4, 4), dx=(1.0, 0.5, 2.0), nu=0.05, nu_b=0.01),
+    dict(lattice="Q27", n=(4, 4, 4), dx=(1.0, 2.0, 1.0), nu=0.05, w_corner=0.001),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_derived_parameters_match_oracle(case):
+    m = O.Model(case)
+    d = rmrt.derive(rmrt.make_params(**case))
+    assert d.q == m.q and d.d == m.d
+    assert abs(d.cs2 - m.cs2) < 1e-15
+    np.testing.assert_allclose(np.array(d.w)[: m.q], m.w, rtol=0, atol=1e-15)
+    assert abs(d.s_nu - m.s_ab) < 1e-14
+    np.testing.assert_allclose(np.array(d.s_s)[: m.d], m.s_s, atol=1e-14)
+    np.testing.assert_allclose(np.array(d.s_b)[: m.d], m.s_b, atol=1e-14)
+    Sb = np.array([[d.Sbar2[i][k] for k in range(m.d)] for i in range(m.d)])
+    np.testing.assert_allclose(Sb, m.Sbar21, atol=1e-13)
+    assert abs(d.s_hi - m.s_hi) < 1e-14
+
+
+def test_population_bytes():
+    p = rmrt.make_params(lattice="Q27", storage="f16dev", n=(10, 20, 30), nu=0.05)
+    assert rmrt.population_bytes(p) == 27 * 6000 * 2
+    p = rmrt.make_params(lattice="Q9", storage="f64", n=(10, 20, 1), nu=0.05)
+    assert rmrt.population_bytes(p) == 9 * 200 * 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(lattice="Q9", n=(8, 8, 2)),                                 # 2D with nz > 1
+    dict(lattice="Q9", n=(8, 8, 1), cs2=0.5, dx=(1.0, 0.5, 1.0)),    # cs2 >= c_y^2
+    dict(lattice="Q19", n=(4, 4, 4), dx=(1.0, 0.5, 0.5), cs2=0.2),   # negative Q19 weight
+    dict(lattice="Q9", n=(8, 8, 1), nu=-0.1),
+    dict(lattice="Q9", n=(8, 8, 1), equation="NCDE", D0=0.0),
+    dict(lattice="Q9", n=(0, 8, 1)),
+    dict(lattice="Q9", n=(8, 8, 1), dx=(0.0, 1.0, 1.0)),
+])
+def test_invalid_parameters_rejected(bad):
+    with pytest.raises(rmrt.RMRTError) as ei:
+        rmrt.derive(rmrt.make_params(**bad))
+    assert ei.value.code == rmrt.EINVAL
+    assert rmrt.lib().rmrt_last_error()
+
+
+def test_init_argument_errors_need_no_gpu():
+    """Argument validation returns RMRT_EINVAL before any device call."""
+    p = rmrt.make_params(lattice="Q9", n=(8, 8, 1), pattern="AB")
+    ctx = ctypes.c_void_p()
+    rc = rmrt.lib().rmrt_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(16), None, None,
+                              ctypes.c_void_p(16), None, 0, None)
+    assert rc == rmrt.EINVAL  # AB without f1
+    assert rmrt.lib().rmrt_step(None, 1, None) == rmrt.EINVAL

@@ -1,0 +1,332 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: FP64 storage max|f - f_oracle| / max|f_oracle| <= 1e-12 on every fluid
+population; FP32 deviation storage max|rho - rho_oracle| / rho0 and
+max|u - u_oracle| / U_ref <= 1e-5 (phi: relative to its peak); FP16 deviation
+storage is reported and held to a loose bound only."""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+from gpu_util import WALLS, circle_mask, random_fields, rel_err
+from inputs import gaussian_hill_field, grid_coords, taylor_green_2d, taylor_green_3d
+from oracle import rmrt_oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rmrt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_00366_amd import rmrt as R
+    return R
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = {
+    # name: (oracle/GPU parameters, solid-mask builder or None, steps)
+    "q9_periodic": (dict(lattice="Q9", n=(37, 23, 1), dx=(1.0, 0.5, 1.0), nu=0.02, nu_b=0.05), None, 25),
+    "q9_channel_solid_force": (dict(lattice="Q9", n=(40, 21, 1), dx=(1.0, 0.5, 1.0), nu=0.05,
+                                    force=(2e-5, 1e-6, 0.0), source=1e-6, wall_faces=WALLS["y"]),
+                               lambda n: circle_mask(n, (12, 10), 4), 25),
+    "q9_ncde_nonlinear": (dict(lattice="Q9", equation="NCDE", n=(33, 17, 1), dx=(1.0, 0.5, 1.0), D0=0.01,
+                               D2=1.0, adv=(0.05, 0.02, 0.0), rho0=0.0, source=1e-3), None, 25),
+    "q19_periodic": (dict(lattice="Q19", n=(13, 11, 9), dx=(1.0, 0.5, 2.0), nu=0.03, nu_b=0.08), None, 15),
+    "q19_channel_force": (dict(lattice="Q19", n=(12, 10, 8), dx=(1.0, 1.0, 2.0), nu=0.04,
+                               force=(1e-5, 0.0, 2e-6), wall_faces=WALLS["yz"]), None, 15),
+    "q19_ncde": (dict(lattice="Q19", equation="NCDE", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), D0=0.02, D2=0.5,
+                      adv=(0.03, -0.01, 0.02), rho0=0.0), None, 15),
+    "q27_periodic": (dict(lattice="Q27", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), nu=0.05, nu_b=0.01), None, 15),
+    "q27_channel_solid_force": (dict(lattice="Q27", n=(14, 9, 8), dx=(1.0, 2.0, 1.0), nu=0.05,
+                                     force=(1e-5, 0.0, 0.0), source=-1e-6, wall_faces=WALLS["yz"],
+                                     w_corner=0.0008), lambda n: circle_mask(n, (6, 4), 2), 15),
+}
+
+
+def _build(case, R, storage="f64", pattern="AB"):
+    prm, solid_fn, steps = CASES[case]
+    m = O.Model(prm, solid=None if solid_fn is None else solid_fn(prm["n"]))
+    rho, u = random_fields(m, seed=zlib.crc32(case.encode()) % 1000, du=0.02 if m.nse else 0.0)
+    if not m.nse:
+        u = None
+    gp = R.make_params(**prm, storage=storage, pattern=pattern)
+    solid = None if solid_fn is None else m.solid.astype(np.uint8)
+    dom = R.Domain(gp, rho, u, solid=solid)
+    return m, dom, rho, u, steps
+
+
+_oracle_cache = {}
+
+
+def _oracle_run(case, m, rho, u, steps):
+    if case not in _oracle_cache:
+        f = m.init(rho, u)
+        _oracle_cache[case] = (f, m.step(f, steps))
+    return _oracle_cache[case]
+
+
+@pytest.mark.parametrize("pattern", ["AB", "AA"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_f64_populations_match_oracle(rmrt, case, pattern):
+    say(f"[parity f64] {case} {pattern}")
+    m, dom, rho, u, steps = _build(case, rmrt, "f64", pattern)
+    f0, f_or = _oracle_run(case, m, rho, u, steps)
+    fl = m.fluid
+    # the initial state first (init kernel vs oracle init)
+    g0 = dom.populations().cpu().numpy()
+    assert rel_err(g0[:, fl], f0[:, fl]) < 1e-14
+    dom.step(steps)                  # odd step counts end AA on the swapped layout
+    g = dom.populations().cpu().numpy()
+    err = rel_err(g[:, fl], f_or[:, fl])
+    say(f"   max rel |f - f_oracle| = {err:.3e}")
+    assert err < 1e-12
+    rho_g, u_g = dom.moments()
+    rho_o, u_o = m.macroscopic(f_or)
+    assert np.abs(rho_g.cpu().numpy()[fl] - rho_o[fl]).max() < 1e-12 * max(1.0, np.abs(rho_o).max())
+    if m.nse:
+        assert rel_err(u_g.cpu().numpy()[:, fl], u_o[:, fl]) < 1e-11
+    dom.close()
+
+
+@pytest.mark.parametrize("case", ["q9_channel_solid_force", "q19_periodic", "q27_channel_solid_force"])
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+def test_aa_equals_ab_bitwise(rmrt, case, storage):
+    say(f"[AA==AB] {case} {storage}")
+    out = {}
+    for pattern in ("AB", "AA"):
+        m, dom, rho, u, steps = _build(case, rmrt, storage, pattern)
+        res = []
+        for n in (steps, 1):          # an odd total ends AA on the swapped layout
+            dom.step(n)
+            res.append(dom.populations().cpu().numpy())
+        out[pattern] = res
+        dom.close()
+    for a, b in zip(out["AB"], out["AA"]):
+        assert np.array_equal(a[:, m.fluid], b[:, m.fluid])
+
+
+@pytest.mark.parametrize("storage,tol", [("f32dev", 1e-5), ("f16dev", 3e-3)])
+@pytest.mark.parametrize("case", ["q9_periodic", "q9_channel_solid_force", "q9_ncde_nonlinear", "q19_periodic",
+                                  "q19_channel_force", "q27_periodic", "q27_channel_solid_force", "q19_ncde"])
+def test_reduced_precision_storage(rmrt, case, storage, tol):
+    say(f"[parity {storage}] {case}")
+    m, dom, rho, u, steps = _build(case, rmrt, storage, "AA")
+    f0, f_or = _oracle_run(case, m, rho, u, steps)
+    dom.step(steps)
+    rho_g, u_g = dom.moments()
+    rho_o, u_o = m.macroscopic(f_or)
+    fl = m.fluid
+    if m.nse:
+        e_rho = np.abs(rho_g.cpu().numpy()[fl] - rho_o[fl]).max() / m.rho0
+        e_u = np.abs(u_g.cpu().numpy()[:, fl] - u_o[:, fl]).max() / np.abs(u_o[:, fl]).max()
+    else:
+        e_rho = np.abs(rho_g.cpu().numpy()[fl] - rho_o[fl]).max() / np.abs(rho_o).max()
+        e_u = 0.0
+    say(f"   {storage}: rho err {e_rho:.2e}, u err {e_u:.2e}")
+    assert e_rho < tol and e_u < tol
+    dom.close()
+
+
+def test_config1_taylor_green_2d_fp64_full(rmrt):
+    """rD2Q9 NSE Taylor-Green, 64x32, dx = 1, dy = 0.5, U0 = 0.01, nu = 0.02, nu_b = 0.05,
+    rho0 = 1 plus seeded 1e-4 noise, FP64, 2000 steps (graph replay)."""
+    say("[config1] rD2Q9 TG 64x32 2000 steps")
+    nx, ny, dx, dy = 64, 32, 1.0, 0.5
+    prm = dict(lattice="Q9", n=(nx, ny, 1), dx=(dx, dy, 1.0), nu=0.02, nu_b=0.05)
+    m = O.Model(prm)
+    rho, u, (kx, ky) = taylor_green_2d(nx, ny, dx, dy, 0.01, m.cs2, noise=1e-4, seed=1)
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage="f64", pattern="AA"), rho, u)
+    f = m.init(rho, u)
+    X, Y, _ = grid_coords((nx, ny, 1), (dx, dy, 1.0))
+    mode = np.sin(kx * X) * np.cos(ky * Y)
+    ts, amps = [], []
+    for t in range(100, 2001, 100):
+        dom.step(100)
+        f = m.step(f, 100)
+        if t in (100, 1000, 2000):
+            g = dom.populations().cpu().numpy()
+            err = rel_err(g, f)
+            say(f"   t={t}: max rel |f - f_oracle| = {err:.3e}")
+            assert err < 1e-12
+        _, ug = dom.moments()
+        ts.append(t)
+        amps.append((ug[1].cpu().numpy() * mode).sum() / (mode * mode).sum())
+    rate = -np.polyfit(ts, np.log(np.abs(amps)), 1)[0]
+    exact = 0.02 * (kx**2 + ky**2)
+    say(f"   decay rate {rate:.6e} vs nu(kx^2+ky^2) {exact:.6e}")
+    assert abs(rate / exact - 1) < 0.01
+    dom.close()
+
+
+@pytest.fixture(scope="module")
+def c3_small_oracle():
+    n, dx = (32, 32, 32), (1.0, 1.0, 2.0)
+    prm = dict(lattice="Q19", n=n, dx=dx, nu=0.005, cs2=1.0 / 3.0)
+    m = O.Model(prm)
+    rho, u, _ = taylor_green_3d(n, dx, 0.02, m.cs2, with_pressure=False)
+    steps = 200
+    f = m.step(m.init(rho, u), steps)
+    r, uu = m.macroscopic(f)
+    return prm, rho, u, steps, r, uu
+
+
+@pytest.mark.parametrize("storage,tol", [("f32dev", 1e-5), ("f16dev", 3e-3)])
+def test_config3_parity_on_32cubed(rmrt, c3_small_oracle, storage, tol):
+    """rD3Q19 3D Taylor-Green with dz = 2 dx on 32^3, FP32/FP16 deviation storage vs FP64 oracle."""
+    prm, rho, u, steps, r_o, u_o = c3_small_oracle
+    say(f"[config3 32^3] {storage}")
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage=storage, pattern="AA"), rho, u)
+    dom.step(steps)
+    r_g, u_g = dom.moments()
+    e_rho = np.abs(r_g.cpu().numpy() - r_o).max()
+    e_u = np.abs(u_g.cpu().numpy() - u_o).max() / 0.02
+    say(f"   {storage}: rho err {e_rho:.2e}, u err / U0 {e_u:.2e}")
+    assert e_rho < tol and e_u < tol
+    dom.close()
+
+
+def test_config2_ncde_reduced_grid(rmrt):
+    """rD2Q9 NCDE Gaussian hill with D(phi) = 0.01 (1 + phi^2), u = (0.05, 0.02), dy = 0.5,
+    FP32 deviation storage, on a 256 x 128 box (oracle-sized), 300 steps."""
+    say("[config2 reduced] NCDE 256x128 f32dev")
+    nx, ny, dx, dy = 256, 128, 1.0, 0.5
+    prm = dict(lattice="Q9", equation="NCDE", n=(nx, ny, 1), dx=(dx, dy, 1.0), D0=0.01, D2=1.0,
+               adv=(0.05, 0.02, 0.0), rho0=0.0)
+    m = O.Model(prm)
+    phi = gaussian_hill_field(nx, ny, dx, dy, 10.0, 128.0, 32.0)
+    f = m.step(m.init(phi, None), 300)
+    p_o, _ = m.macroscopic(f)
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage="f32dev", pattern="AA"), phi)
+    dom.step(300)
+    p_g, _ = dom.moments(with_u=False)
+    err = np.abs(p_g.cpu().numpy() - p_o).max() / phi.max()
+    say(f"   phi err / peak {err:.2e}")
+    assert err < 1e-5
+    dom.close()
+
+
+def _sampled_one_step(rmrt, prm, rho, u, storage, pattern, samples, seed):
+    """Full-size launch, one step; oracle collision evaluated only at the
+    upstream nodes of `samples` sampled outputs (periodic, no walls)."""
+    g = rmrt.make_params(**prm, storage=storage, pattern=pattern)
+    dom = rmrt.Domain(g, rho, u)
+    dom.step(1)
+    f_g = dom.populations()
+    nx, ny, nz = prm["n"]
+    rng = np.random.default_rng(seed)
+    idx = np.concatenate([rng.integers(0, nx * ny * nz, size=samples), [0, nx * ny * nz - 1]])
+    # oracle: a model of len(idx)*q nodes is only used for its matrices and per-node collision
+    lat = prm["lattice"]
+    E = O.unit_offsets(lat)
+    q = E.shape[0]
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    E3 = np.zeros((q, 3), dtype=np.int64)
+    E3[:, : E.shape[1]] = E
+    ups = []
+    for j in range(q):
+        ups.append(((x - E3[j, 0]) % nx) + nx * (((y - E3[j, 1]) % ny) + ny * ((z - E3[j, 2]) % nz)))
+    ups = np.stack(ups)                                  # (q, S) upstream node of population j
+    flat = ups.reshape(-1)
+    sub = dict(prm)
+    sub["n"] = (flat.size, 1, 1)
+    sub["wall_faces"] = 0
+    mo = O.Model(sub)
+    rr = rho[flat]
+    uu = None if u is None else u[:, flat]
+    fstar = mo.collide(mo.init(rr, uu))                  # (q, q*S)
+    S = idx.size
+    expect = np.stack([fstar[j, j * S:(j + 1) * S] for j in range(q)])
+    got = f_g[:, torch.as_tensor(idx, device=f_g.device)].cpu().numpy()
+    dom.close()
+    return got, expect
+
+
+@pytest.mark.parametrize("storage,tol", [("f32dev", 2e-6), ("f16dev", 2e-3)])
+def test_config3_full_size_sampled(rmrt, storage, tol):
+    """rD3Q19 256 x 256 x 128, dz = 2 dx, U0 = 0.02, nu = 0.005: one step at full size in the
+    benchmark's launch configuration, 4096 sampled nodes against the oracle."""
+    say(f"[config3 full] {storage}")
+    n, dx = (256, 256, 128), (1.0, 1.0, 2.0)
+    prm = dict(lattice="Q19", n=n, dx=dx, nu=0.005, cs2=1.0 / 3.0)
+    rho, u, _ = taylor_green_3d(n, dx, 0.02, 1.0 / 3.0)
+    got, expect = _sampled_one_step(rmrt, prm, rho, u, storage, "AA", 4096, 3)
+    err = np.abs(got - expect).max() / np.abs(expect).max()
+    say(f"   sampled max rel err {err:.2e}")
+    assert err < tol
+
+
+def test_config2_full_size_sampled(rmrt):
+    say("[config2 full] NCDE 2048x1024 f32dev")
+    nx, ny, dx, dy = 2048, 1024, 1.0, 0.5
+    prm = dict(lattice="Q9", equation="NCDE", n=(nx, ny, 1), dx=(dx, dy, 1.0), D0=0.01, D2=1.0,
+               adv=(0.05, 0.02, 0.0), rho0=0.0)
+    phi = gaussian_hill_field(nx, ny, dx, dy, 40.0, 1024.0, 256.0)
+    got, expect = _sampled_one_step(rmrt, prm, phi, None, "f32dev", "AA", 4096, 2)
+    err = np.abs(got - expect).max() / np.abs(expect).max()
+    say(f"   sampled max rel err {err:.2e}")
+    assert err < 2e-6
+
+
+def test_conservation_and_reductions(rmrt):
+    say("[reductions] Q27 periodic with force, FP64")
+    prm = dict(lattice="Q27", n=(17, 13, 11), dx=(1.0, 0.5, 2.0), nu=0.03, force=(1e-5, -2e-5, 3e-6))
+    m = O.Model(prm)
+    rho, u = random_fields(m, 5)
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage="f64", pattern="AA"), rho, u)
+    r0 = dom.reduce()
+    F = np.array(prm["force"])
+    for k in range(1, 4):
+        dom.step(7)
+        r = dom.reduce()
+        assert abs(r[0] - r0[0]) < 1e-13 * r0[0]
+        np.testing.assert_allclose(r[1:], np.array(r0[1:]) + 7 * k * m.N * F, rtol=0, atol=1e-12)
+    # the reduction equals the sum of the macroscopic fields
+    rho_g, u_g = dom.moments()
+    rho_g, u_g = rho_g.cpu().numpy(), u_g.cpu().numpy()
+    r = dom.reduce()
+    assert abs(r[0] - rho_g.sum()) < 1e-10
+    np.testing.assert_allclose(r[1:], (rho_g[None] * u_g).sum(axis=1), atol=1e-12)
+    # steady residual against numpy on the same fields
+    assert dom.residual() == float("inf")
+    prev = u_g.copy()
+    dom.step(3)
+    r_res = dom.residual()
+    _, u2 = dom.moments()
+    u2 = u2.cpu().numpy()
+    expect = np.sqrt(((u2 - prev) ** 2).sum() / (u2**2).sum())
+    assert abs(r_res - expect) < 1e-12 * max(1.0, expect)
+    dom.close()
+
+
+@pytest.mark.parametrize("case", ["q9_channel_solid_force", "q19_channel_force", "q27_periodic"])
+def test_init_with_nonequilibrium_part(rmrt, case):
+    say(f"[init fne] {case}")
+    prm, solid_fn, _ = CASES[case]
+    m = O.Model(prm, solid=None if solid_fn is None else solid_fn(prm["n"]))
+    rho, u = random_fields(m, 9)
+    solid = None if solid_fn is None else m.solid.astype(np.uint8)
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage="f64", pattern="AB"), rho, u, solid=solid, with_fne=True)
+    g = dom.populations().cpu().numpy()
+    f = m.init(rho, u, with_fne=True)
+    assert rel_err(g[:, m.fluid], f[:, m.fluid]) < 1e-13
+    dom.close()
+
+
+def test_nonfinite_detected_by_health_check(rmrt):
+    say("[health] NaN in the initial density")
+    prm = dict(lattice="Q9", n=(16, 8, 1), dx=(1.0, 0.5, 1.0), nu=0.05)
+    rho = np.ones(128)
+    rho[5] = np.nan
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage="f64", check_every=2), rho, np.zeros((2, 128)))
+    with pytest.raises(rmrt.RMRTError) as ei:
+        dom.step(4)
+    assert ei.value.code == rmrt.ENONFINITE
+    dom.close()
