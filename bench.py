@@ -1,0 +1,270 @@
+"""Benchmark of the RMRT-LB collide-and-stream hot path on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--only LIST] [--no-cpu-baseline]
+
+Headline (value): rD3Q19 NSE 3D Taylor-Green, 256 x 256 x 128 nodes with
+dz = 2 dx (a physical 256^3 cube), U0 = 0.02, nu = 0.005, FP32 deviation
+storage with FP32 collision arithmetic, AA pattern: whole-job MLUPS of K timed
+steps (one fused launch per step, replayed from a HIP graph).  The same JSON
+line carries the roofline of that kernel, the FP64 oracle timed on the host
+cores, the HBM copy ceiling, and per-lattice MLUPS / % HBM of the other
+workloads (rD2Q9 NCDE 2048 x 1024, rD3Q19 FP16, rD3Q27, the 64-domain batched
+rD3Q27 channel launch, rD2Q9 Taylor-Green 64 x 32 FP64).  Inputs are seeded
+and synthetic and are resident in HBM before the timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+METRIC = "MLUPS and % HBM peak per lattice; steps/time-to-1e-6 residual plain vs warm-start"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sizeof(storage):
+    return {"f64": 8, "f32dev": 4, "f16dev": 2}[storage]
+
+
+def timed_steps(torch, step_fn, steps, warmup):
+    """Warm up, then time exactly `steps` steps: wall clock between two
+    synchronisations and HIP events on the current stream (where the kernels run)."""
+    step_fn(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    step_fn(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    return wall, ev_ms
+
+
+def c3_fields(n, dx, U0, cs2):
+    from inputs import taylor_green_3d
+    rho, u, _ = taylor_green_3d(n, dx, U0, cs2)
+    return rho, u
+
+
+def run_single(torch, R, prm, rho, u, steps, warmup, solid=None):
+    dom = R.Domain(R.make_params(**prm), rho, u, solid=solid)
+    torch.cuda.synchronize()
+    wall, ev_ms = timed_steps(torch, dom.step, steps, warmup)
+    red = dom.reduce()
+    finite = all(math.isfinite(v) for v in red)
+    dom.close()
+    del dom
+    torch.cuda.empty_cache()
+    return wall, ev_ms, finite
+
+
+def lattice_entry(name, q, storage, N, steps, wall, ev_ms, note=None):
+    mlups = N * steps / wall / 1e6
+    bpu = 2 * q * sizeof(storage)
+    gbs_ev = N * bpu / (ev_ms / steps * 1e-3) / 1e9
+    e = {"workload": name, "MLUPS": round(mlups, 1), "bytes_per_update": bpu,
+         "kernel_GBps": round(gbs_ev, 1), "pct_hbm_peak": round(100 * gbs_ev / HBM_PEAK_GBS, 1),
+         "ms_per_step": round(wall / steps * 1e3, 4)}
+    if note:
+        e["note"] = note
+    return e
+
+
+def copy_ceiling(torch, R, nbytes=2 << 30, reps=20):
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        R.stream_copy(dst, src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        R.stream_copy(dst, src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_per_launch": 2 * nbytes, "GBps": round(2 * nbytes / (ms * 1e-3) / 1e9, 1),
+            "pct_hbm_peak": round(100 * 2 * nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1)}
+
+
+def cpu_baseline():
+    """The FP64 oracle as it stands, on a bounded sample of the headline workload."""
+    import numpy as np
+    from oracle import rmrt_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
+    except Exception:
+        threads = 1
+    n, dx = (32, 32, 32), (1.0, 1.0, 2.0)
+    m = O.Model(dict(lattice="Q19", n=n, dx=dx, nu=0.005, cs2=1.0 / 3.0))
+    rho, u = c3_fields(n, dx, 0.02, m.cs2)
+    f = m.init(rho, u)
+    f = m.step(f, 2)
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 12.0 or steps < 10:
+        f = m.step(f, 5)
+        steps += 5
+    dt = time.perf_counter() - t0
+    assert np.isfinite(f).all()
+    return {"value": round(m.N * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"rD3Q19 NSE Taylor-Green 32x32x32 (dz = 2 dx, nu = 0.005), {steps} steps of the dense "
+                      f"FP64 numpy oracle ({dt:.1f} s); numpy BLAS threads = {threads}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--only", default="all",
+                    help="comma list of: c3,c3f16,c3f64,c2,q27,c4,c1,copy (headline c3 always runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    from paper_2206_00366_amd import rmrt as R
+
+    only = set(args.only.split(",")) if args.only != "all" else {"c3f16", "c3f64", "c2", "q27", "c4", "c1", "copy"}
+    K, W = args.steps, args.warmup
+
+    # ---------------- headline: rD3Q19 FP32-dev 256 x 256 x 128 ----------------
+    n3, dx3 = (256, 256, 128), (1.0, 1.0, 2.0)
+    N3 = n3[0] * n3[1] * n3[2]
+    prm3 = dict(lattice="Q19", equation="NSE", n=n3, dx=dx3, nu=0.005, cs2=1.0 / 3.0, rho0=1.0,
+                storage="f32dev", pattern="AA")
+    log("[bench] headline rD3Q19 256x256x128 f32dev AA")
+    rho3, u3 = c3_fields(n3, dx3, 0.02, 1.0 / 3.0)
+    wall, ev_ms, finite = run_single(torch, R, prm3, rho3, u3, K, W)
+    head = lattice_entry("rD3Q19 NSE TG 256x256x128 dz=2dx FP32-dev AA", 19, "f32dev", N3, K, wall, ev_ms)
+    head["finite"] = finite
+    bytes_per_launch = 2 * 19 * 4 * N3
+    avg_launch_s = ev_ms / K * 1e-3
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_step<Q19, F32, NSE, no force, periodic, AA even/odd>",
+                "algorithmic_bytes_per_launch": bytes_per_launch,
+                "avg_launch_us": round(avg_launch_s * 1e6, 2)}
+
+    per = {"rD3Q19_f32dev": head}
+    ceiling = None
+    if "copy" in only:
+        log("[bench] HBM copy ceiling")
+        ceiling = copy_ceiling(torch, R)
+    if "c3f16" in only:
+        log("[bench] rD3Q19 f16dev")
+        prm = dict(prm3, storage="f16dev")
+        w2, e2, fin = run_single(torch, R, prm, rho3, u3, K, W)
+        per["rD3Q19_f16dev"] = lattice_entry("rD3Q19 NSE TG 256x256x128 FP16-dev AA", 19, "f16dev", N3, K, w2, e2)
+        per["rD3Q19_f16dev"]["finite"] = fin
+        per["rD3Q19_f16dev"]["speedup_vs_f32dev"] = round(per["rD3Q19_f16dev"]["MLUPS"] / head["MLUPS"], 3)
+    if "c3f64" in only:
+        log("[bench] rD3Q19 f64")
+        prm = dict(prm3, storage="f64")
+        w2, e2, fin = run_single(torch, R, prm, rho3, u3, max(K // 2, 10), W)
+        per["rD3Q19_f64"] = lattice_entry("rD3Q19 NSE TG 256x256x128 FP64 AA", 19, "f64", N3, max(K // 2, 10), w2, e2)
+    del rho3, u3
+    if "q27" in only:
+        log("[bench] rD3Q27 f32dev 256x256x128")
+        prm = dict(prm3, lattice="Q27")
+        rho, u = c3_fields(n3, dx3, 0.02, 1.0 / 3.0)
+        w2, e2, fin = run_single(torch, R, prm, rho, u, K, W)
+        per["rD3Q27_f32dev"] = lattice_entry("rD3Q27 NSE TG 256x256x128 dz=2dx FP32-dev AA", 27, "f32dev", N3, K, w2, e2)
+        per["rD3Q27_f32dev"]["finite"] = fin
+        del rho, u
+    if "c2" in only:
+        log("[bench] rD2Q9 NCDE 2048x1024 f32dev")
+        from inputs import gaussian_hill_field
+        n2 = (2048, 1024, 1)
+        prm = dict(lattice="Q9", equation="NCDE", n=n2, dx=(1.0, 0.5, 1.0), D0=0.01, D2=1.0, adv=(0.05, 0.02, 0.0),
+                   rho0=0.0, storage="f32dev", pattern="AA")
+        phi = gaussian_hill_field(2048, 1024, 1.0, 0.5, 40.0, 1024.0, 256.0)
+        w2, e2, fin = run_single(torch, R, prm, phi, None, 4 * K, W)
+        per["rD2Q9_ncde_f32dev"] = lattice_entry(
+            "rD2Q9 NCDE Gaussian hill 2048x1024 dy=0.5 FP32-dev AA", 9, "f32dev", 2048 * 1024, 4 * K, w2, e2,
+            note="75.5 MB working set fits the 256 MB MALL: % HBM may be cache-inflated")
+        per["rD2Q9_ncde_f32dev"]["finite"] = fin
+    if "c1" in only:
+        log("[bench] rD2Q9 TG 64x32 f64")
+        from inputs import taylor_green_2d
+        prm = dict(lattice="Q9", n=(64, 32, 1), dx=(1.0, 0.5, 1.0), nu=0.02, nu_b=0.05, storage="f64", pattern="AA")
+        rho, u, _ = taylor_green_2d(64, 32, 1.0, 0.5, 0.01, 0.25 / 3.0, noise=1e-4, seed=1)
+        w2, e2, fin = run_single(torch, R, prm, rho, u, 2000, W)
+        per["rD2Q9_tg_f64"] = lattice_entry("rD2Q9 NSE TG 64x32 dy=0.5 FP64 (launch-bound, MLUPS only)", 9, "f64",
+                                            2048, 2000, w2, e2)
+        per["rD2Q9_tg_f64"].pop("pct_hbm_peak")
+    if "c4" in only:
+        log("[bench] rD3Q27 batch of 64 channels f32dev")
+        per["rD3Q27_batch64_f32dev"] = bench_batch(torch, R, max(K // 10, 20), W)
+
+    out = {"metric": METRIC, "value": head["MLUPS"], "unit": "MLUPS", "n_gpus": 1, "steps": K, "warmup": W,
+           "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "rD3Q19 NSE 3D Taylor-Green, periodic 256x256x128 nodes, dz = 2 dx, U0 = 0.02, "
+                                  "nu = 0.005, FP32 deviation storage, FP32 collision, AA pattern",
+                      "lattice": "rD3Q19", "nodes": N3, "storage": "f32dev", "pattern": "AA"},
+           "roofline": roofline}
+    if ceiling:
+        out["hbm_copy_ceiling"] = ceiling
+        roofline["frac_of_copy_ceiling"] = round(achieved / ceiling["GBps"], 4)
+    out["per_lattice"] = per
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+def bench_batch(torch, R, steps, warmup):
+    from inputs import channel_batch
+    doms = channel_batch(seed=4, nd=64)
+    params = []
+    total = 0
+    for d in doms:
+        params.append(R.make_params(lattice="Q27", n=d["n"], dx=d["dx"], nu=d["nu"], nu_b=d["nu_b"],
+                                    force=d["force"], wall_faces=R.WALL_YM | R.WALL_YP | R.WALL_ZM | R.WALL_ZP,
+                                    storage="f32dev", pattern="AA", rho0=1.0))
+        total += d["n"][0] * d["n"][1] * d["n"][2]
+    b = R.Batch(params)
+    torch.cuda.synchronize()
+    cfg = b.autotune(steps=4)
+    wall, ev_ms = timed_steps(torch, b.step, steps, warmup)
+    red = b.domains[0].reduce()
+    fin = all(math.isfinite(v) for v in red)
+    e = lattice_entry(f"rD3Q27 batch of 64 force-driven channels (seed 4), {total} nodes, FP32-dev AA, "
+                      f"one persistent launch per step", 27, "f32dev", total, steps, wall, ev_ms)
+    e["autotuned_config"] = dict(zip(("threads", "tile_nodes", "blocks_per_cu"), R.Batch.configs()[cfg]))
+    e["finite"] = fin
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return e
+
+
+if __name__ == "__main__":
+    main()

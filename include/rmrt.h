@@ -126,6 +126,13 @@ const char* rmrt_last_error(void);
 const char* rmrt_version(void);
 
 /*
+ * HBM bandwidth probe (not part of the method): copies `bytes` (a multiple of
+ * 16) from src to dst on stream with 16-byte vector loads and stores.  Used to
+ * measure the achievable copy ceiling next to the lattice kernels.
+ */
+int rmrt_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/*
  * Validate a parameter set and fill *out with the derived lattice weights and
  * relaxation rates (Sec. III eq. 3-3-5 / 3-3-8; Sec. IV eq. 4-31; Sec. V
  * eq. 5-8-1).  Host only.  Returns RMRT_EINVAL for: an unknown enumeration,

@@ -615,5 +615,6 @@ hipError_t launch_reduce(const AuxLaunch& a);
 template <int L, int ST>
 hipError_t launch_residual(const AuxLaunch& a);
 hipError_t launch_reduce_final(const double* partials, uint32_t nb, double* out, int K, hipStream_t s);
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 }  // namespace rmrt

@@ -524,6 +524,14 @@ const char* rmrt_last_error(void) { return g_last_error.c_str(); }
 
 const char* rmrt_version(void) { return "rmrt 0.1 (gfx950)"; }
 
+int rmrt_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!dst || !src) return fail(RMRT_EINVAL, "NULL pointer");
+  if (bytes % 16) return fail(RMRT_EINVAL, "bytes must be a multiple of 16");
+  hipError_t e = launch_stream_copy(dst, src, bytes, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "copy launch: %s", hipGetErrorString(e));
+  return RMRT_OK;
+}
+
 int rmrt_derive(const rmrt_params* p, rmrt_derived* out) {
   Derived v;
   int rc = derive(p, v);
@@ -726,9 +734,11 @@ namespace {
 struct TileConfig {
   int threads, tile_nodes, blocks_per_cu;  // blocks_per_cu <= 0: one workgroup per tile
 };
+// threads per block never exceed the kernels' launch bound of 256
+constexpr int kMaxThreads = 256;
 const TileConfig kConfigs[] = {
     {256, 256, 0},  {256, 1024, 8}, {256, 2048, 8}, {256, 4096, 8},
-    {512, 2048, 4}, {512, 8192, 4}, {128, 512, 16}, {256, 1024, 4},
+    {256, 512, 8},  {256, 8192, 4}, {128, 512, 16}, {256, 1024, 4},
 };
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
@@ -792,6 +802,7 @@ int batch_launch(rmrt_batch* b, long long step_index, hipStream_t s) {
   a.force = b->force;
   a.bc = b->bc;
   a.phase = b->pattern == RMRT_AB ? PH_AB : ((step_index & 1) ? PH_AA_ODD : PH_AA_EVEN);
+  if (tc.threads > kMaxThreads) return fail(RMRT_EINVAL, "config uses %d threads > %d", tc.threads, kMaxThreads);
   const uint32_t persistent = tc.blocks_per_cu > 0 ? (uint32_t)(b->cus * tc.blocks_per_cu) : b->ntiles;
   a.grid = std::min(b->ntiles, persistent);
   a.block = (unsigned)tc.threads;

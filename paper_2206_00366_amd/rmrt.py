@@ -57,6 +57,7 @@ _vp = C.c_void_p
 _sig = {
     "rmrt_last_error": (C.c_char_p, []),
     "rmrt_version": (C.c_char_p, []),
+    "rmrt_stream_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
     "rmrt_derive": (C.c_int, [C.POINTER(Params), C.POINTER(Derived)]),
     "rmrt_population_bytes": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_size_t)]),
     "rmrt_init": (C.c_int, [C.POINTER(_vp), C.POINTER(Params), _vp, _vp, _vp, _vp, _vp, C.c_int, _vp]),
@@ -104,6 +105,12 @@ def lib():
 
 def version() -> str:
     return _lib.rmrt_version().decode()
+
+
+def stream_copy(dst, src):
+    """HBM probe: copy src into dst (torch tensors of equal byte size) on the current stream."""
+    nbytes = src.numel() * src.element_size()
+    _check(_lib.rmrt_stream_copy(_ptr(dst), _ptr(src), nbytes, _stream()), "rmrt_stream_copy")
 
 
 def make_params(lattice="Q9", equation="NSE", storage="f64", pattern="AB", n=(8, 8, 1),

@@ -88,3 +88,11 @@ def test_init_argument_errors_need_no_gpu():
                               ctypes.c_void_p(16), None, 0, None)
     assert rc == rmrt.EINVAL  # AB without f1
     assert rmrt.lib().rmrt_step(None, 1, None) == rmrt.EINVAL
+
+
+def test_batch_configs_within_launch_bound():
+    cfgs = rmrt.Batch.configs()
+    assert len(cfgs) >= 4
+    for threads, tile_nodes, per_cu in cfgs:
+        assert 64 <= threads <= 256 and threads % 64 == 0
+        assert tile_nodes >= threads

@@ -1,0 +1,152 @@
+"""GPU parity of the batched persistent path (many uneven domains in one
+launch per step, graph-replayed, tile shapes from the autotuner)."""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_util import WALLS, rel_err
+from inputs import channel_batch, grid_coords
+from oracle import rmrt_oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rmrt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_00366_amd import rmrt as R
+    return R
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+SMALL = [
+    dict(lattice="Q27", n=(17, 9, 11), dx=(1.0, 0.5, 2.0), nu=0.03, nu_b=0.02, force=(2e-5, 0.0, 0.0), wall_faces=WALLS["yz"]),
+    dict(lattice="Q27", n=(9, 13, 7), dx=(1.0, 2.0, 1.0), nu=0.08, force=(1e-5, 0.0, 0.0), wall_faces=WALLS["yz"]),
+    dict(lattice="Q27", n=(23, 7, 5), dx=(1.0, 1.0, 0.5), nu=0.05, force=(3e-5, 0.0, 0.0), wall_faces=WALLS["yz"]),
+    dict(lattice="Q27", n=(5, 6, 31), dx=(1.0, 0.5, 0.5), nu=0.02, force=(1e-5, 0.0, 0.0), wall_faces=WALLS["z"]),
+]
+
+
+def _fields(m, seed):
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + 1e-3 * rng.uniform(-1, 1, m.N)
+    u = 0.01 * rng.uniform(-1, 1, (m.d, m.N))
+    return rho, u
+
+
+@pytest.fixture(scope="module")
+def small_oracle():
+    out = []
+    for k, prm in enumerate(SMALL):
+        m = O.Model(prm)
+        rho, u = _fields(m, 100 + k)
+        out.append((m, rho, u, m.step(m.init(rho, u), 21)))
+    return out
+
+
+@pytest.mark.parametrize("pattern", ["AB", "AA"])
+def test_batch_every_tile_config_matches_oracle(rmrt, small_oracle, pattern):
+    ncfg = len(rmrt.Batch.configs())
+    for cfg in range(ncfg):
+        say(f"[batch f64] {pattern} config {cfg} {rmrt.Batch.configs()[cfg]}")
+        b = rmrt.Batch([rmrt.make_params(**p, storage="f64", pattern=pattern) for p in SMALL])
+        b.set_config(cfg)
+        for d, (m, rho, u, _) in zip(b.domains, small_oracle):
+            d.set_fields(rho, u)
+        b.step(20)
+        b.step(1)                               # odd total: AA ends on the swapped layout
+        for d, (m, rho, u, f_or) in zip(b.domains, small_oracle):
+            g = d.populations().cpu().numpy()
+            err = rel_err(g, f_or)
+            assert err < 1e-12, (cfg, err)
+        b.close()
+
+
+def test_batch_autotune_then_fp32_parity(rmrt, small_oracle):
+    say("[batch f32] autotune + parity")
+    b = rmrt.Batch([rmrt.make_params(**p, storage="f32dev", pattern="AA") for p in SMALL])
+    cfg = b.autotune(steps=3)
+    assert 0 <= cfg < len(rmrt.Batch.configs())
+    for d, (m, rho, u, _) in zip(b.domains, small_oracle):
+        d.set_fields(rho, u)          # the autotuner advanced the state; restart it
+    b.step(21)
+    for d, (m, rho, u, f_or) in zip(b.domains, small_oracle):
+        r_g, u_g = d.moments()
+        r_o, u_o = m.macroscopic(f_or)
+        assert np.abs(r_g.cpu().numpy() - r_o).max() < 1e-5
+        assert np.abs(u_g.cpu().numpy() - u_o).max() / np.abs(u_o).max() < 1e-5
+    b.close()
+
+
+def test_batch_plane_poiseuille(rmrt):
+    """Plane channels inside one batch (walls on z or y faces, anisotropic spacing)
+    reach the parabolic profile u = g y (H - y) / (2 nu) to O(dy^2)."""
+    say("[batch] plane Poiseuille")
+    specs = [
+        dict(lattice="Q27", n=(4, 4, 24), dx=(1.0, 1.0, 0.5), nu=0.03, force=(1e-5, 0, 0), wall_faces=WALLS["z"]),
+        dict(lattice="Q27", n=(4, 24, 4), dx=(1.0, 2.0, 1.0), nu=0.1, force=(3e-6, 0, 0), wall_faces=WALLS["y"]),
+    ]
+    b = rmrt.Batch([rmrt.make_params(**p, storage="f64", pattern="AA") for p in specs])
+    b.step(30000)
+    for d, p in zip(b.domains, specs):
+        _, u = d.moments()
+        u = u.cpu().numpy()
+        axis = 2 if p["wall_faces"] == WALLS["z"] else 1
+        X, Y, Z = grid_coords(p["n"], p["dx"], centered=True)
+        yc = (X, Y, Z)[axis]
+        H = p["n"][axis] * p["dx"][axis]
+        exact = O.poiseuille(yc, H, p["force"][0], p["nu"])
+        err = np.abs(u[0] - exact).max() / exact.max()
+        say(f"   {p['n']} dx={p['dx']}: profile error {err:.2e}")
+        assert err < 1e-2
+    b.close()
+
+
+def test_c4_full_batch_sampled_one_step(rmrt):
+    """The 64-domain rD3Q27 channel batch (seed 4, about 2e8 nodes, FP32-dev, AA):
+    one persistent launch, then 256 sampled nodes of each of the 4 smallest
+    domains against the oracle collision at their upstream nodes (with bounce-back)."""
+    say("[batch] C4 full size, sampled")
+    doms = channel_batch(seed=4, nd=64)
+    walls = WALLS["yz"]
+    params = [rmrt.make_params(lattice="Q27", n=d["n"], dx=d["dx"], nu=d["nu"], nu_b=d["nu_b"], force=d["force"],
+                               wall_faces=walls, storage="f32dev", pattern="AA") for d in doms]
+    b = rmrt.Batch(params)
+    b.autotune(steps=2)
+    order = np.argsort([d["n"][0] * d["n"][1] * d["n"][2] for d in doms])[:4]
+    for k in order:                       # restart the 4 checked domains from a known state
+        d = doms[k]
+        N = d["n"][0] * d["n"][1] * d["n"][2]
+        b.domains[k].set_fields(np.ones(N), np.zeros((3, N)))
+    b.step(1)
+    E = O.unit_offsets("Q27")
+    rng = np.random.default_rng(4)
+    for k in order:
+        d = doms[k]
+        nx, ny, nz = d["n"]
+        N = nx * ny * nz
+        f_g = b.domains[k].populations()
+        idx = np.concatenate([rng.integers(0, N, 256), [0, N - 1]])
+        x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+        prm = dict(lattice="Q27", n=(1, 1, 1), dx=d["dx"], nu=d["nu"], nu_b=d["nu_b"], force=d["force"])
+        mo = O.Model(prm)
+        fstar = mo.collide(mo.init(np.ones(1), np.zeros((3, 1))))[:, 0]   # every node starts at rest
+        opp = mo.opp
+        expect = np.empty((27, idx.size))
+        for j in range(27):
+            sx, sy, sz = x - E[j, 0], y - E[j, 1], z - E[j, 2]
+            wall = (sy < 0) | (sy >= ny) | (sz < 0) | (sz >= nz)
+            # pulled from the upstream node, or bounced back at this node (opp(j) leaving toward the wall)
+            expect[j] = np.where(wall, fstar[opp[j]], fstar[j])
+        got = f_g[:, torch.as_tensor(idx, device=f_g.device)].cpu().numpy()
+        err = np.abs(got - expect).max() / np.abs(expect).max()
+        say(f"   domain {k} n={d['n']}: sampled max rel err {err:.2e}")
+        assert err < 2e-6
+    b.close()
