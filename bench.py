@@ -25,6 +25,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+
+# HBM bytes per launch of the headline step kernel from the rocprofv3 FETCH_SIZE
+# and WRITE_SIZE passes (profiles/k_step_q19_f32dev_256x256x128_pmc.md), scaled
+# by the counters of a plain copy of known size.  Keyed by the hash of the
+# kernel sources the counters were taken on: any later kernel change reports null.
+MEASURED_TRAFFIC = {"c963d5fc85672ac3": 1275171502}
+KERNEL_SOURCES = ["lbm_device.hpp", "lbm_kernels.hpp", "lbm_params.hpp", "lbm_launch.hpp", "lbm_q19_f32.hip"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2206_00366_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 METRIC = "MLUPS and % HBM peak per lattice; steps/time-to-1e-6 residual plain vs warm-start"
 
 
@@ -59,12 +75,14 @@ def c3_fields(n, dx, U0, cs2):
     return rho, u
 
 
-def run_single(torch, R, prm, rho, u, steps, warmup, solid=None):
+def run_single(torch, R, prm, rho, u, steps, warmup, solid=None, launch=None):
     dom = R.Domain(R.make_params(**prm), rho, u, solid=solid)
     torch.cuda.synchronize()
     wall, ev_ms = timed_steps(torch, dom.step, steps, warmup)
     red = dom.reduce()
     finite = all(math.isfinite(v) for v in red)
+    if launch is not None:
+        launch.update(dict(zip(("blocks_per_cu_cap", "flags"), dom.get_launch())))
     dom.close()
     del dom
     torch.cuda.empty_cache()
@@ -160,17 +178,21 @@ def main():
                 storage="f32dev", pattern="AA")
     log("[bench] headline rD3Q19 256x256x128 f32dev AA")
     rho3, u3 = c3_fields(n3, dx3, 0.02, 1.0 / 3.0)
-    wall, ev_ms, finite = run_single(torch, R, prm3, rho3, u3, K, W)
+    launch = {}
+    wall, ev_ms, finite = run_single(torch, R, prm3, rho3, u3, K, W, launch=launch)
     head = lattice_entry("rD3Q19 NSE TG 256x256x128 dz=2dx FP32-dev AA", 19, "f32dev", N3, K, wall, ev_ms)
     head["finite"] = finite
     bytes_per_launch = 2 * 19 * 4 * N3
     avg_launch_s = ev_ms / K * 1e-3
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    src_hash = kernel_source_hash()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": MEASURED_TRAFFIC.get(src_hash),
+                "kernel_source_hash": src_hash,
                 "kernel": "k_step<Q19, F32, NSE, no force, periodic, AA even/odd>",
                 "algorithmic_bytes_per_launch": bytes_per_launch,
-                "avg_launch_us": round(avg_launch_s * 1e6, 2)}
+                "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                "launch": dict(launch, workgroup=256, tile_nodes=256)}
 
     per = {"rD3Q19_f32dev": head}
     ceiling = None
@@ -258,7 +280,7 @@ def bench_batch(torch, R, steps, warmup):
     fin = all(math.isfinite(v) for v in red)
     e = lattice_entry(f"rD3Q27 batch of 64 force-driven channels (seed 4), {total} nodes, FP32-dev AA, "
                       f"one persistent launch per step", 27, "f32dev", total, steps, wall, ev_ms)
-    e["autotuned_config"] = dict(zip(("threads", "tile_nodes", "blocks_per_cu"), R.Batch.configs()[cfg]))
+    e["autotuned_config"] = dict(zip(("threads", "tile_nodes", "blocks_per_cu", "persistent"), R.Batch.configs()[cfg]))
     e["finite"] = fin
     b.close()
     del b

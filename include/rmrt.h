@@ -196,6 +196,29 @@ int rmrt_residual(rmrt_ctx* ctx, double* r, void* stream);
 /* Number of steps taken since init (the AA pattern's parity is its low bit). */
 int rmrt_steps_taken(const rmrt_ctx* ctx, long long* steps);
 
+/*
+ * Launch shape of rmrt_step.  flags = 0: one workgroup per 256-node tile
+ * (hardware scheduling); blocks_per_cu > 0 then caps the resident workgroups
+ * per compute unit through dynamic LDS (0 = no cap).  flags & RMRT_LAUNCH_
+ * PERSISTENT: a persistent grid of blocks_per_cu workgroups per CU walks the
+ * tiles, contiguously per XCD when flags & RMRT_LAUNCH_XCD_ORDER.
+ * Default (measured on MI355X): one workgroup per tile; a cap of 3 for rD3Q19
+ * and rD3Q27 with FP32/FP64 storage; XCD order for rD2Q9.  Invalidates the
+ * context's cached graphs.
+ */
+#define RMRT_LAUNCH_XCD_ORDER 1
+#define RMRT_LAUNCH_PERSISTENT 2
+int rmrt_set_launch(rmrt_ctx* ctx, int blocks_per_cu, int flags);
+int rmrt_get_launch(const rmrt_ctx* ctx, int* blocks_per_cu, int* flags);
+
+/*
+ * Time rmrt_step over `steps` steps for one workgroup per tile with the
+ * residency cap blocks_per_cu in {0 (none), 2, 3, 4, 5, 6, 8} (HIP events on
+ * stream), keep the fastest and return it in *blocks_per_cu (may be NULL).
+ * The timing runs advance the state.
+ */
+int rmrt_tune(rmrt_ctx* ctx, int steps, void* stream, int* blocks_per_cu);
+
 /* Release the context (does not free the caller's buffers). */
 int rmrt_free(rmrt_ctx* ctx);
 
@@ -228,8 +251,13 @@ int rmrt_batch_autotune(rmrt_batch* b, int steps, void* stream, int* chosen);
 /* Select tile configuration `cfg` (0 .. rmrt_batch_num_configs()-1) explicitly. */
 int rmrt_batch_set_config(rmrt_batch* b, int cfg);
 int rmrt_batch_num_configs(void);
-/* Describe configuration cfg: threads per block, nodes per tile, blocks per CU. */
-int rmrt_batch_config_info(int cfg, int* threads, int* tile_nodes, int* blocks_per_cu);
+/*
+ * Describe configuration cfg: threads per workgroup, nodes per tile, workgroups
+ * per CU and whether the grid is persistent (1: cus * blocks_per_cu workgroups
+ * walk the tile list in XCD-contiguous order; 0: one workgroup per tile with
+ * residency capped at blocks_per_cu per CU, 0 = no cap).
+ */
+int rmrt_batch_config_info(int cfg, int* threads, int* tile_nodes, int* blocks_per_cu, int* persistent);
 
 /* Advance every domain nsteps steps (graph replay of persistent launches). */
 int rmrt_batch_step(rmrt_batch* b, int nsteps, void* stream);

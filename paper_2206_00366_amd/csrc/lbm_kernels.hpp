@@ -183,14 +183,38 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
   return xcd * per + (xcd < rem ? xcd : rem) + local;
 }
 
+// Tile order.  With one workgroup per tile (gridDim == ntiles) tiles follow
+// xcd_remap.  With a persistent grid (gridDim < ntiles, a multiple of 8 when
+// XCD_ORDER is set) each XCD walks its own contiguous eighth of the tile list,
+// so that the tiles resident at one time on an XCD are neighbours; the grid
+// size is the occupancy knob (fewer resident waves keep the q concurrent
+// address streams per wave from oversubscribing HBM).
+enum : uint32_t { STEP_XCD_ORDER = 1u, STEP_PERSISTENT = 2u };
+
 template <int L, int ST, int EQ, bool FORCE, int BC, int PH>
 __global__ void __launch_bounds__(256)
     k_step(const DomainDev* __restrict__ doms, const Tile* __restrict__ tiles, uint32_t ntiles,
-           uint32_t tile_nodes, uint32_t parity) {
+           uint32_t tile_nodes, uint32_t parity, uint32_t flags) {
   using SS = Store<ST>;
   using S = typename SS::S;
   using T = typename SS::T;
-  for (uint32_t tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+  const uint32_t G = gridDim.x;
+  const bool xcd = (flags & STEP_XCD_ORDER) != 0;
+  const uint32_t per = (ntiles + 7u) >> 3;
+  for (uint32_t it = 0;; ++it) {
+    uint32_t tt;
+    if (G >= ntiles) {
+      if (it > 0 || blockIdx.x >= ntiles) break;
+      tt = xcd ? xcd_remap(blockIdx.x, ntiles) : blockIdx.x;
+    } else if (xcd) {
+      const uint32_t local = (blockIdx.x >> 3) + it * (G >> 3);
+      if (local >= per) break;
+      tt = (blockIdx.x & 7u) * per + local;
+      if (tt >= ntiles) break;
+    } else {
+      tt = blockIdx.x + it * G;
+      if (tt >= ntiles) break;
+    }
     uint32_t dom, start, count;
     if (tiles != nullptr) {
       const Tile tl = tiles[tt];
@@ -198,9 +222,8 @@ __global__ void __launch_bounds__(256)
       start = tl.start;
       count = tl.count;
     } else {
-      const uint32_t t = (gridDim.x == ntiles) ? xcd_remap(tt, ntiles) : tt;
       dom = 0;
-      start = t * tile_nodes;
+      start = tt * tile_nodes;
       const uint32_t N = doms[0].N;
       count = (N - start < tile_nodes) ? N - start : tile_nodes;
     }
@@ -583,7 +606,8 @@ __global__ void __launch_bounds__(256)
 struct StepLaunch {
   const DomainDev* doms;
   const Tile* tiles;
-  uint32_t ntiles, tile_nodes, parity;
+  uint32_t ntiles, tile_nodes, parity, flags;
+  uint32_t lds_bytes;  // dynamic LDS per workgroup: caps resident workgroups per CU
   int eq, force, bc, phase;
   unsigned grid, block;
   hipStream_t stream;

@@ -343,6 +343,25 @@ hipError_t dispatch_reduce(int lat, int st, const AuxLaunch& a) { RMRT_DISPATCH(
 hipError_t dispatch_residual(int lat, int st, const AuxLaunch& a) { RMRT_DISPATCH(launch_residual, lat, st, a); }
 
 constexpr unsigned kAuxBlock = 256;
+// Launch shape of the single-domain step.  Measured on MI355X: one workgroup
+// per 256-node tile with hardware scheduling beats persistent grids (whose
+// tile loop serialises loads behind the previous tile's stores).  For the 3D
+// lattices with 4- and 8-byte storage a cap of 3 resident workgroups per CU
+// (12 waves) raises the step from 5.2 to 5.5-5.65 TB/s: fewer waves issuing q
+// concurrent address streams keep HBM rows open longer.  FP16 storage and
+// rD2Q9 prefer no cap, rD2Q9 the XCD-contiguous tile order.
+constexpr int kDefaultBlocksPerCU = 0;
+constexpr uint32_t kDefaultFlags = 0u;
+void default_launch(const rmrt_params& p, int& blocks_per_cu, uint32_t& flags) {
+  blocks_per_cu = 0;
+  flags = 0u;
+  if (p.lattice == RMRT_Q9) {
+    flags = STEP_XCD_ORDER;
+  } else if (p.storage != RMRT_F16DEV) {
+    blocks_per_cu = 3;
+  }
+}
+constexpr uint32_t kLdsPerCU = 160u * 1024u;  // gfx950 LDS per compute unit
 constexpr unsigned kMaxAuxGrid = 2048;
 
 }  // namespace
@@ -366,6 +385,9 @@ struct rmrt_ctx {
   bool have_prev = false;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   hipStream_t cap = nullptr;   // capture stream
+  int cus = 256;               // compute units of the device
+  int blocks_per_cu = kDefaultBlocksPerCU;  // resident workgroups per CU (0: hardware limit)
+  uint32_t flags = kDefaultFlags;
 };
 
 namespace {
@@ -373,6 +395,30 @@ namespace {
 unsigned aux_grid(uint32_t N) {
   unsigned g = (N + kAuxBlock - 1) / kAuxBlock;
   return std::max(1u, std::min(g, kMaxAuxGrid));
+}
+
+// grid of a step launch: one block per tile, or (STEP_PERSISTENT) a persistent
+// grid of cus * blocks_per_cu workgroups (a multiple of 8 when XCD-ordered)
+// dynamic LDS that caps a non-persistent launch at blocks_per_cu resident workgroups per CU
+uint32_t residency_lds(int blocks_per_cu, uint32_t flags) {
+  if (blocks_per_cu <= 0 || (flags & STEP_PERSISTENT)) return 0;
+  return (kLdsPerCU / (uint32_t)blocks_per_cu) & ~255u;
+}
+
+unsigned persistent_grid(uint32_t ntiles, int cus, int blocks_per_cu, uint32_t flags) {
+  if (blocks_per_cu <= 0 || !(flags & STEP_PERSISTENT)) return ntiles;
+  uint32_t g = (uint32_t)cus * (uint32_t)blocks_per_cu;
+  if (flags & STEP_XCD_ORDER) g &= ~7u;
+  if (g < 8) g = 8;
+  return g >= ntiles ? ntiles : g;
+}
+
+int device_cus() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    return prop.multiProcessorCount;
+  return 256;
 }
 
 AuxLaunch aux_of(const rmrt_ctx* c, hipStream_t s) {
@@ -428,12 +474,14 @@ int launch_one_step(rmrt_ctx* c, long long step_index, hipStream_t s) {
   a.tiles = nullptr;
   a.tile_nodes = 256;
   a.ntiles = (c->hdom.N + a.tile_nodes - 1) / a.tile_nodes;
+  a.flags = c->flags;
   a.parity = (uint32_t)(step_index & 1);
   a.eq = c->p.equation;
   a.force = has_force(&c->p);
   a.bc = (c->hdom.walls != 0 || c->hdom.has_solid) ? 1 : 0;
   a.phase = c->p.pattern == RMRT_AB ? PH_AB : ((step_index & 1) ? PH_AA_ODD : PH_AA_EVEN);
-  a.grid = a.ntiles;
+  a.grid = persistent_grid(a.ntiles, c->cus, c->blocks_per_cu, c->flags);
+  a.lds_bytes = residency_lds(c->blocks_per_cu, c->flags);
   a.block = 256;
   a.stream = s;
   hipError_t e = dispatch_step(c->p.lattice, c->p.storage, a);
@@ -597,6 +645,8 @@ static int ctx_create(rmrt_ctx** out, const rmrt_params* p, void* f0, void* f1, 
     delete c;
     return rc;
   }
+  c->cus = device_cus();
+  default_launch(*p, c->blocks_per_cu, c->flags);
   *out = c;
   return RMRT_OK;
 }
@@ -716,6 +766,64 @@ int rmrt_steps_taken(const rmrt_ctx* c, long long* steps) {
   return RMRT_OK;
 }
 
+int rmrt_set_launch(rmrt_ctx* c, int blocks_per_cu, int flags) {
+  if (!c) return fail(RMRT_EINVAL, "ctx is NULL");
+  if (blocks_per_cu < 0 || blocks_per_cu > 32) return fail(RMRT_EINVAL, "blocks_per_cu must be in [0, 32]");
+  if (flags & ~3) return fail(RMRT_EINVAL, "unknown launch flags 0x%x", flags);
+  if (blocks_per_cu == 1 && !(flags & STEP_PERSISTENT))
+    return fail(RMRT_EINVAL, "a residency cap of 1 workgroup per CU is not supported (use >= 2)");
+  c->blocks_per_cu = blocks_per_cu;
+  c->flags = (uint32_t)flags;
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  return RMRT_OK;
+}
+
+int rmrt_get_launch(const rmrt_ctx* c, int* blocks_per_cu, int* flags) {
+  if (!c) return fail(RMRT_EINVAL, "ctx is NULL");
+  if (blocks_per_cu) *blocks_per_cu = c->blocks_per_cu;
+  if (flags) *flags = (int)c->flags;
+  return RMRT_OK;
+}
+
+int rmrt_tune(rmrt_ctx* c, int steps, void* stream, int* blocks_per_cu) {
+  if (!c) return fail(RMRT_EINVAL, "ctx is NULL");
+  if (c->batch) return fail(RMRT_EINVAL, "domain belongs to a batch: use rmrt_batch_autotune");
+  if (steps < 1) return fail(RMRT_EINVAL, "steps must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  const int cands[] = {0, 2, 3, 4, 5, 6, 8};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int best = kDefaultBlocksPerCU;
+  float best_ms = 1e30f;
+  for (int k : cands) {
+    int rc = rmrt_set_launch(c, k, 0);
+    if (rc == RMRT_OK) rc = step_impl(c, 2, s);
+    if (rc == RMRT_OK) rc = step_impl(c, steps, s);
+    if (rc != RMRT_OK) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return rc;
+    }
+    HIP_TRY(hipEventRecord(e0, s));
+    rc = step_impl(c, steps, s);
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    if (rc != RMRT_OK) return rc;
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = k;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (blocks_per_cu) *blocks_per_cu = best;
+  return rmrt_set_launch(c, best, 0);
+}
+
 int rmrt_free(rmrt_ctx* c) {
   if (!c) return RMRT_OK;
   if (c->batch) return fail(RMRT_EINVAL, "domain belongs to a batch: use rmrt_batch_free");
@@ -733,12 +841,14 @@ namespace {
 
 struct TileConfig {
   int threads, tile_nodes, blocks_per_cu;  // blocks_per_cu <= 0: one workgroup per tile
+  int persistent;  // 1: persistent grid of blocks_per_cu per CU; 0: one workgroup per tile,
+                   //    blocks_per_cu > 0 caps residency through dynamic LDS
 };
 // threads per block never exceed the kernels' launch bound of 256
 constexpr int kMaxThreads = 256;
 const TileConfig kConfigs[] = {
-    {256, 256, 0},  {256, 1024, 8}, {256, 2048, 8}, {256, 4096, 8},
-    {256, 512, 8},  {256, 8192, 4}, {128, 512, 16}, {256, 1024, 4},
+    {256, 256, 0, 0},  {256, 256, 2, 0},  {256, 256, 3, 0},  {256, 256, 4, 0},  {256, 256, 2, 1},
+    {256, 256, 3, 1},  {256, 1024, 2, 1}, {256, 1024, 4, 1}, {256, 2048, 8, 1}, {128, 512, 4, 1},
 };
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
@@ -803,8 +913,9 @@ int batch_launch(rmrt_batch* b, long long step_index, hipStream_t s) {
   a.bc = b->bc;
   a.phase = b->pattern == RMRT_AB ? PH_AB : ((step_index & 1) ? PH_AA_ODD : PH_AA_EVEN);
   if (tc.threads > kMaxThreads) return fail(RMRT_EINVAL, "config uses %d threads > %d", tc.threads, kMaxThreads);
-  const uint32_t persistent = tc.blocks_per_cu > 0 ? (uint32_t)(b->cus * tc.blocks_per_cu) : b->ntiles;
-  a.grid = std::min(b->ntiles, persistent);
+  a.flags = (tc.persistent && tc.blocks_per_cu > 0) ? (STEP_PERSISTENT | STEP_XCD_ORDER) : 0u;
+  a.grid = persistent_grid(b->ntiles, b->cus, tc.blocks_per_cu, a.flags);
+  a.lds_bytes = residency_lds(tc.blocks_per_cu, a.flags);
   a.block = (unsigned)tc.threads;
   a.stream = s;
   hipError_t e = dispatch_step(b->lattice, b->storage, a);
@@ -884,11 +995,12 @@ extern "C" {
 
 int rmrt_batch_num_configs(void) { return kNumConfigs; }
 
-int rmrt_batch_config_info(int cfg, int* threads, int* tile_nodes, int* blocks_per_cu) {
+int rmrt_batch_config_info(int cfg, int* threads, int* tile_nodes, int* blocks_per_cu, int* persistent) {
   if (cfg < 0 || cfg >= kNumConfigs) return fail(RMRT_EINVAL, "config %d out of range", cfg);
   if (threads) *threads = kConfigs[cfg].threads;
   if (tile_nodes) *tile_nodes = kConfigs[cfg].tile_nodes;
   if (blocks_per_cu) *blocks_per_cu = kConfigs[cfg].blocks_per_cu;
+  if (persistent) *persistent = kConfigs[cfg].persistent;
   return RMRT_OK;
 }
 

@@ -17,6 +17,11 @@ LIB_PATH = os.path.join(_HERE, "librmrt.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2206_00366_amd.build` first")
 
+# One HIP runtime per process: torch bundles its own libamdhip64.so.7, so it is
+# loaded first and librmrt.so binds to that same runtime (loading the library
+# first would pull a second runtime from /opt/rocm into the process).
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 # ---- constants (include/rmrt.h) ----
@@ -26,6 +31,7 @@ NSE, NCDE = 0, 1
 F64, F32DEV, F16DEV = 0, 1, 2
 AB, AA = 0, 1
 OUT_F64, OUT_F32 = 0, 1
+LAUNCH_XCD_ORDER, LAUNCH_PERSISTENT = 1, 2
 WALL_XM, WALL_XP, WALL_YM, WALL_YP, WALL_ZM, WALL_ZP = 1, 2, 4, 8, 16, 32
 
 LATTICES = {"Q9": Q9, "Q19": Q19, "Q27": Q27}
@@ -68,6 +74,9 @@ _sig = {
     "rmrt_reduce": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
     "rmrt_residual": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
     "rmrt_steps_taken": (C.c_int, [_vp, C.POINTER(C.c_longlong)]),
+    "rmrt_set_launch": (C.c_int, [_vp, C.c_int, C.c_int]),
+    "rmrt_get_launch": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "rmrt_tune": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(C.c_int)]),
     "rmrt_free": (C.c_int, [_vp]),
     "rmrt_batch_create": (C.c_int, [C.POINTER(_vp), C.c_int, C.POINTER(Params), C.POINTER(_vp),
                                      C.POINTER(_vp), C.POINTER(_vp), _vp]),
@@ -75,7 +84,8 @@ _sig = {
     "rmrt_batch_autotune": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(C.c_int)]),
     "rmrt_batch_set_config": (C.c_int, [_vp, C.c_int]),
     "rmrt_batch_num_configs": (C.c_int, []),
-    "rmrt_batch_config_info": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "rmrt_batch_config_info": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                          C.POINTER(C.c_int)]),
     "rmrt_batch_step": (C.c_int, [_vp, C.c_int, _vp]),
     "rmrt_batch_free": (C.c_int, [_vp]),
 }
@@ -233,6 +243,19 @@ class Domain:
         _check(_lib.rmrt_steps_taken(self._ctx, C.byref(s)), "rmrt_steps_taken")
         return s.value
 
+    def set_launch(self, blocks_per_cu, flags=0):
+        _check(_lib.rmrt_set_launch(self._ctx, int(blocks_per_cu), int(flags)), "rmrt_set_launch")
+
+    def get_launch(self):
+        b, x = C.c_int(), C.c_int()
+        _check(_lib.rmrt_get_launch(self._ctx, C.byref(b), C.byref(x)), "rmrt_get_launch")
+        return b.value, x.value
+
+    def tune(self, steps=20):
+        b = C.c_int()
+        _check(_lib.rmrt_tune(self._ctx, int(steps), _stream(), C.byref(b)), "rmrt_tune")
+        return b.value
+
     def close(self):
         if getattr(self, "_borrowed", False):
             return
@@ -291,9 +314,10 @@ class Batch:
     def configs():
         out = []
         for k in range(_lib.rmrt_batch_num_configs()):
-            t, n, b = C.c_int(), C.c_int(), C.c_int()
-            _check(_lib.rmrt_batch_config_info(k, C.byref(t), C.byref(n), C.byref(b)), "rmrt_batch_config_info")
-            out.append((t.value, n.value, b.value))
+            t, n, b, p = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+            _check(_lib.rmrt_batch_config_info(k, C.byref(t), C.byref(n), C.byref(b), C.byref(p)),
+                   "rmrt_batch_config_info")
+            out.append((t.value, n.value, b.value, p.value))
         return out
 
     def close(self):

@@ -93,6 +93,20 @@ def test_init_argument_errors_need_no_gpu():
 def test_batch_configs_within_launch_bound():
     cfgs = rmrt.Batch.configs()
     assert len(cfgs) >= 4
-    for threads, tile_nodes, per_cu in cfgs:
+    for threads, tile_nodes, per_cu, persistent in cfgs:
         assert 64 <= threads <= 256 and threads % 64 == 0
         assert tile_nodes >= threads
+        assert persistent in (0, 1)
+        assert persistent == 0 or per_cu >= 1
+        assert per_cu != 1 or persistent == 1
+
+
+def test_single_hip_runtime_in_process():
+    """The binding loads torch before the library, so only one libamdhip64 is mapped."""
+    import subprocess
+    import sys
+    code = ("import paper_2206_00366_amd.rmrt as r, torch;"
+            "m = open('/proc/self/maps').read();"
+            "print(len(set(l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l)))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.stdout.strip() == "1", out.stdout + out.stderr

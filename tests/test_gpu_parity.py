@@ -330,3 +330,43 @@ def test_nonfinite_detected_by_health_check(rmrt):
         dom.step(4)
     assert ei.value.code == rmrt.ENONFINITE
     dom.close()
+
+
+def test_launch_shapes_agree_and_match_oracle(rmrt):
+    """Persistent grids of 1..8 workgroups per CU (XCD-ordered or not) and one
+    workgroup per tile give bitwise-identical states that match the oracle,
+    on a grid large enough (640 tiles) for the persistent walk."""
+    say("[launch shapes] Q19 80x64x32 FP64")
+    prm = dict(lattice="Q19", n=(80, 64, 32), dx=(1.0, 0.5, 2.0), nu=0.03, nu_b=0.05)
+    m = O.Model(prm)
+    rho, u = random_fields(m, 21)
+    f_or = m.step(m.init(rho, u), 9)
+    ref = None
+    P, X = rmrt.LAUNCH_PERSISTENT, rmrt.LAUNCH_XCD_ORDER
+    for bpc, fl in [(0, 0), (0, X), (3, 0), (8, 0), (1, P | X), (2, P | X), (3, P), (8, P | X)]:
+        dom = rmrt.Domain(rmrt.make_params(**prm, storage="f64", pattern="AA"), rho, u)
+        dom.set_launch(bpc, fl)
+        assert dom.get_launch() == (bpc, fl)
+        dom.step(9)
+        g = dom.populations().cpu().numpy()
+        dom.close()
+        if ref is None:
+            ref = g
+            err = rel_err(g, f_or)
+            say(f"   max rel |f - f_oracle| = {err:.3e}")
+            assert err < 1e-12
+        else:
+            assert np.array_equal(g, ref), (bpc, fl)
+
+
+def test_tune_picks_a_valid_shape(rmrt):
+    say("[tune] Q19 64x64x64 f32dev")
+    prm = dict(lattice="Q19", n=(64, 64, 64), dx=(1.0, 1.0, 2.0), nu=0.01)
+    N = 64 ** 3
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage="f32dev", pattern="AA"), np.ones(N), np.zeros((3, N)))
+    k = dom.tune(steps=4)
+    assert k in (0, 2, 3, 4, 5, 6, 8)
+    assert dom.get_launch() == (k, 0)
+    r = dom.reduce()
+    assert abs(r[0] - N) < 1e-6 * N
+    dom.close()
