@@ -262,7 +262,100 @@ int rmrt_batch_config_info(int cfg, int* threads, int* tile_nodes, int* blocks_p
 /* Advance every domain nsteps steps (graph replay of persistent launches). */
 int rmrt_batch_step(rmrt_batch* b, int nsteps, void* stream);
 
+/*
+ * rmrt_residual for every domain of the batch with one host synchronisation:
+ * r[d] = ||u^n - u^prev||_2 / ||u^n||_2 (phi for the NCDE) against the
+ * previous call (first call: +inf).  r holds nd doubles (host).  Returns
+ * RMRT_ENONFINITE (r[d] = NaN) when a domain's sums are not finite.
+ */
+int rmrt_batch_residual(rmrt_batch* b, double* r, void* stream);
+
 int rmrt_batch_free(rmrt_batch* b);
+
+/* ===========================================================================
+ * Warm-start surrogate (not part of the paper's method): a network of 3x3
+ * dilated convolutions that predicts a steady channel flow from its geometry,
+ * used to initialise the populations through rmrt_set_fields with
+ * with_fne = 1 (Sec. IV eq. fne).  All kernels are hand-written for gfx950;
+ * convolutions are implicit GEMMs on MFMA (bf16 inputs, fp32 accumulation).
+ *
+ * Layouts: activations (B, H, W, C) channels-last with C = 16 or 32; weights
+ * (Cout, 3, 3, Cin); bf16 tensors are raw 16-bit bfloat16.  Tap (ky, kx)
+ * reads (h + (ky - 1) dil, w + (kx - 1) dil), zero outside the image.
+ * Every pointer is caller-owned device memory; every call is asynchronous on
+ * stream.
+ * ======================================================================== */
+
+/* epilogues of rmrt_nn_conv_forward */
+#define RMRT_NN_EPI_NONE 0       /* a = y                                   */
+#define RMRT_NN_EPI_SILU 1       /* a = silu(y)                             */
+#define RMRT_NN_EPI_SILU_GRAD 2  /* a = y * silu'(aux)  (backward pass)     */
+
+/*
+ * y = bias + conv3x3(x, w, dil); y_pre (fp32, may be NULL) receives y and
+ * a_out (bf16, may be NULL) the epilogue applied to y.  bias may be NULL.
+ * Cin, Cout in {16, 32}.
+ */
+int rmrt_nn_conv_forward(const void* x, const void* w, const float* bias, float* y_pre, void* a_out,
+                         const float* aux, int B, int H, int W, int Cin, int Cout, int dil, int epilogue,
+                         void* stream);
+
+/* wt[ci][ky][kx][co] = w[co][2-ky][2-kx][ci]: backward-data is rmrt_nn_conv_forward with wt. */
+int rmrt_nn_flip_weights(const void* w, void* wt, int Cout, int Cin, void* stream);
+
+/* Scratch floats needed by rmrt_nn_conv_backward_weight. Host only. */
+size_t rmrt_nn_wgrad_scratch_floats(int B, int H, int W, int Cin, int Cout);
+
+/*
+ * dw[co][ky][kx][ci] = sum_p dy[p][co] x[p + tap][ci] and db[co] = sum_p dy[p][co]
+ * (db may be NULL); x, dy bf16, dw, db fp32; deterministic (fixed-order sums).
+ */
+int rmrt_nn_conv_backward_weight(const void* x, const void* dy, int B, int H, int W, int Cin, int Cout, int dil,
+                                 float* dw, float* db, float* scratch, size_t scratch_floats, void* stream);
+
+/*
+ * Weighted MSE over the first C channels of out (fp32, row stride out_stride):
+ * loss = sum_p weight[p] sum_c (out - target)^2 / sum_p weight[p] into *loss
+ * (device double); dout (bf16, stride out_stride) = dloss/dout, zero in the
+ * padding channels.  target is (P, C) fp32; scratch holds 1024 doubles and
+ * inv_den one float.
+ */
+int rmrt_nn_masked_mse(const float* out, int out_stride, const float* target, const float* weight, long P, int C,
+                       void* dout, double* scratch, float* inv_den, double* loss, void* stream);
+
+/* Adam step t >= 1 (bias-corrected) on n fp32 parameters; w_bf16 (may be NULL) receives a bf16 copy. */
+int rmrt_nn_adam(float* w, void* w_bf16, const float* g, float* m, float* v, long n, float lr, float b1, float b2,
+                 float eps, int t, void* stream);
+
+/* dst (bf16) = round-to-nearest-even(src). */
+int rmrt_nn_to_bf16(const float* src, void* dst, long n, void* stream);
+
+/*
+ * Network input on the k-coarsened grid of B channels of nx x ny nodes (walls
+ * at the y faces, spacing dy): channel 0 = solid fraction of each k x k block,
+ * 1 = Poiseuille prior 4 y (H - y) / H^2 at the block centre, 2 = Re / re_scale,
+ * the rest 0.  solid is (B, ny, nx) uint8, re is B floats, x0 is
+ * (B, ny/k, nx/k, channels) bf16.
+ */
+int rmrt_nn_features(const uint8_t* solid, const float* re, int B, int nx, int ny, int k, float dy, float re_scale,
+                     void* x0, int channels, void* stream);
+
+/*
+ * Training targets from steady fields (rho: B x N, u: B x 2 x N doubles, the
+ * layout of rmrt_moments): fluid means over each block of u / Ut - prior(y),
+ * v / Ut and (rho - 1) rho_scale into tgt (B, ny/k, nx/k, 3) fp32, and the
+ * fluid fraction of the block into wgt.
+ */
+int rmrt_nn_targets(const double* rho, const double* u, const uint8_t* solid, int B, int nx, int ny, int k, float dy,
+                    float Ut, float rho_scale, float* tgt, float* wgt, void* stream);
+
+/*
+ * Initial fields from the network output (B, ny/k, nx/k, out_stride) fp32:
+ * bilinear upsampling to the nodes, then u = Ut (prior + o0), v = Ut o1,
+ * rho = 1 + o2 / rho_scale, u = 0 in solid nodes (solid may be NULL).
+ */
+int rmrt_nn_warm_fields(const float* out, int out_stride, int B, int nx, int ny, int k, float dy, float Ut,
+                        float rho_scale, const uint8_t* solid, double* rho, double* u, void* stream);
 
 #ifdef __cplusplus
 }

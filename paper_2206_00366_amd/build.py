@@ -25,7 +25,7 @@ FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
 
 def sources():
     srcs = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
-    srcs.append("rmrt_capi.cpp")
+    srcs += ["rmrt_capi.cpp", "nn_capi.cpp"]
     return [os.path.join(CSRC, s) for s in srcs]
 
 

@@ -366,6 +366,12 @@ constexpr unsigned kMaxAuxGrid = 2048;
 
 }  // namespace
 
+// shared error channel for the surrogate kernels' ABI (nn_capi.cpp)
+int rmrt_set_error_(int code, const char* msg) {
+  g_last_error = msg;
+  return code;
+}
+
 // ---------------------------------------------------------------------------
 // Contexts
 // ---------------------------------------------------------------------------
@@ -866,6 +872,8 @@ struct rmrt_batch {
   int lattice = 0, storage = 0, equation = 0, pattern = 0, force = 0, bc = 0;
   std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
   hipStream_t cap = nullptr;
+  double* dres_all = nullptr;  // 2 * nd residual sums (device)
+  double* hres_all = nullptr;  // pinned host copy
 };
 
 namespace {
@@ -987,6 +995,8 @@ void batch_release(rmrt_batch* b) {
   b->ctxs.clear();
   if (b->dtiles) hipFree(b->dtiles);
   if (b->ddoms) hipFree(b->ddoms);
+  if (b->dres_all) hipFree(b->dres_all);
+  if (b->hres_all) hipHostFree(b->hres_all);
 }
 
 }  // namespace
@@ -1121,6 +1131,43 @@ int rmrt_batch_autotune(rmrt_batch* b, int steps, void* stream, int* chosen) {
   if (rc != RMRT_OK) return rc;
   if (chosen) *chosen = best;
   return RMRT_OK;
+}
+
+int rmrt_batch_residual(rmrt_batch* b, double* r, void* stream) {
+  if (!b || !r) return fail(RMRT_EINVAL, "batch or r is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if (!b->dres_all) HIP_TRY(hipMalloc(&b->dres_all, sizeof(double) * 2 * b->nd));
+  if (!b->hres_all) HIP_TRY(hipHostMalloc(&b->hres_all, sizeof(double) * 2 * b->nd, hipHostMallocDefault));
+  for (int d = 0; d < b->nd; ++d) {
+    rmrt_ctx* c = b->ctxs[d];
+    const int K = c->p.equation == RMRT_NSE ? c->v.d : 1;
+    if (!c->uprev) HIP_TRY(hipMalloc(&c->uprev, sizeof(double) * (size_t)K * c->hdom.N));
+    AuxLaunch a = aux_of(c, s);
+    a.out0 = c->partials;
+    a.out1 = c->uprev;
+    a.flag = c->have_prev ? 1 : 0;
+    hipError_t e = dispatch_residual(c->p.lattice, c->p.storage, a);
+    if (e != hipSuccess) return fail(RMRT_EHIP, "residual launch: %s", hipGetErrorString(e));
+    e = launch_reduce_final(c->partials, a.grid, b->dres_all + 2 * d, 2, s);
+    if (e != hipSuccess) return fail(RMRT_EHIP, "residual final: %s", hipGetErrorString(e));
+  }
+  HIP_TRY(hipMemcpyAsync(b->hres_all, b->dres_all, sizeof(double) * 2 * b->nd, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int rc = RMRT_OK;
+  for (int d = 0; d < b->nd; ++d) {
+    rmrt_ctx* c = b->ctxs[d];
+    const double num = b->hres_all[2 * d], den = b->hres_all[2 * d + 1];
+    if (!c->have_prev) {
+      r[d] = INFINITY;
+    } else if (!std::isfinite(num) || !std::isfinite(den)) {
+      r[d] = NAN;
+      rc = fail(RMRT_ENONFINITE, "non-finite residual in domain %d", d);
+    } else {
+      r[d] = den > 0 ? std::sqrt(num / den) : (num > 0 ? INFINITY : 0.0);
+    }
+    c->have_prev = true;
+  }
+  return rc;
 }
 
 int rmrt_batch_free(rmrt_batch* b) {

@@ -87,7 +87,24 @@ _sig = {
     "rmrt_batch_config_info": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                           C.POINTER(C.c_int)]),
     "rmrt_batch_step": (C.c_int, [_vp, C.c_int, _vp]),
+    "rmrt_batch_residual": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
     "rmrt_batch_free": (C.c_int, [_vp]),
+    "rmrt_nn_conv_forward": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                       C.c_int, C.c_int, _vp]),
+    "rmrt_nn_flip_weights": (C.c_int, [_vp, _vp, C.c_int, C.c_int, _vp]),
+    "rmrt_nn_wgrad_scratch_floats": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "rmrt_nn_conv_backward_weight": (C.c_int, [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp,
+                                               _vp, _vp, C.c_size_t, _vp]),
+    "rmrt_nn_masked_mse": (C.c_int, [_vp, C.c_int, _vp, _vp, C.c_long, C.c_int, _vp, _vp, _vp, _vp, _vp]),
+    "rmrt_nn_adam": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_long, C.c_float, C.c_float, C.c_float, C.c_float,
+                               C.c_int, _vp]),
+    "rmrt_nn_to_bf16": (C.c_int, [_vp, _vp, C.c_long, _vp]),
+    "rmrt_nn_features": (C.c_int, [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float, C.c_float, _vp,
+                                   C.c_int, _vp]),
+    "rmrt_nn_targets": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float, C.c_float,
+                                  C.c_float, _vp, _vp, _vp]),
+    "rmrt_nn_warm_fields": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float, C.c_float,
+                                      C.c_float, _vp, _vp, _vp, _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -310,6 +327,14 @@ class Batch:
     def set_config(self, cfg):
         _check(_lib.rmrt_batch_set_config(self._b, int(cfg)), "rmrt_batch_set_config")
 
+    def residuals(self):
+        n = len(self.domains)
+        out = (C.c_double * n)()
+        code = _lib.rmrt_batch_residual(self._b, out, _stream())
+        if code not in (OK, ENONFINITE):
+            _check(code, "rmrt_batch_residual")
+        return list(out)
+
     @staticmethod
     def configs():
         out = []
@@ -330,3 +355,64 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Surrogate kernels (bf16 tensors are torch.bfloat16 / int16 views)
+# ---------------------------------------------------------------------------
+NN_EPI_NONE, NN_EPI_SILU, NN_EPI_SILU_GRAD = 0, 1, 2
+
+
+def nn_conv_forward(x, w, bias, y_pre, a_out, aux, dil, epilogue):
+    B, H, W, Cin = x.shape
+    Cout = w.shape[0]
+    _check(_lib.rmrt_nn_conv_forward(_ptr(x), _ptr(w), _ptr(bias), _ptr(y_pre), _ptr(a_out), _ptr(aux),
+                                     B, H, W, Cin, Cout, int(dil), int(epilogue), _stream()), "rmrt_nn_conv_forward")
+
+
+def nn_flip_weights(w, wt):
+    _check(_lib.rmrt_nn_flip_weights(_ptr(w), _ptr(wt), w.shape[0], w.shape[3], _stream()), "rmrt_nn_flip_weights")
+
+
+def nn_wgrad_scratch_floats(B, H, W, Cin, Cout):
+    return _lib.rmrt_nn_wgrad_scratch_floats(B, H, W, Cin, Cout)
+
+
+def nn_conv_backward_weight(x, dy, dil, dw, db, scratch):
+    B, H, W, Cin = x.shape
+    Cout = dy.shape[3]
+    _check(_lib.rmrt_nn_conv_backward_weight(_ptr(x), _ptr(dy), B, H, W, Cin, Cout, int(dil), _ptr(dw), _ptr(db),
+                                             _ptr(scratch), scratch.numel(), _stream()),
+           "rmrt_nn_conv_backward_weight")
+
+
+def nn_masked_mse(out, target, weight, dout, scratch, inv_den, loss):
+    Cs = out.shape[-1]
+    P = out.numel() // Cs
+    C_used = target.shape[-1]
+    _check(_lib.rmrt_nn_masked_mse(_ptr(out), Cs, _ptr(target), _ptr(weight), P, C_used, _ptr(dout), _ptr(scratch),
+                                   _ptr(inv_den), _ptr(loss), _stream()), "rmrt_nn_masked_mse")
+
+
+def nn_adam(w, w_bf16, g, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-8):
+    _check(_lib.rmrt_nn_adam(_ptr(w), _ptr(w_bf16), _ptr(g), _ptr(m), _ptr(v), w.numel(), float(lr), float(b1),
+                             float(b2), float(eps), int(t), _stream()), "rmrt_nn_adam")
+
+
+def nn_to_bf16(src, dst):
+    _check(_lib.rmrt_nn_to_bf16(_ptr(src), _ptr(dst), src.numel(), _stream()), "rmrt_nn_to_bf16")
+
+
+def nn_features(solid, re, B, nx, ny, k, dy, re_scale, x0):
+    _check(_lib.rmrt_nn_features(_ptr(solid), _ptr(re), B, nx, ny, k, float(dy), float(re_scale), _ptr(x0),
+                                 x0.shape[-1], _stream()), "rmrt_nn_features")
+
+
+def nn_targets(rho, u, solid, B, nx, ny, k, dy, Ut, rho_scale, tgt, wgt):
+    _check(_lib.rmrt_nn_targets(_ptr(rho), _ptr(u), _ptr(solid), B, nx, ny, k, float(dy), float(Ut),
+                                float(rho_scale), _ptr(tgt), _ptr(wgt), _stream()), "rmrt_nn_targets")
+
+
+def nn_warm_fields(out, B, nx, ny, k, dy, Ut, rho_scale, solid, rho, u):
+    _check(_lib.rmrt_nn_warm_fields(_ptr(out), out.shape[-1], B, nx, ny, k, float(dy), float(Ut), float(rho_scale),
+                                    _ptr(solid), _ptr(rho), _ptr(u), _stream()), "rmrt_nn_warm_fields")

@@ -150,3 +150,22 @@ def test_c4_full_batch_sampled_one_step(rmrt):
         say(f"   domain {k} n={d['n']}: sampled max rel err {err:.2e}")
         assert err < 2e-6
     b.close()
+
+
+def test_batch_residuals_match_per_domain(rmrt):
+    say("[batch] residuals")
+    b = rmrt.Batch([rmrt.make_params(**p, storage="f64", pattern="AA") for p in SMALL])
+    for d, p in zip(b.domains, SMALL):
+        m = O.Model(p)
+        rho, u = _fields(m, 7)
+        d.set_fields(rho, u)
+    r0 = b.residuals()
+    assert all(v == float("inf") for v in r0)
+    prev = [d.moments()[1].cpu().numpy() for d in b.domains]
+    b.step(5)
+    r = b.residuals()
+    for k, d in enumerate(b.domains):
+        u = d.moments()[1].cpu().numpy()
+        expect = np.sqrt(((u - prev[k]) ** 2).sum() / (u**2).sum())
+        assert abs(r[k] - expect) < 1e-12 * max(1.0, expect)
+    b.close()
