@@ -155,6 +155,14 @@ def main():
     ap.add_argument("--only", default="all",
                     help="comma list of: c3,c3f16,c3f64,c2,q27,c4,c1,copy (headline c3 always runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warmstart", action="store_true",
+                    help="run the warm-start study (solver-generated training set, training, held-out evaluation)")
+    ap.add_argument("--ws-train", type=int, default=512)
+    ap.add_argument("--ws-test", type=int, default=100)
+    ap.add_argument("--ws-epochs", type=int, default=40)
+    ap.add_argument("--ws-train-tol", type=float, default=1e-5)
+    ap.add_argument("--ws-max-steps", type=int, default=300_000)
+    ap.add_argument("--ws-log", default=None, help="file receiving one JSON line per finished stage")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -167,6 +175,10 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     from paper_2206_00366_amd import rmrt as R
+
+    if args.warmstart:
+        print(json.dumps(warmstart_study(torch, args)))
+        return
 
     only = set(args.only.split(",")) if args.only != "all" else {"c3f16", "c3f64", "c2", "q27", "c4", "c1", "copy"}
     K, W = args.steps, args.warmup
@@ -286,6 +298,118 @@ def bench_batch(torch, R, steps, warmup):
     del b
     torch.cuda.empty_cache()
     return e
+
+
+def warmstart_study(torch, args):
+    """Steps and time to a 1e-6 steady residual for cold, Poiseuille-prior and
+    surrogate warm starts on held-out rD2Q9 obstacle channels (512 x 256,
+    dy = 0.5, walls at the y faces, force-driven, Re 10..100)."""
+    import numpy as np
+    from inputs import obstacle_channel
+    from paper_2206_00366_amd import surrogate as S
+
+    stages = []
+
+    def record(name, **kw):
+        kw["stage"] = name
+        stages.append(kw)
+        log(json.dumps(kw))
+        if args.ws_log:
+            with open(args.ws_log, "a") as fh:
+                fh.write(json.dumps(kw) + "\n")
+
+    nb = 64
+    t_start = time.perf_counter()
+    # ---- training set: steady fields from the solver (Poiseuille-prior start) ----
+    X, T, Wt = [], [], []
+    gen_steps = 0
+    cfg = None
+    for s0 in range(0, args.ws_train, nb):
+        geoms = [obstacle_channel(seed) for seed in range(s0, min(s0 + nb, args.ws_train))]
+        b = S.make_batch(geoms)
+        if cfg is None:
+            cfg = b.autotune(steps=20)
+            record("autotune", config=dict(zip(("threads", "tile_nodes", "blocks_per_cu", "persistent"),
+                                                b.configs()[cfg])))
+        else:
+            b.set_config(cfg)
+        rho, u = S.initial_fields(geoms)
+        S.apply_initial(b, rho, u)
+        steps, conv, wall, n = S.run_to_steady(b, tol=args.ws_train_tol, max_steps=args.ws_max_steps, log=log,
+                                               label=f"train batch {s0 // nb}")
+        tgt, wgt = S.steady_targets(b, geoms)
+        x0, _ = S.features(geoms)
+        X.append(x0)
+        T.append(tgt)
+        Wt.append(wgt)
+        gen_steps += n
+        record("train_batch", first_seed=s0, domains=len(geoms), steps=int(n), converged=int(conv.sum()),
+               wall_s=round(wall, 1))
+        b.close()
+        del b
+    X, T, Wt = torch.cat(X), torch.cat(T), torch.cat(Wt)
+    t_gen = time.perf_counter() - t_start
+    # ---- training ----
+    net = S.Surrogate(seed=0, B=16, H=X.shape[1], W=X.shape[2])
+    t0 = time.perf_counter()
+    hist = S.train(net, X, T, Wt, epochs=args.ws_epochs, batch_size=16, lr=2e-3, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    record("train", samples=int(X.shape[0]), epochs=args.ws_epochs, loss_first=hist[0], loss_last=hist[-1],
+           wall_s=round(t_train, 1))
+    # ---- evaluation on held-out geometries ----
+    test = [obstacle_channel(seed) for seed in range(2000, 2000 + args.ws_test)]
+    results = {}
+    for mode in ("cold", "prior", "warm"):
+        all_steps, all_conv, all_time, wall_tot, inf_tot = [], [], [], 0.0, 0.0
+        for s0 in range(0, len(test), 50):
+            geoms = test[s0:s0 + 50]
+            b = S.make_batch(geoms)
+            b.set_config(cfg)
+            t_inf = 0.0
+            if mode != "cold":
+                torch.cuda.synchronize()
+                ti = time.perf_counter()
+                out = S.predict(net, geoms)[0] if mode == "warm" else None
+                rho, u = S.initial_fields(geoms, out)
+                S.apply_initial(b, rho, u)
+                torch.cuda.synchronize()
+                t_inf = time.perf_counter() - ti
+            steps, conv, wall, n = S.run_to_steady(b, tol=1e-6, max_steps=args.ws_max_steps, log=log,
+                                                   label=f"{mode} batch {s0 // 50}")
+            all_steps.append(steps)
+            all_conv.append(conv)
+            # per-domain time: its steps at the batch's cost per domain-step, plus its share of the init
+            all_time.append(steps * wall / (len(geoms) * max(n, 1)) + t_inf / len(geoms))
+            wall_tot += wall
+            inf_tot += t_inf
+            b.close()
+            del b
+        st = np.concatenate(all_steps)
+        cv = np.concatenate(all_conv)
+        tm = np.concatenate(all_time)
+        ok = st[cv]
+        results[mode] = {"converged": int(cv.sum()), "not_converged": int((~cv).sum()),
+                         "mean_steps": float(ok.mean()) if ok.size else None,
+                         "median_steps": float(np.median(ok)) if ok.size else None,
+                         "mean_time_s": float(tm[cv].mean()) if ok.size else None,
+                         "median_time_s": float(np.median(tm[cv])) if ok.size else None,
+                         "batch_wall_s": round(wall_tot, 1), "init_s": round(inf_tot, 3),
+                         "steps_per_domain": st.tolist()}
+        record("eval", mode=mode, **{k: v for k, v in results[mode].items() if k != "steps_per_domain"})
+    cold = np.array(results["cold"]["steps_per_domain"], dtype=float)
+    for mode in ("prior", "warm"):
+        st = np.array(results[mode]["steps_per_domain"], dtype=float)
+        results[mode]["median_step_ratio_vs_cold"] = float(np.median(st / cold))
+    results["warm"]["median_step_ratio_vs_prior"] = float(
+        np.median(np.array(results["warm"]["steps_per_domain"], float) /
+                  np.array(results["prior"]["steps_per_domain"], float)))
+    return {"metric": "steps and time to a 1e-6 steady residual: cold vs Poiseuille prior vs surrogate warm start",
+            "workload": "rD2Q9 NSE obstacle channels 512x256, dy = 0.5, Re 10-100, 1-8 obstacles, FP32-dev AA, "
+                        "batches of 50 domains per launch",
+            "train_fields": int(X.shape[0]), "train_tol": args.ws_train_tol, "generation_s": round(t_gen, 1),
+            "training_s": round(t_train, 1), "test_fields": len(test), "max_steps": args.ws_max_steps,
+            "results": results, "stages": stages}
 
 
 if __name__ == "__main__":

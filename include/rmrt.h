@@ -334,11 +334,13 @@ int rmrt_nn_to_bf16(const float* src, void* dst, long n, void* stream);
  * Network input on the k-coarsened grid of B channels of nx x ny nodes (walls
  * at the y faces, spacing dy): channel 0 = solid fraction of each k x k block,
  * 1 = Poiseuille prior 4 y (H - y) / H^2 at the block centre, 2 = Re / re_scale,
- * the rest 0.  solid is (B, ny, nx) uint8, re is B floats, x0 is
- * (B, ny/k, nx/k, channels) bf16.
+ * 3 = solid fraction of the block's columns over the full height, 4 = solid
+ * fraction of the whole channel, the rest 0.  solid is (B, ny, nx) uint8, re
+ * is B floats, x0 is (B, ny/k, nx/k, channels >= 5) bf16, scratch holds
+ * B (nx + 1) floats.
  */
 int rmrt_nn_features(const uint8_t* solid, const float* re, int B, int nx, int ny, int k, float dy, float re_scale,
-                     void* x0, int channels, void* stream);
+                     void* x0, int channels, float* scratch, void* stream);
 
 /*
  * Training targets from steady fields (rho: B x N, u: B x 2 x N doubles, the

@@ -100,6 +100,15 @@ struct Geo {
   }
 };
 
+// Per-node link bits of the solid-mask boundary mode (BC == 2): built once by
+// k_links from the walls and the solid mask, so the step reads one word per
+// node instead of a byte per neighbour.
+template <int L>
+struct LinkBits {
+  using W = typename std::conditional<L == LAT_Q9, uint16_t, uint32_t>::type;
+  static constexpr W kSolid = (W)1 << (sizeof(W) * 8 - 1);
+};
+
 // Element offset (in S units, from the buffer start) of the slot read for
 // population j of node idx, in the natural (own) or swapped layout.
 template <int L, int BC, bool SWAPPED, int J, int D>
@@ -129,8 +138,13 @@ __device__ __forceinline__ void step_node(const DomainDev& Dm, const Coef<typena
   using S = typename SS::S;
   using T = typename SS::T;
   constexpr int Q = Lat<L>::Q, NS = Lat<L>::NS, D = Lat<L>::D;
+  using LW = typename LinkBits<L>::W;
+  LW lb = 0;
   if constexpr (BC == 1) {
     if (Dm.has_solid && Dm.solid[idx]) return;
+  } else if constexpr (BC == 2) {
+    lb = ((const LW*)Dm.links)[idx];
+    if (lb & LinkBits<L>::kSolid) return;
   }
   Geo<D> g;
   if constexpr (PH != PH_AA_EVEN) g.make(Dm, idx);
@@ -144,7 +158,12 @@ __device__ __forceinline__ void step_node(const DomainDev& Dm, const Coef<typena
   static_for<0, Q>([&](auto j_) {
     constexpr int J = decltype(j_)::value;
     S v;
-    if constexpr (PH == PH_AA_ODD) {
+    if constexpr (PH == PH_AA_ODD && BC == 2) {
+      constexpr int O = Lat<L>::opp(J);
+      const size_t e = ((lb >> O) & 1) ? (size_t)J * N + idx
+                                       : (size_t)O * N + (uint32_t)(idx + (uint32_t)g.template off<L, O>());
+      v = fin[e];
+    } else if constexpr (PH == PH_AA_ODD) {
       v = fin[read_elem<L, BC, true, J>(Dm, g, idx)];
     } else {
       const S* __restrict__ pj = fin + (size_t)J * N;
@@ -167,7 +186,11 @@ __device__ __forceinline__ void step_node(const DomainDev& Dm, const Coef<typena
       S* __restrict__ pj = fout + (size_t)J * N;
       pj[(uint32_t)(idx + (uint32_t)g.template off<L, J>())] = v;
     } else {
-      const bool b = g.template bounce<L, J>(Dm, idx);
+      bool b;
+      if constexpr (BC == 2)
+        b = (lb >> J) & 1;
+      else
+        b = g.template bounce<L, J>(Dm, idx);
       const size_t e = b ? (size_t)O * N + idx
                          : (size_t)J * N + (uint32_t)(idx + (uint32_t)g.template off<L, J>());
       fout[e] = v;
@@ -600,6 +623,24 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+template <int L>
+__global__ void __launch_bounds__(256) k_links(const DomainDev* __restrict__ doms, uint32_t dom, void* out) {
+  using LW = typename LinkBits<L>::W;
+  const DomainDev& Dm = doms[dom];
+  const uint32_t N = Dm.N;
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+    Geo<Lat<L>::D> g;
+    g.make(Dm, idx);
+    LW bits = 0;
+    static_for<1, Lat<L>::Q>([&](auto j_) {
+      constexpr int J = decltype(j_)::value;
+      if (g.template bounce<L, J>(Dm, idx)) bits |= (LW)1 << J;
+    });
+    if (Dm.has_solid && Dm.solid[idx]) bits |= LinkBits<L>::kSolid;
+    ((LW*)out)[idx] = bits;
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Host-side launch descriptors (defined per lattice/storage translation unit)
 // ----------------------------------------------------------------------------
@@ -638,6 +679,8 @@ template <int L, int ST>
 hipError_t launch_reduce(const AuxLaunch& a);
 template <int L, int ST>
 hipError_t launch_residual(const AuxLaunch& a);
+template <int L>
+hipError_t launch_links(const DomainDev* doms, uint32_t dom, void* out, unsigned grid, hipStream_t s);
 hipError_t launch_reduce_final(const double* partials, uint32_t nb, double* out, int K, hipStream_t s);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 

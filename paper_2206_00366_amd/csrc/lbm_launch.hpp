@@ -22,7 +22,12 @@ hipError_t step_ph(const StepLaunch& a) {
 }
 template <int L, int ST, int EQ, bool F>
 hipError_t step_bc(const StepLaunch& a) {
-  return a.bc ? step_ph<L, ST, EQ, F, 1>(a) : step_ph<L, ST, EQ, F, 0>(a);
+  switch (a.bc) {
+    case 0: return step_ph<L, ST, EQ, F, 0>(a);
+    case 1: return step_ph<L, ST, EQ, F, 1>(a);
+    case 2: return step_ph<L, ST, EQ, F, 2>(a);
+  }
+  return hipErrorInvalidValue;
 }
 template <int L, int ST, int EQ>
 hipError_t step_f(const StepLaunch& a) {
@@ -110,6 +115,14 @@ hipError_t launch_init(const AuxLaunch& a) {
 #undef K_INIT
   return hipGetLastError();
 }
+
+template <int L>
+hipError_t launch_links(const DomainDev* doms, uint32_t dom, void* out, unsigned grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_links<L>), dim3(grid), dim3(256), 0, s, doms, dom, out);
+  return hipGetLastError();
+}
+
+#define RMRT_INSTANTIATE_LINKS(L) template hipError_t launch_links<L>(const DomainDev*, uint32_t, void*, unsigned, hipStream_t);
 
 #define RMRT_INSTANTIATE(L, ST)                                 \
   template hipError_t launch_step<L, ST>(const StepLaunch&);    \

@@ -52,6 +52,8 @@ struct DomainDev {
   void* fa;                 // population buffer 0
   void* fb;                 // population buffer 1 (two-lattice pattern)
   const uint8_t* solid;     // 1 byte per node or null
+  const void* links;        // per-node link bits (uint16 for rD2Q9, uint32 otherwise) or null:
+                            // bit j = link x -> x + e_j hits a wall or solid; top bit = solid node
 };
 
 // One unit of persistent-kernel work: nodes [start, start + count) of a domain.

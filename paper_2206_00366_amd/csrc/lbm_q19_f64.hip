@@ -2,4 +2,5 @@
 #include "lbm_launch.hpp"
 namespace rmrt {
 RMRT_INSTANTIATE(LAT_Q19, ST_F64)
+RMRT_INSTANTIATE_LINKS(LAT_Q19)
 }  // namespace rmrt

@@ -2,4 +2,5 @@
 #include "lbm_launch.hpp"
 namespace rmrt {
 RMRT_INSTANTIATE(LAT_Q9, ST_F64)
+RMRT_INSTANTIATE_LINKS(LAT_Q9)
 }  // namespace rmrt

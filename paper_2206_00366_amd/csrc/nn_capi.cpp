@@ -20,7 +20,8 @@ hipError_t launch_mse(const float*, int, const float*, const float*, long, int, 
 hipError_t launch_adam(float*, uint16_t*, const float*, float*, float*, long, float, float, float, float, float, float,
                        hipStream_t);
 hipError_t launch_to_bf16(const float*, uint16_t*, long, hipStream_t);
-hipError_t launch_features(const uint8_t*, const float*, int, int, int, int, float, float, uint16_t*, int, hipStream_t);
+hipError_t launch_features(const uint8_t*, const float*, int, int, int, int, float, float, uint16_t*, int, float*,
+                           hipStream_t);
 hipError_t launch_targets(const double*, const double*, const uint8_t*, int, int, int, int, float, float, float, float*,
                           float*, hipStream_t);
 hipError_t launch_warm_fields(const float*, int, int, int, int, int, float, float, float, const uint8_t*, double*,
@@ -110,10 +111,11 @@ int rmrt_nn_to_bf16(const float* src, void* dst, long n, void* stream) {
 }
 
 int rmrt_nn_features(const uint8_t* solid, const float* re, int B, int nx, int ny, int k, float dy, float re_scale,
-                     void* x0, int channels, void* stream) {
-  if (!solid || !re || !x0) return nn_fail(RMRT_EINVAL, "NULL pointer");
-  if (k < 1 || nx % k || ny % k || channels < 3) return nn_fail(RMRT_EINVAL, "bad sizes");
-  return hip_rc(launch_features(solid, re, B, nx, ny, k, dy, re_scale, (uint16_t*)x0, channels, (hipStream_t)stream),
+                     void* x0, int channels, float* scratch, void* stream) {
+  if (!solid || !re || !x0 || !scratch) return nn_fail(RMRT_EINVAL, "NULL pointer");
+  if (k < 1 || nx % k || ny % k || channels < 5) return nn_fail(RMRT_EINVAL, "bad sizes");
+  return hip_rc(launch_features(solid, re, B, nx, ny, k, dy, re_scale, (uint16_t*)x0, channels, scratch,
+                                (hipStream_t)stream),
                 "features launch");
 }
 

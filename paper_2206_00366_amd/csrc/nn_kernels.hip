@@ -284,9 +284,29 @@ __global__ void k_to_bf16(const float* __restrict__ src, uint16_t* __restrict__ 
 // Coarse pixel (b, i, j): rows i (y), columns j (x).  The Poiseuille prior is
 // 4 y (H - y) / H^2 at the physical height y of the cell centre.
 // ---------------------------------------------------------------------------
-// features: ch0 = solid fraction of the block, ch1 = prior, ch2 = Re / re_scale, ch3.. = 0
+// colfrac[b][x] = solid fraction of column x; gfrac[b] = solid fraction of sample b
+__global__ void k_colfrac(const uint8_t* __restrict__ solid, int B, int nx, int ny, float* __restrict__ colfrac) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)B * nx) return;
+  const int b = (int)(t / nx), x = (int)(t - (long)b * nx);
+  int cnt = 0;
+  for (int y = 0; y < ny; ++y) cnt += solid[((long)b * ny + y) * nx + x] ? 1 : 0;
+  colfrac[t] = (float)cnt / (float)ny;
+}
+__global__ void k_gfrac(const float* __restrict__ colfrac, int B, int nx, float* __restrict__ gfrac) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double s = 0.0;
+  for (int x = 0; x < nx; ++x) s += colfrac[(long)b * nx + x];
+  gfrac[b] = (float)(s / nx);
+}
+
+// features: ch0 = solid fraction of the block, ch1 = prior, ch2 = Re / re_scale,
+// ch3 = solid fraction of the block's columns over the full height (local
+// constriction), ch4 = solid fraction of the whole channel, ch5.. = 0
 __global__ void k_features(const uint8_t* __restrict__ solid, const float* __restrict__ re, int B, int nx, int ny, int k,
-                           float dy, float re_scale, uint16_t* __restrict__ x0, int Cs) {
+                           float dy, float re_scale, const float* __restrict__ colfrac, const float* __restrict__ gfrac,
+                           uint16_t* __restrict__ x0, int Cs) {
   const int hc = ny / k, wc = nx / k;
   const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= (long)B * hc * wc) return;
@@ -299,11 +319,16 @@ __global__ void k_features(const uint8_t* __restrict__ solid, const float* __res
   const float Hh = ny * dy;
   const float y = (i * k + 0.5f * k) * dy;
   const float prior = 4.f * y * (Hh - y) / (Hh * Hh);
+  float col = 0.f;
+  for (int c = 0; c < k; ++c) col += colfrac[(long)b * nx + j * k + c];
+  col /= (float)k;
   for (int c = 0; c < Cs; ++c) {
     float v = 0.f;
     if (c == 0) v = (float)cnt / (float)(k * k);
     if (c == 1) v = prior;
     if (c == 2) v = re[b] / re_scale;
+    if (c == 3) v = col;
+    if (c == 4) v = gfrac[b];
     x0[p * Cs + c] = f2bf(v);
   }
 }
@@ -458,11 +483,16 @@ hipError_t launch_to_bf16(const float* src, uint16_t* dst, long n, hipStream_t s
   return hipGetLastError();
 }
 
+// scratch: B * (nx + 1) floats
 hipError_t launch_features(const uint8_t* solid, const float* re, int B, int nx, int ny, int k, float dy, float re_scale,
-                           uint16_t* x0, int Cs, hipStream_t s) {
+                           uint16_t* x0, int Cs, float* scratch, hipStream_t s) {
   const long P = (long)B * (ny / k) * (nx / k);
+  float* colfrac = scratch;
+  float* gfrac = scratch + (long)B * nx;
+  hipLaunchKernelGGL(k_colfrac, dim3((unsigned)(((long)B * nx + 255) / 256)), dim3(256), 0, s, solid, B, nx, ny, colfrac);
+  hipLaunchKernelGGL(k_gfrac, dim3((B + 63) / 64), dim3(64), 0, s, colfrac, B, nx, gfrac);
   hipLaunchKernelGGL(k_features, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, solid, re, B, nx, ny, k, dy,
-                     re_scale, x0, Cs);
+                     re_scale, colfrac, gfrac, x0, Cs);
   return hipGetLastError();
 }
 

@@ -341,6 +341,14 @@ hipError_t dispatch_populations(int lat, int st, const AuxLaunch& a) {
 }
 hipError_t dispatch_reduce(int lat, int st, const AuxLaunch& a) { RMRT_DISPATCH(launch_reduce, lat, st, a); }
 hipError_t dispatch_residual(int lat, int st, const AuxLaunch& a) { RMRT_DISPATCH(launch_residual, lat, st, a); }
+hipError_t dispatch_links(int lat, const DomainDev* doms, uint32_t dom, void* out, unsigned grid, hipStream_t s) {
+  switch (lat) {
+    case LAT_Q9: return launch_links<LAT_Q9>(doms, dom, out, grid, s);
+    case LAT_Q19: return launch_links<LAT_Q19>(doms, dom, out, grid, s);
+    case LAT_Q27: return launch_links<LAT_Q27>(doms, dom, out, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 constexpr unsigned kAuxBlock = 256;
 // Launch shape of the single-domain step.  Measured on MI355X: one workgroup
@@ -392,6 +400,8 @@ struct rmrt_ctx {
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   hipStream_t cap = nullptr;   // capture stream
   int cus = 256;               // compute units of the device
+  void* links = nullptr;       // per-node link bits (solid-mask boundary mode)
+  int step_bc = 0;             // 0 periodic, 1 walls from coordinates, 2 link bits
   int blocks_per_cu = kDefaultBlocksPerCU;  // resident workgroups per CU (0: hardware limit)
   uint32_t flags = kDefaultFlags;
 };
@@ -458,7 +468,24 @@ void ctx_release(rmrt_ctx* c) {
   if (c->dres) hipFree(c->dres);
   if (c->hres) hipHostFree(c->hres);
   if (c->uprev) hipFree(c->uprev);
+  if (c->links) hipFree(c->links);
   if (c->owns_ddoms && c->ddoms) hipFree(c->ddoms);
+}
+
+// Allocate the link bits of a context (hdom.links set); the caller uploads
+// the parameter block and then runs build_links.
+int alloc_links(rmrt_ctx* c) {
+  const size_t w = c->p.lattice == RMRT_Q9 ? 2 : 4;
+  HIP_TRY(hipMalloc(&c->links, w * c->hdom.N));
+  c->hdom.links = c->links;
+  c->step_bc = 2;
+  return RMRT_OK;
+}
+
+int build_links(rmrt_ctx* c, hipStream_t s) {
+  hipError_t e = dispatch_links(c->p.lattice, c->ddoms, c->dom, c->links, aux_grid(c->hdom.N), s);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "links launch: %s", hipGetErrorString(e));
+  return RMRT_OK;
 }
 
 int launch_init_fields(rmrt_ctx* c, const double* rho, const double* u, int with_fne, hipStream_t s) {
@@ -484,7 +511,7 @@ int launch_one_step(rmrt_ctx* c, long long step_index, hipStream_t s) {
   a.parity = (uint32_t)(step_index & 1);
   a.eq = c->p.equation;
   a.force = has_force(&c->p);
-  a.bc = (c->hdom.walls != 0 || c->hdom.has_solid) ? 1 : 0;
+  a.bc = c->step_bc;
   a.phase = c->p.pattern == RMRT_AB ? PH_AB : ((step_index & 1) ? PH_AA_ODD : PH_AA_EVEN);
   a.grid = persistent_grid(a.ntiles, c->cus, c->blocks_per_cu, c->flags);
   a.lds_bytes = residency_lds(c->blocks_per_cu, c->flags);
@@ -653,6 +680,15 @@ static int ctx_create(rmrt_ctx** out, const rmrt_params* p, void* f0, void* f1, 
   }
   c->cus = device_cus();
   default_launch(*p, c->blocks_per_cu, c->flags);
+  c->step_bc = c->hdom.walls != 0 ? 1 : 0;
+  if (c->hdom.has_solid) {
+    rc = alloc_links(c);
+    if (rc != RMRT_OK) {
+      ctx_release(c);
+      delete c;
+      return rc;
+    }
+  }
   *out = c;
   return RMRT_OK;
 }
@@ -675,7 +711,8 @@ int rmrt_init(rmrt_ctx** out, const rmrt_params* p, void* f0, void* f1, const ui
     delete c;
     return fail(RMRT_EINVAL, "rho is NULL");
   }
-  rc = launch_init_fields(c, rho, u, with_fne, s);
+  if (c->links) rc = build_links(c, s);
+  if (rc == RMRT_OK) rc = launch_init_fields(c, rho, u, with_fne, s);
   if (rc != RMRT_OK) {
     ctx_release(c);
     delete c;
@@ -1055,9 +1092,22 @@ int rmrt_batch_create(rmrt_batch** out, int nd, const rmrt_params* params, void*
     }
     c->batch = b;
     b->ctxs.push_back(c);
-    host[d] = c->hdom;
     b->force |= has_force(&params[d]) ? 1 : 0;
-    b->bc |= (c->hdom.walls != 0 || c->hdom.has_solid) ? 1 : 0;
+    b->bc = std::max(b->bc, c->step_bc);
+  }
+  // one boundary mode per batch: link bits everywhere when any domain has a solid mask
+  for (int d = 0; d < nd; ++d) {
+    rmrt_ctx* c = b->ctxs[d];
+    if (b->bc == 2 && !c->links) {
+      int rc2 = alloc_links(c);
+      if (rc2 != RMRT_OK) {
+        batch_release(b);
+        delete b;
+        return rc2;
+      }
+    }
+    c->step_bc = b->bc;
+    host[d] = c->hdom;
   }
   e = hipMemcpyAsync(b->ddoms, host.data(), sizeof(DomainDev) * nd, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1067,6 +1117,8 @@ int rmrt_batch_create(rmrt_batch** out, int nd, const rmrt_params* params, void*
     return fail(RMRT_EHIP, "param upload: %s", hipGetErrorString(e));
   }
   int rc = batch_build_tiles(b, 1, s);
+  for (int d = 0; d < nd && rc == RMRT_OK; ++d)
+    if (b->ctxs[d]->links) rc = build_links(b->ctxs[d], s);
   for (int d = 0; d < nd && rc == RMRT_OK; ++d) rc = launch_init_fields(b->ctxs[d], nullptr, nullptr, 0, s);
   if (rc != RMRT_OK) {
     batch_release(b);

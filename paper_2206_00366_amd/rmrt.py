@@ -100,7 +100,7 @@ _sig = {
                                C.c_int, _vp]),
     "rmrt_nn_to_bf16": (C.c_int, [_vp, _vp, C.c_long, _vp]),
     "rmrt_nn_features": (C.c_int, [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float, C.c_float, _vp,
-                                   C.c_int, _vp]),
+                                   C.c_int, _vp, _vp]),
     "rmrt_nn_targets": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float, C.c_float,
                                   C.c_float, _vp, _vp, _vp]),
     "rmrt_nn_warm_fields": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float, C.c_float,
@@ -404,8 +404,10 @@ def nn_to_bf16(src, dst):
 
 
 def nn_features(solid, re, B, nx, ny, k, dy, re_scale, x0):
+    import torch
+    scratch = torch.empty(B * (nx + 1), dtype=torch.float32, device=x0.device)
     _check(_lib.rmrt_nn_features(_ptr(solid), _ptr(re), B, nx, ny, k, float(dy), float(re_scale), _ptr(x0),
-                                 x0.shape[-1], _stream()), "rmrt_nn_features")
+                                 x0.shape[-1], _ptr(scratch), _stream()), "rmrt_nn_features")
 
 
 def nn_targets(rho, u, solid, B, nx, ny, k, dy, Ut, rho_scale, tgt, wgt):

@@ -218,7 +218,7 @@ def train(net, X, T, Wt, epochs, batch_size, lr, seed=0, log=None):
             tot += loss
             cnt += 1
         hist.append(tot / max(cnt, 1))
-        if log:
+        if log and (ep % 10 == 0 or ep == epochs - 1):
             log(f"epoch {ep}: mean loss {hist[-1]:.4e}")
     return hist
 

@@ -145,7 +145,12 @@ def test_features_targets_and_warm_fields(R):
     np.testing.assert_allclose(f[..., 0], C.to_bf16(frac), atol=0)
     np.testing.assert_allclose(f[..., 1], C.to_bf16(np.broadcast_to(prior_c[None, :, None], frac.shape)), atol=0)
     np.testing.assert_allclose(f[..., 2], C.to_bf16(np.broadcast_to((re / 100.0)[:, None, None], frac.shape)), atol=0)
-    assert np.all(f[..., 3:] == 0)
+    col = solid.astype(np.float64).mean(axis=1)                       # (B, nx): over the full height
+    colc = col.reshape(B, nx // k, k).mean(axis=2)
+    np.testing.assert_allclose(f[..., 3], np.broadcast_to(colc[:, None, :], frac.shape), rtol=2.0**-7, atol=1e-7)
+    gf = solid.astype(np.float64).mean(axis=(1, 2))
+    np.testing.assert_allclose(f[..., 4], np.broadcast_to(gf[:, None, None], frac.shape), rtol=2.0**-7, atol=1e-7)
+    assert np.all(f[..., 5:] == 0)
     # targets: fluid means per block
     N = nx * ny
     rho = 1 + 0.01 * rng.standard_normal((B, N))
