@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--ws-train-tol", type=float, default=1e-5)
     ap.add_argument("--ws-max-steps", type=int, default=300_000)
     ap.add_argument("--ws-log", default=None, help="file receiving one JSON line per finished stage")
+    ap.add_argument("--no-warmstart", action="store_true",
+                    help="skip the reduced warm-start study of the default run")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -268,6 +270,16 @@ def main():
         out["hbm_copy_ceiling"] = ceiling
         roofline["frac_of_copy_ceiling"] = round(achieved / ceiling["GBps"], 4)
     out["per_lattice"] = per
+    if args.only == "all" and not args.no_warmstart:
+        # reduced live study (the full one: --warmstart --ws-train 1024 --ws-test 100 --ws-epochs 150)
+        log("[bench] warm-start study (reduced)")
+        ws_args = argparse.Namespace(ws_train=384, ws_test=50, ws_epochs=100, ws_train_tol=1e-5,
+                                     ws_max_steps=300_000, ws_log=None)
+        ws = warmstart_study(torch, ws_args)
+        for m in ws["results"].values():
+            m.pop("steps_per_domain", None)
+        ws.pop("stages", None)
+        out["warm_start"] = ws
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()
