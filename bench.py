@@ -69,7 +69,7 @@ def timed_steps(torch, step_fn, steps, warmup):
     return wall, ev_ms
 
 
-def c3_fields(n, dx, U0, cs2):
+def tg3d_fields(n, dx, U0, cs2):
     from inputs import taylor_green_3d
     rho, u, _ = taylor_green_3d(n, dx, U0, cs2)
     return rho, u
@@ -132,7 +132,7 @@ def cpu_baseline():
         threads = 1
     n, dx = (32, 32, 32), (1.0, 1.0, 2.0)
     m = O.Model(dict(lattice="Q19", n=n, dx=dx, nu=0.005, cs2=1.0 / 3.0))
-    rho, u = c3_fields(n, dx, 0.02, m.cs2)
+    rho, u = tg3d_fields(n, dx, 0.02, m.cs2)
     f = m.init(rho, u)
     f = m.step(f, 2)
     steps = 0
@@ -153,7 +153,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--only", default="all",
-                    help="comma list of: c3,c3f16,c3f64,c2,q27,c4,c1,copy (headline c3 always runs)")
+                    help="comma list of: q19,q19f16,q19f64,q9ncde,q27,q27batch,q9tg,copy (the q19 headline always runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--warmstart", action="store_true",
                     help="run the warm-start study (solver-generated training set, training, held-out evaluation)")
@@ -182,21 +182,21 @@ def main():
         print(json.dumps(warmstart_study(torch, args)))
         return
 
-    only = set(args.only.split(",")) if args.only != "all" else {"c3f16", "c3f64", "c2", "q27", "c4", "c1", "copy"}
+    only = set(args.only.split(",")) if args.only != "all" else {"q19f16", "q19f64", "q9ncde", "q27", "q27batch", "q9tg", "copy"}
     K, W = args.steps, args.warmup
 
     # ---------------- headline: rD3Q19 FP32-dev 256 x 256 x 128 ----------------
-    n3, dx3 = (256, 256, 128), (1.0, 1.0, 2.0)
-    N3 = n3[0] * n3[1] * n3[2]
-    prm3 = dict(lattice="Q19", equation="NSE", n=n3, dx=dx3, nu=0.005, cs2=1.0 / 3.0, rho0=1.0,
+    n_h, dx_h = (256, 256, 128), (1.0, 1.0, 2.0)
+    N_h = n_h[0] * n_h[1] * n_h[2]
+    prm_h = dict(lattice="Q19", equation="NSE", n=n_h, dx=dx_h, nu=0.005, cs2=1.0 / 3.0, rho0=1.0,
                 storage="f32dev", pattern="AA")
     log("[bench] headline rD3Q19 256x256x128 f32dev AA")
-    rho3, u3 = c3_fields(n3, dx3, 0.02, 1.0 / 3.0)
+    rho_h, u_h = tg3d_fields(n_h, dx_h, 0.02, 1.0 / 3.0)
     launch = {}
-    wall, ev_ms, finite = run_single(torch, R, prm3, rho3, u3, K, W, launch=launch)
-    head = lattice_entry("rD3Q19 NSE TG 256x256x128 dz=2dx FP32-dev AA", 19, "f32dev", N3, K, wall, ev_ms)
+    wall, ev_ms, finite = run_single(torch, R, prm_h, rho_h, u_h, K, W, launch=launch)
+    head = lattice_entry("rD3Q19 NSE TG 256x256x128 dz=2dx FP32-dev AA", 19, "f32dev", N_h, K, wall, ev_ms)
     head["finite"] = finite
-    bytes_per_launch = 2 * 19 * 4 * N3
+    bytes_per_launch = 2 * 19 * 4 * N_h
     avg_launch_s = ev_ms / K * 1e-3
     achieved = bytes_per_launch / avg_launch_s / 1e9
     src_hash = kernel_source_hash()
@@ -213,28 +213,28 @@ def main():
     if "copy" in only:
         log("[bench] HBM copy ceiling")
         ceiling = copy_ceiling(torch, R)
-    if "c3f16" in only:
+    if "q19f16" in only:
         log("[bench] rD3Q19 f16dev")
-        prm = dict(prm3, storage="f16dev")
-        w2, e2, fin = run_single(torch, R, prm, rho3, u3, K, W)
-        per["rD3Q19_f16dev"] = lattice_entry("rD3Q19 NSE TG 256x256x128 FP16-dev AA", 19, "f16dev", N3, K, w2, e2)
+        prm = dict(prm_h, storage="f16dev")
+        w2, e2, fin = run_single(torch, R, prm, rho_h, u_h, K, W)
+        per["rD3Q19_f16dev"] = lattice_entry("rD3Q19 NSE TG 256x256x128 FP16-dev AA", 19, "f16dev", N_h, K, w2, e2)
         per["rD3Q19_f16dev"]["finite"] = fin
         per["rD3Q19_f16dev"]["speedup_vs_f32dev"] = round(per["rD3Q19_f16dev"]["MLUPS"] / head["MLUPS"], 3)
-    if "c3f64" in only:
+    if "q19f64" in only:
         log("[bench] rD3Q19 f64")
-        prm = dict(prm3, storage="f64")
-        w2, e2, fin = run_single(torch, R, prm, rho3, u3, max(K // 2, 10), W)
-        per["rD3Q19_f64"] = lattice_entry("rD3Q19 NSE TG 256x256x128 FP64 AA", 19, "f64", N3, max(K // 2, 10), w2, e2)
-    del rho3, u3
+        prm = dict(prm_h, storage="f64")
+        w2, e2, fin = run_single(torch, R, prm, rho_h, u_h, max(K // 2, 10), W)
+        per["rD3Q19_f64"] = lattice_entry("rD3Q19 NSE TG 256x256x128 FP64 AA", 19, "f64", N_h, max(K // 2, 10), w2, e2)
+    del rho_h, u_h
     if "q27" in only:
         log("[bench] rD3Q27 f32dev 256x256x128")
-        prm = dict(prm3, lattice="Q27")
-        rho, u = c3_fields(n3, dx3, 0.02, 1.0 / 3.0)
+        prm = dict(prm_h, lattice="Q27")
+        rho, u = tg3d_fields(n_h, dx_h, 0.02, 1.0 / 3.0)
         w2, e2, fin = run_single(torch, R, prm, rho, u, K, W)
-        per["rD3Q27_f32dev"] = lattice_entry("rD3Q27 NSE TG 256x256x128 dz=2dx FP32-dev AA", 27, "f32dev", N3, K, w2, e2)
+        per["rD3Q27_f32dev"] = lattice_entry("rD3Q27 NSE TG 256x256x128 dz=2dx FP32-dev AA", 27, "f32dev", N_h, K, w2, e2)
         per["rD3Q27_f32dev"]["finite"] = fin
         del rho, u
-    if "c2" in only:
+    if "q9ncde" in only:
         log("[bench] rD2Q9 NCDE 2048x1024 f32dev")
         from inputs import gaussian_hill_field
         n2 = (2048, 1024, 1)
@@ -246,7 +246,7 @@ def main():
             "rD2Q9 NCDE Gaussian hill 2048x1024 dy=0.5 FP32-dev AA", 9, "f32dev", 2048 * 1024, 4 * K, w2, e2,
             note="75.5 MB working set fits the 256 MB MALL: % HBM may be cache-inflated")
         per["rD2Q9_ncde_f32dev"]["finite"] = fin
-    if "c1" in only:
+    if "q9tg" in only:
         log("[bench] rD2Q9 TG 64x32 f64")
         from inputs import taylor_green_2d
         prm = dict(lattice="Q9", n=(64, 32, 1), dx=(1.0, 0.5, 1.0), nu=0.02, nu_b=0.05, storage="f64", pattern="AA")
@@ -255,7 +255,7 @@ def main():
         per["rD2Q9_tg_f64"] = lattice_entry("rD2Q9 NSE TG 64x32 dy=0.5 FP64 (launch-bound, MLUPS only)", 9, "f64",
                                             2048, 2000, w2, e2)
         per["rD2Q9_tg_f64"].pop("pct_hbm_peak")
-    if "c4" in only:
+    if "q27batch" in only:
         log("[bench] rD3Q27 batch of 64 channels f32dev")
         per["rD3Q27_batch64_f32dev"] = bench_batch(torch, R, max(K // 10, 20), W)
 
@@ -264,7 +264,7 @@ def main():
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": "rD3Q19 NSE 3D Taylor-Green, periodic 256x256x128 nodes, dz = 2 dx, U0 = 0.02, "
                                   "nu = 0.005, FP32 deviation storage, FP32 collision, AA pattern",
-                      "lattice": "rD3Q19", "nodes": N3, "storage": "f32dev", "pattern": "AA"},
+                      "lattice": "rD3Q19", "nodes": N_h, "storage": "f32dev", "pattern": "AA"},
            "roofline": roofline}
     if ceiling:
         out["hbm_copy_ceiling"] = ceiling

@@ -889,11 +889,11 @@ struct TileConfig {
 };
 // threads per block never exceed the kernels' launch bound of 256
 constexpr int kMaxThreads = 256;
-const TileConfig kConfigs[] = {
+const TileConfig kTileShapes[] = {
     {256, 256, 0, 0},  {256, 256, 2, 0},  {256, 256, 3, 0},  {256, 256, 4, 0},  {256, 256, 2, 1},
     {256, 256, 3, 1},  {256, 1024, 2, 1}, {256, 1024, 4, 1}, {256, 2048, 8, 1}, {128, 512, 4, 1},
 };
-constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
+constexpr int kNumTileShapes = sizeof(kTileShapes) / sizeof(kTileShapes[0]);
 
 }  // namespace
 
@@ -916,7 +916,7 @@ struct rmrt_batch {
 namespace {
 
 int batch_build_tiles(rmrt_batch* b, int cfg, hipStream_t s) {
-  const TileConfig& tc = kConfigs[cfg];
+  const TileConfig& tc = kTileShapes[cfg];
   std::vector<Tile> tiles;
   for (int d = 0; d < b->nd; ++d) {
     const uint32_t N = b->ctxs[d]->hdom.N;
@@ -945,7 +945,7 @@ int batch_build_tiles(rmrt_batch* b, int cfg, hipStream_t s) {
 }
 
 int batch_launch(rmrt_batch* b, long long step_index, hipStream_t s) {
-  const TileConfig& tc = kConfigs[b->cfg];
+  const TileConfig& tc = kTileShapes[b->cfg];
   StepLaunch a;
   std::memset(&a, 0, sizeof(a));
   a.doms = b->ddoms;
@@ -1040,14 +1040,14 @@ void batch_release(rmrt_batch* b) {
 
 extern "C" {
 
-int rmrt_batch_num_configs(void) { return kNumConfigs; }
+int rmrt_batch_num_configs(void) { return kNumTileShapes; }
 
 int rmrt_batch_config_info(int cfg, int* threads, int* tile_nodes, int* blocks_per_cu, int* persistent) {
-  if (cfg < 0 || cfg >= kNumConfigs) return fail(RMRT_EINVAL, "config %d out of range", cfg);
-  if (threads) *threads = kConfigs[cfg].threads;
-  if (tile_nodes) *tile_nodes = kConfigs[cfg].tile_nodes;
-  if (blocks_per_cu) *blocks_per_cu = kConfigs[cfg].blocks_per_cu;
-  if (persistent) *persistent = kConfigs[cfg].persistent;
+  if (cfg < 0 || cfg >= kNumTileShapes) return fail(RMRT_EINVAL, "config %d out of range", cfg);
+  if (threads) *threads = kTileShapes[cfg].threads;
+  if (tile_nodes) *tile_nodes = kTileShapes[cfg].tile_nodes;
+  if (blocks_per_cu) *blocks_per_cu = kTileShapes[cfg].blocks_per_cu;
+  if (persistent) *persistent = kTileShapes[cfg].persistent;
   return RMRT_OK;
 }
 
@@ -1137,7 +1137,7 @@ int rmrt_batch_domain(rmrt_batch* b, int d, rmrt_ctx** out) {
 
 int rmrt_batch_set_config(rmrt_batch* b, int cfg) {
   if (!b) return fail(RMRT_EINVAL, "batch is NULL");
-  if (cfg < 0 || cfg >= kNumConfigs) return fail(RMRT_EINVAL, "config %d out of range", cfg);
+  if (cfg < 0 || cfg >= kNumTileShapes) return fail(RMRT_EINVAL, "config %d out of range", cfg);
   return batch_build_tiles(b, cfg, nullptr);
 }
 
@@ -1156,7 +1156,7 @@ int rmrt_batch_autotune(rmrt_batch* b, int steps, void* stream, int* chosen) {
   HIP_TRY(hipEventCreate(&e1));
   int best = -1;
   float best_ms = 1e30f;
-  for (int cfg = 0; cfg < kNumConfigs; ++cfg) {
+  for (int cfg = 0; cfg < kNumTileShapes; ++cfg) {
     int rc = batch_build_tiles(b, cfg, s);
     if (rc == RMRT_OK) rc = batch_step_impl(b, 2, s);  // warm-up (and graph capture)
     if (rc == RMRT_OK) rc = batch_step_impl(b, steps, s);  // captures the timed graph

@@ -109,11 +109,11 @@ def test_batch_plane_poiseuille(rmrt):
     b.close()
 
 
-def test_c4_full_batch_sampled_one_step(rmrt):
+def test_q27_64_channel_batch_one_step_sampled(rmrt):
     """The 64-domain rD3Q27 channel batch (seed 4, about 2e8 nodes, FP32-dev, AA):
     one persistent launch, then 256 sampled nodes of each of the 4 smallest
     domains against the oracle collision at their upstream nodes (with bounce-back)."""
-    say("[batch] C4 full size, sampled")
+    say("[batch] 64 rD3Q27 channels, sampled")
     doms = channel_batch(seed=4, nd=64)
     walls = WALLS["yz"]
     params = [rmrt.make_params(lattice="Q27", n=d["n"], dx=d["dx"], nu=d["nu"], nu_b=d["nu_b"], force=d["force"],

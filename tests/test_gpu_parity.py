@@ -135,10 +135,10 @@ def test_reduced_precision_storage(rmrt, case, storage, tol):
     dom.close()
 
 
-def test_config1_taylor_green_2d_fp64_full(rmrt):
+def test_taylor_green_2d_64x32_fp64_2000_steps(rmrt):
     """rD2Q9 NSE Taylor-Green, 64x32, dx = 1, dy = 0.5, U0 = 0.01, nu = 0.02, nu_b = 0.05,
     rho0 = 1 plus seeded 1e-4 noise, FP64, 2000 steps (graph replay)."""
-    say("[config1] rD2Q9 TG 64x32 2000 steps")
+    say("[tg2d] rD2Q9 TG 64x32 2000 steps")
     nx, ny, dx, dy = 64, 32, 1.0, 0.5
     prm = dict(lattice="Q9", n=(nx, ny, 1), dx=(dx, dy, 1.0), nu=0.02, nu_b=0.05)
     m = O.Model(prm)
@@ -167,7 +167,7 @@ def test_config1_taylor_green_2d_fp64_full(rmrt):
 
 
 @pytest.fixture(scope="module")
-def c3_small_oracle():
+def tg3d_q19_32cubed_oracle():
     n, dx = (32, 32, 32), (1.0, 1.0, 2.0)
     prm = dict(lattice="Q19", n=n, dx=dx, nu=0.005, cs2=1.0 / 3.0)
     m = O.Model(prm)
@@ -179,10 +179,10 @@ def c3_small_oracle():
 
 
 @pytest.mark.parametrize("storage,tol", [("f32dev", 1e-5), ("f16dev", 3e-3)])
-def test_config3_parity_on_32cubed(rmrt, c3_small_oracle, storage, tol):
+def test_taylor_green_3d_q19_32cubed_reduced_storage(rmrt, tg3d_q19_32cubed_oracle, storage, tol):
     """rD3Q19 3D Taylor-Green with dz = 2 dx on 32^3, FP32/FP16 deviation storage vs FP64 oracle."""
-    prm, rho, u, steps, r_o, u_o = c3_small_oracle
-    say(f"[config3 32^3] {storage}")
+    prm, rho, u, steps, r_o, u_o = tg3d_q19_32cubed_oracle
+    say(f"[tg3d 32^3] {storage}")
     dom = rmrt.Domain(rmrt.make_params(**prm, storage=storage, pattern="AA"), rho, u)
     dom.step(steps)
     r_g, u_g = dom.moments()
@@ -193,10 +193,10 @@ def test_config3_parity_on_32cubed(rmrt, c3_small_oracle, storage, tol):
     dom.close()
 
 
-def test_config2_ncde_reduced_grid(rmrt):
+def test_ncde_gaussian_hill_256x128_f32dev(rmrt):
     """rD2Q9 NCDE Gaussian hill with D(phi) = 0.01 (1 + phi^2), u = (0.05, 0.02), dy = 0.5,
     FP32 deviation storage, on a 256 x 128 box (oracle-sized), 300 steps."""
-    say("[config2 reduced] NCDE 256x128 f32dev")
+    say("[ncde 256x128] f32dev")
     nx, ny, dx, dy = 256, 128, 1.0, 0.5
     prm = dict(lattice="Q9", equation="NCDE", n=(nx, ny, 1), dx=(dx, dy, 1.0), D0=0.01, D2=1.0,
                adv=(0.05, 0.02, 0.0), rho0=0.0)
@@ -250,10 +250,10 @@ def _sampled_one_step(rmrt, prm, rho, u, storage, pattern, samples, seed):
 
 
 @pytest.mark.parametrize("storage,tol", [("f32dev", 2e-6), ("f16dev", 2e-3)])
-def test_config3_full_size_sampled(rmrt, storage, tol):
+def test_q19_256x256x128_one_step_sampled(rmrt, storage, tol):
     """rD3Q19 256 x 256 x 128, dz = 2 dx, U0 = 0.02, nu = 0.005: one step at full size in the
     benchmark's launch configuration, 4096 sampled nodes against the oracle."""
-    say(f"[config3 full] {storage}")
+    say(f"[q19 256x256x128 sampled] {storage}")
     n, dx = (256, 256, 128), (1.0, 1.0, 2.0)
     prm = dict(lattice="Q19", n=n, dx=dx, nu=0.005, cs2=1.0 / 3.0)
     rho, u, _ = taylor_green_3d(n, dx, 0.02, 1.0 / 3.0)
@@ -263,8 +263,8 @@ def test_config3_full_size_sampled(rmrt, storage, tol):
     assert err < tol
 
 
-def test_config2_full_size_sampled(rmrt):
-    say("[config2 full] NCDE 2048x1024 f32dev")
+def test_ncde_2048x1024_one_step_sampled(rmrt):
+    say("[ncde 2048x1024 sampled] f32dev")
     nx, ny, dx, dy = 2048, 1024, 1.0, 0.5
     prm = dict(lattice="Q9", equation="NCDE", n=(nx, ny, 1), dx=(dx, dy, 1.0), D0=0.01, D2=1.0,
                adv=(0.05, 0.02, 0.0), rho0=0.0)
