@@ -122,7 +122,8 @@ def copy_ceiling(torch, R, nbytes=2 << 30, reps=20):
 
 
 def cpu_baseline():
-    """The FP64 oracle as it stands, on a bounded sample of the headline workload."""
+    """The FP64 oracle as it stands, on a bounded sample of the headline workload.
+    Returns the baseline record and the oracle's final state for the accuracy check."""
     import numpy as np
     from oracle import rmrt_oracle as O
     try:
@@ -131,10 +132,10 @@ def cpu_baseline():
     except Exception:
         threads = 1
     n, dx = (32, 32, 32), (1.0, 1.0, 2.0)
-    m = O.Model(dict(lattice="Q19", n=n, dx=dx, nu=0.005, cs2=1.0 / 3.0))
+    prm = dict(lattice="Q19", n=n, dx=dx, nu=0.005, cs2=1.0 / 3.0)
+    m = O.Model(prm)
     rho, u = tg3d_fields(n, dx, 0.02, m.cs2)
     f = m.init(rho, u)
-    f = m.step(f, 2)
     steps = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < 12.0 or steps < 10:
@@ -142,9 +143,27 @@ def cpu_baseline():
         steps += 5
     dt = time.perf_counter() - t0
     assert np.isfinite(f).all()
-    return {"value": round(m.N * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"rD3Q19 NSE Taylor-Green 32x32x32 (dz = 2 dx, nu = 0.005), {steps} steps of the dense "
-                      f"FP64 numpy oracle ({dt:.1f} s); numpy BLAS threads = {threads}"}
+    rec = {"value": round(m.N * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"rD3Q19 NSE Taylor-Green 32x32x32 (dz = 2 dx, nu = 0.005), {steps} steps of the dense "
+                     f"FP64 numpy oracle ({dt:.1f} s); numpy BLAS threads = {threads}"}
+    r_o, u_o = m.macroscopic(f)
+    return rec, dict(prm=prm, rho=rho, u=u, steps=steps, rho_o=r_o, u_o=u_o)
+
+
+def accuracy_vs_oracle(torch, R, ref):
+    """Error of each storage mode against the oracle state of the CPU-baseline sample."""
+    import numpy as np
+    out = {}
+    for storage in ("f64", "f32dev", "f16dev"):
+        dom = R.Domain(R.make_params(**ref["prm"], storage=storage, pattern="AA"), ref["rho"], ref["u"])
+        dom.step(ref["steps"])
+        r, u = dom.moments()
+        r, u = r.cpu().numpy(), u.cpu().numpy()
+        dom.close()
+        out[storage] = {"max_abs_rho_err": float(np.abs(r - ref["rho_o"]).max()),
+                        "max_u_err_over_U0": float(np.abs(u - ref["u_o"]).max() / 0.02)}
+    out["sample"] = f"rD3Q19 TG 32^3, {ref['steps']} steps against the FP64 oracle"
+    return out
 
 
 def main():
@@ -282,7 +301,8 @@ def main():
         out["warm_start"] = ws
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"], ref = cpu_baseline()
+        out["accuracy_vs_fp64_oracle"] = accuracy_vs_oracle(torch, R, ref)
     print(json.dumps(out))
 
 

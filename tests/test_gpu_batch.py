@@ -169,3 +169,20 @@ def test_batch_residuals_match_per_domain(rmrt):
         expect = np.sqrt(((u - prev[k]) ** 2).sum() / (u**2).sum())
         assert abs(r[k] - expect) < 1e-12 * max(1.0, expect)
     b.close()
+
+
+@pytest.mark.parametrize("pattern", ["AA", "AB"])
+def test_batch_set_fields_at_odd_parity(rmrt, small_oracle, pattern):
+    """Re-initialising a batch domain after an odd number of steps writes the
+    layout that parity expects (the swapped one for AA)."""
+    say(f"[batch] set_fields at odd parity, {pattern}")
+    b = rmrt.Batch([rmrt.make_params(**p, storage="f64", pattern=pattern) for p in SMALL])
+    b.step(3)                                   # odd: AA state is swapped
+    for d, (m, rho, u, _) in zip(b.domains, small_oracle):
+        d.set_fields(rho, u)
+        assert d.steps_taken() == 3
+    b.step(21)
+    for d, (m, rho, u, f_or) in zip(b.domains, small_oracle):
+        g = d.populations().cpu().numpy()
+        assert rel_err(g, f_or) < 1e-12
+    b.close()

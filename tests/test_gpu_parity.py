@@ -172,7 +172,7 @@ def tg3d_q19_32cubed_oracle():
     prm = dict(lattice="Q19", n=n, dx=dx, nu=0.005, cs2=1.0 / 3.0)
     m = O.Model(prm)
     rho, u, _ = taylor_green_3d(n, dx, 0.02, m.cs2, with_pressure=False)
-    steps = 200
+    steps = 1000
     f = m.step(m.init(rho, u), steps)
     r, uu = m.macroscopic(f)
     return prm, rho, u, steps, r, uu
