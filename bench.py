@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+CONFIG_KEYS = ("threads", "tile_nodes", "blocks_per_cu", "persistent", "nodes_per_thread")
 
 # HBM bytes per launch of the headline step kernel from the rocprofv3 FETCH_SIZE
 # and WRITE_SIZE passes (profiles/k_step_q19_f32dev_256x256x128_pmc.md), scaled
@@ -324,7 +325,7 @@ def bench_batch(torch, R, steps, warmup):
     fin = all(math.isfinite(v) for v in red)
     e = lattice_entry(f"rD3Q27 batch of 64 force-driven channels (seed 4), {total} nodes, FP32-dev AA, "
                       f"one persistent launch per step", 27, "f32dev", total, steps, wall, ev_ms)
-    e["autotuned_config"] = dict(zip(("threads", "tile_nodes", "blocks_per_cu", "persistent"), R.Batch.configs()[cfg]))
+    e["autotuned_config"] = dict(zip(CONFIG_KEYS, R.Batch.configs()[cfg]))
     e["finite"] = fin
     b.close()
     del b
@@ -361,8 +362,7 @@ def warmstart_study(torch, args):
         b = S.make_batch(geoms)
         if cfg is None:
             cfg = b.autotune(steps=20)
-            record("autotune", config=dict(zip(("threads", "tile_nodes", "blocks_per_cu", "persistent"),
-                                                b.configs()[cfg])))
+            record("autotune", config=dict(zip(CONFIG_KEYS, b.configs()[cfg])))
         else:
             b.set_config(cfg)
         rho, u = S.initial_fields(geoms)

@@ -208,14 +208,16 @@ int rmrt_steps_taken(const rmrt_ctx* ctx, long long* steps);
  */
 #define RMRT_LAUNCH_XCD_ORDER 1
 #define RMRT_LAUNCH_PERSISTENT 2
+#define RMRT_LAUNCH_WIDE_TILES 4   /* 512-node tiles, two nodes per thread read before either collides */
 int rmrt_set_launch(rmrt_ctx* ctx, int blocks_per_cu, int flags);
 int rmrt_get_launch(const rmrt_ctx* ctx, int* blocks_per_cu, int* flags);
 
 /*
  * Time rmrt_step over `steps` steps for one workgroup per tile with the
- * residency cap blocks_per_cu in {0 (none), 2, 3, 4, 5, 6, 8} (HIP events on
- * stream), keep the fastest and return it in *blocks_per_cu (may be NULL).
- * The timing runs advance the state.
+ * residency cap blocks_per_cu in {0 (none), 2, 3, 4, 5, 6, 8}, with 256- and
+ * 512-node tiles (HIP events on stream), keep the fastest and return its cap
+ * in *blocks_per_cu (may be NULL; rmrt_get_launch gives the flags).  The
+ * timing runs advance the state.
  */
 int rmrt_tune(rmrt_ctx* ctx, int steps, void* stream, int* blocks_per_cu);
 
@@ -253,11 +255,14 @@ int rmrt_batch_set_config(rmrt_batch* b, int cfg);
 int rmrt_batch_num_configs(void);
 /*
  * Describe configuration cfg: threads per workgroup, nodes per tile, workgroups
- * per CU and whether the grid is persistent (1: cus * blocks_per_cu workgroups
+ * per CU, whether the grid is persistent (1: cus * blocks_per_cu workgroups
  * walk the tile list in XCD-contiguous order; 0: one workgroup per tile with
- * residency capped at blocks_per_cu per CU, 0 = no cap).
+ * residency capped at blocks_per_cu per CU, 0 = no cap) and nodes per thread
+ * per pass (2: each thread reads two nodes before colliding either).  Any
+ * output pointer may be NULL.
  */
-int rmrt_batch_config_info(int cfg, int* threads, int* tile_nodes, int* blocks_per_cu, int* persistent);
+int rmrt_batch_config_info(int cfg, int* threads, int* tile_nodes, int* blocks_per_cu, int* persistent,
+                           int* nodes_per_thread);
 
 /* Advance every domain nsteps steps (graph replay of persistent launches). */
 int rmrt_batch_step(rmrt_batch* b, int nsteps, void* stream);

@@ -281,6 +281,30 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C) {
     if constexpr (D == 3) t[szz] -= rz;
   }
 
+  // Every other moment relaxes as m* = m - r (m - eq) + src.  g_eq is linear
+  // in its arguments, so with eq = g_eq(e) and src = g_eq(s) this is
+  // m* = (1 - r) m + g_eq(r e + s): one table evaluation per moment, with the
+  // combined arguments formed once per rate.
+  auto combine = [&](T r, T& cA, T (&cB)[3], T (&cMd)[3], T (&cMo)[3]) {
+    cA = r * eA;
+    for (int k = 0; k < 3; ++k) {
+      cB[k] = r * eB[k];
+      cMd[k] = r * eMd[k];
+      cMo[k] = r * eMo[k];
+    }
+    if constexpr (FORCE) {
+      cA += sA;
+      for (int k = 0; k < 3; ++k) {
+        cB[k] += sB[k];
+        cMd[k] += sMd[k];
+        cMo[k] += sMo[k];
+      }
+    }
+  };
+  T hA, hB[3], hMd[3], hMo[3];       // higher moments, rate s_hi
+  combine(C.s_hi, hA, hB, hMd, hMo);
+  const T keep_hi = T(1) - C.s_hi;
+
   static_for<0, NS>([&](auto n_) {
     constexpr int n = decltype(n_)::value;
     constexpr int a = n % 3, b = (n / 3) % 3, p = n / 9;
@@ -288,31 +312,21 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C) {
     constexpr bool diag2 = (n == sxx || n == syy || n == szz);
     if constexpr (Lat<L>::dropped(n)) {
       t[n] = T(0);
+    } else if constexpr (ord == 0 || (EQ == EQ_NSE && (ord == 1 || diag2))) {
+      // conserved (eq. 4-18-1), or NSE momentum (its rate is irrelevant), or
+      // the diagonal second moments relaxed above: only the source is added
+      if constexpr (FORCE) t[n] += gmom<L, n>(C, sA, sB, sMd, sMo);
+    } else if constexpr (EQ == EQ_NSE && ord == 2) {
+      constexpr int pr = (p == 0) ? 0 : ((a == 1) ? 1 : 2);
+      T cA, cB[3], cMd[3], cMo[3];
+      combine(C.s_off[pr], cA, cB, cMd, cMo);
+      t[n] = (T(1) - C.s_off[pr]) * t[n] + gmom<L, n>(C, cA, cB, cMd, cMo);
+    } else if constexpr (EQ == EQ_NCDE && ord == 1) {
+      T cA, cB[3], cMd[3], cMo[3];
+      combine(s1, cA, cB, cMd, cMo);
+      t[n] = (T(1) - s1) * t[n] + gmom<L, n>(C, cA, cB, cMd, cMo);
     } else {
-      T src = T(0);
-      if constexpr (FORCE) src = gmom<L, n>(C, sA, sB, sMd, sMo);
-      if constexpr (ord == 0) {
-        t[n] += src;                                   // conserved (eq. 4-18-1)
-      } else if constexpr (ord == 1) {
-        if constexpr (EQ == EQ_NSE) {
-          t[n] += src;                                 // conserved; rate irrelevant
-        } else {
-          const T eq = gmom<L, n>(C, eA, eB, eMd, eMo);
-          t[n] = t[n] - s1 * (t[n] - eq) + src;
-        }
-      } else if constexpr (EQ == EQ_NSE && diag2) {
-        t[n] += src;                                   // relaxed above
-      } else {
-        T rate;
-        if constexpr (EQ == EQ_NSE && ord == 2) {
-          constexpr int pr = (p == 0) ? 0 : ((a == 1) ? 1 : 2);
-          rate = C.s_off[pr];
-        } else {
-          rate = C.s_hi;
-        }
-        const T eq = gmom<L, n>(C, eA, eB, eMd, eMo);
-        t[n] = t[n] - rate * (t[n] - eq) + src;
-      }
+      t[n] = keep_hi * t[n] + gmom<L, n>(C, hA, hB, hMd, hMo);
     }
   });
 

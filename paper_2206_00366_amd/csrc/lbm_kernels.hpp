@@ -26,6 +26,29 @@ namespace rmrt {
 #define RMRT_WALL_ZM 16u
 #define RMRT_WALL_ZP 32u
 
+// Buffers reach the kernels through the parameter block, so the compiler
+// cannot see that they live in global memory; casting them to address space 1
+// turns flat loads/stores (64-bit addresses, both wait counters) into global
+// ones with a scalar base and a 32-bit lane offset.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gmem<T>* to_global(T* p) {
+  return (gmem<T>*)p;
+}
+template <typename T>
+__device__ __forceinline__ const gmem<T>* to_global(const T* p) {
+  return (const gmem<T>*)p;
+}
+
+// Element i of one population stream (a per-lane 64-bit address: a scalar
+// base plus 32-bit offset form needs 2 q live scalar registers per node and
+// spills them).
+template <typename T>
+__device__ __forceinline__ T ld_elem(const gmem<T>* base, uint32_t i) { return base[i]; }
+template <typename T>
+__device__ __forceinline__ void st_elem(gmem<T>* base, uint32_t i, T v) { base[i] = v; }
+
 // exact n / d for n < 2^32 with m = floor(2^32 / d) (0xffffffff for d = 1)
 __device__ __forceinline__ uint32_t fast_div(uint32_t n, uint32_t d, uint32_t m, uint32_t& r) {
   uint32_t q = __umulhi(n, m);
@@ -95,7 +118,7 @@ struct Geo {
     if constexpr (ey > 0) b = b || hi[1];
     if constexpr (ez < 0) b = b || lo[2];
     if constexpr (ez > 0) b = b || hi[2];
-    if (Dm.has_solid) b = b || (Dm.solid[idx + (uint32_t)off<L, J>()] != 0);
+    if (Dm.has_solid) b = b || (to_global(Dm.solid)[idx + (uint32_t)off<L, J>()] != 0);
     return b;
   }
 };
@@ -131,72 +154,90 @@ __device__ __forceinline__ size_t read_elem(const DomainDev& Dm, const Geo<D>& g
 // tiles of `tile_nodes` nodes with one tile per workgroup.
 // ----------------------------------------------------------------------------
 template <int L, int ST, int EQ, bool FORCE, int BC, int PH>
-__device__ __forceinline__ void step_node(const DomainDev& Dm, const Coef<typename Store<ST>::T>& C,
-                                          typename Store<ST>::S* fin, typename Store<ST>::S* fout,
-                                          uint32_t idx) {
+struct NodeStep {
   using SS = Store<ST>;
   using S = typename SS::S;
   using T = typename SS::T;
-  constexpr int Q = Lat<L>::Q, NS = Lat<L>::NS, D = Lat<L>::D;
   using LW = typename LinkBits<L>::W;
-  LW lb = 0;
-  if constexpr (BC == 1) {
-    if (Dm.has_solid && Dm.solid[idx]) return;
-  } else if constexpr (BC == 2) {
-    lb = ((const LW*)Dm.links)[idx];
-    if (lb & LinkBits<L>::kSolid) return;
-  }
-  Geo<D> g;
-  if constexpr (PH != PH_AA_EVEN) g.make(Dm, idx);
-  const uint32_t N = Dm.N;
+  static constexpr int Q = Lat<L>::Q, NS = Lat<L>::NS, D = Lat<L>::D;
+
   T t[NS];
-  static_for<0, NS>([&](auto s_) {
-    constexpr int s = decltype(s_)::value;
-    if constexpr (Lat<L>::absent(s)) t[s] = T(0);
-  });
-  // gather
-  static_for<0, Q>([&](auto j_) {
-    constexpr int J = decltype(j_)::value;
-    S v;
-    if constexpr (PH == PH_AA_ODD && BC == 2) {
+  Geo<D> g;
+  LW lb;
+  uint32_t idx;
+  bool live;   // a fluid node to update
+
+  // Read the q populations of node idx_ (nothing for solid or invalid nodes).
+  __device__ __forceinline__ void load(const DomainDev& Dm, const Coef<T>& C, const gmem<S>* fin, uint32_t idx_,
+                                       bool valid) {
+    idx = idx_;
+    live = valid;
+    lb = 0;
+    if constexpr (BC == 1) {
+      if (live && Dm.has_solid && to_global(Dm.solid)[idx]) live = false;
+    } else if constexpr (BC == 2) {
+      if (live) {
+        lb = to_global((const LW*)Dm.links)[idx];
+        if (lb & LinkBits<L>::kSolid) live = false;
+      }
+    }
+    if (!live) return;
+    if constexpr (PH != PH_AA_EVEN) g.make(Dm, idx);
+    const uint32_t N = Dm.N;
+    static_for<0, NS>([&](auto s_) {
+      constexpr int s = decltype(s_)::value;
+      if constexpr (Lat<L>::absent(s)) t[s] = T(0);
+    });
+    static_for<0, Q>([&](auto j_) {
+      constexpr int J = decltype(j_)::value;
+      S v;
+      if constexpr (PH == PH_AA_ODD) {
+        // swapped layout: the value for direction J sits in slot O of the
+        // upstream node, or in this node's own slot J when that link bounced
+        constexpr int O = Lat<L>::opp(J);
+        bool b = false;
+        if constexpr (BC == 2)
+          b = (lb >> O) & 1;
+        else if constexpr (BC == 1)
+          b = g.template bounce<L, O>(Dm, idx);
+        if (b)
+          v = ld_elem(fin + (size_t)J * N, idx);
+        else
+          v = ld_elem(fin + (size_t)O * N, (uint32_t)(idx + (uint32_t)g.template off<L, O>()));
+      } else {
+        v = ld_elem(fin + (size_t)J * N, idx);
+      }
+      t[Lat<L>::slot(J)] = SS::template dec<J>(v, C);
+    });
+  }
+
+  // Collide and write the q post-collision populations.
+  __device__ __forceinline__ void finish(const DomainDev& Dm, const Coef<T>& C, gmem<S>* fout) {
+    if (!live) return;
+    collide<L, EQ, FORCE>(t, C);
+    const uint32_t N = Dm.N;
+    static_for<0, Q>([&](auto j_) {
+      constexpr int J = decltype(j_)::value;
       constexpr int O = Lat<L>::opp(J);
-      const size_t e = ((lb >> O) & 1) ? (size_t)J * N + idx
-                                       : (size_t)O * N + (uint32_t)(idx + (uint32_t)g.template off<L, O>());
-      v = fin[e];
-    } else if constexpr (PH == PH_AA_ODD) {
-      v = fin[read_elem<L, BC, true, J>(Dm, g, idx)];
-    } else {
-      const S* __restrict__ pj = fin + (size_t)J * N;
-      v = pj[idx];
-    }
-    t[Lat<L>::slot(J)] = SS::template dec<J>(v, C);
-  });
-
-  collide<L, EQ, FORCE>(t, C);
-
-  // scatter
-  static_for<0, Q>([&](auto j_) {
-    constexpr int J = decltype(j_)::value;
-    constexpr int O = Lat<L>::opp(J);
-    const S v = SS::template enc<J>(t[Lat<L>::slot(J)], C);
-    if constexpr (PH == PH_AA_EVEN) {
-      S* __restrict__ po = fout + (size_t)O * N;
-      po[idx] = v;
-    } else if constexpr (BC == 0) {
-      S* __restrict__ pj = fout + (size_t)J * N;
-      pj[(uint32_t)(idx + (uint32_t)g.template off<L, J>())] = v;
-    } else {
-      bool b;
-      if constexpr (BC == 2)
-        b = (lb >> J) & 1;
-      else
-        b = g.template bounce<L, J>(Dm, idx);
-      const size_t e = b ? (size_t)O * N + idx
-                         : (size_t)J * N + (uint32_t)(idx + (uint32_t)g.template off<L, J>());
-      fout[e] = v;
-    }
-  });
-}
+      const S v = SS::template enc<J>(t[Lat<L>::slot(J)], C);
+      if constexpr (PH == PH_AA_EVEN) {
+        st_elem(fout + (size_t)O * N, idx, v);
+      } else if constexpr (BC == 0) {
+        st_elem(fout + (size_t)J * N, (uint32_t)(idx + (uint32_t)g.template off<L, J>()), v);
+      } else {
+        bool b;
+        if constexpr (BC == 2)
+          b = (lb >> J) & 1;
+        else
+          b = g.template bounce<L, J>(Dm, idx);
+        if (b)
+          st_elem(fout + (size_t)O * N, idx, v);
+        else
+          st_elem(fout + (size_t)J * N, (uint32_t)(idx + (uint32_t)g.template off<L, J>()), v);
+      }
+    });
+  }
+};
 
 __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
   // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
@@ -212,9 +253,12 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
 // so that the tiles resident at one time on an XCD are neighbours; the grid
 // size is the occupancy knob (fewer resident waves keep the q concurrent
 // address streams per wave from oversubscribing HBM).
-enum : uint32_t { STEP_XCD_ORDER = 1u, STEP_PERSISTENT = 2u };
+enum : uint32_t { STEP_XCD_ORDER = 1u, STEP_PERSISTENT = 2u, STEP_WIDE_TILES = 4u };
 
-template <int L, int ST, int EQ, bool FORCE, int BC, int PH>
+// NPT nodes per thread per pass (1, or 2 with tiles of 2 blockDim nodes: both
+// nodes are read before either collides, so each wave keeps 2 q loads in
+// flight).
+template <int L, int ST, int EQ, bool FORCE, int BC, int PH, int NPT>
 __global__ void __launch_bounds__(256)
     k_step(const DomainDev* __restrict__ doms, const Tile* __restrict__ tiles, uint32_t ntiles,
            uint32_t tile_nodes, uint32_t parity, uint32_t flags) {
@@ -252,10 +296,10 @@ __global__ void __launch_bounds__(256)
     }
     const DomainDev& Dm = doms[dom];
     const Coef<T>& C = coef<T>(Dm);
-    S* fa = (S*)Dm.fa;
-    S* fb = (S*)Dm.fb;
-    S* fin;
-    S* fout;
+    gmem<S>* fa = to_global((S*)Dm.fa);
+    gmem<S>* fb = to_global((S*)Dm.fb);
+    gmem<S>* fin;
+    gmem<S>* fout;
     if constexpr (PH == PH_AB) {
       fin = parity ? fb : fa;
       fout = parity ? fa : fb;
@@ -263,8 +307,23 @@ __global__ void __launch_bounds__(256)
       fin = fa;
       fout = fa;
     }
-    for (uint32_t i = threadIdx.x; i < count; i += blockDim.x)
-      step_node<L, ST, EQ, FORCE, BC, PH>(Dm, C, fin, fout, start + i);
+    using NSp = NodeStep<L, ST, EQ, FORCE, BC, PH>;
+    if constexpr (NPT == 2) {
+      for (uint32_t i = threadIdx.x; i < count; i += 2 * blockDim.x) {
+        const uint32_t i1 = i + blockDim.x;
+        NSp a, b;
+        a.load(Dm, C, fin, start + i, true);
+        b.load(Dm, C, fin, start + (i1 < count ? i1 : i), i1 < count);
+        a.finish(Dm, C, fout);
+        b.finish(Dm, C, fout);
+      }
+    } else {
+      for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) {
+        NSp a;
+        a.load(Dm, C, fin, start + i, true);
+        a.finish(Dm, C, fout);
+      }
+    }
   }
 }
 

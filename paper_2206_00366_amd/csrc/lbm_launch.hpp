@@ -7,8 +7,12 @@ namespace rmrt {
 
 template <int L, int ST, int EQ, bool F, int BC, int PH>
 hipError_t do_step(const StepLaunch& a) {
-  hipLaunchKernelGGL((k_step<L, ST, EQ, F, BC, PH>), dim3(a.grid), dim3(a.block), a.lds_bytes, a.stream, a.doms,
-                     a.tiles, a.ntiles, a.tile_nodes, a.parity, a.flags);
+  if (a.flags & STEP_WIDE_TILES)
+    hipLaunchKernelGGL((k_step<L, ST, EQ, F, BC, PH, 2>), dim3(a.grid), dim3(a.block), a.lds_bytes, a.stream,
+                       a.doms, a.tiles, a.ntiles, a.tile_nodes, a.parity, a.flags);
+  else
+    hipLaunchKernelGGL((k_step<L, ST, EQ, F, BC, PH, 1>), dim3(a.grid), dim3(a.block), a.lds_bytes, a.stream,
+                       a.doms, a.tiles, a.ntiles, a.tile_nodes, a.parity, a.flags);
   return hipGetLastError();
 }
 template <int L, int ST, int EQ, bool F, int BC>

@@ -363,10 +363,15 @@ constexpr uint32_t kDefaultFlags = 0u;
 void default_launch(const rmrt_params& p, int& blocks_per_cu, uint32_t& flags) {
   blocks_per_cu = 0;
   flags = 0u;
+  // measured on MI355X at 256 x 256 x 128: FP32/FP64 3D gain from a cap of 3
+  // workgroups per CU; FP16 rD3Q19 from two nodes per thread (its 128-byte
+  // wave loads leave too few bytes in flight with one)
   if (p.lattice == RMRT_Q9) {
     flags = STEP_XCD_ORDER;
   } else if (p.storage != RMRT_F16DEV) {
     blocks_per_cu = 3;
+  } else if (p.lattice == RMRT_Q19) {
+    flags = STEP_WIDE_TILES;
   }
 }
 constexpr uint32_t kLdsPerCU = 160u * 1024u;  // gfx950 LDS per compute unit
@@ -505,7 +510,7 @@ int launch_one_step(rmrt_ctx* c, long long step_index, hipStream_t s) {
   std::memset(&a, 0, sizeof(a));
   a.doms = c->ddoms + c->dom;
   a.tiles = nullptr;
-  a.tile_nodes = 256;
+  a.tile_nodes = (c->flags & STEP_WIDE_TILES) ? 512 : 256;
   a.ntiles = (c->hdom.N + a.tile_nodes - 1) / a.tile_nodes;
   a.flags = c->flags;
   a.parity = (uint32_t)(step_index & 1);
@@ -812,7 +817,7 @@ int rmrt_steps_taken(const rmrt_ctx* c, long long* steps) {
 int rmrt_set_launch(rmrt_ctx* c, int blocks_per_cu, int flags) {
   if (!c) return fail(RMRT_EINVAL, "ctx is NULL");
   if (blocks_per_cu < 0 || blocks_per_cu > 32) return fail(RMRT_EINVAL, "blocks_per_cu must be in [0, 32]");
-  if (flags & ~3) return fail(RMRT_EINVAL, "unknown launch flags 0x%x", flags);
+  if (flags & ~7) return fail(RMRT_EINVAL, "unknown launch flags 0x%x", flags);
   if (blocks_per_cu == 1 && !(flags & STEP_PERSISTENT))
     return fail(RMRT_EINVAL, "a residency cap of 1 workgroup per CU is not supported (use >= 2)");
   c->blocks_per_cu = blocks_per_cu;
@@ -838,10 +843,12 @@ int rmrt_tune(rmrt_ctx* c, int steps, void* stream, int* blocks_per_cu) {
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  int best = kDefaultBlocksPerCU;
+  int best = kDefaultBlocksPerCU, best_flags = 0;
   float best_ms = 1e30f;
+  for (int wide = 0; wide < 2; ++wide)
   for (int k : cands) {
-    int rc = rmrt_set_launch(c, k, 0);
+    const int fl = wide ? (int)STEP_WIDE_TILES : 0;
+    int rc = rmrt_set_launch(c, k, fl);
     if (rc == RMRT_OK) rc = step_impl(c, 2, s);
     if (rc == RMRT_OK) rc = step_impl(c, steps, s);
     if (rc != RMRT_OK) {
@@ -859,12 +866,13 @@ int rmrt_tune(rmrt_ctx* c, int steps, void* stream, int* blocks_per_cu) {
     if (ms < best_ms) {
       best_ms = ms;
       best = k;
+      best_flags = fl;
     }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (blocks_per_cu) *blocks_per_cu = best;
-  return rmrt_set_launch(c, best, 0);
+  return rmrt_set_launch(c, best, best_flags);
 }
 
 int rmrt_free(rmrt_ctx* c) {
@@ -886,12 +894,15 @@ struct TileConfig {
   int threads, tile_nodes, blocks_per_cu;  // blocks_per_cu <= 0: one workgroup per tile
   int persistent;  // 1: persistent grid of blocks_per_cu per CU; 0: one workgroup per tile,
                    //    blocks_per_cu > 0 caps residency through dynamic LDS
+  int nodes_per_thread;  // 1, or 2: two nodes read before either collides
 };
 // threads per block never exceed the kernels' launch bound of 256
 constexpr int kMaxThreads = 256;
 const TileConfig kTileShapes[] = {
-    {256, 256, 0, 0},  {256, 256, 2, 0},  {256, 256, 3, 0},  {256, 256, 4, 0},  {256, 256, 2, 1},
-    {256, 256, 3, 1},  {256, 1024, 2, 1}, {256, 1024, 4, 1}, {256, 2048, 8, 1}, {128, 512, 4, 1},
+    {256, 256, 0, 0, 1},  {256, 256, 2, 0, 1},  {256, 256, 3, 0, 1},  {256, 256, 4, 0, 1},
+    {256, 256, 2, 1, 1},  {256, 256, 3, 1, 1},  {256, 1024, 2, 1, 1}, {256, 1024, 4, 1, 1},
+    {256, 2048, 8, 1, 1}, {128, 512, 4, 1, 1},  {256, 512, 0, 0, 2},  {256, 512, 2, 0, 2},
+    {256, 512, 3, 0, 2},  {256, 512, 4, 0, 2},  {256, 1024, 2, 1, 2}, {256, 1024, 3, 1, 2},
 };
 constexpr int kNumTileShapes = sizeof(kTileShapes) / sizeof(kTileShapes[0]);
 
@@ -959,6 +970,7 @@ int batch_launch(rmrt_batch* b, long long step_index, hipStream_t s) {
   a.phase = b->pattern == RMRT_AB ? PH_AB : ((step_index & 1) ? PH_AA_ODD : PH_AA_EVEN);
   if (tc.threads > kMaxThreads) return fail(RMRT_EINVAL, "config uses %d threads > %d", tc.threads, kMaxThreads);
   a.flags = (tc.persistent && tc.blocks_per_cu > 0) ? (STEP_PERSISTENT | STEP_XCD_ORDER) : 0u;
+  if (tc.nodes_per_thread == 2) a.flags |= STEP_WIDE_TILES;
   a.grid = persistent_grid(b->ntiles, b->cus, tc.blocks_per_cu, a.flags);
   a.lds_bytes = residency_lds(tc.blocks_per_cu, a.flags);
   a.block = (unsigned)tc.threads;
@@ -1042,8 +1054,10 @@ extern "C" {
 
 int rmrt_batch_num_configs(void) { return kNumTileShapes; }
 
-int rmrt_batch_config_info(int cfg, int* threads, int* tile_nodes, int* blocks_per_cu, int* persistent) {
+int rmrt_batch_config_info(int cfg, int* threads, int* tile_nodes, int* blocks_per_cu, int* persistent,
+                           int* nodes_per_thread) {
   if (cfg < 0 || cfg >= kNumTileShapes) return fail(RMRT_EINVAL, "config %d out of range", cfg);
+  if (nodes_per_thread) *nodes_per_thread = kTileShapes[cfg].nodes_per_thread;
   if (threads) *threads = kTileShapes[cfg].threads;
   if (tile_nodes) *tile_nodes = kTileShapes[cfg].tile_nodes;
   if (blocks_per_cu) *blocks_per_cu = kTileShapes[cfg].blocks_per_cu;

@@ -31,7 +31,7 @@ NSE, NCDE = 0, 1
 F64, F32DEV, F16DEV = 0, 1, 2
 AB, AA = 0, 1
 OUT_F64, OUT_F32 = 0, 1
-LAUNCH_XCD_ORDER, LAUNCH_PERSISTENT = 1, 2
+LAUNCH_XCD_ORDER, LAUNCH_PERSISTENT, LAUNCH_WIDE_TILES = 1, 2, 4
 WALL_XM, WALL_XP, WALL_YM, WALL_YP, WALL_ZM, WALL_ZP = 1, 2, 4, 8, 16, 32
 
 LATTICES = {"Q9": Q9, "Q19": Q19, "Q27": Q27}
@@ -85,7 +85,7 @@ _sig = {
     "rmrt_batch_set_config": (C.c_int, [_vp, C.c_int]),
     "rmrt_batch_num_configs": (C.c_int, []),
     "rmrt_batch_config_info": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                          C.POINTER(C.c_int)]),
+                                          C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "rmrt_batch_step": (C.c_int, [_vp, C.c_int, _vp]),
     "rmrt_batch_residual": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
     "rmrt_batch_free": (C.c_int, [_vp]),
@@ -339,10 +339,10 @@ class Batch:
     def configs():
         out = []
         for k in range(_lib.rmrt_batch_num_configs()):
-            t, n, b, p = C.c_int(), C.c_int(), C.c_int(), C.c_int()
-            _check(_lib.rmrt_batch_config_info(k, C.byref(t), C.byref(n), C.byref(b), C.byref(p)),
+            t, n, b, p, w = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_int()
+            _check(_lib.rmrt_batch_config_info(k, C.byref(t), C.byref(n), C.byref(b), C.byref(p), C.byref(w)),
                    "rmrt_batch_config_info")
-            out.append((t.value, n.value, b.value, p.value))
+            out.append((t.value, n.value, b.value, p.value, w.value))
         return out
 
     def close(self):

@@ -72,6 +72,8 @@ def test_population_bytes():
     dict(lattice="Q9", n=(8, 8, 1), equation="NCDE", D0=0.0),
     dict(lattice="Q9", n=(0, 8, 1)),
     dict(lattice="Q9", n=(8, 8, 1), dx=(0.0, 1.0, 1.0)),
+    dict(lattice="Q9", n=(8, 8, 1), nu=0.1, s_hi=2.5),                  # rate outside (0, 2)
+    dict(lattice="Q19", n=(4, 4, 4), nu=0.1, nu_b=0.0),
 ])
 def test_invalid_parameters_rejected(bad):
     with pytest.raises(rmrt.RMRTError) as ei:
@@ -93,9 +95,10 @@ def test_init_argument_errors_need_no_gpu():
 def test_batch_configs_within_launch_bound():
     cfgs = rmrt.Batch.configs()
     assert len(cfgs) >= 4
-    for threads, tile_nodes, per_cu, persistent in cfgs:
+    for threads, tile_nodes, per_cu, persistent, npt in cfgs:
         assert 64 <= threads <= 256 and threads % 64 == 0
-        assert tile_nodes >= threads
+        assert npt in (1, 2)
+        assert tile_nodes >= npt * threads
         assert persistent in (0, 1)
         assert persistent == 0 or per_cu >= 1
         assert per_cu != 1 or persistent == 1
@@ -110,3 +113,52 @@ def test_single_hip_runtime_in_process():
             "print(len(set(l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l)))")
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert out.stdout.strip() == "1", out.stdout + out.stderr
+
+
+def test_header_is_valid_c(tmp_path):
+    """include/rmrt.h compiles as C99 and its declarations link against the library."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "t.c"
+    src.write_text('#include "rmrt.h"\n#include <stdio.h>\n'
+                   "int main(void) {\n"
+                   "  rmrt_params p = {0}; rmrt_derived d;\n"
+                   "  p.lattice = RMRT_Q19; p.n[0] = p.n[1] = p.n[2] = 4; p.dx[0] = p.dx[1] = 1; p.dx[2] = 2;\n"
+                   "  p.nu = 0.01; p.nu_b = -1; p.cs2 = -1; p.s_hi = -1; p.w_corner = -1;\n"
+                   "  int rc = rmrt_derive(&p, &d);\n"
+                   "  printf(\"%d %d %.17g\\n\", rc, d.q, d.w[0]);\n"
+                   "  return rc;\n}\n")
+    exe = tmp_path / "t"
+    inc = os.path.join(ROOT, "include")
+    libdir = os.path.dirname(rmrt.LIB_PATH)
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", inc, str(src), "-L", libdir, "-lrmrt",
+                        f"-Wl,-rpath,{libdir}", "-o", str(exe)], capture_output=True, text=True)
+    if r.returncode != 0 and "cannot find -lrmrt" in r.stderr:
+        # the library is named librmrt.so: link it by path
+        r = subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", inc, str(src), rmrt.LIB_PATH,
+                            f"-Wl,-rpath,{libdir}", "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    rc, q, w0 = out.stdout.split()
+    m = O.Model(dict(lattice="Q19", n=(4, 4, 4), dx=(1.0, 1.0, 2.0), nu=0.01))
+    assert int(q) == 19 and abs(float(w0) - m.w[0]) < 1e-15
+
+
+def test_batch_rejects_mixed_lattices_without_gpu():
+    ps = (rmrt.Params * 2)(rmrt.make_params(lattice="Q19", n=(4, 4, 4)), rmrt.make_params(lattice="Q27", n=(4, 4, 4)))
+    f0 = (ctypes.c_void_p * 2)(16, 16)
+    f1 = (ctypes.c_void_p * 2)(16, 16)
+    b = ctypes.c_void_p()
+    assert rmrt.lib().rmrt_batch_create(ctypes.byref(b), 2, ps, f0, f1, None, None) == rmrt.EINVAL
+    assert b.value is None
+
+
+def test_domains_beyond_32bit_indexing_are_refused():
+    with pytest.raises(rmrt.RMRTError) as ei:
+        rmrt.derive(rmrt.make_params(lattice="Q27", n=(1024, 1024, 256), nu=0.05))
+    assert ei.value.code == rmrt.EUNSUPPORTED
+    rmrt.derive(rmrt.make_params(lattice="Q27", n=(512, 512, 512), nu=0.05))   # 27 * 2^27 < 2^32

@@ -45,6 +45,7 @@ CASES = {
     "q19_ncde": (dict(lattice="Q19", equation="NCDE", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), D0=0.02, D2=0.5,
                       adv=(0.03, -0.01, 0.02), rho0=0.0), None, 15),
     "q27_periodic": (dict(lattice="Q27", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), nu=0.05, nu_b=0.01), None, 15),
+    "q19_standard_lattice": (dict(lattice="Q19", n=(12, 10, 9), dx=(1.0, 1.0, 1.0), cs2=1.0 / 3.0, nu=0.02), None, 15),
     "q27_channel_solid_force": (dict(lattice="Q27", n=(14, 9, 8), dx=(1.0, 2.0, 1.0), nu=0.05,
                                      force=(1e-5, 0.0, 0.0), source=-1e-6, wall_faces=WALLS["yz"],
                                      w_corner=0.0008), lambda n: circle_mask(n, (6, 4), 2), 15),
@@ -111,6 +112,24 @@ def test_aa_equals_ab_bitwise(rmrt, case, storage):
         dom.close()
     for a, b in zip(out["AB"], out["AA"]):
         assert np.array_equal(a[:, m.fluid], b[:, m.fluid])
+
+
+@pytest.mark.parametrize("pattern", ["AB", "AA"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_two_nodes_per_thread_is_bitwise_identical(rmrt, case, pattern):
+    """The paired-node launch (both nodes read before either collides, ragged
+    last tile, solid nodes skipped per node) writes exactly what the one-node
+    launch writes."""
+    say(f"[two nodes per thread] {case} {pattern}")
+    out = []
+    for fl in (0, rmrt.LAUNCH_WIDE_TILES, rmrt.LAUNCH_WIDE_TILES | rmrt.LAUNCH_PERSISTENT):
+        m, dom, rho, u, steps = _build(case, rmrt, "f32dev", pattern)
+        dom.set_launch(1 if fl & rmrt.LAUNCH_PERSISTENT else 0, fl)
+        dom.step(steps)
+        out.append(dom.populations().cpu().numpy())
+        dom.close()
+    for g in out[1:]:
+        assert np.array_equal(g[:, m.fluid], out[0][:, m.fluid])
 
 
 @pytest.mark.parametrize("storage,tol", [("f32dev", 1e-5), ("f16dev", 3e-3)])
@@ -342,8 +361,9 @@ def test_launch_shapes_agree_and_match_oracle(rmrt):
     rho, u = random_fields(m, 21)
     f_or = m.step(m.init(rho, u), 9)
     ref = None
-    P, X = rmrt.LAUNCH_PERSISTENT, rmrt.LAUNCH_XCD_ORDER
-    for bpc, fl in [(0, 0), (0, X), (3, 0), (8, 0), (1, P | X), (2, P | X), (3, P), (8, P | X)]:
+    P, X, Wd = rmrt.LAUNCH_PERSISTENT, rmrt.LAUNCH_XCD_ORDER, rmrt.LAUNCH_WIDE_TILES
+    for bpc, fl in [(0, 0), (0, X), (3, 0), (8, 0), (1, P | X), (2, P | X), (3, P), (8, P | X), (0, Wd),
+                    (3, Wd | X), (2, Wd | P | X)]:
         dom = rmrt.Domain(rmrt.make_params(**prm, storage="f64", pattern="AA"), rho, u)
         dom.set_launch(bpc, fl)
         assert dom.get_launch() == (bpc, fl)
@@ -366,7 +386,44 @@ def test_tune_picks_a_valid_shape(rmrt):
     dom = rmrt.Domain(rmrt.make_params(**prm, storage="f32dev", pattern="AA"), np.ones(N), np.zeros((3, N)))
     k = dom.tune(steps=4)
     assert k in (0, 2, 3, 4, 5, 6, 8)
-    assert dom.get_launch() == (k, 0)
+    bpc, fl = dom.get_launch()
+    assert bpc == k and fl in (0, rmrt.LAUNCH_WIDE_TILES)
     r = dom.reduce()
     assert abs(r[0] - N) < 1e-6 * N
+    dom.close()
+
+
+def test_q27_with_zero_corner_weight_matches_q19(rmrt):
+    """Cross-lattice check of the embedded rD3Q19 transform: rD3Q27 with
+    omega_19 = 0 reproduces rD3Q19 and keeps its corners at zero."""
+    say("[q27 w19=0 vs q19]")
+    prm = dict(n=(13, 11, 9), dx=(1.0, 0.5, 2.0), nu=0.03, nu_b=0.07, force=(1e-5, 2e-5, 0.0))
+    m = O.Model(dict(prm, lattice="Q19"))
+    rho, u = random_fields(m, 17)
+    d19 = rmrt.Domain(rmrt.make_params(**prm, lattice="Q19", storage="f64", pattern="AA"), rho, u)
+    d27 = rmrt.Domain(rmrt.make_params(**prm, lattice="Q27", w_corner=0.0, storage="f64", pattern="AA"), rho, u)
+    d19.step(11)
+    d27.step(11)
+    g19 = d19.populations().cpu().numpy()
+    g27 = d27.populations().cpu().numpy()
+    assert np.abs(g27[:19] - g19).max() < 1e-13
+    assert np.abs(g27[19:]).max() < 1e-13
+    d19.close()
+    d27.close()
+
+
+@pytest.mark.parametrize("lat,n", [("Q27", (1, 1, 1)), ("Q19", (1, 3, 1)), ("Q9", (1, 1, 1)), ("Q9", (5, 1, 1))])
+def test_degenerate_single_node_extents(rmrt, lat, n):
+    """Axes of one node: every link along them wraps to the node itself."""
+    say(f"[degenerate] {lat} {n}")
+    d = 2 if lat == "Q9" else 3
+    prm = dict(lattice=lat, n=n, dx=(1.0, 0.5, 2.0)[:d] + ((1.0,) if d == 2 else ()), nu=0.04)
+    m = O.Model(prm)
+    rho, u = random_fields(m, 23)
+    f_or = m.step(m.init(rho, u), 7)
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage="f64", pattern="AA"), rho, u)
+    dom.step(0)                                   # no-op
+    assert dom.steps_taken() == 0
+    dom.step(7)
+    assert rel_err(dom.populations().cpu().numpy(), f_or) < 1e-12
     dom.close()

@@ -159,3 +159,19 @@ def test_nonequilibrium_second_moment_matches_eq_4_34_at_steady_state():
     scale = np.abs(rho * nu * dudy).max()
     assert np.abs(m2[0, 1, interior] - mne[0, 1, interior]).max() < 0.02 * scale
     assert np.abs(m2[0, 0, interior] - mne[0, 0, interior]).max() < 0.02 * scale
+
+
+def test_q27_with_zero_corner_weight_reduces_to_q19():
+    """With omega_19 = 0 the rD3Q27 model never populates its corners and its
+    other 19 populations evolve exactly as the rD3Q19 model (Sec. III: rD3Q19
+    is rD3Q27 with omega_19 = 0)."""
+    prm = dict(n=(6, 5, 4), dx=(1.0, 0.5, 2.0), nu=0.03, nu_b=0.07, force=(1e-5, 2e-5, 0.0))
+    m19 = O.Model(dict(prm, lattice="Q19"))
+    m27 = O.Model(dict(prm, lattice="Q27", w_corner=0.0))
+    rng = np.random.default_rng(13)
+    rho = 1 + 1e-3 * rng.standard_normal(m19.N)
+    u = 0.02 * rng.standard_normal((3, m19.N))
+    f19 = m19.step(m19.init(rho, u), 6)
+    f27 = m27.step(m27.init(rho, u), 6)
+    np.testing.assert_allclose(f27[:19], f19, rtol=0, atol=1e-13)
+    assert np.abs(f27[19:]).max() < 1e-13
