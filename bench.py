@@ -31,7 +31,7 @@ CONFIG_KEYS = ("threads", "tile_nodes", "blocks_per_cu", "persistent", "nodes_pe
 # and WRITE_SIZE passes (profiles/k_step_q19_f32dev_256x256x128_pmc.md), scaled
 # by the counters of a plain copy of known size.  Keyed by the hash of the
 # kernel sources the counters were taken on: any later kernel change reports null.
-MEASURED_TRAFFIC = {"c963d5fc85672ac3": 1275171502}
+MEASURED_TRAFFIC = {"98cac74b20b73bc2": 1275170838}
 KERNEL_SOURCES = ["lbm_device.hpp", "lbm_kernels.hpp", "lbm_params.hpp", "lbm_launch.hpp", "lbm_q19_f32.hip"]
 
 
@@ -291,7 +291,7 @@ def main():
         roofline["frac_of_copy_ceiling"] = round(achieved / ceiling["GBps"], 4)
     out["per_lattice"] = per
     if args.only == "all" and not args.no_warmstart:
-        # reduced live study (the full one: --warmstart --ws-train 1024 --ws-test 100 --ws-epochs 150)
+        # reduced live study (the full one: --warmstart --ws-train 2000 --ws-test 100 --ws-epochs 120)
         log("[bench] warm-start study (reduced)")
         ws_args = argparse.Namespace(ws_train=384, ws_test=50, ws_epochs=100, ws_train_tol=1e-5,
                                      ws_max_steps=300_000, ws_log=None)
