@@ -31,6 +31,14 @@ GPU side can take the same ones; numbering as in the design notes):
   A11 nu_b < 0 selects 2 nu / d (eq. 4-27-1 with a = 0, Remark V of Sec. IV).
   A14 NCDE: D = phi I, beta = 1, K = D(phi) I with D(phi) = D0 (1 + D2 phi^2),
       B = phi u_adv with constant u_adv, C = phi u_adv u_adv.
+  A18 the reduced lattices rD2Q5 (the rD2Q5I subset of rD2Q9) and rD3Q7 carry
+      the NCDE only, in the C = 0 form of eq. 4-16: linear equilibrium
+      g_eq(phi, phi u_adv, 0), F_j = w_j S and
+      G_j = g_eq(0, (1 - s_1/2) dB/dt, 0) with the first-order difference
+      dB/dt = u_adv (phi(t) - phi(t - dt)) / dt.  phi(t - dt) is model state
+      (the history field); at t = 0 it is the initial phi, so the first step
+      sees dB/dt = 0.  Moment rows are the monomials with at most one non-zero
+      exponent; rates of order 2 default to 1 as in A5.
 """
 from __future__ import annotations
 
@@ -57,10 +65,18 @@ _E_Q27 = [
 WALL_XM, WALL_XP, WALL_YM, WALL_YP, WALL_ZM, WALL_ZP = 1, 2, 4, 8, 16, 32
 
 
+LINEAR_LATTICES = ("Q5", "Q7")
+
+
 def unit_offsets(lattice: str) -> np.ndarray:
-    """Integer offsets e_j, shape (q, d). rD3Q19 = first 19 of rD3Q27 (Sec. III)."""
+    """Integer offsets e_j, shape (q, d). rD3Q19 = first 19 of rD3Q27, rD2Q5 =
+    first 5 of rD2Q9 (the rD2Q5I subset), rD3Q7 = first 7 of rD3Q27 (Sec. III)."""
     if lattice == "Q9":
         return np.array(_E_Q9, dtype=np.int64)
+    if lattice == "Q5":
+        return np.array(_E_Q9[:5], dtype=np.int64)
+    if lattice == "Q7":
+        return np.array(_E_Q27[:7], dtype=np.int64)
     if lattice == "Q27":
         return np.array(_E_Q27, dtype=np.int64)
     if lattice == "Q19":
@@ -80,10 +96,13 @@ def opposite(E: np.ndarray) -> np.ndarray:
 
 
 def weights(lattice: str, c: np.ndarray, cs2: float, w_corner: float | None = None) -> np.ndarray:
-    """Weights of eq. 3-3-5 (rD2Q9) and eq. 3-3-8 (rD3Q27; rD3Q19 has omega_19 = 0)."""
+    """Weights of eq. 3-3-5 (rD2Q9), eq. 3-3-8 (rD3Q27; rD3Q19 has omega_19 = 0)
+    and Remark I of Sec. III (rD2Q5I, rD3Q7: omega_a = c_s^2 / (2 c_a^2))."""
     c = np.asarray(c, dtype=np.float64)
     r = cs2 / c**2
-    if lattice == "Q9":
+    if lattice in LINEAR_LATTICES:
+        w = np.concatenate([[0.0], r / 2.0, r / 2.0])
+    elif lattice == "Q9":
         w5 = r[0] * r[1] / 4.0
         w1 = r[0] / 2.0 - 2.0 * w5
         w2 = r[1] / 2.0 - 2.0 * w5
@@ -114,6 +133,10 @@ def moment_exponents(lattice: str) -> list[tuple[int, ...]]:
     follow reading A4 (by total degree, diagonal second moments first)."""
     if lattice == "Q9":
         return [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (1, 1), (1, 2), (2, 1), (2, 2)]
+    if lattice == "Q5":
+        return [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2)]
+    if lattice == "Q7":
+        return [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (0, 2, 0), (0, 0, 2)]
     rows = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1),
             (2, 0, 0), (0, 2, 0), (0, 0, 2), (1, 1, 0), (1, 0, 1), (0, 1, 1),
             (2, 1, 0), (2, 0, 1), (1, 2, 0), (0, 2, 1), (1, 0, 2), (0, 1, 2), (1, 1, 1),
@@ -206,6 +229,9 @@ class Model:
         self.p = p
         self.lattice = p["lattice"]
         self.nse = p["equation"] == "NSE"
+        self.linear = self.lattice in LINEAR_LATTICES                          # A18
+        if self.linear and self.nse:
+            raise ValueError("rD2Q5 / rD3Q7 carry the NCDE only (linear equilibrium)")
         E = unit_offsets(self.lattice)
         self.E = E
         self.q, self.d = E.shape
@@ -239,7 +265,9 @@ class Model:
         self.rows1 = [row[unit[a]] for a in range(d)]
         self.rows2d = [row[tuple(2 * v for v in unit[a])] for a in range(d)]
         self.pairs = [(a, b) for a in range(d) for b in range(a + 1, d)]
-        self.rows2o = [row[tuple(unit[a][k] + unit[b][k] for k in range(d))] for a, b in self.pairs]
+        # off-diagonal second moments (absent on the reduced lattices)
+        self.rows2o = [row[tuple(unit[a][k] + unit[b][k] for k in range(d))] for a, b in self.pairs
+                       if tuple(unit[a][k] + unit[b][k] for k in range(d)) in row]
 
         S = np.zeros((q, q))
         if self.nse:
@@ -331,8 +359,10 @@ class Model:
         D = self.p["D0"] * (1.0 + self.p["D2"] * phi**2)
         return 1.0 / (0.5 + D / (self.cs2 * self.dt))
 
-    def distributions(self, fbar):
-        """f_eq, F and G of the node states in fbar (eq. NSEfeq/NSEFeq/NSEGeq or eq. 4-14/4-14-1)."""
+    def distributions(self, fbar, phi_prev=None):
+        """f_eq, F and G of the node states in fbar (eq. NSEfeq/NSEFeq/NSEGeq,
+        eq. 4-14/4-14-1, or eq. 4-16 on the reduced lattices, which need the
+        previous step's phi in phi_prev)."""
         d, n = self.d, fbar.shape[1]
         I = np.eye(d)[:, :, None]
         if self.nse:
@@ -349,12 +379,17 @@ class Model:
             return feq, F, G, None
         phi, u = self.macroscopic(fbar)
         B = phi[None] * u
-        feq = g_eq(self.C, self.w, self.c, self.cs2, phi, B,
-                   phi[None, None] * np.einsum("an,bn->abn", u, u))
         S = self.source
         F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, S), np.zeros((d, n)), np.zeros((d, d, n)))
         s1 = self.s1_ncde(phi)
-        M1G = (1.0 - s1[None] / 2.0) * u * S                                   # eq. 4-11, B' = u_adv
+        if self.linear:
+            feq = g_eq(self.C, self.w, self.c, self.cs2, phi, B, np.zeros((d, d, n)))   # eq. 4-16a
+            dBdt = u * (phi - phi_prev)[None] / self.dt                        # first-order difference
+            M1G = (1.0 - s1[None] / 2.0) * dBdt                                # eq. 4-16b
+        else:
+            feq = g_eq(self.C, self.w, self.c, self.cs2, phi, B,
+                       phi[None, None] * np.einsum("an,bn->abn", u, u))
+            M1G = (1.0 - s1[None] / 2.0) * u * S                               # eq. 4-11, B' = u_adv
         G = g_eq(self.C, self.w, self.c, self.cs2, np.zeros(n), M1G, np.zeros((d, d, n)))
         return feq, F, G, s1
 
@@ -384,9 +419,9 @@ class Model:
         return y
 
     # --------------------------------------------------------------- collision
-    def collide(self, fbar):
+    def collide(self, fbar, phi_prev=None):
         """Post-collision fbar* in moment space, eq. 2-2-3 (before propagation)."""
-        feq, F, G, s1 = self.distributions(fbar)
+        feq, F, G, s1 = self.distributions(fbar, phi_prev)
         m = self.M @ fbar
         meq = self.M @ feq
         mF = self.M @ F
@@ -394,9 +429,9 @@ class Model:
         mstar = m - self.apply_S(m - meq, s1) + self.dt * (mG + mF - 0.5 * self.apply_S(mF, s1))
         return np.linalg.solve(self.M, mstar)
 
-    def collide_velocity_space(self, fbar):
+    def collide_velocity_space(self, fbar, phi_prev=None):
         """Same collision written in velocity space with Lambda = M^-1 S M (eq. 2-3, eq. 5-1)."""
-        feq, F, G, s1 = self.distributions(fbar)
+        feq, F, G, s1 = self.distributions(fbar, phi_prev)
 
         def Lam(x):
             return self.Minv @ self.apply_S(self.M @ x, s1)
@@ -419,12 +454,29 @@ class Model:
             out[self.opp[j], back] = fstar[j, back]
         return out
 
-    def step(self, fbar, nsteps=1):
+    def step(self, fbar, nsteps=1, hist=None):
+        """nsteps collide-and-stream steps.  On the reduced lattices (A18) hist
+        is the previous step's phi per node (init_history gives it at t = 0)
+        and the call returns (fbar, hist); otherwise it returns fbar."""
+        if self.linear != (hist is not None):
+            raise ValueError("hist is required on rD2Q5 / rD3Q7 and meaningless elsewhere")
+        fl = self.fluid
+        if hist is not None:
+            hist = np.array(hist, dtype=np.float64).reshape(self.N)
         for _ in range(nsteps):
             fstar = fbar.copy()
-            fstar[:, self.fluid] = self.collide(fbar[:, self.fluid])
+            if self.linear:
+                phi, _ = self.macroscopic(fbar[:, fl])
+                fstar[:, fl] = self.collide(fbar[:, fl], hist[fl])
+                hist[fl] = phi
+            else:
+                fstar[:, fl] = self.collide(fbar[:, fl])
             fbar = self.stream(fstar, fbar)
-        return fbar
+        return fbar if hist is None else (fbar, hist)
+
+    def init_history(self, phi):
+        """phi(t - dt) at t = 0 for the reduced lattices: the initial phi (A18)."""
+        return np.array(phi, dtype=np.float64).reshape(self.N)
 
     # ---------------------------------------------------------- initialisation
     def init(self, rho, u, with_fne=False):
@@ -446,8 +498,8 @@ class Model:
                      np.repeat(Fb[:, None], n, axis=1), -self.cs2 * Sb * np.repeat(I, n, axis=2))
         else:
             u = np.repeat(self.adv[:, None], n, axis=1)
-            feq = g_eq(self.C, self.w, self.c, self.cs2, rho, rho[None] * u,
-                       rho[None, None] * np.einsum("an,bn->abn", u, u))
+            Mt = np.zeros((d, d, n)) if self.linear else rho[None, None] * np.einsum("an,bn->abn", u, u)
+            feq = g_eq(self.C, self.w, self.c, self.cs2, rho, rho[None] * u, Mt)
             F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, self.source),
                      np.zeros((d, n)), np.zeros((d, d, n)))
         return feq - 0.5 * self.dt * F
@@ -525,6 +577,22 @@ def gaussian_hill(xp, yp, t, sigma0, D, xc, yc, adv, Lx, Ly, images=2):
             dx = xp - (xc + adv[0] * t) - i * Lx
             dy = yp - (yc + adv[1] * t) - k * Ly
             out += amp * np.exp(-(dx**2 + dy**2) / (2.0 * s2))
+    return out
+
+
+def gaussian_hill_nd(coords, t, sigma0, D, centre, adv, L, images=2):
+    """d-dimensional advected Gaussian with constant diffusivity on a periodic
+    box (peak 1 at t = 0); the advected centre is wrapped into the box before
+    the periodic images are summed."""
+    d = len(coords)
+    s2 = sigma0**2 + 2.0 * D * t
+    out = np.full(np.shape(coords[0]), (sigma0**2 / s2) ** (d / 2.0))
+    for a in range(d):
+        xc = np.mod(centre[a] + adv[a] * t, L[a])
+        acc = np.zeros(np.shape(coords[a]))
+        for i in range(-images, images + 1):
+            acc += np.exp(-((coords[a] - xc - i * L[a]) ** 2) / (2.0 * s2))
+        out = out * acc
     return out
 
 
