@@ -90,9 +90,11 @@ def run_single(torch, R, prm, rho, u, steps, warmup, solid=None, launch=None):
     return wall, ev_ms, finite
 
 
-def lattice_entry(name, q, storage, N, steps, wall, ev_ms, note=None):
+def lattice_entry(name, q, storage, N, steps, wall, ev_ms, note=None, extra_bytes=0):
+    """extra_bytes: algorithmic bytes per update beyond the 2 q populations
+    (the rD2Q5 / rD3Q7 history field: one read and one write)."""
     mlups = N * steps / wall / 1e6
-    bpu = 2 * q * sizeof(storage)
+    bpu = 2 * q * sizeof(storage) + extra_bytes
     gbs_ev = N * bpu / (ev_ms / steps * 1e-3) / 1e9
     e = {"workload": name, "MLUPS": round(mlups, 1), "bytes_per_update": bpu,
          "kernel_GBps": round(gbs_ev, 1), "pct_hbm_peak": round(100 * gbs_ev / HBM_PEAK_GBS, 1),
@@ -173,7 +175,8 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--only", default="all",
-                    help="comma list of: q19,q19f16,q19f64,q9ncde,q27,q27batch,q9tg,copy (the q19 headline always runs)")
+                    help="comma list of: q19,q19f16,q19f64,q9ncde,q5ncde,q7ncde,q27,q27batch,q9tg,copy "
+                         "(the q19 headline always runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--warmstart", action="store_true",
                     help="run the warm-start study (solver-generated training set, training, held-out evaluation)")
@@ -202,7 +205,8 @@ def main():
         print(json.dumps(warmstart_study(torch, args)))
         return
 
-    only = set(args.only.split(",")) if args.only != "all" else {"q19f16", "q19f64", "q9ncde", "q27", "q27batch", "q9tg", "copy"}
+    only = set(args.only.split(",")) if args.only != "all" else {"q19f16", "q19f64", "q9ncde", "q27", "q27batch", "q9tg",
+                                                                 "q5ncde", "q7ncde", "copy"}
     K, W = args.steps, args.warmup
 
     # ---------------- headline: rD3Q19 FP32-dev 256 x 256 x 128 ----------------
@@ -266,6 +270,36 @@ def main():
             "rD2Q9 NCDE Gaussian hill 2048x1024 dy=0.5 FP32-dev AA", 9, "f32dev", 2048 * 1024, 4 * K, w2, e2,
             note="75.5 MB working set fits the 256 MB MALL: % HBM may be cache-inflated")
         per["rD2Q9_ncde_f32dev"]["finite"] = fin
+    if "q5ncde" in only:
+        log("[bench] rD2Q5 NCDE 2048x1024 f32dev")
+        from inputs import gaussian_hill_field
+        n2 = (2048, 1024, 1)
+        prm = dict(lattice="Q5", equation="NCDE", n=n2, dx=(1.0, 0.5, 1.0), D0=0.01, D2=1.0, adv=(0.05, 0.02, 0.0),
+                   rho0=0.0, storage="f32dev", pattern="AA")
+        phi = gaussian_hill_field(2048, 1024, 1.0, 0.5, 40.0, 1024.0, 256.0)
+        w2, e2, fin = run_single(torch, R, prm, phi, None, 4 * K, W)
+        per["rD2Q5_ncde_f32dev"] = lattice_entry(
+            "rD2Q5 NCDE Gaussian hill 2048x1024 dy=0.5 FP32-dev AA, linear equilibrium + dB/dt history",
+            5, "f32dev", 2048 * 1024, 4 * K, w2, e2, extra_bytes=8,
+            note="50 MB working set fits the 256 MB MALL: % HBM may be cache-inflated")
+        per["rD2Q5_ncde_f32dev"]["finite"] = fin
+    if "q7ncde" in only:
+        import numpy as np
+        n3 = (256, 256, 128)
+        x = np.arange(n3[0]) * 1.0
+        Z, Y, X = np.meshgrid(np.arange(n3[2]) * 2.0, np.arange(n3[1]) * 1.0, x, indexing="ij")
+        phi = np.exp(-((X - 128) ** 2 + (Y - 128) ** 2 + (Z - 128) ** 2) / (2 * 24.0**2)).reshape(-1)
+        del X, Y, Z
+        for st in ("f32dev", "f16dev"):
+            log(f"[bench] rD3Q7 NCDE 256x256x128 {st}")
+            prm = dict(lattice="Q7", equation="NCDE", n=n3, dx=(1.0, 1.0, 2.0), D0=0.01, D2=1.0,
+                       adv=(0.05, 0.02, 0.01), rho0=0.0, storage=st, pattern="AA")
+            w2, e2, fin = run_single(torch, R, prm, phi, None, K, W)
+            key = f"rD3Q7_ncde_{st}"
+            per[key] = lattice_entry(f"rD3Q7 NCDE 3D Gaussian 256x256x128 dz=2dx {st} AA, linear equilibrium + "
+                                     f"dB/dt history", 7, st, N_h, K, w2, e2, extra_bytes=8)
+            per[key]["finite"] = fin
+        del phi
     if "q9tg" in only:
         log("[bench] rD2Q9 TG 64x32 f64")
         from inputs import taylor_green_2d

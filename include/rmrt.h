@@ -50,7 +50,14 @@ extern "C" {
 #define RMRT_ENOMEM (-5)        /* host or device allocation failed             */
 
 /* ---- enumerations ---- */
-enum { RMRT_Q9 = 0, RMRT_Q19 = 1, RMRT_Q27 = 2 };                  /* rD2Q9, rD3Q19, rD3Q27 */
+enum { RMRT_Q9 = 0, RMRT_Q19 = 1, RMRT_Q27 = 2, RMRT_Q5 = 3, RMRT_Q7 = 4 };
+/* rD2Q9, rD3Q19, rD3Q27 (Sec. III); rD2Q5 (the rD2Q5I subset) and rD3Q7 with
+ * the weights of Remark I of Sec. III carry the NCDE only, in the C = 0 form
+ * of eq. 4-16: linear equilibrium g_eq(phi, phi adv, 0), F_j = w_j S and
+ * G_j = g_eq(0, (1 - s_1/2) dB/dt, 0) with dB/dt = adv (phi - phi_prev) / dt
+ * from the previous step's phi, which the context keeps in a library-owned
+ * field of N doubles (FP64 storage) or floats (else); rmrt_init and
+ * rmrt_set_fields set it to the initial phi (dB/dt = 0 on the first step). */
 enum { RMRT_NSE = 0, RMRT_NCDE = 1 };                              /* Sec. IV B / IV A      */
 enum { RMRT_F64 = 0, RMRT_F32DEV = 1, RMRT_F16DEV = 2 };           /* population storage    */
 enum { RMRT_AB = 0, RMRT_AA = 1 };                                 /* two-lattice / in-place */
@@ -68,8 +75,9 @@ enum { RMRT_OUT_F64 = 0, RMRT_OUT_F32 = 1 };                       /* macroscopi
  * Parameters of one rectangular domain.  Zero or negative values of the
  * "default" fields select the documented defaults.
  *
- *   lattice, equation, storage, pattern : enumerations above
- *   n[3]      nodes per axis (n[2] = 1 for rD2Q9)
+ *   lattice, equation, storage, pattern : enumerations above (FP16
+ *             deviation storage needs every weight > 0)
+ *   n[3]      nodes per axis (n[2] = 1 for rD2Q9 and rD2Q5)
  *   dx[3]     grid spacings dx_a; dt time step (<= 0 -> 1)          (Sec. III)
  *   cs2       sound speed squared c_s^2 (<= 0 -> min_a c_a^2 / 3); must satisfy
  *             0 < c_s^2 / c_a^2 < 1 (eq. 3-3-3 / eq. 3-3-8 bounds)

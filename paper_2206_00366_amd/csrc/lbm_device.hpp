@@ -11,7 +11,9 @@
 // diagonal D is folded into host-side coefficient tables.  rD3Q19 runs the
 // 27-slot transform with the 8 corner populations and the 8 moments with three
 // non-zero exponents fixed at zero (those monomials vanish on rD3Q19, so the
-// embedded inverse returns zero corners).
+// embedded inverse returns zero corners).  rD2Q5 and rD3Q7 run the 9- and
+// 27-slot transforms in the same way, with every population slot and every
+// moment that has two or more non-zero entries fixed at zero.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,10 +40,12 @@ constexpr int kE9[9][3] = {{0, 0, 0}, {1, 0, 0},  {0, 1, 0},   {-1, 0, 0}, {0, -
 
 template <int L>
 struct Lat {
-  static constexpr int D = (L == LAT_Q9) ? 2 : 3;
-  static constexpr int Q = (L == LAT_Q9) ? 9 : (L == LAT_Q19 ? 19 : 27);
-  static constexpr int NS = (L == LAT_Q9) ? 9 : 27;  // tensor slots
-  static constexpr int e(int j, int a) { return (L == LAT_Q9) ? kE9[j][a] : kE27[j][a]; }
+  static constexpr int D = (L == LAT_Q9 || L == LAT_Q5) ? 2 : 3;
+  static constexpr int Q = L == LAT_Q9 ? 9 : L == LAT_Q19 ? 19 : L == LAT_Q27 ? 27 : L == LAT_Q5 ? 5 : 7;
+  static constexpr int NS = (D == 2) ? 9 : 27;  // tensor slots
+  // rD2Q5 / rD3Q7: NCDE with the linear equilibrium and the dB/dt term (eq. 4-16)
+  static constexpr bool linear = (L == LAT_Q5 || L == LAT_Q7);
+  static constexpr int e(int j, int a) { return (D == 2) ? kE9[j][a] : kE27[j][a]; }
   static constexpr int slot(int j) {
     return (e(j, 0) + 1) + 3 * (e(j, 1) + 1) + (D == 3 ? 9 * (e(j, 2) + 1) : 0);
   }
@@ -50,13 +54,17 @@ struct Lat {
       if (e(k, 0) == -e(j, 0) && e(k, 1) == -e(j, 1) && e(k, 2) == -e(j, 2)) return k;
     return -1;
   }
-  // moment slot with three non-zero exponents: not a moment of rD3Q19
+  static constexpr int nonzero_exps(int n) { return ((n % 3) != 0) + (((n / 3) % 3) != 0) + ((n / 9) != 0); }
+  static constexpr int off_centre(int s) { return ((s % 3) != 1) + (((s / 3) % 3) != 1) + (D == 3 && (s / 9) != 1); }
+  // moment slot that is not a moment of the lattice: three non-zero exponents
+  // on rD3Q19, two or more on rD2Q5 / rD3Q7
   static constexpr bool dropped(int n) {
-    return L == LAT_Q19 && (n % 3) != 0 && ((n / 3) % 3) != 0 && (n / 9) != 0;
+    return (L == LAT_Q19 && nonzero_exps(n) == 3) || (linear && nonzero_exps(n) >= 2);
   }
-  // population slot not present in the lattice (rD3Q19 corners)
+  // population slot not present in the lattice (rD3Q19 corners; rD2Q5 /
+  // rD3Q7 everything off the axes)
   static constexpr bool absent(int s) {
-    return L == LAT_Q19 && (s % 3) != 1 && ((s / 3) % 3) != 1 && (s / 9) != 1;
+    return (L == LAT_Q19 && off_centre(s) == 3) || (linear && off_centre(s) >= 2);
   }
 };
 
@@ -159,9 +167,11 @@ __device__ __forceinline__ T gmom(const Coef<T>& C, T A, const T (&B)[3], const 
     return T(0);
   } else if constexpr (nodd == 0) {
     T r = A * C.E0[n];
-    r += Md[0] * C.E2[n][0];
-    r += Md[1] * C.E2[n][1];
-    if constexpr (Lat<L>::D == 3) r += Md[2] * C.E2[n][2];
+    if constexpr (!Lat<L>::linear) {   // the linear equilibrium has M = 0
+      r += Md[0] * C.E2[n][0];
+      r += Md[1] * C.E2[n][1];
+      if constexpr (Lat<L>::D == 3) r += Md[2] * C.E2[n][2];
+    }
     return r;
   } else if constexpr (nodd == 1) {
     constexpr int ax = (a & 1) ? 0 : ((b & 1) ? 1 : 2);
@@ -181,13 +191,16 @@ __device__ __forceinline__ T gmom(const Coef<T>& C, T A, const T (&B)[3], const 
 // and m_G + m_F = g_eq(Sbar, Fbar, M_2G - cs2 Sbar I) for the NSE
 // (eq. NSEfeq, NSEFeq, NSEGeq, M2GComput a), or
 // m_eq' = g_eq(phi - S/2, phi u, phi u u), m_G + m_F = g_eq(S, M_1G, 0) with
-// M_1G = (1 - s1/2) u S for the NCDE (eq. 4-14, 4-14-1, 4-11).
+// M_1G = (1 - s1/2) u S for the NCDE (eq. 4-14, 4-14-1, 4-11).  On rD2Q5 /
+// rD3Q7 (C = 0 form, eq. 4-16) m_eq' = g_eq(phi - S/2, phi u, 0) and
+// M_1G = (1 - s1/2) u (phi - phi_prev) / dt, with phi_prev the previous
+// step's phi of the node; phi is returned in phi_out for the next step.
 // t[] holds the deviation populations in tensor slots on entry and the
-// post-collision deviations on exit.  Returns nothing; macroscopic values are
-// recomputed by the moments kernel when needed.
+// post-collision deviations on exit.
 // ----------------------------------------------------------------------------
 template <int L, int EQ, bool FORCE, typename T, int NS>
-__device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C) {
+__device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, T phi_prev = T(0),
+                                        T* phi_out = nullptr) {
   constexpr int D = Lat<L>::D;
   moments_fwd<D>(t);
 
@@ -247,18 +260,31 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C) {
     eB[0] = phi * C.adv[0];
     eB[1] = phi * C.adv[1];
     eB[2] = phi * C.adv[2];
-    eMd[0] = eB[0] * C.adv[0];
-    eMd[1] = eB[1] * C.adv[1];
-    eMd[2] = eB[2] * C.adv[2];
-    eMo[0] = eB[0] * C.adv[1];
-    eMo[1] = eB[0] * C.adv[2];
-    eMo[2] = eB[1] * C.adv[2];
-    if constexpr (FORCE) {
-      const T g = (T(1) - T(0.5) * s1) * C.source;                      // eq. 4-11
-      sA = C.source;
-      sB[0] = g * C.adv[0];
-      sB[1] = g * C.adv[1];
-      sB[2] = g * C.adv[2];
+    if constexpr (Lat<L>::linear) {
+      for (int k = 0; k < 3; ++k) eMd[k] = eMo[k] = T(0);
+      if (phi_out) *phi_out = phi;
+      if constexpr (FORCE) {
+        // G from dB/dt = u (phi - phi_prev) / dt, first-order difference (eq. 4-16)
+        const T g = (T(1) - T(0.5) * s1) * (phi - phi_prev) * C.inv_dt;
+        sA = C.source;
+        sB[0] = g * C.adv[0];
+        sB[1] = g * C.adv[1];
+        sB[2] = g * C.adv[2];
+      }
+    } else {
+      eMd[0] = eB[0] * C.adv[0];
+      eMd[1] = eB[1] * C.adv[1];
+      eMd[2] = eB[2] * C.adv[2];
+      eMo[0] = eB[0] * C.adv[1];
+      eMo[1] = eB[0] * C.adv[2];
+      eMo[2] = eB[1] * C.adv[2];
+      if constexpr (FORCE) {
+        const T g = (T(1) - T(0.5) * s1) * C.source;                    // eq. 4-11
+        sA = C.source;
+        sB[0] = g * C.adv[0];
+        sB[1] = g * C.adv[1];
+        sB[2] = g * C.adv[2];
+      }
     }
   }
 

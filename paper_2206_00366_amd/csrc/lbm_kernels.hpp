@@ -128,7 +128,7 @@ struct Geo {
 // node instead of a byte per neighbour.
 template <int L>
 struct LinkBits {
-  using W = typename std::conditional<L == LAT_Q9, uint16_t, uint32_t>::type;
+  using W = typename std::conditional<(Lat<L>::Q <= 15), uint16_t, uint32_t>::type;
   static constexpr W kSolid = (W)1 << (sizeof(W) * 8 - 1);
 };
 
@@ -166,6 +166,7 @@ struct NodeStep {
   LW lb;
   uint32_t idx;
   bool live;   // a fluid node to update
+  T phi_prev;  // rD2Q5 / rD3Q7: phi of the previous step
 
   // Read the q populations of node idx_ (nothing for solid or invalid nodes).
   __device__ __forceinline__ void load(const DomainDev& Dm, const Coef<T>& C, const gmem<S>* fin, uint32_t idx_,
@@ -182,6 +183,7 @@ struct NodeStep {
       }
     }
     if (!live) return;
+    if constexpr (Lat<L>::linear) phi_prev = to_global((const T*)Dm.hist)[idx];
     if constexpr (PH != PH_AA_EVEN) g.make(Dm, idx);
     const uint32_t N = Dm.N;
     static_for<0, NS>([&](auto s_) {
@@ -214,7 +216,13 @@ struct NodeStep {
   // Collide and write the q post-collision populations.
   __device__ __forceinline__ void finish(const DomainDev& Dm, const Coef<T>& C, gmem<S>* fout) {
     if (!live) return;
-    collide<L, EQ, FORCE>(t, C);
+    if constexpr (Lat<L>::linear) {
+      T phi;
+      collide<L, EQ, FORCE>(t, C, phi_prev, &phi);
+      to_global((T*)Dm.hist)[idx] = phi;
+    } else {
+      collide<L, EQ, FORCE>(t, C);
+    }
     const uint32_t N = Dm.N;
     static_for<0, Q>([&](auto j_) {
       constexpr int J = decltype(j_)::value;
@@ -558,6 +566,7 @@ __global__ void k_reduce_final(const double* __restrict__ partials, uint32_t nb,
 //   NSE : A = rho - rho0 - Sbar/2, B = rho u - Fbar/2,
 //         M = rho u u + cs2 Sbar I / 2 [+ m_2^ne of eq. 4-34]
 //   NCDE: A = phi - phi0 - S/2,    B = phi adv,  M = phi adv adv
+//         (M = 0 on rD2Q5 / rD3Q7, which also set their history field to phi)
 // written in the natural layout, or through the swapped addressing when the
 // state is expected after an odd number of AA steps.
 // ----------------------------------------------------------------------------
@@ -641,8 +650,11 @@ __global__ void __launch_bounds__(256)
     } else {
       A = r - C.rho0 - C.half_source;
       for (int a = 0; a < 3; ++a) B[a] = r * C.adv[a];
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) M[a][b] = r * C.adv[a] * C.adv[b];
+      if constexpr (!Lat<L>::linear)
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) M[a][b] = r * C.adv[a] * C.adv[b];
+      else if (!(Dm.has_solid && Dm.solid[idx]))
+        ((typename Store<ST>::T*)Dm.hist)[idx] = (typename Store<ST>::T)r;   // dB/dt = 0 at the first step
     }
     // g_eq_j = w_j (A + c_j.B / cs2 + sum_a M_aa (c_ja^2 - cs2) / (cs2 (c_a^2 - cs2))
     //               + sum_{a<b} M_ab c_ja c_jb / cs2^2)

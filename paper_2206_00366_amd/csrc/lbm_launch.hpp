@@ -39,7 +39,10 @@ hipError_t step_f(const StepLaunch& a) {
 }
 template <int L, int ST>
 hipError_t launch_step(const StepLaunch& a) {
-  return a.eq == EQ_NCDE ? step_f<L, ST, EQ_NCDE>(a) : step_f<L, ST, EQ_NSE>(a);
+  if constexpr (Lat<L>::linear)   // rD2Q5 / rD3Q7 carry the NCDE only
+    return a.eq == EQ_NCDE ? step_f<L, ST, EQ_NCDE>(a) : hipErrorInvalidValue;
+  else
+    return a.eq == EQ_NCDE ? step_f<L, ST, EQ_NCDE>(a) : step_f<L, ST, EQ_NSE>(a);
 }
 
 // ---- companions: dispatch over (eq, bc, swapped) ----

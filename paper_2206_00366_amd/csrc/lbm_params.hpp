@@ -6,7 +6,7 @@
 
 namespace rmrt {
 
-enum { LAT_Q9 = 0, LAT_Q19 = 1, LAT_Q27 = 2 };
+enum { LAT_Q9 = 0, LAT_Q19 = 1, LAT_Q27 = 2, LAT_Q5 = 3, LAT_Q7 = 4 };
 enum { EQ_NSE = 0, EQ_NCDE = 1 };
 enum { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2 };
 enum { PH_AB = 0, PH_AA_EVEN = 1, PH_AA_ODD = 2 };
@@ -29,7 +29,7 @@ struct Coef {
   T ihs_off[3];             // 1 - s_off/2
   T force[3], half_force[3];
   T source, half_source, cs2_source, half_cs2_source;
-  T adv[3], D0, D2, inv_cs2_dt;
+  T adv[3], D0, D2, inv_cs2_dt, inv_dt;
 };
 
 // Initialisation-only quantities (always FP64).
@@ -52,8 +52,10 @@ struct DomainDev {
   void* fa;                 // population buffer 0
   void* fb;                 // population buffer 1 (two-lattice pattern)
   const uint8_t* solid;     // 1 byte per node or null
-  const void* links;        // per-node link bits (uint16 for rD2Q9, uint32 otherwise) or null:
+  const void* links;        // per-node link bits (uint16 for q <= 15, uint32 otherwise) or null:
                             // bit j = link x -> x + e_j hits a wall or solid; top bit = solid node
+  void* hist;               // rD2Q5 / rD3Q7: phi of the previous step per node (double for FP64
+                            // storage, float otherwise); null on the other lattices
 };
 
 // One unit of persistent-kernel work: nodes [start, start + count) of a domain.

@@ -1,0 +1,5 @@
+// Kernel instances for LAT_Q7 with ST_F32 storage.
+#include "lbm_launch.hpp"
+namespace rmrt {
+RMRT_INSTANTIATE(LAT_Q7, ST_F32)
+}  // namespace rmrt

@@ -52,21 +52,33 @@ struct Derived {
   int e[27][3];
 };
 
-int lattice_q(int lat) { return lat == RMRT_Q9 ? 9 : (lat == RMRT_Q19 ? 19 : 27); }
+int lattice_q(int lat) {
+  switch (lat) {
+    case RMRT_Q9: return 9;
+    case RMRT_Q19: return 19;
+    case RMRT_Q27: return 27;
+    case RMRT_Q5: return 5;
+    default: return 7;
+  }
+}
+bool lattice_2d(int lat) { return lat == RMRT_Q9 || lat == RMRT_Q5; }
+bool lattice_linear(int lat) { return lat == RMRT_Q5 || lat == RMRT_Q7; }
 
 int derive(const rmrt_params* p, Derived& v) {
   if (!p) return fail(RMRT_EINVAL, "params is NULL");
-  if (p->lattice < RMRT_Q9 || p->lattice > RMRT_Q27) return fail(RMRT_EINVAL, "unknown lattice %d", p->lattice);
+  if (p->lattice < RMRT_Q9 || p->lattice > RMRT_Q7) return fail(RMRT_EINVAL, "unknown lattice %d", p->lattice);
   if (p->equation != RMRT_NSE && p->equation != RMRT_NCDE)
     return fail(RMRT_EINVAL, "unknown equation %d", p->equation);
   if (p->storage < RMRT_F64 || p->storage > RMRT_F16DEV) return fail(RMRT_EINVAL, "unknown storage %d", p->storage);
   if (p->pattern != RMRT_AB && p->pattern != RMRT_AA) return fail(RMRT_EINVAL, "unknown pattern %d", p->pattern);
   v.lattice = p->lattice;
   v.q = lattice_q(p->lattice);
-  v.d = p->lattice == RMRT_Q9 ? 2 : 3;
+  v.d = lattice_2d(p->lattice) ? 2 : 3;
+  if (lattice_linear(p->lattice) && p->equation != RMRT_NCDE)
+    return fail(RMRT_EINVAL, "rD2Q5 / rD3Q7 carry the NCDE only (linear equilibrium, eq. 4-16)");
   for (int a = 0; a < 3; ++a)
     if (p->n[a] < 1) return fail(RMRT_EINVAL, "n[%d] = %d < 1", a, p->n[a]);
-  if (v.d == 2 && p->n[2] != 1) return fail(RMRT_EINVAL, "rD2Q9 needs n[2] == 1");
+  if (v.d == 2 && p->n[2] != 1) return fail(RMRT_EINVAL, "2D lattices need n[2] == 1");
   const double N = (double)p->n[0] * p->n[1] * p->n[2];
   if (N * v.q >= 4294967295.0) return fail(RMRT_EUNSUPPORTED, "q * N must be below 2^32");
   v.dt = p->dt > 0 ? p->dt : 1.0;
@@ -84,11 +96,14 @@ int derive(const rmrt_params* p, Derived& v) {
       return fail(RMRT_EINVAL, "need 0 < cs2 / c_%d^2 < 1 (got %g)", a, v.r[a]);
   }
   for (int j = 0; j < 27; ++j)
-    for (int a = 0; a < 3; ++a) v.e[j][a] = (p->lattice == RMRT_Q9) ? (j < 9 ? kE9[j][a] : 0) : kE27[j][a];
-  // weights: eq. 3-3-5 (rD2Q9), eq. 3-3-8 (rD3Q27; omega_19 = 0 gives rD3Q19)
+    for (int a = 0; a < 3; ++a) v.e[j][a] = (v.d == 2) ? (j < 9 ? kE9[j][a] : 0) : kE27[j][a];
+  // weights: eq. 3-3-5 (rD2Q9), eq. 3-3-8 (rD3Q27; omega_19 = 0 gives rD3Q19),
+  // Remark I of Sec. III (rD2Q5, rD3Q7: omega_a = r_a / 2 on the axes)
   std::fill(v.w, v.w + 27, 0.0);
   const double* r = v.r;
-  if (p->lattice == RMRT_Q9) {
+  if (lattice_linear(p->lattice)) {
+    for (int a = 0; a < v.d; ++a) v.w[1 + a] = v.w[1 + v.d + a] = r[a] / 2.0;
+  } else if (p->lattice == RMRT_Q9) {
     const double w5 = r[0] * r[1] / 4.0;
     const double w1 = r[0] / 2.0 - 2.0 * w5, w2 = r[1] / 2.0 - 2.0 * w5;
     const double ws[9] = {0, w1, w2, w1, w2, w5, w5, w5, w5};
@@ -112,8 +127,13 @@ int derive(const rmrt_params* p, Derived& v) {
   double sum = 0;
   for (int j = 1; j < v.q; ++j) sum += v.w[j];
   v.w[0] = 1.0 - sum;
+  if (std::fabs(v.w[0]) < 1e-14) v.w[0] = 0.0;   // rounding of an exact zero (e.g. rD3Q7, c_s^2 = c^2 / 3)
   for (int j = 0; j < v.q; ++j)
     if (!(v.w[j] >= 0)) return fail(RMRT_EINVAL, "weight w_%d = %g is negative", j, v.w[j]);
+  if (p->storage == RMRT_F16DEV)
+    for (int j = 0; j < v.q; ++j)
+      if (!(v.w[j] > 0))
+        return fail(RMRT_EINVAL, "FP16 deviation storage divides by the weights: w_%d = 0", j);
 
   v.D0 = p->D0;
   v.D2 = p->D2;
@@ -266,6 +286,7 @@ void fill_coef(const rmrt_params* p, const Derived& v, Coef<T>& C) {
   C.D0 = (T)p->D0;
   C.D2 = (T)p->D2;
   C.inv_cs2_dt = (T)(1.0 / (cs2 * dt));
+  C.inv_dt = (T)(1.0 / dt);
 }
 
 uint32_t magic(uint32_t d) { return d <= 1 ? 0xffffffffu : (uint32_t)(0x100000000ull / d); }
@@ -303,6 +324,9 @@ void fill_domain(const rmrt_params* p, const Derived& v, DomainDev& D, void* fa,
 
 bool has_force(const rmrt_params* p) {
   if (p->source != 0.0) return true;
+  if (lattice_linear(p->lattice))   // the dB/dt term G of eq. 4-16
+    for (int a = 0; a < 3; ++a)
+      if (p->adv[a] != 0.0) return true;
   if (p->equation == RMRT_NSE)
     for (int a = 0; a < 3; ++a)
       if (p->force[a] != 0.0) return true;
@@ -329,6 +353,12 @@ struct Unused {};
       case 6: return FN<LAT_Q27, ST_F64>(arg);                                        \
       case 7: return FN<LAT_Q27, ST_F32>(arg);                                        \
       case 8: return FN<LAT_Q27, ST_F16>(arg);                                        \
+      case 9: return FN<LAT_Q5, ST_F64>(arg);                                         \
+      case 10: return FN<LAT_Q5, ST_F32>(arg);                                        \
+      case 11: return FN<LAT_Q5, ST_F16>(arg);                                        \
+      case 12: return FN<LAT_Q7, ST_F64>(arg);                                        \
+      case 13: return FN<LAT_Q7, ST_F32>(arg);                                        \
+      case 14: return FN<LAT_Q7, ST_F16>(arg);                                        \
     }                                                                                 \
     return hipErrorInvalidValue;                                                      \
   } while (0)
@@ -346,6 +376,8 @@ hipError_t dispatch_links(int lat, const DomainDev* doms, uint32_t dom, void* ou
     case LAT_Q9: return launch_links<LAT_Q9>(doms, dom, out, grid, s);
     case LAT_Q19: return launch_links<LAT_Q19>(doms, dom, out, grid, s);
     case LAT_Q27: return launch_links<LAT_Q27>(doms, dom, out, grid, s);
+    case LAT_Q5: return launch_links<LAT_Q5>(doms, dom, out, grid, s);
+    case LAT_Q7: return launch_links<LAT_Q7>(doms, dom, out, grid, s);
   }
   return hipErrorInvalidValue;
 }
@@ -406,6 +438,7 @@ struct rmrt_ctx {
   hipStream_t cap = nullptr;   // capture stream
   int cus = 256;               // compute units of the device
   void* links = nullptr;       // per-node link bits (solid-mask boundary mode)
+  void* hist = nullptr;        // rD2Q5 / rD3Q7: previous-step phi per node (library-owned)
   int step_bc = 0;             // 0 periodic, 1 walls from coordinates, 2 link bits
   int blocks_per_cu = kDefaultBlocksPerCU;  // resident workgroups per CU (0: hardware limit)
   uint32_t flags = kDefaultFlags;
@@ -474,13 +507,14 @@ void ctx_release(rmrt_ctx* c) {
   if (c->hres) hipHostFree(c->hres);
   if (c->uprev) hipFree(c->uprev);
   if (c->links) hipFree(c->links);
+  if (c->hist) hipFree(c->hist);
   if (c->owns_ddoms && c->ddoms) hipFree(c->ddoms);
 }
 
 // Allocate the link bits of a context (hdom.links set); the caller uploads
 // the parameter block and then runs build_links.
 int alloc_links(rmrt_ctx* c) {
-  const size_t w = c->p.lattice == RMRT_Q9 ? 2 : 4;
+  const size_t w = lattice_q(c->p.lattice) <= 15 ? 2 : 4;
   HIP_TRY(hipMalloc(&c->links, w * c->hdom.N));
   c->hdom.links = c->links;
   c->step_bc = 2;
@@ -682,6 +716,15 @@ static int ctx_create(rmrt_ctx** out, const rmrt_params* p, void* f0, void* f1, 
     ctx_release(c);
     delete c;
     return rc;
+  }
+  if (lattice_linear(p->lattice)) {
+    hipError_t e = hipMalloc(&c->hist, (p->storage == RMRT_F64 ? 8 : 4) * (size_t)c->hdom.N);
+    if (e != hipSuccess) {
+      ctx_release(c);
+      delete c;
+      return fail(RMRT_EHIP, "hipMalloc(history field): %s", hipGetErrorString(e));
+    }
+    c->hdom.hist = c->hist;
   }
   c->cus = device_cus();
   default_launch(*p, c->blocks_per_cu, c->flags);

@@ -26,7 +26,7 @@ _lib = C.CDLL(LIB_PATH)
 
 # ---- constants (include/rmrt.h) ----
 OK, EINVAL, EUNSUPPORTED, EHIP, ENONFINITE, ENOMEM = 0, -1, -2, -3, -4, -5
-Q9, Q19, Q27 = 0, 1, 2
+Q9, Q19, Q27, Q5, Q7 = 0, 1, 2, 3, 4
 NSE, NCDE = 0, 1
 F64, F32DEV, F16DEV = 0, 1, 2
 AB, AA = 0, 1
@@ -34,11 +34,12 @@ OUT_F64, OUT_F32 = 0, 1
 LAUNCH_XCD_ORDER, LAUNCH_PERSISTENT, LAUNCH_WIDE_TILES = 1, 2, 4
 WALL_XM, WALL_XP, WALL_YM, WALL_YP, WALL_ZM, WALL_ZP = 1, 2, 4, 8, 16, 32
 
-LATTICES = {"Q9": Q9, "Q19": Q19, "Q27": Q27}
+LATTICES = {"Q9": Q9, "Q19": Q19, "Q27": Q27, "Q5": Q5, "Q7": Q7}
 EQUATIONS = {"NSE": NSE, "NCDE": NCDE}
 STORAGES = {"f64": F64, "f32dev": F32DEV, "f16dev": F16DEV}
 PATTERNS = {"AB": AB, "AA": AA}
-Q_OF = {Q9: 9, Q19: 19, Q27: 27}
+Q_OF = {Q9: 9, Q19: 19, Q27: 27, Q5: 5, Q7: 7}
+DIM_OF = {Q9: 2, Q19: 3, Q27: 3, Q5: 2, Q7: 3}
 
 
 class Params(C.Structure):
@@ -196,7 +197,7 @@ class Domain:
         import torch
         self.params = params
         self.q = Q_OF[params.lattice]
-        self.d = 2 if params.lattice == Q9 else 3
+        self.d = DIM_OF[params.lattice]
         self.N = params.n[0] * params.n[1] * params.n[2]
         dt = getattr(torch, _STORE_DTYPES[params.storage])
         self.f0 = torch.empty(self.q * self.N, dtype=dt, device=device)
@@ -214,7 +215,7 @@ class Domain:
         self = cls.__new__(cls)
         self.params = params
         self.q = Q_OF[params.lattice]
-        self.d = 2 if params.lattice == Q9 else 3
+        self.d = DIM_OF[params.lattice]
         self.N = params.n[0] * params.n[1] * params.n[2]
         self.f0, self.f1, self.solid = f0, f1, solid
         self._ctx = ctx

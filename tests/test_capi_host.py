@@ -57,6 +57,22 @@ def test_derived_parameters_match_oracle(case):
     assert abs(d.s_hi - m.s_hi) < 1e-14
 
 
+@pytest.mark.parametrize("case", [
+    dict(lattice="Q5", equation="NCDE", n=(8, 8, 1), dx=(1.0, 0.5, 1.0), D0=0.01),
+    dict(lattice="Q5", equation="NCDE", n=(8, 8, 1), dx=(1.0, 1.0, 1.0), cs2=1.0 / 3.0, D0=0.01),
+    dict(lattice="Q7", equation="NCDE", n=(4, 4, 4), dx=(1.0, 0.5, 2.0), D0=0.01, s_hi=1.2),
+    dict(lattice="Q7", equation="NCDE", n=(4, 4, 4), dx=(1.0, 1.0, 1.0), D0=0.01),   # w_0 = 0
+])
+def test_reduced_lattice_weights_match_oracle(case):
+    m = O.Model(dict(case, rho0=0.0))
+    d = rmrt.derive(rmrt.make_params(**case))
+    assert d.q == m.q and d.d == m.d
+    assert abs(d.cs2 - m.cs2) < 1e-15
+    np.testing.assert_allclose(np.array(d.w)[: m.q], m.w, rtol=0, atol=1e-15)
+    assert min(d.w[: m.q]) >= 0.0
+    assert abs(d.s_hi - m.s_hi) < 1e-14
+
+
 def test_population_bytes():
     p = rmrt.make_params(lattice="Q27", storage="f16dev", n=(10, 20, 30), nu=0.05)
     assert rmrt.population_bytes(p) == 27 * 6000 * 2
@@ -74,6 +90,12 @@ def test_population_bytes():
     dict(lattice="Q9", n=(8, 8, 1), dx=(0.0, 1.0, 1.0)),
     dict(lattice="Q9", n=(8, 8, 1), nu=0.1, s_hi=2.5),                  # rate outside (0, 2)
     dict(lattice="Q19", n=(4, 4, 4), nu=0.1, nu_b=0.0),
+    dict(lattice="Q5", n=(8, 8, 1), nu=0.1),                          # reduced lattices: NCDE only
+    dict(lattice="Q7", n=(4, 4, 4), equation="NCDE", D0=0.01, storage="f16dev"),  # w_0 = 0 with FP16
+    dict(lattice="Q5", n=(8, 8, 2), equation="NCDE", D0=0.01),
+    dict(lattice="Q5", n=(8, 8, 1), equation="NCDE", D0=0.01, cs2=0.6),   # w_0 < 0
+    dict(lattice="Q27", n=(4, 4, 4), nu=0.05, w_corner=0.0, storage="f16dev"),
+    dict(lattice=5, n=(4, 4, 4), equation="NCDE", D0=0.01),           # unknown lattice
 ])
 def test_invalid_parameters_rejected(bad):
     with pytest.raises(rmrt.RMRTError) as ei:

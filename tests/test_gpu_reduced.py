@@ -1,0 +1,210 @@
+"""GPU parity of the reduced NCDE lattices rD2Q5 and rD3Q7 (linear
+equilibrium, dB/dt auxiliary term from the library-held history field,
+eq. 4-16) against the FP64 oracle, through the C ABI."""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+from gpu_util import WALLS, circle_mask, rel_err
+from inputs import gaussian_hill_field
+from oracle import rmrt_oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rmrt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_00366_amd import rmrt as R
+    return R
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = {
+    # name: (parameters, solid-mask builder or None, steps)
+    "q5_periodic": (dict(lattice="Q5", equation="NCDE", n=(37, 23, 1), dx=(1.0, 0.5, 1.0), D0=0.02, D2=0.5,
+                         adv=(0.04, -0.02, 0.0), rho0=0.0), None, 25),
+    "q5_channel_solid_source": (dict(lattice="Q5", equation="NCDE", n=(40, 21, 1), dx=(1.0, 2.0, 1.0), D0=0.05,
+                                     D2=1.0, adv=(0.06, 0.0, 0.0), source=1e-3, wall_faces=WALLS["y"], rho0=0.0),
+                                lambda n: circle_mask(n, (12, 10), 4), 25),
+    "q5_standard_no_advection": (dict(lattice="Q5", equation="NCDE", n=(16, 12, 1), dx=(1.0, 1.0, 1.0),
+                                      cs2=1.0 / 3.0, D0=0.1, rho0=0.0, s_hi=1.3), None, 21),
+    "q7_periodic": (dict(lattice="Q7", equation="NCDE", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), D0=0.02, D2=0.5,
+                         adv=(0.03, -0.01, 0.02), rho0=0.0), None, 15),
+    "q7_walls_source": (dict(lattice="Q7", equation="NCDE", n=(9, 10, 12), dx=(1.0, 1.0, 0.5), cs2=0.05, D0=0.03,
+                             D2=0.2, adv=(0.02, 0.01, 0.0), source=-2e-4, wall_faces=WALLS["z"], rho0=0.0), None, 15),
+}
+
+
+def _fields(m, case):
+    rng = np.random.default_rng(zlib.crc32(case.encode()) % 1000)
+    return 0.2 + 0.8 * rng.uniform(0.0, 1.0, size=m.N)
+
+
+def _build(case, R, storage="f64", pattern="AB"):
+    prm, solid_fn, steps = CASES[case]
+    m = O.Model(prm, solid=None if solid_fn is None else solid_fn(prm["n"]))
+    phi = _fields(m, case)
+    solid = None if solid_fn is None else m.solid.astype(np.uint8)
+    dom = R.Domain(R.make_params(**prm, storage=storage, pattern=pattern), phi, None, solid=solid)
+    return m, dom, phi, steps
+
+
+_oracle_cache = {}
+
+
+def _oracle(case, m, phi, steps):
+    if case not in _oracle_cache:
+        f0 = m.init(phi, None)
+        f, h = m.step(f0, steps, m.init_history(phi))
+        _oracle_cache[case] = (f0, f)
+    return _oracle_cache[case]
+
+
+@pytest.mark.parametrize("pattern", ["AB", "AA"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_f64_populations_match_oracle(rmrt, case, pattern):
+    say(f"[reduced f64] {case} {pattern}")
+    m, dom, phi, steps = _build(case, rmrt, "f64", pattern)
+    f0, f_or = _oracle(case, m, phi, steps)
+    fl = m.fluid
+    assert rel_err(dom.populations().cpu().numpy()[:, fl], f0[:, fl]) < 1e-14
+    dom.step(steps)                   # odd counts end AA on the swapped layout
+    g = dom.populations().cpu().numpy()
+    err = rel_err(g[:, fl], f_or[:, fl])
+    say(f"   max rel |f - f_oracle| = {err:.3e}")
+    assert err < 1e-12
+    p_g, _ = dom.moments(with_u=False)
+    p_o, _ = m.macroscopic(f_or)
+    assert np.abs(p_g.cpu().numpy()[fl] - p_o[fl]).max() < 1e-12 * np.abs(p_o).max()
+    dom.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("f32dev", 1e-5), ("f16dev", 3e-3)])
+@pytest.mark.parametrize("case", list(CASES))
+def test_reduced_precision_storage(rmrt, case, storage, tol):
+    say(f"[reduced {storage}] {case}")
+    m, dom, phi, steps = _build(case, rmrt, storage, "AA")
+    _, f_or = _oracle(case, m, phi, steps)
+    dom.step(steps)
+    p_g, _ = dom.moments(with_u=False)
+    p_o, _ = m.macroscopic(f_or)
+    fl = m.fluid
+    err = np.abs(p_g.cpu().numpy()[fl] - p_o[fl]).max() / np.abs(phi).max()
+    say(f"   max |phi - phi_oracle| / peak = {err:.3e}")
+    assert err < tol
+    dom.close()
+
+
+@pytest.mark.parametrize("case", ["q5_channel_solid_source", "q7_periodic"])
+def test_aa_ab_and_two_nodes_per_thread_bitwise(rmrt, case):
+    say(f"[reduced AA==AB, paired] {case}")
+    out = []
+    for pattern, fl in (("AB", 0), ("AA", 0), ("AA", rmrt.LAUNCH_WIDE_TILES)):
+        m, dom, phi, steps = _build(case, rmrt, "f32dev", pattern)
+        dom.set_launch(0, fl)
+        dom.step(steps)
+        out.append(dom.populations().cpu().numpy()[:, m.fluid])
+        dom.close()
+    for g in out[1:]:
+        assert np.array_equal(g, out[0])
+
+
+def test_set_fields_resets_the_history(rmrt):
+    """Re-initialising after some steps (odd parity included) behaves exactly
+    like a fresh domain: the history field restarts at the new phi."""
+    say("[reduced] set_fields resets history")
+    case = "q5_periodic"
+    m, dom, phi, steps = _build(case, rmrt, "f64", "AA")
+    dom.step(7)
+    phi2 = 0.3 + 0.5 * np.random.default_rng(11).uniform(size=m.N)
+    dom.set_fields(phi2, None)
+    dom.step(9)
+    g = dom.populations().cpu().numpy()
+    dom.close()
+    f, _ = m.step(m.init(phi2, None), 9, m.init_history(phi2))
+    assert rel_err(g, f) < 1e-12
+
+
+def test_batch_of_q5_domains_matches_oracle(rmrt):
+    say("[reduced] batch of rD2Q5 domains")
+    specs = [dict(lattice="Q5", equation="NCDE", n=(19, 11, 1), dx=(1.0, 0.5, 1.0), D0=0.02, D2=0.3,
+                  adv=(0.03, 0.01, 0.0), rho0=0.0),
+             dict(lattice="Q5", equation="NCDE", n=(8, 30, 1), dx=(1.0, 2.0, 1.0), D0=0.05,
+                  adv=(0.0, 0.05, 0.0), source=1e-3, wall_faces=WALLS["y"], rho0=0.0)]
+    b = rmrt.Batch([rmrt.make_params(**p, storage="f64", pattern="AA") for p in specs])
+    ref = []
+    for k, (d, p) in enumerate(zip(b.domains, specs)):
+        m = O.Model(p)
+        phi = 0.2 + 0.7 * np.random.default_rng(40 + k).uniform(size=m.N)
+        d.set_fields(phi, None)
+        ref.append(m.step(m.init(phi, None), 13, m.init_history(phi))[0])
+    b.step(13)
+    for d, f in zip(b.domains, ref):
+        assert rel_err(d.populations().cpu().numpy(), f) < 1e-12
+    b.close()
+
+
+def _sampled_next_step(rmrt, prm, phi0, storage, warm, samples, seed):
+    """Full-size launch: `warm` steps, then one step checked at sampled nodes
+    against the oracle collision of the GPU's own state and history."""
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage=storage, pattern="AA"), phi0, None)
+    dom.step(warm - 1)
+    phi_prev = dom.moments(with_u=False)[0].cpu().numpy()     # history after the next step
+    dom.step(1)
+    f_now = dom.populations().cpu().numpy()
+    dom.step(1)
+    f_next = dom.populations()
+    nx, ny, nz = prm["n"]
+    N = nx * ny * nz
+    rng = np.random.default_rng(seed)
+    idx = np.concatenate([rng.integers(0, N, size=samples), [0, N - 1]])
+    E = O.unit_offsets(prm["lattice"])
+    q = E.shape[0]
+    E3 = np.zeros((q, 3), dtype=np.int64)
+    E3[:, : E.shape[1]] = E
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    ups = np.stack([((x - E3[j, 0]) % nx) + nx * (((y - E3[j, 1]) % ny) + ny * ((z - E3[j, 2]) % nz))
+                    for j in range(q)]).reshape(-1)
+    sub = dict(prm, n=(ups.size, 1, 1), wall_faces=0)   # one node per (sample, direction)
+    mo = O.Model(sub)
+    fstar = mo.collide(f_now[:, ups], phi_prev[ups])
+    S = idx.size
+    expect = np.stack([fstar[j, j * S:(j + 1) * S] for j in range(q)])
+    got = f_next[:, torch.as_tensor(idx, device=f_next.device)].cpu().numpy()
+    dom.close()
+    return got, expect
+
+
+@pytest.mark.parametrize("lat,n,dx,storage,tol", [
+    ("Q5", (2048, 1024, 1), (1.0, 0.5, 1.0), "f32dev", 2e-6),
+    ("Q7", (256, 256, 128), (1.0, 1.0, 2.0), "f32dev", 2e-6),
+    ("Q7", (256, 256, 128), (1.0, 1.0, 2.0), "f16dev", 2e-3),
+])
+def test_full_size_sampled_step(rmrt, lat, n, dx, storage, tol):
+    """The benchmark workloads at full size in the benchmark's launch
+    configuration: after 9 steps (so dB/dt is non-zero), one more step at 4096
+    sampled nodes against the oracle collision of the GPU state."""
+    say(f"[reduced full size sampled] {lat} {n} {storage}")
+    prm = dict(lattice=lat, equation="NCDE", n=n, dx=dx, D0=0.01, D2=1.0, adv=(0.05, 0.02, 0.01)[: 2 if lat == "Q5" else 3],
+               rho0=0.0)
+    if lat == "Q5":
+        phi0 = gaussian_hill_field(n[0], n[1], dx[0], dx[1], 40.0, 1024.0, 256.0)
+    else:
+        x = np.arange(n[0]) * dx[0]
+        y = np.arange(n[1]) * dx[1]
+        z = np.arange(n[2]) * dx[2]
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+        phi0 = np.exp(-((X - 128) ** 2 + (Y - 128) ** 2 + (Z - 128) ** 2) / (2 * 24.0**2)).reshape(-1)
+    got, expect = _sampled_next_step(rmrt, prm, phi0, storage, 9, 4096, 7)
+    err = np.abs(got - expect).max() / np.abs(expect).max()
+    say(f"   sampled max rel err {err:.2e}")
+    assert err < tol
