@@ -13,8 +13,12 @@
  *   - Lattice units: c_a = dx_a / dt.  Nodes are indexed x-fastest:
  *     node = x + nx * (y + ny * z); 2D problems use nz = 1.
  *   - Population buffers are structure-of-arrays: slot j of node i lives at
- *     element j * N + i (N = nx*ny*nz), j in the paper's velocity order
- *     (rD2Q9 eq. 3-1, rD3Q27 eq. 3-2; rD3Q19 = first 19 of rD3Q27).
+ *     element j * ld + i, j in the paper's velocity order (rD2Q9 eq. 3-1,
+ *     rD3Q27 eq. 3-2; rD3Q19 = first 19 of rD3Q27; rD2Q5 / rD3Q7 = first
+ *     5 / 7).  The stream stride ld >= N = nx*ny*nz is the library's choice
+ *     for N and the storage: size buffers with rmrt_population_bytes
+ *     (= q * ld * element size); elements [j ld + N, (j + 1) ld) are padding
+ *     that no call reads or writes.
  *   - Stored values are deviations from the rest equilibrium:
  *       RMRT_F64    : double  d_j = fbar_j - w_j rho0
  *       RMRT_F32DEV : float   d_j = fbar_j - w_j rho0
@@ -149,7 +153,8 @@ int rmrt_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
  */
 int rmrt_derive(const rmrt_params* p, rmrt_derived* out);
 
-/* Bytes of one population buffer for p (q * N * element size). Host only. */
+/* Bytes of one population buffer for p (q * ld * element size, ld >= N the
+ * stream stride above). Host only. */
 int rmrt_population_bytes(const rmrt_params* p, size_t* bytes);
 
 /*

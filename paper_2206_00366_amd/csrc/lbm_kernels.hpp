@@ -106,8 +106,9 @@ struct Geo {
     constexpr int ex = Lat<L>::e(J, 0), ey = Lat<L>::e(J, 1), ez = Lat<L>::e(J, 2);
     return ox[ex + 1] + oy[ey + 1] + oz[ez + 1];
   }
-  // does the link from this node along e_J hit a wall face or a solid node?
-  template <int L, int J>
+  // does the link from this node along e_J hit a wall face (or, with SOLID, a
+  // solid node of the byte mask)?
+  template <int L, int J, bool SOLID = true>
   __device__ __forceinline__ bool bounce(const DomainDev& Dm, uint32_t idx) const {
     constexpr int ex = Lat<L>::e(J, 0), ey = Lat<L>::e(J, 1), ez = Lat<L>::e(J, 2);
     if constexpr (ex == 0 && ey == 0 && ez == 0) return false;
@@ -118,7 +119,8 @@ struct Geo {
     if constexpr (ey > 0) b = b || hi[1];
     if constexpr (ez < 0) b = b || lo[2];
     if constexpr (ez > 0) b = b || hi[2];
-    if (Dm.has_solid) b = b || (to_global(Dm.solid)[idx + (uint32_t)off<L, J>()] != 0);
+    if constexpr (SOLID)
+      if (Dm.has_solid) b = b || (to_global(Dm.solid)[idx + (uint32_t)off<L, J>()] != 0);
     return b;
   }
 };
@@ -136,15 +138,15 @@ struct LinkBits {
 // population j of node idx, in the natural (own) or swapped layout.
 template <int L, int BC, bool SWAPPED, int J, int D>
 __device__ __forceinline__ size_t read_elem(const DomainDev& Dm, const Geo<D>& g, uint32_t idx) {
-  const size_t N = Dm.N;
+  const size_t LD = Dm.ld;
   if constexpr (!SWAPPED) {
-    return (size_t)J * N + idx;
+    return (size_t)J * LD + idx;
   } else {
     constexpr int O = Lat<L>::opp(J);
     if constexpr (BC == 1) {
-      if (g.template bounce<L, O>(Dm, idx)) return (size_t)J * N + idx;
+      if (g.template bounce<L, O>(Dm, idx)) return (size_t)J * LD + idx;
     }
-    return (size_t)O * N + (uint32_t)(idx + (uint32_t)g.template off<L, O>());
+    return (size_t)O * LD + (uint32_t)(idx + (uint32_t)g.template off<L, O>());
   }
 }
 
@@ -168,15 +170,18 @@ struct NodeStep {
   bool live;   // a fluid node to update
   T phi_prev;  // rD2Q5 / rD3Q7: phi of the previous step
 
+  // Boundary modes: 0 periodic; 1 wall faces from the coordinates (the host
+  // never pairs it with a solid mask: a mask selects mode 2); 2 link words.
+  // Bounced links pick their address with a select, not a branch, so the
+  // wave's q loads and stores stay back to back.
+
   // Read the q populations of node idx_ (nothing for solid or invalid nodes).
   __device__ __forceinline__ void load(const DomainDev& Dm, const Coef<T>& C, const gmem<S>* fin, uint32_t idx_,
                                        bool valid) {
     idx = idx_;
     live = valid;
     lb = 0;
-    if constexpr (BC == 1) {
-      if (live && Dm.has_solid && to_global(Dm.solid)[idx]) live = false;
-    } else if constexpr (BC == 2) {
+    if constexpr (BC == 2) {
       if (live) {
         lb = to_global((const LW*)Dm.links)[idx];
         if (lb & LinkBits<L>::kSolid) live = false;
@@ -185,7 +190,7 @@ struct NodeStep {
     if (!live) return;
     if constexpr (Lat<L>::linear) phi_prev = to_global((const T*)Dm.hist)[idx];
     if constexpr (PH != PH_AA_EVEN) g.make(Dm, idx);
-    const uint32_t N = Dm.N;
+    const uint32_t LD = Dm.ld;   // stream stride
     static_for<0, NS>([&](auto s_) {
       constexpr int s = decltype(s_)::value;
       if constexpr (Lat<L>::absent(s)) t[s] = T(0);
@@ -197,17 +202,20 @@ struct NodeStep {
         // swapped layout: the value for direction J sits in slot O of the
         // upstream node, or in this node's own slot J when that link bounced
         constexpr int O = Lat<L>::opp(J);
-        bool b = false;
-        if constexpr (BC == 2)
-          b = (lb >> O) & 1;
-        else if constexpr (BC == 1)
-          b = g.template bounce<L, O>(Dm, idx);
-        if (b)
-          v = ld_elem(fin + (size_t)J * N, idx);
-        else
-          v = ld_elem(fin + (size_t)O * N, (uint32_t)(idx + (uint32_t)g.template off<L, O>()));
+        const gmem<S>* pu = fin + (size_t)O * LD + (uint32_t)(idx + (uint32_t)g.template off<L, O>());
+        if constexpr (BC == 0) {
+          v = *pu;
+        } else {
+          bool b;
+          if constexpr (BC == 2)
+            b = (lb >> O) & 1;
+          else
+            b = g.template bounce<L, O, false>(Dm, idx);
+          const gmem<S>* po = fin + (size_t)J * LD + idx;
+          v = *(b ? po : pu);
+        }
       } else {
-        v = ld_elem(fin + (size_t)J * N, idx);
+        v = ld_elem(fin + (size_t)J * LD, idx);
       }
       t[Lat<L>::slot(J)] = SS::template dec<J>(v, C);
     });
@@ -223,25 +231,24 @@ struct NodeStep {
     } else {
       collide<L, EQ, FORCE>(t, C);
     }
-    const uint32_t N = Dm.N;
+    const uint32_t LD = Dm.ld;   // stream stride
     static_for<0, Q>([&](auto j_) {
       constexpr int J = decltype(j_)::value;
       constexpr int O = Lat<L>::opp(J);
       const S v = SS::template enc<J>(t[Lat<L>::slot(J)], C);
       if constexpr (PH == PH_AA_EVEN) {
-        st_elem(fout + (size_t)O * N, idx, v);
+        st_elem(fout + (size_t)O * LD, idx, v);
       } else if constexpr (BC == 0) {
-        st_elem(fout + (size_t)J * N, (uint32_t)(idx + (uint32_t)g.template off<L, J>()), v);
+        st_elem(fout + (size_t)J * LD, (uint32_t)(idx + (uint32_t)g.template off<L, J>()), v);
       } else {
         bool b;
         if constexpr (BC == 2)
           b = (lb >> J) & 1;
         else
-          b = g.template bounce<L, J>(Dm, idx);
-        if (b)
-          st_elem(fout + (size_t)O * N, idx, v);
-        else
-          st_elem(fout + (size_t)J * N, (uint32_t)(idx + (uint32_t)g.template off<L, J>()), v);
+          b = g.template bounce<L, J, false>(Dm, idx);
+        gmem<S>* pd = fout + (size_t)J * LD + (uint32_t)(idx + (uint32_t)g.template off<L, J>());
+        gmem<S>* pb = fout + (size_t)O * LD + idx;
+        *(b ? pb : pd) = v;
       }
     });
   }
@@ -685,9 +692,9 @@ __global__ void __launch_bounds__(256)
         constexpr int O = Lat<L>::opp(J);
         bool b = false;
         b = g.template bounce<L, O>(Dm, idx);
-        e_out = b ? (size_t)J * N + idx : (size_t)O * N + (uint32_t)(idx + (uint32_t)g.template off<L, O>());
+        e_out = b ? (size_t)J * Dm.ld + idx : (size_t)O * Dm.ld + (uint32_t)(idx + (uint32_t)g.template off<L, O>());
       } else {
-        e_out = (size_t)J * N + idx;
+        e_out = (size_t)J * Dm.ld + idx;
       }
       if (!(Dm.has_solid && Dm.solid[idx])) f[e_out] = enc64<ST, J>(v, C);
     });

@@ -44,6 +44,7 @@ struct DomainDev {
   Coef<float> cf;
   InitCoef ic;
   uint32_t nx, ny, nz, N;
+  uint32_t ld;              // stream stride: population j of node i is element j * ld + i
   uint32_t nxny;
   uint32_t mnx, mnxny;      // floor(2^32 / divisor) (0xffffffff for divisor 1)
   uint32_t walls;           // RMRT_WALL_* bits

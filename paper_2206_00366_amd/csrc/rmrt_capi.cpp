@@ -62,6 +62,24 @@ int lattice_q(int lat) {
   }
 }
 bool lattice_2d(int lat) { return lat == RMRT_Q9 || lat == RMRT_Q5; }
+
+size_t elem_size(int storage) { return storage == RMRT_F64 ? 8 : (storage == RMRT_F32DEV ? 4 : 2); }
+
+// Stream stride (in elements) of the population layout for N nodes: stream j
+// occupies elements [j ld, j ld + N) of a population buffer.  Measured on
+// MI355X (rD3Q19 FP32, cap 3): with ld = N, 256 x 256 x 127 and 200 x 160 x 260
+// run at 4.6 TB/s against 5.6 TB/s at 256 x 256 x 128; a stream stride of
+// 31.75 MiB (64 KiB-aligned) is as slow, strides that are whole MiB run at
+// 5.3-5.6 TB/s.  Streams of 16 MiB and more are therefore padded to whole MiB,
+// streams of 1-16 MiB to 64 KiB (the 64-domain rD3Q27 batch: 4.6 -> 5.0 TB/s),
+// smaller ones to 4 KiB; the padding costs at most 1/16 of the buffer beyond
+// 1 MiB per stream.
+uint32_t stream_ld(uint32_t N, int storage) {
+  const uint64_t es = elem_size(storage);
+  const uint64_t bytes = (uint64_t)N * es;
+  const uint64_t align = bytes >= (16u << 20) ? (1u << 20) : (bytes >= (1u << 20) ? (64u << 10) : 4096u);
+  return (uint32_t)((bytes + align - 1) / align * align / es);
+}
 bool lattice_linear(int lat) { return lat == RMRT_Q5 || lat == RMRT_Q7; }
 
 int derive(const rmrt_params* p, Derived& v) {
@@ -81,6 +99,8 @@ int derive(const rmrt_params* p, Derived& v) {
   if (v.d == 2 && p->n[2] != 1) return fail(RMRT_EINVAL, "2D lattices need n[2] == 1");
   const double N = (double)p->n[0] * p->n[1] * p->n[2];
   if (N * v.q >= 4294967295.0) return fail(RMRT_EUNSUPPORTED, "q * N must be below 2^32");
+  if ((double)stream_ld((uint32_t)N, p->storage) * v.q >= 4294967295.0)
+    return fail(RMRT_EUNSUPPORTED, "q * stream stride must be below 2^32");
   v.dt = p->dt > 0 ? p->dt : 1.0;
   for (int a = 0; a < 3; ++a) {
     double dx = (a < v.d) ? p->dx[a] : 1.0;
@@ -309,6 +329,7 @@ void fill_domain(const rmrt_params* p, const Derived& v, DomainDev& D, void* fa,
   D.nz = p->n[2];
   D.nxny = D.nx * D.ny;
   D.N = D.nxny * D.nz;
+  D.ld = stream_ld(D.N, p->storage);
   D.mnx = magic(D.nx);
   D.mnxny = magic(D.nxny);
   D.walls = p->wall_faces & 63u;
@@ -333,7 +354,6 @@ bool has_force(const rmrt_params* p) {
   return false;
 }
 
-size_t elem_size(int storage) { return storage == RMRT_F64 ? 8 : (storage == RMRT_F32DEV ? 4 : 2); }
 
 // ---------------------------------------------------------------------------
 // Dispatch onto the per-(lattice, storage) instantiations
@@ -395,11 +415,20 @@ constexpr uint32_t kDefaultFlags = 0u;
 void default_launch(const rmrt_params& p, int& blocks_per_cu, uint32_t& flags) {
   blocks_per_cu = 0;
   flags = 0u;
-  // measured on MI355X at 256 x 256 x 128: FP32/FP64 3D gain from a cap of 3
-  // workgroups per CU; FP16 rD3Q19 from two nodes per thread (its 128-byte
-  // wave loads leave too few bytes in flight with one)
+  // measured on MI355X at 256 x 256 x 128: FP32/FP64 rD3Q19/rD3Q27 gain from a
+  // cap of 3 workgroups per CU; FP16 rD3Q19 from two nodes per thread (its
+  // 128-byte wave loads leave too few bytes in flight with one).  The reduced
+  // lattices have only 5 or 7 loads per node and want every wave they can get
+  // (rD3Q7 FP32: 6.9 TB/s uncapped, 5.9 with the cap).
   if (p.lattice == RMRT_Q9) {
     flags = STEP_XCD_ORDER;
+  } else if (p.lattice == RMRT_Q5) {
+    flags = p.storage == RMRT_F16DEV ? STEP_XCD_ORDER : 0u;
+  } else if (p.lattice == RMRT_Q7) {
+    if (p.storage == RMRT_F64)
+      blocks_per_cu = 3;
+    else
+      flags = STEP_XCD_ORDER;
   } else if (p.storage != RMRT_F16DEV) {
     blocks_per_cu = 3;
   } else if (p.lattice == RMRT_Q19) {
@@ -679,7 +708,8 @@ int rmrt_population_bytes(const rmrt_params* p, size_t* bytes) {
   int rc = derive(p, v);
   if (rc != RMRT_OK) return rc;
   if (!bytes) return fail(RMRT_EINVAL, "bytes is NULL");
-  *bytes = (size_t)v.q * p->n[0] * p->n[1] * p->n[2] * elem_size(p->storage);
+  const uint32_t N = (uint32_t)p->n[0] * (uint32_t)p->n[1] * (uint32_t)p->n[2];
+  *bytes = (size_t)v.q * stream_ld(N, p->storage) * elem_size(p->storage);
   return RMRT_OK;
 }
 

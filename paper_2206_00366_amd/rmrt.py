@@ -200,7 +200,8 @@ class Domain:
         self.d = DIM_OF[params.lattice]
         self.N = params.n[0] * params.n[1] * params.n[2]
         dt = getattr(torch, _STORE_DTYPES[params.storage])
-        self.f0 = torch.empty(self.q * self.N, dtype=dt, device=device)
+        esize = torch.empty(0, dtype=dt).element_size()
+        self.f0 = torch.empty(population_bytes(params) // esize, dtype=dt, device=device)
         self.f1 = torch.empty_like(self.f0) if params.pattern == AB else None
         self.solid = None if solid is None else torch.as_tensor(solid, dtype=torch.uint8, device=device).contiguous()
         rho = torch.as_tensor(rho, dtype=torch.float64, device=device).contiguous()
@@ -298,10 +299,9 @@ class Batch:
         arr = (Params * nd)(*self.params)
         self.f0, self.f1, self.solids = [], [], []
         for k, p in enumerate(self.params):
-            q = Q_OF[p.lattice]
-            N = p.n[0] * p.n[1] * p.n[2]
             dt = getattr(torch, _STORE_DTYPES[p.storage])
-            self.f0.append(torch.empty(q * N, dtype=dt, device=device))
+            esize = torch.empty(0, dtype=dt).element_size()
+            self.f0.append(torch.empty(population_bytes(p) // esize, dtype=dt, device=device))
             self.f1.append(torch.empty_like(self.f0[-1]) if p.pattern == AB else None)
             s = None if solids is None or solids[k] is None else torch.as_tensor(
                 solids[k], dtype=torch.uint8, device=device).contiguous()

@@ -74,10 +74,28 @@ def test_reduced_lattice_weights_match_oracle(case):
 
 
 def test_population_bytes():
+    """q streams of stride ld: the stream size rounded up to 4 KiB below 1 MiB,
+    to 64 KiB below 16 MiB and to whole MiB above."""
     p = rmrt.make_params(lattice="Q27", storage="f16dev", n=(10, 20, 30), nu=0.05)
-    assert rmrt.population_bytes(p) == 27 * 6000 * 2
+    assert rmrt.population_bytes(p) == 27 * 12288                      # 12000 B -> 3 x 4 KiB
     p = rmrt.make_params(lattice="Q9", storage="f64", n=(10, 20, 1), nu=0.05)
-    assert rmrt.population_bytes(p) == 9 * 200 * 8
+    assert rmrt.population_bytes(p) == 9 * 4096
+    p = rmrt.make_params(lattice="Q19", storage="f32dev", n=(256, 256, 128), nu=0.05)
+    assert rmrt.population_bytes(p) == 19 * 4 * 256 * 256 * 128        # 32 MiB: no padding
+    p = rmrt.make_params(lattice="Q19", storage="f32dev", n=(256, 256, 127), nu=0.05)
+    assert rmrt.population_bytes(p) == 19 * (32 << 20)                 # 31.75 MiB -> 32 MiB
+    p = rmrt.make_params(lattice="Q27", storage="f32dev", n=(100, 50, 60), nu=0.05)
+    assert rmrt.population_bytes(p) == 27 * (1216 << 10)               # 1.14 MiB -> 19 x 64 KiB
+    for n in [(7, 5, 3), (97, 89, 83), (300, 200, 100), (1000, 1000, 1)]:
+        for st, es in (("f64", 8), ("f32dev", 4), ("f16dev", 2)):
+            p = rmrt.make_params(lattice="Q19" if n[2] > 1 else "Q9", storage=st, n=n, nu=0.05)
+            q = 19 if n[2] > 1 else 9
+            b = rmrt.population_bytes(p)
+            assert b % q == 0
+            stream = b // q
+            N = n[0] * n[1] * n[2]
+            assert N * es <= stream < N * es * 1.0625 + 4096
+            assert stream % 4096 == 0
 
 
 @pytest.mark.parametrize("bad", [
