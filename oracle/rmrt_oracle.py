@@ -478,6 +478,48 @@ class Model:
         """phi(t - dt) at t = 0 for the reduced lattices: the initial phi (A18)."""
         return np.array(phi, dtype=np.float64).reshape(self.N)
 
+    # ------------------------------------------------------- local gradients
+    def local_gradients(self, fbar, hist=None):
+        """Local (no finite differences) derivative outputs of a state.
+
+        NSE: the generalized shear stress of eq. 4-32-0 (first line),
+            tau = -(I - S_2/2) [m_2^ne + dt/2 (u F + F u + (cs2 I - u u) S)],
+        with m_2^ne = sum_k c_k c_k f_k^ne, f = fbar + dt F / 2 (eq. 2-3), and the
+        strain rate E = (grad u + grad u^T) / 2 from eq. 4-28 with the isotropic
+        tensors K_mu = rho nu I, K_mu_b = rho nu_b I of eq. 4-31:
+            tr E = tr tau / (d rho nu_b),  E = (tau - (rho nu_b - 2 rho nu / d) tr E I) / (2 rho nu).
+        Returns (tau, E), each (d, d, N).
+
+        NCDE: grad phi from eq. 4-13 with D = phi I and K = D(phi) I:
+            -D(phi) grad phi = (1 - s_1/2) (m_1^ne + dt/2 X),
+        X = u_adv S for C = phi u u (first branch) or the dB/dt of eq. 4-16
+        (second branch, reduced lattices; hist = phi of the previous step).
+        Returns grad phi, (d, N)."""
+        d = self.d
+        n = fbar.shape[1]
+        feq, F, G, s1 = self.distributions(fbar, hist)
+        fne = fbar + 0.5 * self.dt * F - feq
+        if self.nse:
+            rho, u = self.macroscopic(fbar)
+            I = np.eye(d)[:, :, None]
+            m2ne = np.einsum("ja,jb,jn->abn", self.C, self.C, fne)
+            Sb, Fb = self.source, self.force
+            T = (np.einsum("an,b->abn", u, Fb) + np.einsum("a,bn->abn", Fb, u)
+                 + (self.cs2 * I - np.einsum("an,bn->abn", u, u)) * Sb)
+            tau = -self._apply_I_minus_half_S2(m2ne + 0.5 * self.dt * T)
+            mu, mub = rho * self.nu, rho * self.nu_b
+            trE = np.einsum("aan->n", tau) / (d * mub)
+            E = (tau - (mub - 2.0 * mu / d)[None, None] * trE[None, None] * I) / (2.0 * mu)[None, None]
+            return tau, E
+        phi, u = self.macroscopic(fbar)
+        m1ne = self.C.T @ fne
+        if self.linear:
+            X = u * (phi - hist)[None] / self.dt
+        else:
+            X = u * self.source
+        D = self.p["D0"] * (1.0 + self.p["D2"] * phi**2)
+        return -(1.0 - 0.5 * s1)[None] * (m1ne + 0.5 * self.dt * X) / D[None]
+
     # ---------------------------------------------------------- initialisation
     def init(self, rho, u, with_fne=False):
         """fbar(t=0) = f_eq(rho, u) - dt F / 2 [+ f_ne from eq. fne].
