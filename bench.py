@@ -175,7 +175,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--only", default="all",
-                    help="comma list of: q19,q19f16,q19f64,q9ncde,q5ncde,q7ncde,q27,q27batch,q9tg,copy "
+                    help="comma list of: q19,q19f16,q19f64,q19local,q9ncde,q5ncde,q7ncde,q27,q27batch,q9tg,copy "
                          "(the q19 headline always runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--warmstart", action="store_true",
@@ -206,7 +206,7 @@ def main():
         return
 
     only = set(args.only.split(",")) if args.only != "all" else {"q19f16", "q19f64", "q9ncde", "q27", "q27batch", "q9tg",
-                                                                 "q5ncde", "q7ncde", "copy"}
+                                                                 "q5ncde", "q7ncde", "q19local", "copy"}
     K, W = args.steps, args.warmup
 
     # ---------------- headline: rD3Q19 FP32-dev 256 x 256 x 128 ----------------
@@ -233,6 +233,9 @@ def main():
                 "launch": dict(launch, workgroup=256, tile_nodes=256)}
 
     per = {"rD3Q19_f32dev": head}
+    if "q19local" in only:
+        log("[bench] rD3Q19 strain-rate output")
+        per["rD3Q19_strain_rate_output"] = bench_local(torch, R, prm_h, rho_h, u_h, N_h)
     ceiling = None
     if "copy" in only:
         log("[bench] HBM copy ceiling")
@@ -339,6 +342,30 @@ def main():
         out["cpu_baseline"], ref = cpu_baseline()
         out["accuracy_vs_fp64_oracle"] = accuracy_vs_oracle(torch, R, ref)
     print(json.dumps(out))
+
+
+def bench_local(torch, R, prm, rho, u, N, reps=50):
+    """On-demand strain-rate output of the headline domain (FP32 state, FP32
+    output): HIP-event time per call and its bytes (q populations read, six
+    components written)."""
+    dom = R.Domain(R.make_params(**prm), rho, u)
+    dom.step(3)
+    out = torch.empty(6 * N, dtype=torch.float32, device="cuda")
+    lib = R.lib()
+    def call(n):
+        for _ in range(n):
+            R._check(lib.rmrt_local_gradients(dom._ctx, R.GRAD_STRAIN, R._ptr(out), R.OUT_F32, R._stream()),
+                     "rmrt_local_gradients")
+    wall, ev_ms = timed_steps(torch, call, reps, 3)
+    dom.close()
+    del out
+    torch.cuda.empty_cache()
+    bpn = 19 * 4 + 6 * 4
+    us = ev_ms / reps * 1e3
+    return {"workload": "rmrt_local_gradients(GRAD_STRAIN) on the rD3Q19 256x256x128 FP32-dev state, FP32 output",
+            "us_per_call": round(us, 1), "bytes_per_node": bpn,
+            "kernel_GBps": round(bpn * N / (us * 1e-6) / 1e9, 1),
+            "pct_hbm_peak": round(100 * bpn * N / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 1)}
 
 
 def bench_batch(torch, R, steps, warmup):

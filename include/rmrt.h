@@ -193,6 +193,30 @@ int rmrt_moments(rmrt_ctx* ctx, void* rho_out, void* u_out, int out_dtype, void*
 int rmrt_populations(rmrt_ctx* ctx, double* f_out, void* stream);
 
 /*
+ * Local derivative outputs of the current state, from the non-equilibrium
+ * moments of each node alone (no finite differences), computed in FP64:
+ *   RMRT_GRAD_STRESS (NSE): the generalized shear stress of eq. 4-32-0,
+ *     tau = -(I - S_2/2) [sum_k c_k c_k f_k^ne + dt/2 (u F + F u + (cs2 I - u u) S)]
+ *     with the full second-order relaxation block S_2 of eq. 4-27;
+ *   RMRT_GRAD_STRAIN (NSE): the strain rate (grad u + grad u^T) / 2 from tau
+ *     through eq. 4-28 with K_mu = rho nu I and K_mu_b = rho nu_b I (eq. 4-31);
+ *   RMRT_GRAD_PHI (NCDE): grad phi from eq. 4-13 with D = phi I, K = D(phi) I:
+ *     -D(phi) grad phi = (1 - s_1/2) (sum_k c_k f_k^ne + dt/2 X), X = adv S,
+ *     or adv (phi - phi_prev) / dt on rD2Q5 / rD3Q7 (eq. 4-16).
+ * out: device array (double, or float with RMRT_OUT_F32) of ncomp * N values,
+ * component k of node i at out[k * N + i]; ncomp = 3 (xx, yy, xy) in 2D and 6
+ * (xx, yy, zz, xy, xz, yz) in 3D for stress and strain, d for grad phi.
+ * Solid nodes get zeros.  RMRT_EINVAL for a kind that does not match the
+ * equation.  Accuracy: the stress scheme is exact for steady plane shear and
+ * carries O(Ma) compressibility errors; the grad phi scheme carries an error
+ * of first order in |adv|.
+ */
+#define RMRT_GRAD_STRAIN 0
+#define RMRT_GRAD_STRESS 1
+#define RMRT_GRAD_PHI 2
+int rmrt_local_gradients(rmrt_ctx* ctx, int kind, void* out, int out_dtype, void* stream);
+
+/*
  * FP64 sums over fluid nodes: out[0] = sum rho (or phi), out[1..3] = sum rho u
  * (eq. 2-4-2; the mass and momentum that eq. 4-18-1 conserves).  Synchronises
  * stream.  Returns RMRT_ENONFINITE if any sum is NaN or Inf.

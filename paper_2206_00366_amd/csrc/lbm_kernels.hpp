@@ -473,6 +473,117 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// ----------------------------------------------------------------------------
+// Local derivative outputs (no finite differences), FP64:
+//   NSE : tau = -(I - S_2/2) [m_2^ne + dt/2 (u F + F u + (cs2 I - u u) S)]
+//         (eq. 4-32-0), and the strain rate E from eq. 4-28 with
+//         K_mu = rho nu I, K_mu_b = rho nu_b I (eq. 4-31):
+//         tr E = tr tau / (d rho nu_b), E = (tau - (rho nu_b - 2 rho nu / d) tr E I) / (2 rho nu)
+//   NCDE: -D(phi) grad phi = (1 - s1/2) (m_1^ne + dt/2 X) (eq. 4-13), X = u S, or
+//         u (phi - phi_prev) / dt on rD2Q5 / rD3Q7 (eq. 4-16)
+// m^ne are moments of f - f_eq with f = fbar + dt F / 2; the second moment of
+// F and the first moment of the NCDE F vanish, so they are moments of fbar.
+// Output component k of node i at out[k N + i]: (xx, yy, [zz,] xy, [xz, yz])
+// for tau / E, (x, y[, z]) for grad phi; zero at solid nodes.
+// ----------------------------------------------------------------------------
+enum { GRAD_STRAIN = 0, GRAD_STRESS = 1, GRAD_PHI = 2 };
+
+template <int L, int ST, int EQ, int BC, bool SWAPPED>
+__global__ void __launch_bounds__(256)
+    k_local(const DomainDev* __restrict__ doms, uint32_t dom, uint32_t parity, int ab, void* out, int kind,
+            int out_f32) {
+  const DomainDev& Dm = doms[dom];
+  const Coef<double>& C = Dm.cd;
+  const auto* f = current_buffer<ST>(Dm, parity, ab);
+  constexpr int D = Lat<L>::D;
+  constexpr int NC = (EQ == EQ_NSE) ? D * (D + 1) / 2 : D;
+  const uint32_t N = Dm.N;
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+    double res[6] = {0, 0, 0, 0, 0, 0};
+    if (!(BC == 1 && Dm.has_solid && Dm.solid[idx])) {
+      double d[Lat<L>::Q];
+      gather64<L, ST, BC, SWAPPED>(Dm, f, idx, d);
+      double drho, m1[3];
+      first_moments<L>(Dm, d, drho, m1);
+      const double r = C.rho0 + drho + C.half_source;
+      if constexpr (EQ == EQ_NSE) {
+        // second moments of the deviations: sum c_a c_b d_j (the rest part
+        // w_j rho0 contributes rho0 cs2 I)
+        double m2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        static_for<0, Lat<L>::Q>([&](auto j_) {
+          constexpr int J = decltype(j_)::value;
+          constexpr int e0 = Lat<L>::e(J, 0), e1 = Lat<L>::e(J, 1), e2 = Lat<L>::e(J, 2);
+          if constexpr (e0 != 0) m2[0][0] += d[J];
+          if constexpr (e1 != 0) m2[1][1] += d[J];
+          if constexpr (e2 != 0) m2[2][2] += d[J];
+          if constexpr (e0 * e1 != 0) m2[0][1] += (double)(e0 * e1) * d[J];
+          if constexpr (e0 * e2 != 0) m2[0][2] += (double)(e0 * e2) * d[J];
+          if constexpr (e1 * e2 != 0) m2[1][2] += (double)(e1 * e2) * d[J];
+        });
+        const double ir = 1.0 / r;
+        double u[3];
+        for (int a = 0; a < 3; ++a) u[a] = (m1[a] + C.half_force[a]) * ir;
+        // v = m_2^ne + dt/2 (u F + F u + (cs2 I - u u) S) on the 2nd-order rows
+        double v[3][3];
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) {
+            const double m2ab = (a <= b ? m2[a][b] : m2[b][a]) * C.c[a] * C.c[b] + (a == b ? C.rho0 * C.cs2 : 0.0);
+            v[a][b] = m2ab - (a == b ? r * C.cs2 : 0.0) - r * u[a] * u[b] + u[a] * C.half_force[b] +
+                      C.half_force[a] * u[b] + (a == b ? C.half_cs2_source : 0.0) - u[a] * u[b] * C.half_source;
+          }
+        double tau[3][3];
+        for (int a = 0; a < 3; ++a) {
+          double s = 0.0;
+          for (int b = 0; b < D; ++b) s += C.IhS[a][b] * v[b][b];
+          tau[a][a] = -s;
+        }
+        tau[0][1] = -C.ihs_off[0] * v[0][1];
+        tau[0][2] = -C.ihs_off[1] * v[0][2];
+        tau[1][2] = -C.ihs_off[2] * v[1][2];
+        double o[3][3];
+        if (kind == GRAD_STRESS) {
+          for (int a = 0; a < 3; ++a)
+            for (int b = a; b < 3; ++b) o[a][b] = tau[a][b];
+        } else {
+          const double mu = r * Dm.ic.nu, mub = r * Dm.ic.nu_b;
+          double tr = 0.0;
+          for (int a = 0; a < D; ++a) tr += tau[a][a];
+          const double trE = tr / (D * mub);
+          const double iso = (mub - 2.0 * mu / D) * trE;
+          for (int a = 0; a < 3; ++a)
+            for (int b = a; b < 3; ++b) o[a][b] = (tau[a][b] - (a == b ? iso : 0.0)) / (2.0 * mu);
+        }
+        res[0] = o[0][0];
+        res[1] = o[1][1];
+        if constexpr (D == 2) {
+          res[2] = o[0][1];
+        } else {
+          res[2] = o[2][2];
+          res[3] = o[0][1];
+          res[4] = o[0][2];
+          res[5] = o[1][2];
+        }
+      } else {
+        const double Dphi = C.D0 * (1.0 + C.D2 * r * r);
+        const double s1 = 1.0 / (0.5 + Dphi * C.inv_cs2_dt);
+        double X = C.source;
+        if constexpr (Lat<L>::linear) {
+          const double prev = (ST == ST_F64) ? ((const double*)Dm.hist)[idx] : (double)((const float*)Dm.hist)[idx];
+          X = (r - prev) * C.inv_dt;
+        }
+        for (int a = 0; a < D; ++a)
+          res[a] = -(1.0 - 0.5 * s1) * (m1[a] - r * C.adv[a] + 0.5 * C.dt * C.adv[a] * X) / Dphi;
+      }
+    }
+    for (int k = 0; k < NC; ++k) {
+      if (out_f32)
+        ((float*)out)[(size_t)k * N + idx] = (float)res[k];
+      else
+        ((double*)out)[(size_t)k * N + idx] = res[k];
+    }
+  }
+}
+
 // ---- block reduction of K doubles ----
 template <int K>
 __device__ __forceinline__ void block_reduce_store(double (&v)[K], double* out) {
@@ -743,6 +854,7 @@ struct AuxLaunch {
   const double* in0;
   const double* in1;
   int flag;
+  int kind;   // k_local: GRAD_*
 };
 
 template <int L, int ST>
@@ -757,6 +869,8 @@ template <int L, int ST>
 hipError_t launch_reduce(const AuxLaunch& a);
 template <int L, int ST>
 hipError_t launch_residual(const AuxLaunch& a);
+template <int L, int ST>
+hipError_t launch_local(const AuxLaunch& a);
 template <int L>
 hipError_t launch_links(const DomainDev* doms, uint32_t dom, void* out, unsigned grid, hipStream_t s);
 hipError_t launch_reduce_final(const double* partials, uint32_t nb, double* out, int K, hipStream_t s);

@@ -123,6 +123,15 @@ hipError_t launch_init(const AuxLaunch& a) {
   return hipGetLastError();
 }
 
+template <int L, int ST>
+hipError_t launch_local(const AuxLaunch& a) {
+#define K_LOC(EQ, BC, SW)                                                                         \
+  hipLaunchKernelGGL((k_local<L, ST, EQ, BC, SW>), dim3(a.grid), dim3(a.block), 0, a.stream, a.doms, \
+                     a.dom, a.parity, a.ab, a.out0, a.kind, a.flag)
+  RMRT_AUX_DISPATCH(K_LOC)
+#undef K_LOC
+}
+
 template <int L>
 hipError_t launch_links(const DomainDev* doms, uint32_t dom, void* out, unsigned grid, hipStream_t s) {
   hipLaunchKernelGGL((k_links<L>), dim3(grid), dim3(256), 0, s, doms, dom, out);
@@ -137,6 +146,7 @@ hipError_t launch_links(const DomainDev* doms, uint32_t dom, void* out, unsigned
   template hipError_t launch_moments<L, ST>(const AuxLaunch&);  \
   template hipError_t launch_populations<L, ST>(const AuxLaunch&); \
   template hipError_t launch_reduce<L, ST>(const AuxLaunch&);   \
-  template hipError_t launch_residual<L, ST>(const AuxLaunch&);
+  template hipError_t launch_residual<L, ST>(const AuxLaunch&); \
+  template hipError_t launch_local<L, ST>(const AuxLaunch&);
 
 }  // namespace rmrt

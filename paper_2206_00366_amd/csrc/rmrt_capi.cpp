@@ -391,6 +391,7 @@ hipError_t dispatch_populations(int lat, int st, const AuxLaunch& a) {
 }
 hipError_t dispatch_reduce(int lat, int st, const AuxLaunch& a) { RMRT_DISPATCH(launch_reduce, lat, st, a); }
 hipError_t dispatch_residual(int lat, int st, const AuxLaunch& a) { RMRT_DISPATCH(launch_residual, lat, st, a); }
+hipError_t dispatch_local(int lat, int st, const AuxLaunch& a) { RMRT_DISPATCH(launch_local, lat, st, a); }
 hipError_t dispatch_links(int lat, const DomainDev* doms, uint32_t dom, void* out, unsigned grid, hipStream_t s) {
   switch (lat) {
     case LAT_Q9: return launch_links<LAT_Q9>(doms, dom, out, grid, s);
@@ -837,6 +838,26 @@ int rmrt_moments(rmrt_ctx* c, void* rho_out, void* u_out, int out_dtype, void* s
   a.flag = out_dtype == RMRT_OUT_F32;
   hipError_t e = dispatch_moments(c->p.lattice, c->p.storage, a);
   if (e != hipSuccess) return fail(RMRT_EHIP, "moments launch: %s", hipGetErrorString(e));
+  return RMRT_OK;
+}
+
+int rmrt_local_gradients(rmrt_ctx* c, int kind, void* out, int out_dtype, void* stream) {
+  if (!c || !out) return fail(RMRT_EINVAL, "ctx or out is NULL");
+  if (out_dtype != RMRT_OUT_F64 && out_dtype != RMRT_OUT_F32) return fail(RMRT_EINVAL, "bad out_dtype");
+  const bool nse = c->p.equation == RMRT_NSE;
+  if (kind == RMRT_GRAD_STRAIN || kind == RMRT_GRAD_STRESS) {
+    if (!nse) return fail(RMRT_EINVAL, "strain rate and stress are NSE outputs");
+  } else if (kind == RMRT_GRAD_PHI) {
+    if (nse) return fail(RMRT_EINVAL, "grad phi is an NCDE output");
+  } else {
+    return fail(RMRT_EINVAL, "unknown kind %d", kind);
+  }
+  AuxLaunch a = aux_of(c, (hipStream_t)stream);
+  a.out0 = out;
+  a.flag = out_dtype == RMRT_OUT_F32;
+  a.kind = kind;
+  hipError_t e = dispatch_local(c->p.lattice, c->p.storage, a);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "local gradients launch: %s", hipGetErrorString(e));
   return RMRT_OK;
 }
 

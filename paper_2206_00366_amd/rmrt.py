@@ -32,6 +32,7 @@ F64, F32DEV, F16DEV = 0, 1, 2
 AB, AA = 0, 1
 OUT_F64, OUT_F32 = 0, 1
 LAUNCH_XCD_ORDER, LAUNCH_PERSISTENT, LAUNCH_WIDE_TILES = 1, 2, 4
+GRAD_STRAIN, GRAD_STRESS, GRAD_PHI = 0, 1, 2
 WALL_XM, WALL_XP, WALL_YM, WALL_YP, WALL_ZM, WALL_ZP = 1, 2, 4, 8, 16, 32
 
 LATTICES = {"Q9": Q9, "Q19": Q19, "Q27": Q27, "Q5": Q5, "Q7": Q7}
@@ -87,6 +88,7 @@ _sig = {
     "rmrt_batch_num_configs": (C.c_int, []),
     "rmrt_batch_config_info": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                           C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "rmrt_local_gradients": (C.c_int, [_vp, C.c_int, _vp, C.c_int, _vp]),
     "rmrt_batch_step": (C.c_int, [_vp, C.c_int, _vp]),
     "rmrt_batch_residual": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
     "rmrt_batch_free": (C.c_int, [_vp]),
@@ -240,6 +242,16 @@ class Domain:
         u = torch.empty(self.d * self.N, dtype=dt, device=self.f0.device) if with_u else None
         _check(_lib.rmrt_moments(self._ctx, _ptr(rho), _ptr(u), int(out_dtype), _stream()), "rmrt_moments")
         return rho, (u.view(self.d, self.N) if u is not None else None)
+
+    def local_gradients(self, kind=GRAD_STRAIN, out_dtype=OUT_F64):
+        """Strain rate / stress components (xx, yy, [zz,] xy, [xz, yz]) or grad phi, shape (ncomp, N)."""
+        import torch
+        dt = torch.float64 if out_dtype == OUT_F64 else torch.float32
+        nc = self.d if kind == GRAD_PHI else self.d * (self.d + 1) // 2
+        out = torch.empty(nc * self.N, dtype=dt, device=self.f0.device)
+        _check(_lib.rmrt_local_gradients(self._ctx, int(kind), _ptr(out), int(out_dtype), _stream()),
+               "rmrt_local_gradients")
+        return out.view(nc, self.N)
 
     def populations(self):
         import torch

@@ -1,0 +1,149 @@
+"""GPU parity of the local derivative outputs (stress and strain rate of
+eq. 4-32-0 / 4-28, grad phi of eq. 4-13) against the FP64 oracle, through the
+C ABI."""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+from gpu_util import WALLS, circle_mask, random_fields
+from inputs import taylor_green_3d
+from oracle import rmrt_oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rmrt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_00366_amd import rmrt as R
+    return R
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = {
+    "q9_full_block": (dict(lattice="Q9", n=(37, 23, 1), dx=(1.0, 0.5, 1.0), nu=0.02, nu_b=0.05), None, 13),
+    "q9_channel_solid_force_source": (dict(lattice="Q9", n=(40, 21, 1), dx=(1.0, 0.5, 1.0), nu=0.05,
+                                           force=(2e-5, 1e-6, 0.0), source=1e-6, wall_faces=WALLS["y"]),
+                                      lambda n: circle_mask(n, (12, 10), 4), 13),
+    "q19_channel_force": (dict(lattice="Q19", n=(12, 10, 8), dx=(1.0, 1.0, 2.0), nu=0.04, nu_b=0.1,
+                               force=(1e-5, 0.0, 2e-6), wall_faces=WALLS["yz"]), None, 9),
+    "q27_solid_force": (dict(lattice="Q27", n=(14, 9, 8), dx=(1.0, 2.0, 1.0), nu=0.05, force=(1e-5, 0.0, 0.0),
+                             source=-1e-6, wall_faces=WALLS["yz"]), lambda n: circle_mask(n, (6, 4), 2), 9),
+    "q9_ncde_source": (dict(lattice="Q9", equation="NCDE", n=(33, 17, 1), dx=(1.0, 0.5, 1.0), D0=0.01, D2=1.0,
+                            adv=(0.05, 0.02, 0.0), rho0=0.0, source=1e-3), None, 13),
+    "q19_ncde": (dict(lattice="Q19", equation="NCDE", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), D0=0.02, D2=0.5,
+                      adv=(0.03, -0.01, 0.02), rho0=0.0), None, 9),
+    "q5_ncde_walls": (dict(lattice="Q5", equation="NCDE", n=(30, 21, 1), dx=(1.0, 2.0, 1.0), D0=0.05, D2=1.0,
+                           adv=(0.06, 0.0, 0.0), source=1e-3, wall_faces=WALLS["y"], rho0=0.0), None, 11),
+    "q7_ncde": (dict(lattice="Q7", equation="NCDE", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), D0=0.02, D2=0.5,
+                     adv=(0.03, -0.01, 0.02), rho0=0.0), None, 9),
+}
+
+
+def _run(rmrt, case, storage, pattern):
+    prm, solid_fn, steps = CASES[case]
+    m = O.Model(prm, solid=None if solid_fn is None else solid_fn(prm["n"]))
+    rng_seed = zlib.crc32(case.encode()) % 1000
+    if m.nse:
+        rho, u = random_fields(m, seed=rng_seed, du=0.02)
+    else:
+        rho, u = 0.2 + 0.8 * np.random.default_rng(rng_seed).uniform(size=m.N), None
+    solid = None if solid_fn is None else m.solid.astype(np.uint8)
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage=storage, pattern=pattern), rho, u, solid=solid)
+    f = m.init(rho, u)
+    if m.linear:
+        f, h = m.step(f, steps, m.init_history(rho))
+    else:
+        f, h = m.step(f, steps), None
+    dom.step(steps)
+    return m, dom, f, h
+
+
+def _oracle_components(m, f, h):
+    fl = m.fluid
+    if m.nse:
+        tau, E = m.local_gradients(f[:, fl])
+        pairs = [(a, a) for a in range(m.d)] + [(a, b) for a in range(m.d) for b in range(a + 1, m.d)]
+        return {rmrt_kind: np.stack([T[a, b] for a, b in pairs])
+                for rmrt_kind, T in ((0, E), (1, tau))}
+    return {2: m.local_gradients(f[:, fl], None if h is None else h[fl])}
+
+
+@pytest.mark.parametrize("pattern", ["AB", "AA"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_local_gradients_match_oracle(rmrt, case, pattern):
+    """FP64 storage: the kernel's outputs against the oracle's formulas on the
+    oracle's own state (the two states agree to 1e-12), relative to the
+    output's magnitude."""
+    say(f"[local gradients] {case} {pattern}")
+    m, dom, f, h = _run(rmrt, case, "f64", pattern)
+    fl = m.fluid
+    for kind, ref in _oracle_components(m, f, h).items():
+        got = dom.local_gradients(kind).cpu().numpy()
+        err = np.abs(got[:, fl] - ref).max() / np.abs(ref).max()
+        say(f"   kind {kind}: max rel err {err:.2e}")
+        assert err < 1e-11
+        assert np.all(got[:, ~fl] == 0.0)
+        got32 = dom.local_gradients(kind, rmrt.OUT_F32).cpu().numpy()
+        assert np.abs(got32[:, fl] - ref).max() / np.abs(ref).max() < 1e-6
+    dom.close()
+
+
+@pytest.mark.parametrize("case", ["q9_full_block", "q19_channel_force", "q9_ncde_source", "q7_ncde"])
+def test_local_gradients_fp32_storage(rmrt, case):
+    say(f"[local gradients f32dev] {case}")
+    m, dom, f, h = _run(rmrt, case, "f32dev", "AA")
+    fl = m.fluid
+    for kind, ref in _oracle_components(m, f, h).items():
+        got = dom.local_gradients(kind).cpu().numpy()
+        err = np.abs(got[:, fl] - ref).max() / np.abs(ref).max()
+        say(f"   kind {kind}: max rel err {err:.2e}")
+        assert err < 2e-2
+    dom.close()
+
+
+def test_kind_must_match_equation(rmrt):
+    m, dom, f, h = _run(rmrt, "q9_full_block", "f64", "AA")
+    with pytest.raises(rmrt.RMRTError) as ei:
+        dom.local_gradients(rmrt.GRAD_PHI)
+    assert ei.value.code == rmrt.EINVAL
+    with pytest.raises(rmrt.RMRTError):
+        dom.local_gradients(7)
+    dom.close()
+    m, dom, f, h = _run(rmrt, "q9_ncde_source", "f64", "AA")
+    with pytest.raises(rmrt.RMRTError):
+        dom.local_gradients(rmrt.GRAD_STRAIN)
+    dom.close()
+
+
+def test_strain_rate_full_size_sampled(rmrt):
+    """The 256 x 256 x 128 rD3Q19 Taylor-Green workload, FP32 storage, after
+    5 steps: the strain rate at 4096 sampled nodes against the oracle formula
+    applied to the GPU's own decoded populations (the scheme is local)."""
+    say("[local gradients] full size sampled")
+    n, dx = (256, 256, 128), (1.0, 1.0, 2.0)
+    prm = dict(lattice="Q19", n=n, dx=dx, nu=0.005, cs2=1.0 / 3.0)
+    rho, u, _ = taylor_green_3d(n, dx, 0.02, 1.0 / 3.0)
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage="f32dev", pattern="AA"), rho, u)
+    dom.step(5)
+    E = dom.local_gradients(rmrt.GRAD_STRAIN)
+    N = n[0] * n[1] * n[2]
+    idx = np.concatenate([np.random.default_rng(5).integers(0, N, size=4096), [0, N - 1]])
+    it = torch.as_tensor(idx, device=E.device)
+    got = E[:, it].cpu().numpy()
+    f = dom.populations()[:, it].cpu().numpy()
+    dom.close()
+    mo = O.Model(dict(prm, n=(idx.size, 1, 1)))
+    _, Eo = mo.local_gradients(f)
+    ref = np.stack([Eo[0, 0], Eo[1, 1], Eo[2, 2], Eo[0, 1], Eo[0, 2], Eo[1, 2]])
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"   sampled max rel err {err:.2e}")
+    assert err < 1e-9
