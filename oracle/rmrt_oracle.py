@@ -31,6 +31,14 @@ GPU side can take the same ones; numbering as in the design notes):
   A11 nu_b < 0 selects 2 nu / d (eq. 4-27-1 with a = 0, Remark V of Sec. IV).
   A14 NCDE: D = phi I, beta = 1, K = D(phi) I with D(phi) = D0 (1 + D2 phi^2),
       B = phi u_adv with constant u_adv, C = phi u_adv u_adv.
+  A19 He-Luo option: f_eq = g_eq(rho, rho0 u, rho0 u u) with rho0 u = sum c f
+      (eq. meqd2q9-HL); every place that uses u (the forcing moments, the
+      stress relation K_mu = rho0 nu, the f_ne initialisation) takes this u
+      and rho0 in place of rho.
+  A20 viscosity tensor of eq. 4-29: per-entry viscosities (xx, yy, zz, xy,
+      xz, yz) set s_s,a (diagonal entries), s_ab (off-diagonal entries) by
+      eq. 4-31 entry by entry, and per-axis bulk viscosities set s_b,a;
+      unset entries take nu and nu_b.
   A18 the reduced lattices rD2Q5 (the rD2Q5I subset of rD2Q9) and rD3Q7 carry
       the NCDE only, in the C = 0 form of eq. 4-16: linear equilibrium
       g_eq(phi, phi u_adv, 0), F_j = w_j S and
@@ -217,7 +225,7 @@ def S2_sherman_morrison(c, cs2, s_s, s_b, d):
 DEFAULTS = dict(lattice="Q9", equation="NSE", n=(8, 8, 1), dx=(1.0, 1.0, 1.0), dt=1.0,
                 cs2=-1.0, nu=0.1, nu_b=-1.0, s_hi=-1.0, w_corner=-1.0,
                 D0=0.0, D2=0.0, adv=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0),
-                source=0.0, rho0=1.0, wall_faces=0)
+                source=0.0, rho0=1.0, wall_faces=0, incompressible=False, nu_tensor=None, nu_b_axis=None)
 
 
 class Model:
@@ -270,6 +278,7 @@ class Model:
                        if tuple(unit[a][k] + unit[b][k] for k in range(d)) in row]
 
         S = np.zeros((q, q))
+        self.hl = bool(p["incompressible"]) and self.nse                        # A19
         if self.nse:
             nu = float(p["nu"])
             nu_b = float(p["nu_b"])
@@ -278,6 +287,18 @@ class Model:
             self.nu, self.nu_b = nu, nu_b
             s_ab, s_s, s_b = nse_rates(c, cs2, nu, nu_b, d, self.dt)
             self.s_ab, self.s_s, self.s_b = s_ab, s_s, s_b
+            # viscosity tensor entries (A20): nu_t[a] diagonal, nu_pair[k] for pairs[k]
+            nt = p["nu_tensor"] if p["nu_tensor"] is not None else [-1.0] * 6
+            nb = p["nu_b_axis"] if p["nu_b_axis"] is not None else [-1.0] * 3
+            self.nu_diag = np.array([float(nt[a]) if nt[a] > 0 else nu for a in range(d)])
+            pair_slot = {(0, 1): 3, (0, 2): 4, (1, 2): 5}
+            self.nu_pair = np.array([float(nt[pair_slot[pr]]) if nt[pair_slot[pr]] > 0 else nu for pr in self.pairs])
+            self.nu_b_ax = np.array([float(nb[a]) if nb[a] >= 0 else nu_b for a in range(d)])
+            g = c**2 - cs2
+            self.s_s = 1.0 / (0.5 + 2.0 * self.nu_diag / (g * self.dt))          # eq. 4-31, per entry
+            self.s_b = 1.0 / (0.5 + d * self.nu_b_ax / (g * self.dt))
+            self.s_pair = 1.0 / (0.5 + self.nu_pair / (cs2 * self.dt))
+            s_s, s_b = self.s_s, self.s_b
             self.S2inv1 = S2_inverse_block(c, cs2, s_s, s_b, d)
             self.Sbar21 = np.linalg.inv(self.S2inv1)                           # eq. 5-8-1 (numeric)
             s_hi = float(p["s_hi"])
@@ -292,8 +313,8 @@ class Model:
             for a in range(d):
                 for b in range(d):
                     S[self.rows2d[a], self.rows2d[b]] = self.Sbar21[a, b]
-            for r in self.rows2o:
-                S[r, r] = s_ab
+            for k, r in enumerate(self.rows2o):
+                S[r, r] = self.s_pair[k]
         else:
             s_hi = float(p["s_hi"])
             if s_hi <= 0:
@@ -349,7 +370,8 @@ class Model:
         """rho (or phi) and u from fbar, eq. 2-4-1 / eq. 2-4-2."""
         if self.nse:
             rho = fbar.sum(axis=0) + self.dt * self.source / 2.0
-            u = (self.C.T @ fbar + self.dt * self.force[:, None] / 2.0) / rho[None, :]
+            den = self.rho0 if self.hl else rho[None, :]                         # A19: rho0 u = j
+            u = (self.C.T @ fbar + self.dt * self.force[:, None] / 2.0) / den
             return rho, u
         phi = fbar.sum(axis=0) + self.dt * self.source / 2.0
         return phi, np.repeat(self.adv[:, None], fbar.shape[1], axis=1)
@@ -367,8 +389,9 @@ class Model:
         I = np.eye(d)[:, :, None]
         if self.nse:
             rho, u = self.macroscopic(fbar)
-            feq = g_eq(self.C, self.w, self.c, self.cs2, rho, rho[None] * u,
-                       rho[None, None] * np.einsum("an,bn->abn", u, u))
+            rr = np.full_like(rho, self.rho0) if self.hl else rho                 # A19
+            feq = g_eq(self.C, self.w, self.c, self.cs2, rho, rr[None] * u,
+                       rr[None, None] * np.einsum("an,bn->abn", u, u))
             Sb, Fb = self.source, self.force
             F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, Sb),
                      np.repeat(Fb[:, None], n, axis=1), -self.cs2 * Sb * np.repeat(I, n, axis=2))
@@ -507,9 +530,20 @@ class Model:
             T = (np.einsum("an,b->abn", u, Fb) + np.einsum("a,bn->abn", Fb, u)
                  + (self.cs2 * I - np.einsum("an,bn->abn", u, u)) * Sb)
             tau = -self._apply_I_minus_half_S2(m2ne + 0.5 * self.dt * T)
-            mu, mub = rho * self.nu, rho * self.nu_b
-            trE = np.einsum("aan->n", tau) / (d * mub)
-            E = (tau - (mub - 2.0 * mu / d)[None, None] * trE[None, None] * I) / (2.0 * mu)[None, None]
+            rr = np.full_like(rho, self.rho0) if self.hl else rho
+            # invert eq. 4-28 with the tensors of eq. 4-29:
+            #   tau_ab = K_ab 2 E_ab (a != b),
+            #   tau_aa = K_aa (2 E_aa - (2/d) tr E) + Kb_a tr E
+            E = np.zeros_like(tau)
+            Kd = rr[None] * self.nu_diag[:, None]
+            Kb = rr[None] * self.nu_b_ax[:, None]
+            num = sum(tau[a, a] / (2.0 * Kd[a]) for a in range(d))
+            den = 1.0 + sum((Kb[a] - 2.0 * Kd[a] / d) / (2.0 * Kd[a]) for a in range(d))
+            trE = num / den
+            for a in range(d):
+                E[a, a] = (tau[a, a] - (Kb[a] - 2.0 * Kd[a] / d) * trE) / (2.0 * Kd[a])
+            for k, (a, b) in enumerate(self.pairs):
+                E[a, b] = E[b, a] = tau[a, b] / (2.0 * rr * self.nu_pair[k])
             return tau, E
         phi, u = self.macroscopic(fbar)
         m1ne = self.C.T @ fne
@@ -531,10 +565,11 @@ class Model:
         I = np.eye(d)[:, :, None]
         if self.nse:
             u = np.asarray(u, dtype=np.float64).reshape(d, n)
-            Mt = rho[None, None] * np.einsum("an,bn->abn", u, u)
+            rr = np.full_like(rho, self.rho0) if self.hl else rho                 # A19
+            Mt = rr[None, None] * np.einsum("an,bn->abn", u, u)
             if with_fne:
-                Mt = Mt + self.m2_ne(rho, u)
-            feq = g_eq(self.C, self.w, self.c, self.cs2, rho, rho[None] * u, Mt)
+                Mt = Mt + self.m2_ne(rr, u)
+            feq = g_eq(self.C, self.w, self.c, self.cs2, rho, rr[None] * u, Mt)
             Sb, Fb = self.source, self.force
             F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, Sb),
                      np.repeat(Fb[:, None], n, axis=1), -self.cs2 * Sb * np.repeat(I, n, axis=2))
@@ -586,8 +621,12 @@ class Model:
         g = self.velocity_gradient(u)
         div = np.einsum("aan->n", g)
         I = np.eye(d)[:, :, None]
-        tau = (rho[None, None] * self.nu * (g + g.transpose(1, 0, 2) - (2.0 / d) * div[None, None] * I)
-               + rho[None, None] * self.nu_b * div[None, None] * I)
+        # eq. 4-28 with the tensors of eq. 4-29 (A20)
+        tau = np.zeros((d, d, n))
+        for a in range(d):
+            tau[a, a] = rho * (self.nu_diag[a] * (2.0 * g[a, a] - (2.0 / d) * div) + self.nu_b_ax[a] * div)
+        for k, (a, b) in enumerate(self.pairs):
+            tau[a, b] = tau[b, a] = rho * self.nu_pair[k] * (g[a, b] + g[b, a])
         rows = self.rows2d + self.rows2o
         S22 = self.S[np.ix_(rows, rows)]
         K = np.linalg.inv(np.eye(len(rows)) - 0.5 * S22)

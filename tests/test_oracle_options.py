@@ -1,0 +1,156 @@
+"""Pins of the oracle's NSE options: the He-Luo equilibrium (printed rD2Q9
+moments of eq. meqd2q9-HL, its O(Ma^3) agreement with the standard
+equilibrium stated in Remark IV of Sec. IV, conservation and plane Poiseuille
+flow) and the viscosity tensors of eq. 4-29 (isotropic limit, and plane
+channels whose profile follows the shear entry of their own plane)."""
+import numpy as np
+import pytest
+
+from golden_util import read_vector
+from inputs import grid_coords
+from oracle import rmrt_oracle as O
+
+
+def _model(lat, c, **kw):
+    d = 2 if lat == "Q9" else 3
+    n = (3, 3, 1) if d == 2 else (3, 3, 3)
+    dx = tuple(c) + ((1.0,) if d == 2 else ())
+    return O.Model(dict(lattice=lat, n=n, dx=dx, **kw))
+
+
+@pytest.mark.parametrize("c,rho0", [((1.0, 0.5), 1.0), ((1.0, 1.0), 1.3), ((0.8, 1.6), 0.9)])
+def test_he_luo_moments_match_printed(c, rho0):
+    m = _model("Q9", c, nu=0.05, incompressible=True, rho0=rho0)
+    rng = np.random.default_rng(4)
+    n = m.N
+    rho = rho0 + 0.05 * rng.standard_normal(n)
+    u = 0.05 * rng.standard_normal((2, n))
+    feq = O.g_eq(m.C, m.w, m.c, m.cs2, rho, rho0 * u, rho0 * np.einsum("an,bn->abn", u, u))
+    got = m.M @ feq
+    for k in range(n):
+        env = dict(rho=rho[k], rho0=rho0, u=u[0, k], v=u[1, k], cs2=m.cs2)
+        np.testing.assert_allclose(got[:, k], read_vector("meq_d2q9_heluo.txt", env), rtol=0, atol=1e-15)
+    # and the model's own distributions use it (u = j / rho0)
+    f = m.init(rho, u)
+    feq_m, _, _, _ = m.distributions(f)
+    np.testing.assert_allclose(feq_m, feq, atol=1e-15)
+
+
+@pytest.mark.parametrize("lat", ["Q9", "Q19", "Q27"])
+def test_he_luo_differs_at_third_order(lat):
+    """Remark IV: with rho = rho0 + drho, drho = O(eps^2) and u = O(eps), the two
+    equilibria differ by O(eps^3): halving eps divides the difference by 8."""
+    m = _model(lat, (1.0, 0.5, 2.0)[: 2 if lat == "Q9" else 3], nu=0.05)
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal(4)
+    b = rng.standard_normal((m.d, 4))
+    diffs = []
+    for eps in (0.02, 0.01):
+        rho = 1.0 + eps**2 * a
+        u = eps * b
+        std = O.g_eq(m.C, m.w, m.c, m.cs2, rho, rho * u, rho * np.einsum("an,bn->abn", u, u))
+        hl = O.g_eq(m.C, m.w, m.c, m.cs2, rho, u, np.einsum("an,bn->abn", u, u))
+        diffs.append(np.abs(std - hl).max())
+    assert 7.0 < diffs[0] / diffs[1] < 9.0, diffs
+
+
+def test_he_luo_conserves_mass_and_momentum():
+    prm = dict(lattice="Q27", n=(6, 5, 4), dx=(1.0, 0.5, 2.0), nu=0.05, nu_b=0.1, incompressible=True,
+               force=(1e-5, -2e-5, 0.0))
+    m = O.Model(prm)
+    rng = np.random.default_rng(2)
+    f = m.init(1.0 + 1e-3 * rng.standard_normal(m.N), 0.02 * rng.standard_normal((3, m.N)))
+    mass0 = f.sum()
+    mom0 = (m.C.T @ f).sum(axis=1)
+    f = m.step(f, 7)
+    assert abs(f.sum() - mass0) < 1e-12
+    np.testing.assert_allclose((m.C.T @ f).sum(axis=1), mom0 + 7 * m.N * m.force, atol=1e-12)
+
+
+def _channel(lat, ny, dy, g, steps, **kw):
+    d = 2 if lat == "Q9" else 3
+    if d == 2:
+        n, dx, walls = (2, ny, 1), (1.0, dy, 1.0), O.WALL_YM | O.WALL_YP
+    else:
+        n, dx, walls = (2, 2, ny), (1.0, 1.0, dy), O.WALL_ZM | O.WALL_ZP
+    m = O.Model(dict(lattice=lat, n=n, dx=dx, force=(g, 0.0, 0.0)[:d], wall_faces=walls, **kw))
+    f = m.step(m.init(np.ones(m.N), np.zeros((d, m.N))), steps)
+    _, u = m.macroscopic(f)
+    X, Y, Z = grid_coords(n, dx, centered=True)
+    return m, f, u, (Y if d == 2 else Z), ny * dy
+
+
+def test_he_luo_poiseuille_second_order():
+    errs = []
+    for ny in (12, 24):
+        nu, g, dy = 0.03, 1e-5, 0.5
+        H = ny * dy
+        m, f, u, w, H = _channel("Q9", ny, dy, g, int(1.2 * H * H / nu) + 200, nu=nu, incompressible=True)
+        exact = O.poiseuille(w, H, g, nu)
+        errs.append(np.abs(u[0] - exact).max() / exact.max())
+    assert errs[1] < 0.01 and 3.6 < errs[0] / errs[1] < 4.4, errs
+
+
+def test_isotropic_tensor_equals_scalar_viscosity():
+    base = dict(lattice="Q27", n=(3, 3, 3), dx=(1.0, 0.5, 2.0), nu=0.04, nu_b=0.09)
+    a = O.Model(base)
+    b = O.Model(dict(base, nu_tensor=[0.04] * 6, nu_b_axis=[0.09] * 3))
+    np.testing.assert_allclose(a.S, b.S, rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("lat,dy,plane_entry", [("Q9", 0.5, 3), ("Q27", 0.5, 4), ("Q19", 2.0, 4)])
+def test_channel_follows_its_own_shear_entry(lat, dy, plane_entry):
+    """A plane channel sheared in the x-w plane (w = y in 2D, z in 3D) with a
+    full viscosity tensor gives exactly the profile of the isotropic model with
+    nu = nu_xw (the other entries do not enter), which is the Poiseuille
+    profile to the bounce-back error; the local strain rate (eq. 4-32-0
+    inverted through eq. 4-29) matches the exact one with that entry."""
+    nu_xw, g, ny = (0.08 if dy < 1 else 0.4), 1e-5, 16
+    nt = [0.02, 0.05, 0.03, 0.2, 0.2, 0.2]
+    nt[plane_entry] = nu_xw
+    H = ny * dy
+    steps = int(2.5 * H * H / nu_xw)
+    # the base nu differs from nu_xw; s_hi (otherwise s_nu of the base nu)
+    # is pinned to the isotropic model's value so that both runs share it
+    iso, f_iso, u_iso, w, H = _channel(lat, ny, dy, g, steps, nu=nu_xw)
+    m, f, u, w, H = _channel(lat, ny, dy, g, steps, nu=0.1, nu_tensor=nt, nu_b_axis=[0.07, 0.05, 0.06],
+                             s_hi=iso.s_hi)
+    assert np.abs(u - u_iso).max() < 1e-6 * np.abs(u_iso).max()
+    exact = O.poiseuille(w, H, g, nu_xw)
+    assert np.abs(u[0] - exact).max() / exact.max() < 0.05   # bounce-back slip of the isotropic model
+    _, E = m.local_gradients(f)
+    b = 1 if m.d == 2 else 2
+    Eex = g * (H - 2 * w) / (4 * nu_xw)
+    assert np.abs(E[0, b] - Eex).max() < 1e-6 * np.abs(Eex).max()
+
+
+@pytest.mark.parametrize("lat,dx,nt,nb", [
+    ("Q9", (1.0, 0.5, 1.0), [0.05, 0.02, 0.0, 0.03, 0.0, 0.0], [0.12, 0.04, -1.0]),
+    ("Q27", (1.0, 0.5, 2.0), [0.04, 0.02, 0.07, 0.03, 0.05, 0.06], [0.09, 0.03, 0.02]),
+])
+def test_sound_wave_damping_follows_the_longitudinal_entries(lat, dx, nt, nb):
+    """A standing sound wave along x decays at k^2 nu_L / 2 with
+    nu_L = 2 nu_xx (1 - 1/d) + nu_b,x (eq. 4-28 with the tensors of eq. 4-29):
+    the xx and bulk-x entries set it, the isotropic nu = 0.05, nu_b = 0.1 would
+    give a rate 10-20% off."""
+    import math
+    d = 2 if lat == "Q9" else 3
+    nx = 64
+    n = (nx, 2, 1) if d == 2 else (nx, 2, 2)
+    m = O.Model(dict(lattice=lat, n=n, dx=dx, nu=0.05, nu_b=0.1, nu_tensor=nt, nu_b_axis=nb))
+    X, _, _ = grid_coords(n, dx)
+    k = 2 * math.pi / nx
+    u = np.zeros((d, m.N))
+    u[0] = 1e-4 * np.sin(k * X)
+    f = m.init(np.ones(m.N), u)
+    ts, es = [], []
+    for t in range(0, 1201, 10):
+        if t:
+            f = m.step(f, 10)
+        if t >= 200:
+            rho, uu = m.macroscopic(f)
+            ts.append(t)
+            es.append((0.5 * rho * (uu**2).sum(0) + 0.5 * m.cs2 * (rho - 1.0) ** 2).sum())
+    gamma = -np.polyfit(ts, np.log(es), 1)[0] / 2.0
+    nu_L = 2.0 * nt[0] * (1.0 - 1.0 / d) + nb[0]
+    assert abs(gamma / (k * k * nu_L / 2.0) - 1.0) < 0.01, gamma
