@@ -100,6 +100,17 @@ enum { RMRT_OUT_F64 = 0, RMRT_OUT_F32 = 1 };                       /* macroscopi
  *   wall_faces RMRT_WALL_* bits (halfway bounce-back); other faces periodic
  *   check_every if > 0, rmrt_step runs an FP64 mass check every that many
  *             steps and returns RMRT_ENONFINITE when it is not finite
+ *   incompressible  NSE: 1 selects the He-Luo equilibrium
+ *             g_eq(rho, rho0 u, rho0 u u) with rho0 u = sum_j c_j f_j (Sec. V,
+ *             eq. meqd2q9-HL; Remark IV of Sec. IV); rmrt_moments then returns
+ *             u = sum_j c_j f_j / rho0.  0 = the equilibrium of eq. NSEfeq.
+ *   nu_tensor[6]  NSE: viscosity tensor entries of eq. 4-29, in the order
+ *             (xx, yy, zz, xy, xz, yz): K_mu,aa = rho nu_tensor[a] sets s_s,a and
+ *             K_mu,ab = rho nu_tensor[ab] sets s_ab (eq. 4-31 per entry);
+ *             entries <= 0 take nu (the isotropic case)
+ *   nu_b_axis[3]  NSE: per-axis bulk viscosities K_mu_b,aa = rho nu_b_axis[a]
+ *             of eq. 4-29 (set s_b,a); entries <= 0 take nu_b (a zero-initialised
+ *             struct is the isotropic model)
  */
 typedef struct rmrt_params {
   int lattice, equation, storage, pattern;
@@ -116,6 +127,9 @@ typedef struct rmrt_params {
   double rho0;
   unsigned wall_faces;
   int check_every;
+  int incompressible;
+  double nu_tensor[6];
+  double nu_b_axis[3];
 } rmrt_params;
 
 /* Values the library derives from a parameter set (host only, no GPU). */
@@ -126,6 +140,7 @@ typedef struct rmrt_derived {
   double s_nu, s_s[3], s_b[3], s_hi;  /* rates from eq. 4-31                      */
   double Sbar2[3][3];     /* second-order diagonal block, eq. 5-8-1                */
   double nu_b;
+  double s_pair[3];       /* off-diagonal second-order rates (xy, xz, yz), eq. 4-31 */
 } rmrt_derived;
 
 typedef struct rmrt_ctx rmrt_ctx;

@@ -293,7 +293,7 @@ class Model:
             self.nu_diag = np.array([float(nt[a]) if nt[a] > 0 else nu for a in range(d)])
             pair_slot = {(0, 1): 3, (0, 2): 4, (1, 2): 5}
             self.nu_pair = np.array([float(nt[pair_slot[pr]]) if nt[pair_slot[pr]] > 0 else nu for pr in self.pairs])
-            self.nu_b_ax = np.array([float(nb[a]) if nb[a] >= 0 else nu_b for a in range(d)])
+            self.nu_b_ax = np.array([float(nb[a]) if nb[a] > 0 else nu_b for a in range(d)])
             g = c**2 - cs2
             self.s_s = 1.0 / (0.5 + 2.0 * self.nu_diag / (g * self.dt))          # eq. 4-31, per entry
             self.s_b = 1.0 / (0.5 + d * self.nu_b_ax / (g * self.dt))

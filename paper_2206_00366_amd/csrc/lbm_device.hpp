@@ -220,7 +220,8 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, T phi_prev
     const T rho = C.rho0 + drho + C.half_source;                       // eq. 2-4-2
     const T jx = m1[0] + C.half_force[0], jy = m1[1] + C.half_force[1],
             jz = m1[2] + C.half_force[2];
-    const T ir = T(1) / rho;
+    // u = j / rho, or j / rho0 with the He-Luo equilibrium g_eq(rho, rho0 u, rho0 u u)
+    const T ir = (C.hl != T(0)) ? C.inv_rho0 : T(1) / rho;
     const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
     eA = drho;
     eB[0] = m1[0];

@@ -413,7 +413,7 @@ __device__ __forceinline__ void macro_node(const DomainDev& Dm, const typename S
   rho = C.rho0 + drho + C.half_source;
   drho_out = drho + C.half_source;
   if constexpr (EQ == EQ_NSE) {
-    const double ir = 1.0 / rho;
+    const double ir = (C.hl != 0.0) ? C.inv_rho0 : 1.0 / rho;   // He-Luo: rho0 u = j
     u[0] = (m1[0] + C.half_force[0]) * ir;
     u[1] = (m1[1] + C.half_force[1]) * ir;
     u[2] = (m1[2] + C.half_force[2]) * ir;
@@ -520,7 +520,8 @@ __global__ void __launch_bounds__(256)
           if constexpr (e0 * e2 != 0) m2[0][2] += (double)(e0 * e2) * d[J];
           if constexpr (e1 * e2 != 0) m2[1][2] += (double)(e1 * e2) * d[J];
         });
-        const double ir = 1.0 / r;
+        const double ru = (C.hl != 0.0) ? C.rho0 : r;   // He-Luo: f_eq = g_eq(rho, rho0 u, rho0 u u)
+        const double ir = 1.0 / ru;
         double u[3];
         for (int a = 0; a < 3; ++a) u[a] = (m1[a] + C.half_force[a]) * ir;
         // v = m_2^ne + dt/2 (u F + F u + (cs2 I - u u) S) on the 2nd-order rows
@@ -528,7 +529,7 @@ __global__ void __launch_bounds__(256)
         for (int a = 0; a < 3; ++a)
           for (int b = 0; b < 3; ++b) {
             const double m2ab = (a <= b ? m2[a][b] : m2[b][a]) * C.c[a] * C.c[b] + (a == b ? C.rho0 * C.cs2 : 0.0);
-            v[a][b] = m2ab - (a == b ? r * C.cs2 : 0.0) - r * u[a] * u[b] + u[a] * C.half_force[b] +
+            v[a][b] = m2ab - (a == b ? r * C.cs2 : 0.0) - ru * u[a] * u[b] + u[a] * C.half_force[b] +
                       C.half_force[a] * u[b] + (a == b ? C.half_cs2_source : 0.0) - u[a] * u[b] * C.half_source;
           }
         double tau[3][3];
@@ -545,13 +546,23 @@ __global__ void __launch_bounds__(256)
           for (int a = 0; a < 3; ++a)
             for (int b = a; b < 3; ++b) o[a][b] = tau[a][b];
         } else {
-          const double mu = r * Dm.ic.nu, mub = r * Dm.ic.nu_b;
-          double tr = 0.0;
-          for (int a = 0; a < D; ++a) tr += tau[a][a];
-          const double trE = tr / (D * mub);
-          const double iso = (mub - 2.0 * mu / D) * trE;
-          for (int a = 0; a < 3; ++a)
-            for (int b = a; b < 3; ++b) o[a][b] = (tau[a][b] - (a == b ? iso : 0.0)) / (2.0 * mu);
+          // eq. 4-28 with the tensors of eq. 4-29: tau_ab = 2 K_ab E_ab (a != b),
+          // tau_aa = K_aa (2 E_aa - (2/d) tr E) + Kb_a tr E, K = rho nu_entry
+          double num = 0.0, den = 1.0;
+          for (int a = 0; a < D; ++a) {
+            const double Kd = ru * Dm.ic.nu_diag[a], Kb = ru * Dm.ic.nu_b_ax[a];
+            num += tau[a][a] / (2.0 * Kd);
+            den += (Kb - 2.0 * Kd / D) / (2.0 * Kd);
+          }
+          const double trE = num / den;
+          for (int a = 0; a < 3; ++a) o[a][a] = 0.0;
+          for (int a = 0; a < D; ++a) {
+            const double Kd = ru * Dm.ic.nu_diag[a], Kb = ru * Dm.ic.nu_b_ax[a];
+            o[a][a] = (tau[a][a] - (Kb - 2.0 * Kd / D) * trE) / (2.0 * Kd);
+          }
+          o[0][1] = tau[0][1] / (2.0 * ru * Dm.ic.nu_pair[0]);
+          o[0][2] = tau[0][2] / (2.0 * ru * Dm.ic.nu_pair[1]);
+          o[1][2] = tau[1][2] / (2.0 * ru * Dm.ic.nu_pair[2]);
         }
         res[0] = o[0][0];
         res[1] = o[1][1];
@@ -735,21 +746,24 @@ __global__ void __launch_bounds__(256)
       double u[3] = {0, 0, 0};
       if (u_in)
         for (int a = 0; a < D; ++a) u[a] = u_in[(size_t)a * N + idx];
+      const double ru = (C.hl != 0.0) ? C.rho0 : r;   // He-Luo: g_eq(rho, rho0 u, rho0 u u)
       A = r - C.rho0 - C.half_source;
-      for (int a = 0; a < 3; ++a) B[a] = r * u[a] - C.half_force[a];
+      for (int a = 0; a < 3; ++a) B[a] = ru * u[a] - C.half_force[a];
       for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) M[a][b] = r * u[a] * u[b] + (a == b ? C.half_cs2_source : 0.0);
+        for (int b = 0; b < 3; ++b) M[a][b] = ru * u[a] * u[b] + (a == b ? C.half_cs2_source : 0.0);
       if (with_fne && u_in && !(Dm.has_solid && Dm.solid[idx])) {
         // m_2^ne = -(I - S2/2)^-1 tau - dt/2 (u F + F u + cs2 Sbar I)   (eq. 4-34)
         double G[3][3];
         velocity_gradient<D>(Dm, u_in, idx, g, G);
         double div = 0.0;
         for (int a = 0; a < D; ++a) div += G[a][a];
-        double tau[3][3];
-        for (int a = 0; a < 3; ++a)
-          for (int b = 0; b < 3; ++b)
-            tau[a][b] = r * Dm.ic.nu * (G[a][b] + G[b][a] - (a == b ? 2.0 / D * div : 0.0)) +
-                        (a == b ? r * Dm.ic.nu_b * div : 0.0);
+        // eq. 4-28 with the viscosity tensors of eq. 4-29
+        double tau[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int a = 0; a < D; ++a)
+          tau[a][a] = ru * (Dm.ic.nu_diag[a] * (2.0 * G[a][a] - 2.0 / D * div) + Dm.ic.nu_b_ax[a] * div);
+        tau[0][1] = tau[1][0] = ru * Dm.ic.nu_pair[0] * (G[0][1] + G[1][0]);
+        tau[0][2] = tau[2][0] = ru * Dm.ic.nu_pair[1] * (G[0][2] + G[2][0]);
+        tau[1][2] = tau[2][1] = ru * Dm.ic.nu_pair[2] * (G[1][2] + G[2][1]);
         double mne[3][3];
         for (int a = 0; a < 3; ++a) {
           double s = 0.0;

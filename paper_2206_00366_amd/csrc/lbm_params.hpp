@@ -30,6 +30,7 @@ struct Coef {
   T force[3], half_force[3];
   T source, half_source, cs2_source, half_cs2_source;
   T adv[3], D0, D2, inv_cs2_dt, inv_dt;
+  T hl, inv_rho0;           // He-Luo equilibrium flag (1 or 0) and 1 / rho0
 };
 
 // Initialisation-only quantities (always FP64).
@@ -37,6 +38,7 @@ struct InitCoef {
   double Kd[3][3];   // (I - Sbar/2)^-1 on the diagonal second moments
   double k_off[3];   // 1 / (1 - s_off/2)
   double nu, nu_b;
+  double nu_diag[3], nu_pair[3], nu_b_ax[3];   // viscosity tensor entries (eq. 4-29)
 };
 
 struct DomainDev {

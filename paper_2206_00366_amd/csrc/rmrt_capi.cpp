@@ -47,6 +47,9 @@ struct Derived {
   double c[3], cs2, dt, r[3];
   double w[27];
   double nu, nu_b, s_nu, s_s[3], s_b[3], s_hi;
+  double nu_diag[3], nu_pair[3], nu_b_ax[3];  // viscosity tensor entries (eq. 4-29)
+  double s_pair[3];   // off-diagonal rates (xy, xz, yz)
+  int hl;             // He-Luo equilibrium
   double Sbar[3][3];  // second-order diagonal block (eq. 5-8-1)
   double D0, D2;
   int e[27][3];
@@ -157,6 +160,9 @@ int derive(const rmrt_params* p, Derived& v) {
 
   v.D0 = p->D0;
   v.D2 = p->D2;
+  v.hl = p->incompressible != 0;
+  for (int k = 0; k < 3; ++k) v.nu_diag[k] = v.nu_pair[k] = v.nu_b_ax[k] = 0.0, v.s_pair[k] = 1.0;
+  if (v.hl && !(p->rho0 > 0)) return fail(RMRT_EINVAL, "the He-Luo equilibrium needs rho0 > 0");
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) v.Sbar[a][b] = 0.0;
   if (p->equation == RMRT_NSE) {
@@ -164,13 +170,27 @@ int derive(const rmrt_params* p, Derived& v) {
     if (!(v.nu > 0)) return fail(RMRT_EINVAL, "nu must be > 0");
     v.nu_b = p->nu_b < 0 ? 2.0 * v.nu / v.d : p->nu_b;
     if (!(v.nu_b > 0)) return fail(RMRT_EINVAL, "nu_b must be > 0");
-    // eq. 4-31 solved for the rates
+    // viscosity tensor entries of eq. 4-29 (diagonal xx, yy, zz; pairs xy,
+    // xz, yz; bulk per axis); unset entries are isotropic
+    for (int k = 0; k < 6; ++k)
+      if (std::isnan(p->nu_tensor[k]) || (k < 3 && std::isnan(p->nu_b_axis[k])))
+        return fail(RMRT_EINVAL, "viscosity tensor entry %d is NaN", k);
+    for (int k = 0; k < 3; ++k) {
+      v.nu_diag[k] = p->nu_tensor[k] > 0 ? p->nu_tensor[k] : v.nu;
+      v.nu_pair[k] = p->nu_tensor[3 + k] > 0 ? p->nu_tensor[3 + k] : v.nu;
+      v.nu_b_ax[k] = p->nu_b_axis[k] > 0 ? p->nu_b_axis[k] : v.nu_b;
+    }
+    // eq. 4-31 solved for the rates, entry by entry
     v.s_nu = 1.0 / (0.5 + v.nu / (v.cs2 * v.dt));
+    for (int k = 0; k < 3; ++k) {
+      v.s_pair[k] = 1.0 / (0.5 + v.nu_pair[k] / (v.cs2 * v.dt));
+      if (!(v.s_pair[k] > 0 && v.s_pair[k] < 2)) return fail(RMRT_EINVAL, "s_ab = %g outside (0, 2)", v.s_pair[k]);
+    }
     double a[3], b[3], Adiag[3];
     for (int k = 0; k < v.d; ++k) {
       const double g = v.c[k] * v.c[k] - v.cs2;
-      v.s_s[k] = 1.0 / (0.5 + 2.0 * v.nu / (g * v.dt));
-      v.s_b[k] = 1.0 / (0.5 + v.d * v.nu_b / (g * v.dt));
+      v.s_s[k] = 1.0 / (0.5 + 2.0 * v.nu_diag[k] / (g * v.dt));
+      v.s_b[k] = 1.0 / (0.5 + v.d * v.nu_b_ax[k] / (g * v.dt));
       a[k] = (1.0 / v.s_b[k] - 1.0 / v.s_s[k]) * g;
       b[k] = 1.0 / g;
       Adiag[k] = v.s_s[k];
@@ -188,6 +208,7 @@ int derive(const rmrt_params* p, Derived& v) {
         return fail(RMRT_EINVAL, "second-order rates outside (0, 2)");
   } else {
     v.nu = v.nu_b = 0.0;
+    if (p->incompressible) return fail(RMRT_EINVAL, "the He-Luo equilibrium is an NSE option");
     if (!(p->D0 > 0)) return fail(RMRT_EINVAL, "D0 must be > 0 for the NCDE");
     if (p->D2 < 0) return fail(RMRT_EINVAL, "D2 must be >= 0");
     v.s_nu = 1.0;
@@ -288,9 +309,11 @@ void fill_coef(const rmrt_params* p, const Derived& v, Coef<T>& C) {
       C.IhS[a][b] = (T)((a == b ? 1.0 : 0.0) - ((a < d && b < d) ? 0.5 * v.Sbar[a][b] : 0.0));
     }
   for (int k = 0; k < 3; ++k) {
-    C.s_off[k] = (T)v.s_nu;
-    C.ihs_off[k] = (T)(1.0 - 0.5 * v.s_nu);
+    C.s_off[k] = (T)v.s_pair[k];
+    C.ihs_off[k] = (T)(1.0 - 0.5 * v.s_pair[k]);
   }
+  C.hl = (T)(v.hl ? 1.0 : 0.0);
+  C.inv_rho0 = (T)(p->rho0 != 0.0 ? 1.0 / p->rho0 : 0.0);
   C.s_hi = (T)v.s_hi;
   // source terms carry the factor dt (m* gets dt (m_G + (I - S/2) m_F))
   for (int a = 0; a < 3; ++a) {
@@ -321,9 +344,14 @@ void fill_domain(const rmrt_params* p, const Derived& v, DomainDev& D, void* fa,
   invert3(IhS, K, v.d);
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) D.ic.Kd[a][b] = (a < v.d && b < v.d) ? K[a][b] : 0.0;
-  for (int k = 0; k < 3; ++k) D.ic.k_off[k] = 1.0 / (1.0 - 0.5 * v.s_nu);
+  for (int k = 0; k < 3; ++k) D.ic.k_off[k] = 1.0 / (1.0 - 0.5 * v.s_pair[k]);
   D.ic.nu = v.nu;
   D.ic.nu_b = v.nu_b;
+  for (int k = 0; k < 3; ++k) {
+    D.ic.nu_diag[k] = v.nu_diag[k];
+    D.ic.nu_pair[k] = v.nu_pair[k];
+    D.ic.nu_b_ax[k] = v.nu_b_ax[k];
+  }
   D.nx = p->n[0];
   D.ny = p->n[1];
   D.nz = p->n[2];
@@ -701,6 +729,7 @@ int rmrt_derive(const rmrt_params* p, rmrt_derived* out) {
   }
   out->s_hi = v.s_hi;
   out->nu_b = v.nu_b;
+  for (int k = 0; k < 3; ++k) out->s_pair[k] = v.s_pair[k];
   return RMRT_OK;
 }
 

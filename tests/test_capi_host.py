@@ -42,6 +42,22 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("case", [
+    dict(lattice="Q27", n=(4, 4, 4), dx=(1.0, 0.5, 2.0), nu=0.05, nu_b=0.1,
+         nu_tensor=(0.03, 0.06, 0.04, 0.02, 0.07, 0.05), nu_b_axis=(0.08, 0.05, 0.12)),
+    dict(lattice="Q9", n=(8, 8, 1), dx=(1.0, 0.5, 1.0), nu=0.05, nu_tensor=(0.02, -1, -1, 0.09, -1, -1),
+         nu_b_axis=(-1.0, 0.3, -1.0), incompressible=True),
+])
+def test_viscosity_tensor_rates_match_oracle(case):
+    m = O.Model(case)
+    d = rmrt.derive(rmrt.make_params(**case))
+    np.testing.assert_allclose(np.array(d.s_s)[: m.d], m.s_s, atol=1e-14)
+    np.testing.assert_allclose(np.array(d.s_b)[: m.d], m.s_b, atol=1e-14)
+    np.testing.assert_allclose(np.array(d.s_pair)[: len(m.pairs)], m.s_pair, atol=1e-14)
+    Sb = np.array([[d.Sbar2[i][k] for k in range(m.d)] for i in range(m.d)])
+    np.testing.assert_allclose(Sb, m.Sbar21, atol=1e-13)
+
+
 @pytest.mark.parametrize("case", CASES)
 def test_derived_parameters_match_oracle(case):
     m = O.Model(case)
@@ -114,6 +130,9 @@ def test_population_bytes():
     dict(lattice="Q5", n=(8, 8, 1), equation="NCDE", D0=0.01, cs2=0.6),   # w_0 < 0
     dict(lattice="Q27", n=(4, 4, 4), nu=0.05, w_corner=0.0, storage="f16dev"),
     dict(lattice=5, n=(4, 4, 4), equation="NCDE", D0=0.01),           # unknown lattice
+    dict(lattice="Q9", n=(8, 8, 1), equation="NCDE", D0=0.01, incompressible=True),  # He-Luo is NSE only
+    dict(lattice="Q9", n=(8, 8, 1), nu=0.05, incompressible=True, rho0=0.0),
+    dict(lattice="Q9", n=(8, 8, 1), nu=0.05, nu_tensor=(float("nan"), -1, -1, -1, -1, -1)),
 ])
 def test_invalid_parameters_rejected(bad):
     with pytest.raises(rmrt.RMRTError) as ei:

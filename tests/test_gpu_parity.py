@@ -46,6 +46,16 @@ CASES = {
                       adv=(0.03, -0.01, 0.02), rho0=0.0), None, 15),
     "q27_periodic": (dict(lattice="Q27", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), nu=0.05, nu_b=0.01), None, 15),
     "q19_standard_lattice": (dict(lattice="Q19", n=(12, 10, 9), dx=(1.0, 1.0, 1.0), cs2=1.0 / 3.0, nu=0.02), None, 15),
+    "q9_heluo_walls_force": (dict(lattice="Q9", n=(29, 17, 1), dx=(1.0, 0.5, 1.0), nu=0.04, nu_b=0.09,
+                                  force=(2e-5, -1e-5, 0.0), source=1e-6, wall_faces=WALLS["y"], incompressible=True,
+                                  rho0=1.05), None, 21),
+    "q27_viscosity_tensor_heluo": (dict(lattice="Q27", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), nu=0.05, nu_b=0.1,
+                                        nu_tensor=(0.03, 0.06, 0.04, 0.02, 0.07, 0.05), nu_b_axis=(0.08, 0.05, 0.12),
+                                        force=(1e-5, 0.0, 3e-6), wall_faces=WALLS["z"], incompressible=True),
+                                   lambda n: circle_mask(n, (5, 4), 2), 15),
+    "q19_viscosity_tensor": (dict(lattice="Q19", n=(13, 11, 9), dx=(1.0, 2.0, 1.0), nu=0.04,
+                                  nu_tensor=(0.02, 0.05, 0.03, 0.06, 0.025, 0.045), nu_b_axis=(0.1, -1.0, 0.04)),
+                             None, 15),
     "q27_channel_solid_force": (dict(lattice="Q27", n=(14, 9, 8), dx=(1.0, 2.0, 1.0), nu=0.05,
                                      force=(1e-5, 0.0, 0.0), source=-1e-6, wall_faces=WALLS["yz"],
                                      w_corner=0.0008), lambda n: circle_mask(n, (6, 4), 2), 15),
@@ -325,7 +335,8 @@ def test_conservation_and_reductions(rmrt):
     dom.close()
 
 
-@pytest.mark.parametrize("case", ["q9_channel_solid_force", "q19_channel_force", "q27_periodic"])
+@pytest.mark.parametrize("case", ["q9_channel_solid_force", "q19_channel_force", "q27_periodic",
+                                  "q9_heluo_walls_force", "q27_viscosity_tensor_heluo", "q19_viscosity_tensor"])
 def test_init_with_nonequilibrium_part(rmrt, case):
     say(f"[init fne] {case}")
     prm, solid_fn, _ = CASES[case]
