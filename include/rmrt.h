@@ -108,6 +108,12 @@ enum { RMRT_OUT_F64 = 0, RMRT_OUT_F32 = 1 };                       /* macroscopi
  *             (xx, yy, zz, xy, xz, yz): K_mu,aa = rho nu_tensor[a] sets s_s,a and
  *             K_mu,ab = rho nu_tensor[ab] sets s_ab (eq. 4-31 per entry);
  *             entries <= 0 take nu (the isotropic case)
+ *   gamma0    NCDE: 1 selects the gamma = 0 form of eq. 2-1, in which the
+ *             dt^2/2 dF/dt term is the explicit difference of F (zero for the
+ *             constant source S): populations are f itself (no fbar = f -
+ *             dt F / 2 transform), phi = sum_j f_j, and the source enters as
+ *             dt F instead of dt (I - Lambda/2) F.  0 = the gamma = 1 form
+ *             (eq. 2-3), the only one for the NSE.
  *   nu_b_axis[3]  NSE: per-axis bulk viscosities K_mu_b,aa = rho nu_b_axis[a]
  *             of eq. 4-29 (set s_b,a); entries <= 0 take nu_b (a zero-initialised
  *             struct is the isotropic model)
@@ -130,6 +136,7 @@ typedef struct rmrt_params {
   int incompressible;
   double nu_tensor[6];
   double nu_b_axis[3];
+  int gamma0;
 } rmrt_params;
 
 /* Values the library derives from a parameter set (host only, no GPU). */

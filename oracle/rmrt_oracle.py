@@ -39,6 +39,9 @@ GPU side can take the same ones; numbering as in the design notes):
       xz, yz) set s_s,a (diagonal entries), s_ab (off-diagonal entries) by
       eq. 4-31 entry by entry, and per-axis bulk viscosities set s_b,a;
       unset entries take nu and nu_b.
+  A21 gamma = 0 option of eq. 2-1 (NCDE): the dt^2/2 dF/dt term is the
+      explicit difference of F, zero for the constant source; populations are
+      f (no fbar transform), phi = sum f, and the collision adds dt (G + F).
   A18 the reduced lattices rD2Q5 (the rD2Q5I subset of rD2Q9) and rD3Q7 carry
       the NCDE only, in the C = 0 form of eq. 4-16: linear equilibrium
       g_eq(phi, phi u_adv, 0), F_j = w_j S and
@@ -225,7 +228,8 @@ def S2_sherman_morrison(c, cs2, s_s, s_b, d):
 DEFAULTS = dict(lattice="Q9", equation="NSE", n=(8, 8, 1), dx=(1.0, 1.0, 1.0), dt=1.0,
                 cs2=-1.0, nu=0.1, nu_b=-1.0, s_hi=-1.0, w_corner=-1.0,
                 D0=0.0, D2=0.0, adv=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0),
-                source=0.0, rho0=1.0, wall_faces=0, incompressible=False, nu_tensor=None, nu_b_axis=None)
+                source=0.0, rho0=1.0, wall_faces=0, incompressible=False, nu_tensor=None, nu_b_axis=None,
+                gamma0=False)
 
 
 class Model:
@@ -279,6 +283,8 @@ class Model:
 
         S = np.zeros((q, q))
         self.hl = bool(p["incompressible"]) and self.nse                        # A19
+        self.gamma0 = bool(p["gamma0"]) and not self.nse                       # A21
+        self.half_src = 0.0 if self.gamma0 else 0.5                            # phi = sum f (+ dt S / 2)
         if self.nse:
             nu = float(p["nu"])
             nu_b = float(p["nu_b"])
@@ -373,7 +379,7 @@ class Model:
             den = self.rho0 if self.hl else rho[None, :]                         # A19: rho0 u = j
             u = (self.C.T @ fbar + self.dt * self.force[:, None] / 2.0) / den
             return rho, u
-        phi = fbar.sum(axis=0) + self.dt * self.source / 2.0
+        phi = fbar.sum(axis=0) + self.half_src * self.dt * self.source
         return phi, np.repeat(self.adv[:, None], fbar.shape[1], axis=1)
 
     def s1_ncde(self, phi):
@@ -449,7 +455,8 @@ class Model:
         meq = self.M @ feq
         mF = self.M @ F
         mG = self.M @ G
-        mstar = m - self.apply_S(m - meq, s1) + self.dt * (mG + mF - 0.5 * self.apply_S(mF, s1))
+        # gamma = 1 (eq. 2-3): dt (G + (I - Lambda/2) F); gamma = 0 (eq. 2-1, A21): dt (G + F)
+        mstar = m - self.apply_S(m - meq, s1) + self.dt * (mG + mF - self.half_src * self.apply_S(mF, s1))
         return np.linalg.solve(self.M, mstar)
 
     def collide_velocity_space(self, fbar, phi_prev=None):
@@ -459,7 +466,7 @@ class Model:
         def Lam(x):
             return self.Minv @ self.apply_S(self.M @ x, s1)
 
-        return fbar - Lam(fbar - feq) + self.dt * (G + F - 0.5 * Lam(F))
+        return fbar - Lam(fbar - feq) + self.dt * (G + F - self.half_src * Lam(F))
 
     # ------------------------------------------------------------- propagation
     def stream(self, fstar, fprev):
@@ -521,7 +528,7 @@ class Model:
         d = self.d
         n = fbar.shape[1]
         feq, F, G, s1 = self.distributions(fbar, hist)
-        fne = fbar + 0.5 * self.dt * F - feq
+        fne = fbar + self.half_src * self.dt * F - feq
         if self.nse:
             rho, u = self.macroscopic(fbar)
             I = np.eye(d)[:, :, None]
@@ -579,7 +586,7 @@ class Model:
             feq = g_eq(self.C, self.w, self.c, self.cs2, rho, rho[None] * u, Mt)
             F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, self.source),
                      np.zeros((d, n)), np.zeros((d, d, n)))
-        return feq - 0.5 * self.dt * F
+        return feq - self.half_src * self.dt * F
 
     def velocity_gradient(self, u):
         """grad[a, b] = d u_a / d x_b; central differences, one-sided next to walls/solids."""

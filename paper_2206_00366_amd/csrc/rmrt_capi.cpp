@@ -209,6 +209,9 @@ int derive(const rmrt_params* p, Derived& v) {
   } else {
     v.nu = v.nu_b = 0.0;
     if (p->incompressible) return fail(RMRT_EINVAL, "the He-Luo equilibrium is an NSE option");
+  }
+  if (p->equation == RMRT_NSE && p->gamma0) return fail(RMRT_EINVAL, "gamma = 0 is an NCDE option (eq. 2-1)");
+  if (p->equation != RMRT_NSE) {
     if (!(p->D0 > 0)) return fail(RMRT_EINVAL, "D0 must be > 0 for the NCDE");
     if (p->D2 < 0) return fail(RMRT_EINVAL, "D2 must be >= 0");
     v.s_nu = 1.0;
@@ -323,7 +326,8 @@ void fill_coef(const rmrt_params* p, const Derived& v, Coef<T>& C) {
     C.adv[a] = (T)((a < d) ? p->adv[a] : 0.0);
   }
   C.source = (T)(dt * p->source);
-  C.half_source = (T)(0.5 * dt * p->source);
+  // gamma = 0 form (NCDE): populations are f, phi = sum f, no dt S / 2 shift
+  C.half_source = (p->equation == RMRT_NCDE && p->gamma0) ? (T)0 : (T)(0.5 * dt * p->source);
   C.cs2_source = (T)(dt * cs2 * p->source);
   C.half_cs2_source = (T)(0.5 * dt * cs2 * p->source);
   C.D0 = (T)p->D0;

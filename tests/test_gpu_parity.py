@@ -53,6 +53,8 @@ CASES = {
                                         nu_tensor=(0.03, 0.06, 0.04, 0.02, 0.07, 0.05), nu_b_axis=(0.08, 0.05, 0.12),
                                         force=(1e-5, 0.0, 3e-6), wall_faces=WALLS["z"], incompressible=True),
                                    lambda n: circle_mask(n, (5, 4), 2), 15),
+    "q9_ncde_gamma0_source": (dict(lattice="Q9", equation="NCDE", n=(33, 17, 1), dx=(1.0, 0.5, 1.0), D0=0.01,
+                                   D2=1.0, adv=(0.05, 0.02, 0.0), rho0=0.0, source=1e-3, gamma0=True), None, 25),
     "q19_viscosity_tensor": (dict(lattice="Q19", n=(13, 11, 9), dx=(1.0, 2.0, 1.0), nu=0.04,
                                   nu_tensor=(0.02, 0.05, 0.03, 0.06, 0.025, 0.045), nu_b_axis=(0.1, -1.0, 0.04)),
                              None, 15),

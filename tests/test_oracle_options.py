@@ -154,3 +154,36 @@ def test_sound_wave_damping_follows_the_longitudinal_entries(lat, dx, nt, nb):
     gamma = -np.polyfit(ts, np.log(es), 1)[0] / 2.0
     nu_L = 2.0 * nt[0] * (1.0 - 1.0 / d) + nb[0]
     assert abs(gamma / (k * k * nu_L / 2.0) - 1.0) < 0.01, gamma
+
+
+def test_gamma0_equals_gamma1_without_source():
+    """Without a source F = 0, so the two forms of eq. 2-1 are the same scheme."""
+    base = dict(lattice="Q9", equation="NCDE", n=(20, 14, 1), dx=(1.0, 0.5, 1.0), D0=0.02, D2=1.0,
+                adv=(0.04, 0.01, 0.0), rho0=0.0)
+    phi = 0.2 + 0.6 * np.random.default_rng(3).uniform(size=20 * 14)
+    a = O.Model(base)
+    b = O.Model(dict(base, gamma0=True))
+    np.testing.assert_array_equal(a.step(a.init(phi, None), 9), b.step(b.init(phi, None), 9))
+
+
+@pytest.mark.parametrize("lat", ["Q9", "Q5"])
+def test_gamma0_source_mass_balance_and_hill(lat):
+    """gamma = 0 (A21): phi = sum f gains exactly N dt S per step, and an
+    advected Gaussian hill on a uniform source follows hill(t) + S t."""
+    nx, ny, dy, D, S = 128, 128, 0.5, 0.01, 2e-4
+    adv = (0.05, 0.02, 0.0)
+    m = O.Model(dict(lattice=lat, equation="NCDE", n=(nx, ny, 1), dx=(1.0, dy, 1.0), D0=D, D2=0.0, adv=adv,
+                     rho0=0.0, source=S, gamma0=True))
+    X, Y, _ = grid_coords((nx, ny, 1), (1.0, dy, 1.0))
+    phi0 = O.gaussian_hill_nd([X, Y], 0.0, 8.0, D, (64.0, 32.0), adv[:2], (nx, ny * dy))
+    f = m.init(phi0, None)
+    np.testing.assert_allclose(f.sum(axis=0), phi0, atol=1e-15)          # no dt S / 2 shift
+    steps = 300
+    if m.linear:
+        f, _ = m.step(f, steps, m.init_history(phi0))
+    else:
+        f = m.step(f, steps)
+    phi, _ = m.macroscopic(f)
+    assert abs(phi.sum() - phi0.sum() - steps * m.N * S) < 1e-9
+    exact = O.gaussian_hill_nd([X, Y], steps, 8.0, D, (64.0, 32.0), adv[:2], (nx, ny * dy)) + S * steps
+    assert np.sqrt(((phi - exact) ** 2).sum() / (exact**2).sum()) < 2e-3
