@@ -114,6 +114,9 @@ enum { RMRT_OUT_F64 = 0, RMRT_OUT_F32 = 1 };                       /* macroscopi
  *             dt F / 2 transform), phi = sum_j f_j, and the source enters as
  *             dt F instead of dt (I - Lambda/2) F.  0 = the gamma = 1 form
  *             (eq. 2-3), the only one for the NSE.
+ *   diffusive NCDE: 1 selects the diffusive-scaling model of eq. 4-17: the
+ *             dt^2/2 D F term removed (populations f, phi = sum f, as gamma0),
+ *             f_eq = g_eq(phi, phi adv, 0) (C = 0) and G = 0
  *   nu_b_axis[3]  NSE: per-axis bulk viscosities K_mu_b,aa = rho nu_b_axis[a]
  *             of eq. 4-29 (set s_b,a); entries <= 0 take nu_b (a zero-initialised
  *             struct is the isotropic model)
@@ -137,6 +140,7 @@ typedef struct rmrt_params {
   double nu_tensor[6];
   double nu_b_axis[3];
   int gamma0;
+  int diffusive;
 } rmrt_params;
 
 /* Values the library derives from a parameter set (host only, no GPU). */

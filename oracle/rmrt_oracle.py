@@ -42,6 +42,9 @@ GPU side can take the same ones; numbering as in the design notes):
   A21 gamma = 0 option of eq. 2-1 (NCDE): the dt^2/2 dF/dt term is the
       explicit difference of F, zero for the constant source; populations are
       f (no fbar transform), phi = sum f, and the collision adds dt (G + F).
+  A22 diffusive-scaling option (eq. 4-17, NCDE): the dt^2/2 D F term is
+      removed (populations f, phi = sum f, as A21), f_eq = g_eq(phi, phi u, 0)
+      (C = 0) and G = 0; the grad phi output then drops its dt X / 2 term.
   A18 the reduced lattices rD2Q5 (the rD2Q5I subset of rD2Q9) and rD3Q7 carry
       the NCDE only, in the C = 0 form of eq. 4-16: linear equilibrium
       g_eq(phi, phi u_adv, 0), F_j = w_j S and
@@ -229,7 +232,7 @@ DEFAULTS = dict(lattice="Q9", equation="NSE", n=(8, 8, 1), dx=(1.0, 1.0, 1.0), d
                 cs2=-1.0, nu=0.1, nu_b=-1.0, s_hi=-1.0, w_corner=-1.0,
                 D0=0.0, D2=0.0, adv=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0),
                 source=0.0, rho0=1.0, wall_faces=0, incompressible=False, nu_tensor=None, nu_b_axis=None,
-                gamma0=False)
+                gamma0=False, diffusive=False)
 
 
 class Model:
@@ -284,7 +287,8 @@ class Model:
         S = np.zeros((q, q))
         self.hl = bool(p["incompressible"]) and self.nse                        # A19
         self.gamma0 = bool(p["gamma0"]) and not self.nse                       # A21
-        self.half_src = 0.0 if self.gamma0 else 0.5                            # phi = sum f (+ dt S / 2)
+        self.diffusive = bool(p["diffusive"]) and not self.nse                 # A22
+        self.half_src = 0.0 if (self.gamma0 or self.diffusive) else 0.5        # phi = sum f (+ dt S / 2)
         if self.nse:
             nu = float(p["nu"])
             nu_b = float(p["nu_b"])
@@ -411,7 +415,10 @@ class Model:
         S = self.source
         F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, S), np.zeros((d, n)), np.zeros((d, d, n)))
         s1 = self.s1_ncde(phi)
-        if self.linear:
+        if self.diffusive:
+            feq = g_eq(self.C, self.w, self.c, self.cs2, phi, B, np.zeros((d, d, n)))   # eq. 4-17
+            M1G = np.zeros((d, n))
+        elif self.linear:
             feq = g_eq(self.C, self.w, self.c, self.cs2, phi, B, np.zeros((d, d, n)))   # eq. 4-16a
             dBdt = u * (phi - phi_prev)[None] / self.dt                        # first-order difference
             M1G = (1.0 - s1[None] / 2.0) * dBdt                                # eq. 4-16b
@@ -554,7 +561,9 @@ class Model:
             return tau, E
         phi, u = self.macroscopic(fbar)
         m1ne = self.C.T @ fne
-        if self.linear:
+        if self.diffusive:
+            X = np.zeros_like(u)
+        elif self.linear:
             X = u * (phi - hist)[None] / self.dt
         else:
             X = u * self.source
@@ -582,7 +591,8 @@ class Model:
                      np.repeat(Fb[:, None], n, axis=1), -self.cs2 * Sb * np.repeat(I, n, axis=2))
         else:
             u = np.repeat(self.adv[:, None], n, axis=1)
-            Mt = np.zeros((d, d, n)) if self.linear else rho[None, None] * np.einsum("an,bn->abn", u, u)
+            Mt = (np.zeros((d, d, n)) if (self.linear or self.diffusive)
+                  else rho[None, None] * np.einsum("an,bn->abn", u, u))
             feq = g_eq(self.C, self.w, self.c, self.cs2, rho, rho[None] * u, Mt)
             F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, self.source),
                      np.zeros((d, n)), np.zeros((d, d, n)))

@@ -49,6 +49,13 @@ struct Lat {
   static constexpr int slot(int j) {
     return (e(j, 0) + 1) + 3 * (e(j, 1) + 1) + (D == 3 ? 9 * (e(j, 2) + 1) : 0);
   }
+  // weight class of velocity j: 0 rest; 1, 2, 3 on the x, y, z axes; 4, 5, 6
+  // in the xy, xz, yz planes; 7 corners
+  static constexpr int wclass(int j) {
+    const int x = e(j, 0) != 0, y = e(j, 1) != 0, z = e(j, 2) != 0;
+    const int n = x + y + z;
+    return n == 0 ? 0 : n == 3 ? 7 : n == 1 ? (x ? 1 : y ? 2 : 3) : (x && y ? 4 : x && z ? 5 : 6);
+  }
   static constexpr int opp(int j) {
     for (int k = 0; k < Q; ++k)
       if (e(k, 0) == -e(j, 0) && e(k, 1) == -e(j, 1) && e(k, 2) == -e(j, 2)) return k;
@@ -103,11 +110,12 @@ template <>
 struct Store<ST_F16> {
   using S = _Float16;
   using T = float;
-  // h_j = d_j / w_j keeps every slot well inside the normal half range
-  template <int J>
-  __device__ static __forceinline__ T dec(S v, const Coef<T>& C) { return (float)v * C.w[J]; }
-  template <int J>
-  __device__ static __forceinline__ S enc(T v, const Coef<T>& C) { return (_Float16)(v * C.iw[J]); }
+  // h_j = d_j / w_j keeps every slot well inside the normal half range; K is
+  // the weight class of the velocity
+  template <int K>
+  __device__ static __forceinline__ T dec(S v, const Coef<T>& C) { return (float)v * C.wc[K]; }
+  template <int K>
+  __device__ static __forceinline__ S enc(T v, const Coef<T>& C) { return (_Float16)(v * C.iwc[K]); }
 };
 
 template <typename T>
@@ -268,23 +276,24 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, T phi_prev
         // G from dB/dt = u (phi - phi_prev) / dt, first-order difference (eq. 4-16)
         const T g = (T(1) - T(0.5) * s1) * (phi - phi_prev) * C.inv_dt;
         sA = C.source;
-        sB[0] = g * C.adv[0];
-        sB[1] = g * C.adv[1];
-        sB[2] = g * C.adv[2];
+        sB[0] = g * C.adv_g[0];
+        sB[1] = g * C.adv_g[1];
+        sB[2] = g * C.adv_g[2];
       }
     } else {
-      eMd[0] = eB[0] * C.adv[0];
-      eMd[1] = eB[1] * C.adv[1];
-      eMd[2] = eB[2] * C.adv[2];
-      eMo[0] = eB[0] * C.adv[1];
-      eMo[1] = eB[0] * C.adv[2];
-      eMo[2] = eB[1] * C.adv[2];
+      // C = phi u u (adv_c = adv), or C = 0 at the diffusive scaling (adv_c = 0)
+      eMd[0] = eB[0] * C.adv_c[0];
+      eMd[1] = eB[1] * C.adv_c[1];
+      eMd[2] = eB[2] * C.adv_c[2];
+      eMo[0] = eB[0] * C.adv_c[1];
+      eMo[1] = eB[0] * C.adv_c[2];
+      eMo[2] = eB[1] * C.adv_c[2];
       if constexpr (FORCE) {
         const T g = (T(1) - T(0.5) * s1) * C.source;                    // eq. 4-11
         sA = C.source;
-        sB[0] = g * C.adv[0];
-        sB[1] = g * C.adv[1];
-        sB[2] = g * C.adv[2];
+        sB[0] = g * C.adv_g[0];
+        sB[1] = g * C.adv_g[1];
+        sB[2] = g * C.adv_g[2];
       }
     }
   }

@@ -217,7 +217,7 @@ struct NodeStep {
       } else {
         v = ld_elem(fin + (size_t)J * LD, idx);
       }
-      t[Lat<L>::slot(J)] = SS::template dec<J>(v, C);
+      t[Lat<L>::slot(J)] = SS::template dec<Lat<L>::wclass(J)>(v, C);
     });
   }
 
@@ -235,7 +235,7 @@ struct NodeStep {
     static_for<0, Q>([&](auto j_) {
       constexpr int J = decltype(j_)::value;
       constexpr int O = Lat<L>::opp(J);
-      const S v = SS::template enc<J>(t[Lat<L>::slot(J)], C);
+      const S v = SS::template enc<Lat<L>::wclass(J)>(t[Lat<L>::slot(J)], C);
       if constexpr (PH == PH_AA_EVEN) {
         st_elem(fout + (size_t)O * LD, idx, v);
       } else if constexpr (BC == 0) {
@@ -583,7 +583,7 @@ __global__ void __launch_bounds__(256)
           X = (r - prev) * C.inv_dt;
         }
         for (int a = 0; a < D; ++a)
-          res[a] = -(1.0 - 0.5 * s1) * (m1[a] - r * C.adv[a] + 0.5 * C.dt * C.adv[a] * X) / Dphi;
+          res[a] = -(1.0 - 0.5 * s1) * (m1[a] - r * C.adv[a] + 0.5 * C.dt * C.adv_g[a] * X) / Dphi;
       }
     }
     for (int k = 0; k < NC; ++k) {
@@ -784,7 +784,7 @@ __global__ void __launch_bounds__(256)
       for (int a = 0; a < 3; ++a) B[a] = r * C.adv[a];
       if constexpr (!Lat<L>::linear)
         for (int a = 0; a < 3; ++a)
-          for (int b = 0; b < 3; ++b) M[a][b] = r * C.adv[a] * C.adv[b];
+          for (int b = 0; b < 3; ++b) M[a][b] = r * C.adv_c[a] * C.adv_c[b];   // 0 at the diffusive scaling
       else if (!(Dm.has_solid && Dm.solid[idx]))
         ((typename Store<ST>::T*)Dm.hist)[idx] = (typename Store<ST>::T)r;   // dB/dt = 0 at the first step
     }

@@ -19,6 +19,10 @@ struct Coef {
   T rho0, cs2, inv_cs2, dt;
   T c[3];
   T w[27], iw[27];          // weights in paper order and their reciprocals
+  // the same by weight class (0 rest, 1-3 x/y/z axes, 4-6 xy/xz/yz edges, 7
+  // corners): every velocity of a class has the same weight (Sec. III), so
+  // the step reads 8 values instead of q
+  T wc[8], iwc[8];
   // scaled raw moment n of g_eq(A, B, M):
   //   A E0[n] + B_odd E1[n] + sum_a M_aa E2[n][a] + M_pair E3[n]
   T E0[27], E1[27], E2[27][3], E3[27];
@@ -30,6 +34,8 @@ struct Coef {
   T force[3], half_force[3];
   T source, half_source, cs2_source, half_cs2_source;
   T adv[3], D0, D2, inv_cs2_dt, inv_dt;
+  T adv_c[3];               // NCDE: adv in C = phi u u (0 at the diffusive scaling, eq. 4-17)
+  T adv_g[3];               // NCDE: adv in M_1G (0 at the diffusive scaling: G = 0)
   T hl, inv_rho0;           // He-Luo equilibrium flag (1 or 0) and 1 / rho0
 };
 

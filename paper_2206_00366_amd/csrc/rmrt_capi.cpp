@@ -211,6 +211,7 @@ int derive(const rmrt_params* p, Derived& v) {
     if (p->incompressible) return fail(RMRT_EINVAL, "the He-Luo equilibrium is an NSE option");
   }
   if (p->equation == RMRT_NSE && p->gamma0) return fail(RMRT_EINVAL, "gamma = 0 is an NCDE option (eq. 2-1)");
+  if (p->equation == RMRT_NSE && p->diffusive) return fail(RMRT_EINVAL, "the diffusive scaling is an NCDE option");
   if (p->equation != RMRT_NSE) {
     if (!(p->D0 > 0)) return fail(RMRT_EINVAL, "D0 must be > 0 for the NCDE");
     if (p->D2 < 0) return fail(RMRT_EINVAL, "D2 must be >= 0");
@@ -273,6 +274,15 @@ void fill_coef(const rmrt_params* p, const Derived& v, Coef<T>& C) {
     C.w[j] = (T)v.w[j];
     C.iw[j] = v.w[j] > 0 ? (T)(1.0 / v.w[j]) : (T)0;
   }
+  // by weight class (rest, x, y, z axes, xy, xz, yz edges, corners); all
+  // velocities of a class share one weight
+  for (int k = 0; k < 8; ++k) C.wc[k] = C.iwc[k] = (T)0;
+  for (int j = 0; j < v.q; ++j) {
+    const int x = v.e[j][0] != 0, y = v.e[j][1] != 0, z = v.e[j][2] != 0, n = x + y + z;
+    const int k = n == 0 ? 0 : n == 3 ? 7 : n == 1 ? (x ? 1 : y ? 2 : 3) : (x && y ? 4 : x && z ? 5 : 6);
+    C.wc[k] = C.w[j];
+    C.iwc[k] = C.iw[j];
+  }
   // scaled raw-moment tables of g_eq (eq. 3-3, 3-4) for every tensor slot
   const int d = v.d;
   const double cs2 = v.cs2;
@@ -326,8 +336,15 @@ void fill_coef(const rmrt_params* p, const Derived& v, Coef<T>& C) {
     C.adv[a] = (T)((a < d) ? p->adv[a] : 0.0);
   }
   C.source = (T)(dt * p->source);
-  // gamma = 0 form (NCDE): populations are f, phi = sum f, no dt S / 2 shift
-  C.half_source = (p->equation == RMRT_NCDE && p->gamma0) ? (T)0 : (T)(0.5 * dt * p->source);
+  // gamma = 0 form and diffusive scaling (NCDE): populations are f, phi = sum f,
+  // no dt S / 2 shift (eq. 2-1 without the dt^2/2 D F term)
+  const bool no_shift = p->equation == RMRT_NCDE && (p->gamma0 || p->diffusive);
+  C.half_source = no_shift ? (T)0 : (T)(0.5 * dt * p->source);
+  for (int a = 0; a < 3; ++a) {
+    const bool diff = p->equation == RMRT_NCDE && p->diffusive;
+    C.adv_c[a] = diff ? (T)0 : C.adv[a];   // eq. 4-17: C = 0 and G = 0
+    C.adv_g[a] = diff ? (T)0 : C.adv[a];
+  }
   C.cs2_source = (T)(dt * cs2 * p->source);
   C.half_cs2_source = (T)(0.5 * dt * cs2 * p->source);
   C.D0 = (T)p->D0;

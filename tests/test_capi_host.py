@@ -133,6 +133,7 @@ def test_population_bytes():
     dict(lattice="Q9", n=(8, 8, 1), equation="NCDE", D0=0.01, incompressible=True),  # He-Luo is NSE only
     dict(lattice="Q9", n=(8, 8, 1), nu=0.05, incompressible=True, rho0=0.0),
     dict(lattice="Q9", n=(8, 8, 1), nu=0.05, gamma0=True),                          # gamma = 0 is NCDE only
+    dict(lattice="Q9", n=(8, 8, 1), nu=0.05, diffusive=True),                       # so is the diffusive scaling
     dict(lattice="Q9", n=(8, 8, 1), nu=0.05, nu_tensor=(float("nan"), -1, -1, -1, -1, -1)),
 ])
 def test_invalid_parameters_rejected(bad):

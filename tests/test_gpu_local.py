@@ -40,6 +40,8 @@ CASES = {
     "q27_tensor_heluo": (dict(lattice="Q27", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), nu=0.05, nu_b=0.1,
                               nu_tensor=(0.03, 0.06, 0.04, 0.02, 0.07, 0.05), nu_b_axis=(0.08, 0.05, 0.12),
                               force=(1e-5, 0.0, 3e-6), source=1e-6, wall_faces=WALLS["z"], incompressible=True), None, 9),
+    "q9_ncde_diffusive": (dict(lattice="Q9", equation="NCDE", n=(33, 17, 1), dx=(1.0, 0.5, 1.0), D0=0.01, D2=1.0,
+                               adv=(0.01, 0.005, 0.0), rho0=0.0, source=1e-3, diffusive=True), None, 13),
     "q9_ncde_source": (dict(lattice="Q9", equation="NCDE", n=(33, 17, 1), dx=(1.0, 0.5, 1.0), D0=0.01, D2=1.0,
                             adv=(0.05, 0.02, 0.0), rho0=0.0, source=1e-3), None, 13),
     "q19_ncde": (dict(lattice="Q19", equation="NCDE", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), D0=0.02, D2=0.5,

@@ -55,6 +55,9 @@ CASES = {
                                    lambda n: circle_mask(n, (5, 4), 2), 15),
     "q9_ncde_gamma0_source": (dict(lattice="Q9", equation="NCDE", n=(33, 17, 1), dx=(1.0, 0.5, 1.0), D0=0.01,
                                    D2=1.0, adv=(0.05, 0.02, 0.0), rho0=0.0, source=1e-3, gamma0=True), None, 25),
+    "q19_ncde_diffusive_source": (dict(lattice="Q19", equation="NCDE", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), D0=0.02,
+                                       D2=0.5, adv=(0.01, -0.005, 0.004), source=-1e-3, diffusive=True, rho0=0.0),
+                                  None, 15),
     "q19_viscosity_tensor": (dict(lattice="Q19", n=(13, 11, 9), dx=(1.0, 2.0, 1.0), nu=0.04,
                                   nu_tensor=(0.02, 0.05, 0.03, 0.06, 0.025, 0.045), nu_b_axis=(0.1, -1.0, 0.04)),
                              None, 15),

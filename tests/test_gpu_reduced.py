@@ -39,6 +39,8 @@ CASES = {
                                       cs2=1.0 / 3.0, D0=0.1, rho0=0.0, s_hi=1.3), None, 21),
     "q5_gamma0_source": (dict(lattice="Q5", equation="NCDE", n=(30, 19, 1), dx=(1.0, 0.5, 1.0), D0=0.03, D2=0.5,
                               adv=(0.04, 0.02, 0.0), source=5e-4, gamma0=True, rho0=0.0), None, 21),
+    "q7_diffusive_source": (dict(lattice="Q7", equation="NCDE", n=(9, 8, 7), dx=(1.0, 1.0, 0.5), D0=0.03, D2=0.2,
+                                 adv=(0.01, 0.004, 0.0), source=2e-4, diffusive=True, rho0=0.0), None, 13),
     "q7_periodic": (dict(lattice="Q7", equation="NCDE", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), D0=0.02, D2=0.5,
                          adv=(0.03, -0.01, 0.02), rho0=0.0), None, 15),
     "q7_walls_source": (dict(lattice="Q7", equation="NCDE", n=(9, 10, 12), dx=(1.0, 1.0, 0.5), cs2=0.05, D0=0.03,

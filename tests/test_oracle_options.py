@@ -187,3 +187,36 @@ def test_gamma0_source_mass_balance_and_hill(lat):
     assert abs(phi.sum() - phi0.sum() - steps * m.N * S) < 1e-9
     exact = O.gaussian_hill_nd([X, Y], steps, 8.0, D, (64.0, 32.0), adv[:2], (nx, ny * dy)) + S * steps
     assert np.sqrt(((phi - exact) ** 2).sum() / (exact**2).sum()) < 2e-3
+
+
+def test_diffusive_scaling_reduces_to_the_standard_model_without_advection_or_source():
+    """Eq. 4-17 differs from eq. 4-14 only through u u, G and the source shift:
+    with u_adv = 0 and S = 0 the two models are the same scheme."""
+    base = dict(lattice="Q19", equation="NCDE", n=(7, 6, 5), dx=(1.0, 0.5, 2.0), D0=0.02, D2=1.0, rho0=0.0)
+    phi = 0.2 + 0.6 * np.random.default_rng(8).uniform(size=7 * 6 * 5)
+    a = O.Model(base)
+    b = O.Model(dict(base, diffusive=True))
+    np.testing.assert_array_equal(a.step(a.init(phi, None), 7), b.step(b.init(phi, None), 7))
+
+
+@pytest.mark.parametrize("lat", ["Q9", "Q5"])
+def test_diffusive_scaling_hill(lat):
+    """At the diffusive scaling (small u_adv) the linear-equilibrium model
+    without G follows the advected hill with a uniform source; the mass gain is
+    exactly N dt S per step."""
+    nx, ny, dy, D, S = 128, 128, 0.5, 0.02, 1e-4
+    adv = (0.004, 0.002, 0.0)
+    m = O.Model(dict(lattice=lat, equation="NCDE", n=(nx, ny, 1), dx=(1.0, dy, 1.0), D0=D, D2=0.0, adv=adv,
+                     rho0=0.0, source=S, diffusive=True))
+    X, Y, _ = grid_coords((nx, ny, 1), (1.0, dy, 1.0))
+    phi0 = O.gaussian_hill_nd([X, Y], 0.0, 8.0, D, (64.0, 32.0), adv[:2], (nx, ny * dy))
+    f = m.init(phi0, None)
+    steps = 300
+    if m.linear:
+        f, _ = m.step(f, steps, m.init_history(phi0))
+    else:
+        f = m.step(f, steps)
+    phi, _ = m.macroscopic(f)
+    assert abs(phi.sum() - phi0.sum() - steps * m.N * S) < 1e-9
+    exact = O.gaussian_hill_nd([X, Y], steps, 8.0, D, (64.0, 32.0), adv[:2], (nx, ny * dy)) + S * steps
+    assert np.sqrt(((phi - exact) ** 2).sum() / (exact**2).sum()) < 2e-3
