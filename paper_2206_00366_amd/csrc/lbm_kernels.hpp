@@ -28,8 +28,8 @@ namespace rmrt {
 
 // Buffers reach the kernels through the parameter block, so the compiler
 // cannot see that they live in global memory; casting them to address space 1
-// turns flat loads/stores (64-bit addresses, both wait counters) into global
-// ones with a scalar base and a 32-bit lane offset.
+// turns flat loads/stores (which also count against the LDS wait counter)
+// into global ones.
 template <typename T>
 using gmem = __attribute__((address_space(1))) T;
 template <typename T>
