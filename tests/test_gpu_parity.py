@@ -443,3 +443,26 @@ def test_degenerate_single_node_extents(rmrt, lat, n):
     dom.step(7)
     assert rel_err(dom.populations().cpu().numpy(), f_or) < 1e-12
     dom.close()
+
+
+@pytest.mark.parametrize("lat,n,storage", [("Q9", (12000, 12000, 1), "f32dev"), ("Q27", (300, 300, 300), "f64")])
+def test_byte_offsets_beyond_4_gib(rmrt, lat, n, storage):
+    """Population buffers larger than 4 GiB (5.2 GB and 5.8 GB): the highest
+    streams start beyond 2^32 bytes, so every stream offset must be formed in
+    64 bits.  One step, 4096 sampled nodes (and the last node) against the
+    oracle."""
+    say(f"[large buffers] {lat} {n} {storage}")
+    N = n[0] * n[1] * n[2]
+    d = 2 if lat == "Q9" else 3
+    q = 9 if lat == "Q9" else 27
+    es = 4 if storage == "f32dev" else 8
+    prm = dict(lattice=lat, n=n, dx=(1.0, 0.5, 2.0)[:d] + ((1.0,) if d == 2 else ()), nu=0.03)
+    assert (q - 1) * N * es > 2**32
+    rng = np.random.default_rng(13)
+    rho = 1.0 + 1e-3 * rng.uniform(-1, 1, N)
+    u = 0.02 * rng.uniform(-1, 1, (d, N))
+    got, expect = _sampled_one_step(rmrt, prm, rho, u, storage, "AA", 4096, 13)
+    del rho, u
+    err = np.abs(got - expect).max() / np.abs(expect).max()
+    say(f"   sampled max rel err {err:.2e}")
+    assert err < (2e-6 if storage == "f32dev" else 1e-13)
