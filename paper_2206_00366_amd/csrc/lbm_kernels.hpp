@@ -413,7 +413,7 @@ __device__ __forceinline__ void macro_node(const DomainDev& Dm, const typename S
   rho = C.rho0 + drho + C.half_source;
   drho_out = drho + C.half_source;
   if constexpr (EQ == EQ_NSE) {
-    const double ir = (C.hl != 0.0) ? C.inv_rho0 : 1.0 / rho;   // He-Luo: rho0 u = j
+    const double ir = 1.0 / (C.hl ? C.rho0 : rho);   // He-Luo: rho0 u = j
     u[0] = (m1[0] + C.half_force[0]) * ir;
     u[1] = (m1[1] + C.half_force[1]) * ir;
     u[2] = (m1[2] + C.half_force[2]) * ir;
@@ -520,7 +520,7 @@ __global__ void __launch_bounds__(256)
           if constexpr (e0 * e2 != 0) m2[0][2] += (double)(e0 * e2) * d[J];
           if constexpr (e1 * e2 != 0) m2[1][2] += (double)(e1 * e2) * d[J];
         });
-        const double ru = (C.hl != 0.0) ? C.rho0 : r;   // He-Luo: f_eq = g_eq(rho, rho0 u, rho0 u u)
+        const double ru = C.hl ? C.rho0 : r;   // He-Luo: f_eq = g_eq(rho, rho0 u, rho0 u u)
         const double ir = 1.0 / ru;
         double u[3];
         for (int a = 0; a < 3; ++a) u[a] = (m1[a] + C.half_force[a]) * ir;
@@ -746,7 +746,7 @@ __global__ void __launch_bounds__(256)
       double u[3] = {0, 0, 0};
       if (u_in)
         for (int a = 0; a < D; ++a) u[a] = u_in[(size_t)a * N + idx];
-      const double ru = (C.hl != 0.0) ? C.rho0 : r;   // He-Luo: g_eq(rho, rho0 u, rho0 u u)
+      const double ru = C.hl ? C.rho0 : r;   // He-Luo: g_eq(rho, rho0 u, rho0 u u)
       A = r - C.rho0 - C.half_source;
       for (int a = 0; a < 3; ++a) B[a] = ru * u[a] - C.half_force[a];
       for (int a = 0; a < 3; ++a)

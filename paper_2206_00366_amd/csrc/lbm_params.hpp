@@ -36,7 +36,7 @@ struct Coef {
   T adv[3], D0, D2, inv_cs2_dt, inv_dt;
   T adv_c[3];               // NCDE: adv in C = phi u u (0 at the diffusive scaling, eq. 4-17)
   T adv_g[3];               // NCDE: adv in M_1G (0 at the diffusive scaling: G = 0)
-  T hl, inv_rho0;           // He-Luo equilibrium flag (1 or 0) and 1 / rho0
+  uint32_t hl;              // He-Luo equilibrium (1) or eq. NSEfeq (0)
 };
 
 // Initialisation-only quantities (always FP64).

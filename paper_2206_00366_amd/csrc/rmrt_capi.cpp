@@ -325,8 +325,7 @@ void fill_coef(const rmrt_params* p, const Derived& v, Coef<T>& C) {
     C.s_off[k] = (T)v.s_pair[k];
     C.ihs_off[k] = (T)(1.0 - 0.5 * v.s_pair[k]);
   }
-  C.hl = (T)(v.hl ? 1.0 : 0.0);
-  C.inv_rho0 = (T)(p->rho0 != 0.0 ? 1.0 / p->rho0 : 0.0);
+  C.hl = v.hl ? 1u : 0u;
   C.s_hi = (T)v.s_hi;
   // source terms carry the factor dt (m* gets dt (m_G + (I - S/2) m_F))
   for (int a = 0; a < 3; ++a) {
