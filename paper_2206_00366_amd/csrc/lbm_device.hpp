@@ -237,9 +237,12 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, T phi_prev
   T sA = T(0), sB[3] = {T(0), T(0), T(0)}, sMd[3] = {T(0), T(0), T(0)}, sMo[3] = {T(0), T(0), T(0)};
   T s1 = T(0);
   if constexpr (EQ == EQ_NSE) {
-    const T rho = C.rho0 + drho + C.half_source;                       // eq. 2-4-2
-    const T jx = m1[0] + C.half_force[0], jy = m1[1] + C.half_force[1],
-            jz = m1[2] + C.half_force[2];
+    // eq. 2-4-2; without forcing the host guarantees Fbar = 0 and Sbar = 0, so
+    // the kernel does not hold the half-step corrections at all
+    const T rho = FORCE ? C.rho0 + drho + C.half_source : C.rho0 + drho;
+    const T jx = FORCE ? m1[0] + C.half_force[0] : m1[0];
+    const T jy = FORCE ? m1[1] + C.half_force[1] : m1[1];
+    const T jz = FORCE ? m1[2] + C.half_force[2] : m1[2];
     // u = j / rho, or j / rho0 with the He-Luo equilibrium g_eq(rho, rho0 u, rho0 u u)
     const T ir = recip(C.hl ? C.rho0 : rho);
     const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
@@ -274,7 +277,7 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, T phi_prev
       sMo[2] = C.ihs_off[2] * (uy * C.force[2] + uz * C.force[1]);
     }
   } else {
-    const T phi = C.rho0 + drho + C.half_source;                       // eq. 2-4-1
+    const T phi = FORCE ? C.rho0 + drho + C.half_source : C.rho0 + drho;   // eq. 2-4-1
     const T Dphi = C.D0 * (T(1) + C.D2 * phi * phi);
     s1 = recip(T(0.5) + Dphi * C.inv_cs2_dt);                          // eq. 4-10
     eA = drho;
