@@ -466,3 +466,28 @@ def test_byte_offsets_beyond_4_gib(rmrt, lat, n, storage):
     err = np.abs(got - expect).max() / np.abs(expect).max()
     say(f"   sampled max rel err {err:.2e}")
     assert err < (2e-6 if storage == "f32dev" else 1e-13)
+
+
+def test_full_size_taylor_green_decay_rate(rmrt):
+    """The benchmark's rD3Q19 256 x 256 x 128 FP32-dev AA configuration run for
+    2000 steps at U0 = 1e-3 (Re ~ 50, so the vortex stays in its linear decay):
+    the kinetic energy decays at 2 nu (kx^2 + ky^2 + kz^2) within 1%, a
+    property of the recovered Navier-Stokes equations at any size."""
+    say("[full size TG decay] Q19 256x256x128 f32dev")
+    n, dx, nu, U0 = (256, 256, 128), (1.0, 1.0, 2.0), 0.005, 1e-3
+    prm = dict(lattice="Q19", n=n, dx=dx, nu=nu, cs2=1.0 / 3.0)
+    rho, u, (kx, ky, kz) = taylor_green_3d(n, dx, U0, 1.0 / 3.0)
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage="f32dev", pattern="AA"), rho, u)
+    del rho, u
+    ts, es = [], []
+    for t in range(0, 2001, 250):
+        if t:
+            dom.step(250)
+        _, uu = dom.moments()
+        ts.append(t)
+        es.append(float((uu * uu).sum()))
+    dom.close()
+    rate = -np.polyfit(ts, np.log(es), 1)[0]
+    expect = 2.0 * nu * (kx * kx + ky * ky + kz * kz)
+    say(f"   energy decay rate {rate:.6e}, expected {expect:.6e}, ratio {rate / expect:.5f}")
+    assert abs(rate / expect - 1.0) < 0.01
