@@ -265,20 +265,29 @@ int rmrt_steps_taken(const rmrt_ctx* ctx, long long* steps);
  * per compute unit through dynamic LDS (0 = no cap).  flags & RMRT_LAUNCH_
  * PERSISTENT: a persistent grid of blocks_per_cu workgroups per CU walks the
  * tiles, contiguously per XCD when flags & RMRT_LAUNCH_XCD_ORDER.
- * Default (measured on MI355X): one workgroup per tile; a cap of 3 for rD3Q19
- * and rD3Q27 with FP32/FP64 storage; XCD order for rD2Q9.  Invalidates the
- * context's cached graphs.
+ * Default (measured on MI355X): one workgroup per tile with buffer addressing
+ * (RMRT_LAUNCH_BUFFER_OFFSETS); a cap of 3 for rD3Q19 and rD3Q27 with
+ * FP32/FP64 storage and for rD3Q7 FP64; XCD order for rD2Q9, rD2Q5 and rD3Q7
+ * FP32.  Invalidates the context's cached graphs.
  */
 #define RMRT_LAUNCH_XCD_ORDER 1
 #define RMRT_LAUNCH_PERSISTENT 2
 #define RMRT_LAUNCH_WIDE_TILES 4   /* 512-node tiles, two nodes per thread read before either collides */
+/* Buffer addressing of the population streams: the stream start is a scalar
+ * 32-bit byte offset and the node a per-lane one, which saves the per-access
+ * 64-bit address arithmetic.  Honoured for periodic domains (no walls, no
+ * solid mask) whose population buffer is below 4 GiB; a no-op otherwise.
+ * Results are bitwise those of the 64-bit form.  Part of every default
+ * launch. */
+#define RMRT_LAUNCH_BUFFER_OFFSETS 8
 int rmrt_set_launch(rmrt_ctx* ctx, int blocks_per_cu, int flags);
 int rmrt_get_launch(const rmrt_ctx* ctx, int* blocks_per_cu, int* flags);
 
 /*
  * Time rmrt_step over `steps` steps for one workgroup per tile with the
  * residency cap blocks_per_cu in {0 (none), 2, 3, 4, 5, 6, 8}, with 256- and
- * 512-node tiles (HIP events on stream), keep the fastest and return its cap
+ * 512-node tiles, with and without RMRT_LAUNCH_BUFFER_OFFSETS where it
+ * applies (HIP events on stream), keep the fastest and return its cap
  * in *blocks_per_cu (may be NULL; rmrt_get_launch gives the flags).  The
  * timing runs advance the state.
  */

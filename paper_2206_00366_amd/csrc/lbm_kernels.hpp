@@ -49,6 +49,56 @@ __device__ __forceinline__ T ld_elem(const gmem<T>* base, uint32_t i) { return b
 template <typename T>
 __device__ __forceinline__ void st_elem(gmem<T>* base, uint32_t i, T v) { base[i] = v; }
 
+// Buffer addressing of the population streams, for buffers below 4 GiB: a
+// resource over the whole buffer, the stream start as the scalar byte offset
+// and the node as the per-lane byte offset.  The scalar offsets are one
+// 32-bit register per stream and the per-lane offset is shared by the q
+// streams of a node, where the 64-bit form spends a pair of registers and an
+// add per access.  num_records covers the buffer, so the per-lane offset is
+// range checked by the hardware.
+using BufRsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRawBufferWord3 = 0x00020000;   // gfx9 raw buffer: 32-bit data format
+template <typename S>
+__device__ __forceinline__ BufRsrc buf_rsrc(const gmem<S>* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(const S*)p, 0, (int)bytes, kRawBufferWord3);
+}
+// the resource a step kernel passes to its nodes: a buffer resource over the
+// q streams with buffer addressing, an unused placeholder without (which
+// leaves the 64-bit form's code exactly as it is without this option)
+template <bool BUF>
+struct StreamRes {
+  using type = int;
+  template <int Q, typename S>
+  __device__ static __forceinline__ type make(const gmem<S>*, uint32_t) { return 0; }
+};
+template <>
+struct StreamRes<true> {
+  using type = BufRsrc;
+  template <int Q, typename S>
+  __device__ static __forceinline__ type make(const gmem<S>* p, uint32_t ld) {
+    return buf_rsrc(p, (uint32_t)Q * ld * (uint32_t)sizeof(S));
+  }
+};
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <typename S>
+__device__ __forceinline__ S buf_ld(BufRsrc r, uint32_t lane_off, uint32_t stream_off) {
+  if constexpr (sizeof(S) == 2)
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, lane_off, stream_off, 0));
+  else if constexpr (sizeof(S) == 4)
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, stream_off, 0));
+  else
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, stream_off, 0));
+}
+template <typename S>
+__device__ __forceinline__ void buf_st(BufRsrc r, uint32_t lane_off, uint32_t stream_off, S v) {
+  if constexpr (sizeof(S) == 2)
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, lane_off, stream_off, 0);
+  else if constexpr (sizeof(S) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, lane_off, stream_off, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, lane_off, stream_off, 0);
+}
+
 // exact n / d for n < 2^32 with m = floor(2^32 / d) (0xffffffff for d = 1)
 __device__ __forceinline__ uint32_t fast_div(uint32_t n, uint32_t d, uint32_t m, uint32_t& r) {
   uint32_t q = __umulhi(n, m);
@@ -155,8 +205,11 @@ __device__ __forceinline__ size_t read_elem(const DomainDev& Dm, const Geo<D>& g
 // node ranges of a domain); a null tile list means one domain split into
 // tiles of `tile_nodes` nodes with one tile per workgroup.
 // ----------------------------------------------------------------------------
-template <int L, int ST, int EQ, bool FORCE, int BC, int PH>
+// BUF: buffer addressing (periodic domains only, buffers below 4 GiB).
+template <int L, int ST, int EQ, bool FORCE, int BC, int PH, bool BUF>
 struct NodeStep {
+  static_assert(!BUF || BC == 0, "buffer addressing covers the periodic step only");
+  using R = typename StreamRes<BUF>::type;
   using SS = Store<ST>;
   using S = typename SS::S;
   using T = typename SS::T;
@@ -176,8 +229,8 @@ struct NodeStep {
   // wave's q loads and stores stay back to back.
 
   // Read the q populations of node idx_ (nothing for solid or invalid nodes).
-  __device__ __forceinline__ void load(const DomainDev& Dm, const Coef<T>& C, const gmem<S>* fin, uint32_t idx_,
-                                       bool valid) {
+  __device__ __forceinline__ void load(const DomainDev& Dm, const Coef<T>& C, const gmem<S>* fin, R rin,
+                                       uint32_t idx_, bool valid) {
     idx = idx_;
     live = valid;
     lb = 0;
@@ -198,7 +251,14 @@ struct NodeStep {
     static_for<0, Q>([&](auto j_) {
       constexpr int J = decltype(j_)::value;
       S v;
-      if constexpr (PH == PH_AA_ODD) {
+      if constexpr (BUF) {
+        constexpr int O = Lat<L>::opp(J);
+        constexpr uint32_t es = sizeof(S);
+        if constexpr (PH == PH_AA_ODD)
+          v = buf_ld<S>(rin, (uint32_t)(idx + (uint32_t)g.template off<L, O>()) * es, (uint32_t)O * LD * es);
+        else
+          v = buf_ld<S>(rin, idx * es, (uint32_t)J * LD * es);
+      } else if constexpr (PH == PH_AA_ODD) {
         // swapped layout: the value for direction J sits in slot O of the
         // upstream node, or in this node's own slot J when that link bounced
         constexpr int O = Lat<L>::opp(J);
@@ -222,7 +282,7 @@ struct NodeStep {
   }
 
   // Collide and write the q post-collision populations.
-  __device__ __forceinline__ void finish(const DomainDev& Dm, const Coef<T>& C, gmem<S>* fout) {
+  __device__ __forceinline__ void finish(const DomainDev& Dm, const Coef<T>& C, gmem<S>* fout, R rout) {
     if (!live) return;
     if constexpr (Lat<L>::linear) {
       T phi;
@@ -236,7 +296,12 @@ struct NodeStep {
       constexpr int J = decltype(j_)::value;
       constexpr int O = Lat<L>::opp(J);
       const S v = SS::template enc<Lat<L>::wclass(J)>(t[Lat<L>::slot(J)], C);
-      if constexpr (PH == PH_AA_EVEN) {
+      constexpr uint32_t es = sizeof(S);
+      if constexpr (BUF && PH == PH_AA_EVEN) {
+        buf_st<S>(rout, idx * es, (uint32_t)O * LD * es, v);
+      } else if constexpr (BUF) {
+        buf_st<S>(rout, (uint32_t)(idx + (uint32_t)g.template off<L, J>()) * es, (uint32_t)J * LD * es, v);
+      } else if constexpr (PH == PH_AA_EVEN) {
         st_elem(fout + (size_t)O * LD, idx, v);
       } else if constexpr (BC == 0) {
         st_elem(fout + (size_t)J * LD, (uint32_t)(idx + (uint32_t)g.template off<L, J>()), v);
@@ -268,12 +333,13 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
 // so that the tiles resident at one time on an XCD are neighbours; the grid
 // size is the occupancy knob (fewer resident waves keep the q concurrent
 // address streams per wave from oversubscribing HBM).
-enum : uint32_t { STEP_XCD_ORDER = 1u, STEP_PERSISTENT = 2u, STEP_WIDE_TILES = 4u };
+enum : uint32_t { STEP_XCD_ORDER = 1u, STEP_PERSISTENT = 2u, STEP_WIDE_TILES = 4u, STEP_BUFFER_OFFSETS = 8u };
 
 // NPT nodes per thread per pass (1, or 2 with tiles of 2 blockDim nodes: both
 // nodes are read before either collides, so each wave keeps 2 q loads in
-// flight).
-template <int L, int ST, int EQ, bool FORCE, int BC, int PH, int NPT>
+// flight).  BUF selects buffer addressing of the population streams (the host
+// sets it only for periodic domains whose buffers are below 4 GiB).
+template <int L, int ST, int EQ, bool FORCE, int BC, int PH, int NPT, bool BUF>
 __global__ void __launch_bounds__(256)
     k_step(const DomainDev* __restrict__ doms, const Tile* __restrict__ tiles, uint32_t ntiles,
            uint32_t tile_nodes, uint32_t parity, uint32_t flags) {
@@ -322,21 +388,23 @@ __global__ void __launch_bounds__(256)
       fin = fa;
       fout = fa;
     }
-    using NSp = NodeStep<L, ST, EQ, FORCE, BC, PH>;
+    using NSp = NodeStep<L, ST, EQ, FORCE, BC, PH, BUF>;
+    const auto rin = StreamRes<BUF>::template make<Lat<L>::Q>(fin, BUF ? Dm.ld : 0u);
+    const auto rout = StreamRes<BUF>::template make<Lat<L>::Q>((const gmem<S>*)fout, BUF ? Dm.ld : 0u);
     if constexpr (NPT == 2) {
       for (uint32_t i = threadIdx.x; i < count; i += 2 * blockDim.x) {
         const uint32_t i1 = i + blockDim.x;
         NSp a, b;
-        a.load(Dm, C, fin, start + i, true);
-        b.load(Dm, C, fin, start + (i1 < count ? i1 : i), i1 < count);
-        a.finish(Dm, C, fout);
-        b.finish(Dm, C, fout);
+        a.load(Dm, C, fin, rin, start + i, true);
+        b.load(Dm, C, fin, rin, start + (i1 < count ? i1 : i), i1 < count);
+        a.finish(Dm, C, fout, rout);
+        b.finish(Dm, C, fout, rout);
       }
     } else {
       for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) {
         NSp a;
-        a.load(Dm, C, fin, start + i, true);
-        a.finish(Dm, C, fout);
+        a.load(Dm, C, fin, rin, start + i, true);
+        a.finish(Dm, C, fout, rout);
       }
     }
   }

@@ -5,14 +5,26 @@
 
 namespace rmrt {
 
-template <int L, int ST, int EQ, bool F, int BC, int PH>
-hipError_t do_step(const StepLaunch& a) {
+template <int L, int ST, int EQ, bool F, int BC, int PH, bool BUF>
+void do_step_npt(const StepLaunch& a) {
   if (a.flags & STEP_WIDE_TILES)
-    hipLaunchKernelGGL((k_step<L, ST, EQ, F, BC, PH, 2>), dim3(a.grid), dim3(a.block), a.lds_bytes, a.stream,
+    hipLaunchKernelGGL((k_step<L, ST, EQ, F, BC, PH, 2, BUF>), dim3(a.grid), dim3(a.block), a.lds_bytes, a.stream,
                        a.doms, a.tiles, a.ntiles, a.tile_nodes, a.parity, a.flags);
   else
-    hipLaunchKernelGGL((k_step<L, ST, EQ, F, BC, PH, 1>), dim3(a.grid), dim3(a.block), a.lds_bytes, a.stream,
+    hipLaunchKernelGGL((k_step<L, ST, EQ, F, BC, PH, 1, BUF>), dim3(a.grid), dim3(a.block), a.lds_bytes, a.stream,
                        a.doms, a.tiles, a.ntiles, a.tile_nodes, a.parity, a.flags);
+}
+// STEP_BUFFER_OFFSETS reaches here only for periodic domains (the host clears
+// it for walls, solids and buffers of 4 GiB or more).
+template <int L, int ST, int EQ, bool F, int BC, int PH>
+hipError_t do_step(const StepLaunch& a) {
+  if constexpr (BC == 0) {
+    if (a.flags & STEP_BUFFER_OFFSETS) {
+      do_step_npt<L, ST, EQ, F, BC, PH, true>(a);
+      return hipGetLastError();
+    }
+  }
+  do_step_npt<L, ST, EQ, F, BC, PH, false>(a);
   return hipGetLastError();
 }
 template <int L, int ST, int EQ, bool F, int BC>

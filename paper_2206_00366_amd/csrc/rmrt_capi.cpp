@@ -457,31 +457,27 @@ constexpr unsigned kAuxBlock = 256;
 // tile loop serialises loads behind the previous tile's stores).  For the 3D
 // lattices with 4- and 8-byte storage a cap of 3 resident workgroups per CU
 // (12 waves) raises the step from 5.2 to 5.5-5.65 TB/s: fewer waves issuing q
-// concurrent address streams keep HBM rows open longer.  FP16 storage and
-// rD2Q9 prefer no cap, rD2Q9 the XCD-contiguous tile order.
+// concurrent address streams keep HBM rows open longer.  FP16 storage and the
+// 2D lattices prefer no cap, rD2Q9 and rD2Q5 the XCD-contiguous tile order.
 constexpr int kDefaultBlocksPerCU = 0;
 constexpr uint32_t kDefaultFlags = 0u;
 void default_launch(const rmrt_params& p, int& blocks_per_cu, uint32_t& flags) {
   blocks_per_cu = 0;
-  flags = 0u;
-  // measured on MI355X at 256 x 256 x 128: FP32/FP64 rD3Q19/rD3Q27 gain from a
-  // cap of 3 workgroups per CU; FP16 rD3Q19 from two nodes per thread (its
-  // 128-byte wave loads leave too few bytes in flight with one).  The reduced
-  // lattices have only 5 or 7 loads per node and want every wave they can get
-  // (rD3Q7 FP32: 6.9 TB/s uncapped, 5.9 with the cap).
-  if (p.lattice == RMRT_Q9) {
-    flags = STEP_XCD_ORDER;
-  } else if (p.lattice == RMRT_Q5) {
-    flags = p.storage == RMRT_F16DEV ? STEP_XCD_ORDER : 0u;
+  // Buffer addressing everywhere it applies (graph replay at 256 x 256 x 128
+  // or 2048 x 1024: rD3Q19 FP32 5.58 -> 5.73 TB/s, FP16 5.03 -> 5.31, rD3Q27
+  // FP32 5.30 -> 5.45, FP16 4.49 -> 4.85, the others equal or better).  The
+  // reduced lattices have only 5 or 7 loads per node and want every wave they
+  // can get (rD3Q7 FP32: 7.0 TB/s uncapped, 6.1 with a cap of 3).
+  flags = STEP_BUFFER_OFFSETS;
+  if (p.lattice == RMRT_Q9 || p.lattice == RMRT_Q5) {
+    flags |= STEP_XCD_ORDER;
   } else if (p.lattice == RMRT_Q7) {
     if (p.storage == RMRT_F64)
       blocks_per_cu = 3;
-    else
-      flags = STEP_XCD_ORDER;
+    else if (p.storage == RMRT_F32DEV)
+      flags |= STEP_XCD_ORDER;
   } else if (p.storage != RMRT_F16DEV) {
     blocks_per_cu = 3;
-  } else if (p.lattice == RMRT_Q19) {
-    flags = STEP_WIDE_TILES;
   }
 }
 constexpr uint32_t kLdsPerCU = 160u * 1024u;  // gfx950 LDS per compute unit
@@ -617,6 +613,13 @@ int launch_init_fields(rmrt_ctx* c, const double* rho, const double* u, int with
   return RMRT_OK;
 }
 
+// Buffer addressing takes 32-bit byte offsets: it serves periodic domains
+// whose population buffer is below 4 GiB.  Elsewhere the flag is a no-op.
+bool buffer_offsets_apply(const rmrt_ctx* c) {
+  const uint64_t bytes = (uint64_t)lattice_q(c->p.lattice) * c->hdom.ld * elem_size(c->p.storage);
+  return c->step_bc == 0 && bytes < 0xffffffffull;
+}
+
 int launch_one_step(rmrt_ctx* c, long long step_index, hipStream_t s) {
   StepLaunch a;
   std::memset(&a, 0, sizeof(a));
@@ -625,6 +628,7 @@ int launch_one_step(rmrt_ctx* c, long long step_index, hipStream_t s) {
   a.tile_nodes = (c->flags & STEP_WIDE_TILES) ? 512 : 256;
   a.ntiles = (c->hdom.N + a.tile_nodes - 1) / a.tile_nodes;
   a.flags = c->flags;
+  if (!buffer_offsets_apply(c)) a.flags &= ~STEP_BUFFER_OFFSETS;
   a.parity = (uint32_t)(step_index & 1);
   a.eq = c->p.equation;
   a.force = has_force(&c->p);
@@ -960,7 +964,7 @@ int rmrt_steps_taken(const rmrt_ctx* c, long long* steps) {
 int rmrt_set_launch(rmrt_ctx* c, int blocks_per_cu, int flags) {
   if (!c) return fail(RMRT_EINVAL, "ctx is NULL");
   if (blocks_per_cu < 0 || blocks_per_cu > 32) return fail(RMRT_EINVAL, "blocks_per_cu must be in [0, 32]");
-  if (flags & ~7) return fail(RMRT_EINVAL, "unknown launch flags 0x%x", flags);
+  if (flags & ~15) return fail(RMRT_EINVAL, "unknown launch flags 0x%x", flags);
   if (blocks_per_cu == 1 && !(flags & STEP_PERSISTENT))
     return fail(RMRT_EINVAL, "a residency cap of 1 workgroup per CU is not supported (use >= 2)");
   c->blocks_per_cu = blocks_per_cu;
@@ -988,9 +992,11 @@ int rmrt_tune(rmrt_ctx* c, int steps, void* stream, int* blocks_per_cu) {
   HIP_TRY(hipEventCreate(&e1));
   int best = kDefaultBlocksPerCU, best_flags = 0;
   float best_ms = 1e30f;
+  const int nbuf = buffer_offsets_apply(c) ? 2 : 1;
+  for (int buf = 0; buf < nbuf; ++buf)
   for (int wide = 0; wide < 2; ++wide)
   for (int k : cands) {
-    const int fl = wide ? (int)STEP_WIDE_TILES : 0;
+    const int fl = (wide ? (int)STEP_WIDE_TILES : 0) | (buf ? (int)STEP_BUFFER_OFFSETS : 0);
     int rc = rmrt_set_launch(c, k, fl);
     if (rc == RMRT_OK) rc = step_impl(c, 2, s);
     if (rc == RMRT_OK) rc = step_impl(c, steps, s);

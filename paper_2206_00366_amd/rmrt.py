@@ -31,7 +31,7 @@ NSE, NCDE = 0, 1
 F64, F32DEV, F16DEV = 0, 1, 2
 AB, AA = 0, 1
 OUT_F64, OUT_F32 = 0, 1
-LAUNCH_XCD_ORDER, LAUNCH_PERSISTENT, LAUNCH_WIDE_TILES = 1, 2, 4
+LAUNCH_XCD_ORDER, LAUNCH_PERSISTENT, LAUNCH_WIDE_TILES, LAUNCH_BUFFER_OFFSETS = 1, 2, 4, 8
 GRAD_STRAIN, GRAD_STRESS, GRAD_PHI = 0, 1, 2
 WALL_XM, WALL_XP, WALL_YM, WALL_YP, WALL_ZM, WALL_ZP = 1, 2, 4, 8, 16, 32
 

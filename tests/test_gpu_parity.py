@@ -147,6 +147,31 @@ def test_two_nodes_per_thread_is_bitwise_identical(rmrt, case, pattern):
         assert np.array_equal(g[:, m.fluid], out[0][:, m.fluid])
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32dev", "f16dev"])
+@pytest.mark.parametrize("pattern", ["AB", "AA"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_buffer_offsets_are_bitwise_identical(rmrt, case, pattern, storage):
+    """Buffer addressing of the streams (scalar stream offset, per-lane node
+    offset) writes exactly what the 64-bit form writes, with one and with two
+    nodes per thread, over an odd number of steps so that both AA phases run.
+    With walls or a solid mask the option is a no-op, which this checks as well.
+    (One and two nodes per thread are compared with each other for FP32 only:
+    in FP16 and FP64 the compiler may contract a product into a different add
+    when it schedules two nodes together, a last-bit difference.)"""
+    say(f"[buffer offsets] {case} {pattern} {storage}")
+    B, W = rmrt.LAUNCH_BUFFER_OFFSETS, rmrt.LAUNCH_WIDE_TILES
+    out = {}
+    for fl in (0, B, W, B | W):
+        m, dom, rho, u, steps = _build(case, rmrt, storage, pattern)
+        dom.set_launch(0, fl)
+        assert dom.get_launch() == (0, fl)
+        dom.step(steps | 1)
+        out[fl] = dom.populations().cpu().numpy()[:, m.fluid]
+        dom.close()
+    for ref, buf in ((0, B), (W, B | W)):
+        assert np.array_equal(out[buf], out[ref]), (buf, ref)
+
+
 @pytest.mark.parametrize("storage,tol", [("f32dev", 1e-5), ("f16dev", 3e-3)])
 @pytest.mark.parametrize("case", ["q9_periodic", "q9_channel_solid_force", "q9_ncde_nonlinear", "q19_periodic",
                                   "q19_channel_force", "q27_periodic", "q27_channel_solid_force", "q19_ncde"])
@@ -247,11 +272,14 @@ def test_ncde_gaussian_hill_256x128_f32dev(rmrt):
     dom.close()
 
 
-def _sampled_one_step(rmrt, prm, rho, u, storage, pattern, samples, seed):
+def _sampled_one_step(rmrt, prm, rho, u, storage, pattern, samples, seed, flags=None):
     """Full-size launch, one step; oracle collision evaluated only at the
-    upstream nodes of `samples` sampled outputs (periodic, no walls)."""
+    upstream nodes of `samples` sampled outputs (periodic, no walls).  flags:
+    launch flags (None = the default launch)."""
     g = rmrt.make_params(**prm, storage=storage, pattern=pattern)
     dom = rmrt.Domain(g, rho, u)
+    if flags is not None:
+        dom.set_launch(0, flags)
     dom.step(1)
     f_g = dom.populations()
     nx, ny, nz = prm["n"]
@@ -378,8 +406,9 @@ def test_launch_shapes_agree_and_match_oracle(rmrt):
     f_or = m.step(m.init(rho, u), 9)
     ref = None
     P, X, Wd = rmrt.LAUNCH_PERSISTENT, rmrt.LAUNCH_XCD_ORDER, rmrt.LAUNCH_WIDE_TILES
+    B = rmrt.LAUNCH_BUFFER_OFFSETS
     for bpc, fl in [(0, 0), (0, X), (3, 0), (8, 0), (1, P | X), (2, P | X), (3, P), (8, P | X), (0, Wd),
-                    (3, Wd | X), (2, Wd | P | X)]:
+                    (3, Wd | X), (2, Wd | P | X), (3, B), (0, B | X), (1, B | P | X), (2, B | Wd | P | X)]:
         dom = rmrt.Domain(rmrt.make_params(**prm, storage="f64", pattern="AA"), rho, u)
         dom.set_launch(bpc, fl)
         assert dom.get_launch() == (bpc, fl)
@@ -403,7 +432,8 @@ def test_tune_picks_a_valid_shape(rmrt):
     k = dom.tune(steps=4)
     assert k in (0, 2, 3, 4, 5, 6, 8)
     bpc, fl = dom.get_launch()
-    assert bpc == k and fl in (0, rmrt.LAUNCH_WIDE_TILES)
+    W, B = rmrt.LAUNCH_WIDE_TILES, rmrt.LAUNCH_BUFFER_OFFSETS
+    assert bpc == k and fl in (0, W, B, W | B)
     r = dom.reduce()
     assert abs(r[0] - N) < 1e-6 * N
     dom.close()
@@ -445,13 +475,15 @@ def test_degenerate_single_node_extents(rmrt, lat, n):
     dom.close()
 
 
-@pytest.mark.parametrize("lat,n,storage", [("Q9", (12000, 12000, 1), "f32dev"), ("Q27", (300, 300, 300), "f64")])
-def test_byte_offsets_beyond_4_gib(rmrt, lat, n, storage):
+@pytest.mark.parametrize("lat,n,storage,buffer_offsets", [("Q9", (12000, 12000, 1), "f32dev", False),
+                                                          ("Q27", (300, 300, 300), "f64", False),
+                                                          ("Q9", (12000, 12000, 1), "f32dev", True)])
+def test_byte_offsets_beyond_4_gib(rmrt, lat, n, storage, buffer_offsets):
     """Population buffers larger than 4 GiB (5.2 GB and 5.8 GB): the highest
     streams start beyond 2^32 bytes, so every stream offset must be formed in
-    64 bits.  One step, 4096 sampled nodes (and the last node) against the
-    oracle."""
-    say(f"[large buffers] {lat} {n} {storage}")
+    64 bits (buffer addressing, requested or not, must fall back to that form).
+    One step, 4096 sampled nodes (and the last node) against the oracle."""
+    say(f"[large buffers] {lat} {n} {storage} buffer offsets requested: {buffer_offsets}")
     N = n[0] * n[1] * n[2]
     d = 2 if lat == "Q9" else 3
     q = 9 if lat == "Q9" else 27
@@ -461,7 +493,8 @@ def test_byte_offsets_beyond_4_gib(rmrt, lat, n, storage):
     rng = np.random.default_rng(13)
     rho = 1.0 + 1e-3 * rng.uniform(-1, 1, N)
     u = 0.02 * rng.uniform(-1, 1, (d, N))
-    got, expect = _sampled_one_step(rmrt, prm, rho, u, storage, "AA", 4096, 13)
+    got, expect = _sampled_one_step(rmrt, prm, rho, u, storage, "AA", 4096, 13,
+                                    flags=rmrt.LAUNCH_BUFFER_OFFSETS if buffer_offsets else None)
     del rho, u
     err = np.abs(got - expect).max() / np.abs(expect).max()
     say(f"   sampled max rel err {err:.2e}")

@@ -110,9 +110,13 @@ def test_reduced_precision_storage(rmrt, case, storage, tol):
 
 @pytest.mark.parametrize("case", ["q5_channel_solid_source", "q7_periodic"])
 def test_aa_ab_and_two_nodes_per_thread_bitwise(rmrt, case):
+    """AA and AB, one or two nodes per thread, 64-bit or buffer addressing: all
+    write the same bits."""
     say(f"[reduced AA==AB, paired] {case}")
     out = []
-    for pattern, fl in (("AB", 0), ("AA", 0), ("AA", rmrt.LAUNCH_WIDE_TILES)):
+    B = rmrt.LAUNCH_BUFFER_OFFSETS
+    for pattern, fl in (("AB", 0), ("AA", 0), ("AA", rmrt.LAUNCH_WIDE_TILES), ("AB", B), ("AA", B),
+                        ("AA", B | rmrt.LAUNCH_WIDE_TILES)):
         m, dom, phi, steps = _build(case, rmrt, "f32dev", pattern)
         dom.set_launch(0, fl)
         dom.step(steps)
