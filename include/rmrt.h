@@ -275,10 +275,10 @@ int rmrt_steps_taken(const rmrt_ctx* ctx, long long* steps);
 #define RMRT_LAUNCH_WIDE_TILES 4   /* 512-node tiles, two nodes per thread read before either collides */
 /* Buffer addressing of the population streams: the stream start is a scalar
  * 32-bit byte offset and the node a per-lane one, which saves the per-access
- * 64-bit address arithmetic.  Honoured for periodic domains (no walls, no
- * solid mask) whose population buffer is below 4 GiB; a no-op otherwise.
- * Results are bitwise those of the 64-bit form.  Part of every default
- * launch. */
+ * 64-bit address arithmetic (waves with a bounced link select full 32-bit
+ * per-lane offsets instead).  Honoured for population buffers below 4 GiB; a
+ * no-op otherwise.  Results are bitwise those of the 64-bit form.  Part of
+ * every default launch; batches use it whenever every domain qualifies. */
 #define RMRT_LAUNCH_BUFFER_OFFSETS 8
 int rmrt_set_launch(rmrt_ctx* ctx, int blocks_per_cu, int flags);
 int rmrt_get_launch(const rmrt_ctx* ctx, int* blocks_per_cu, int* flags);

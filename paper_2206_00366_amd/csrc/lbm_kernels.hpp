@@ -205,10 +205,9 @@ __device__ __forceinline__ size_t read_elem(const DomainDev& Dm, const Geo<D>& g
 // node ranges of a domain); a null tile list means one domain split into
 // tiles of `tile_nodes` nodes with one tile per workgroup.
 // ----------------------------------------------------------------------------
-// BUF: buffer addressing (periodic domains only, buffers below 4 GiB).
+// BUF: buffer addressing (buffers below 4 GiB).
 template <int L, int ST, int EQ, bool FORCE, int BC, int PH, bool BUF>
 struct NodeStep {
-  static_assert(!BUF || BC == 0, "buffer addressing covers the periodic step only");
   using R = typename StreamRes<BUF>::type;
   using SS = Store<ST>;
   using S = typename SS::S;
@@ -221,12 +220,24 @@ struct NodeStep {
   LW lb;
   uint32_t idx;
   bool live;   // a fluid node to update
+  bool edge;   // buffer addressing with walls: some lane of the wave has a bounced link
   T phi_prev;  // rD2Q5 / rD3Q7: phi of the previous step
 
   // Boundary modes: 0 periodic; 1 wall faces from the coordinates (the host
   // never pairs it with a solid mask: a mask selects mode 2); 2 link words.
   // Bounced links pick their address with a select, not a branch, so the
-  // wave's q loads and stores stay back to back.
+  // wave's q loads and stores stay back to back.  With buffer addressing a
+  // wave none of whose nodes has a bounced link takes the periodic addresses
+  // (scalar stream offset); the other waves select full 32-bit offsets.
+
+  // does link J of this node bounce?
+  template <int J>
+  __device__ __forceinline__ bool bounced(const DomainDev& Dm) const {
+    if constexpr (BC == 2)
+      return (lb >> J) & 1;
+    else
+      return g.template bounce<L, J, false>(Dm, idx);
+  }
 
   // Read the q populations of node idx_ (nothing for solid or invalid nodes).
   __device__ __forceinline__ void load(const DomainDev& Dm, const Coef<T>& C, const gmem<S>* fin, R rin,
@@ -243,11 +254,27 @@ struct NodeStep {
     if (!live) return;
     if constexpr (Lat<L>::linear) phi_prev = to_global((const T*)Dm.hist)[idx];
     if constexpr (PH != PH_AA_EVEN) g.make(Dm, idx);
+    edge = false;
+    if constexpr (BUF && BC != 0 && PH != PH_AA_EVEN) {
+      bool e;
+      if constexpr (BC == 2)
+        e = (lb & (LW)~LinkBits<L>::kSolid) != 0;
+      else
+        e = g.lo[0] | g.hi[0] | g.lo[1] | g.hi[1] | g.lo[2] | g.hi[2];
+      edge = __builtin_amdgcn_ballot_w64(e) != 0;   // wave-uniform
+    }
     const uint32_t LD = Dm.ld;   // stream stride
     static_for<0, NS>([&](auto s_) {
       constexpr int s = decltype(s_)::value;
       if constexpr (Lat<L>::absent(s)) t[s] = T(0);
     });
+    if constexpr (BUF && BC != 0 && PH == PH_AA_ODD) {
+      if (edge)
+        load_buf<true>(C, Dm, rin, LD);
+      else
+        load_buf<false>(C, Dm, rin, LD);
+      return;
+    }
     static_for<0, Q>([&](auto j_) {
       constexpr int J = decltype(j_)::value;
       S v;
@@ -281,6 +308,44 @@ struct NodeStep {
     });
   }
 
+  // Odd AA phase with walls and buffer addressing: EDGE selects, per link,
+  // this node's own slot J (bounced) or slot O of the upstream node.
+  template <bool EDGE>
+  __device__ __forceinline__ void load_buf(const Coef<T>& C, const DomainDev& Dm, R rin, uint32_t LD) {
+    static_for<0, Q>([&](auto j_) {
+      constexpr int J = decltype(j_)::value;
+      constexpr int O = Lat<L>::opp(J);
+      constexpr uint32_t es = sizeof(S);
+      const uint32_t up = (uint32_t)(idx + (uint32_t)g.template off<L, O>());
+      S v;
+      if constexpr (EDGE) {
+        const uint32_t full = bounced<O>(Dm) ? (uint32_t)J * LD + idx : (uint32_t)O * LD + up;
+        v = buf_ld<S>(rin, full * es, 0u);
+      } else {
+        v = buf_ld<S>(rin, up * es, (uint32_t)O * LD * es);
+      }
+      t[Lat<L>::slot(J)] = SS::template dec<Lat<L>::wclass(J)>(v, C);
+    });
+  }
+
+  // Pushing stores with walls and buffer addressing (odd AA phase, AB).
+  template <bool EDGE>
+  __device__ __forceinline__ void store_buf(const Coef<T>& C, const DomainDev& Dm, R rout, uint32_t LD) {
+    static_for<0, Q>([&](auto j_) {
+      constexpr int J = decltype(j_)::value;
+      constexpr int O = Lat<L>::opp(J);
+      constexpr uint32_t es = sizeof(S);
+      const S v = SS::template enc<Lat<L>::wclass(J)>(t[Lat<L>::slot(J)], C);
+      const uint32_t down = (uint32_t)(idx + (uint32_t)g.template off<L, J>());
+      if constexpr (EDGE) {
+        const uint32_t full = bounced<J>(Dm) ? (uint32_t)O * LD + idx : (uint32_t)J * LD + down;
+        buf_st<S>(rout, full * es, 0u, v);
+      } else {
+        buf_st<S>(rout, down * es, (uint32_t)J * LD * es, v);
+      }
+    });
+  }
+
   // Collide and write the q post-collision populations.
   __device__ __forceinline__ void finish(const DomainDev& Dm, const Coef<T>& C, gmem<S>* fout, R rout) {
     if (!live) return;
@@ -292,6 +357,13 @@ struct NodeStep {
       collide<L, EQ, FORCE>(t, C);
     }
     const uint32_t LD = Dm.ld;   // stream stride
+    if constexpr (BUF && BC != 0 && PH != PH_AA_EVEN) {
+      if (edge)
+        store_buf<true>(C, Dm, rout, LD);
+      else
+        store_buf<false>(C, Dm, rout, LD);
+      return;
+    }
     static_for<0, Q>([&](auto j_) {
       constexpr int J = decltype(j_)::value;
       constexpr int O = Lat<L>::opp(J);

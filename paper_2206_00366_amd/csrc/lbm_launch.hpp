@@ -14,17 +14,14 @@ void do_step_npt(const StepLaunch& a) {
     hipLaunchKernelGGL((k_step<L, ST, EQ, F, BC, PH, 1, BUF>), dim3(a.grid), dim3(a.block), a.lds_bytes, a.stream,
                        a.doms, a.tiles, a.ntiles, a.tile_nodes, a.parity, a.flags);
 }
-// STEP_BUFFER_OFFSETS reaches here only for periodic domains (the host clears
-// it for walls, solids and buffers of 4 GiB or more).
+// STEP_BUFFER_OFFSETS reaches here only for buffers below 4 GiB (the host
+// clears it otherwise).
 template <int L, int ST, int EQ, bool F, int BC, int PH>
 hipError_t do_step(const StepLaunch& a) {
-  if constexpr (BC == 0) {
-    if (a.flags & STEP_BUFFER_OFFSETS) {
-      do_step_npt<L, ST, EQ, F, BC, PH, true>(a);
-      return hipGetLastError();
-    }
-  }
-  do_step_npt<L, ST, EQ, F, BC, PH, false>(a);
+  if (a.flags & STEP_BUFFER_OFFSETS)
+    do_step_npt<L, ST, EQ, F, BC, PH, true>(a);
+  else
+    do_step_npt<L, ST, EQ, F, BC, PH, false>(a);
   return hipGetLastError();
 }
 template <int L, int ST, int EQ, bool F, int BC>

@@ -613,11 +613,11 @@ int launch_init_fields(rmrt_ctx* c, const double* rho, const double* u, int with
   return RMRT_OK;
 }
 
-// Buffer addressing takes 32-bit byte offsets: it serves periodic domains
-// whose population buffer is below 4 GiB.  Elsewhere the flag is a no-op.
+// Buffer addressing takes 32-bit byte offsets: it serves domains whose
+// population buffer is below 4 GiB.  Elsewhere the flag is a no-op.
 bool buffer_offsets_apply(const rmrt_ctx* c) {
   const uint64_t bytes = (uint64_t)lattice_q(c->p.lattice) * c->hdom.ld * elem_size(c->p.storage);
-  return c->step_bc == 0 && bytes < 0xffffffffull;
+  return bytes < 0xffffffffull;
 }
 
 int launch_one_step(rmrt_ctx* c, long long step_index, hipStream_t s) {
@@ -1120,6 +1120,9 @@ int batch_launch(rmrt_batch* b, long long step_index, hipStream_t s) {
   if (tc.threads > kMaxThreads) return fail(RMRT_EINVAL, "config uses %d threads > %d", tc.threads, kMaxThreads);
   a.flags = (tc.persistent && tc.blocks_per_cu > 0) ? (STEP_PERSISTENT | STEP_XCD_ORDER) : 0u;
   if (tc.nodes_per_thread == 2) a.flags |= STEP_WIDE_TILES;
+  bool buf = true;
+  for (const rmrt_ctx* c : b->ctxs) buf = buf && buffer_offsets_apply(c);
+  if (buf) a.flags |= STEP_BUFFER_OFFSETS;
   a.grid = persistent_grid(b->ntiles, b->cus, tc.blocks_per_cu, a.flags);
   a.lds_bytes = residency_lds(tc.blocks_per_cu, a.flags);
   a.block = (unsigned)tc.threads;

@@ -154,10 +154,17 @@ def test_buffer_offsets_are_bitwise_identical(rmrt, case, pattern, storage):
     """Buffer addressing of the streams (scalar stream offset, per-lane node
     offset) writes exactly what the 64-bit form writes, with one and with two
     nodes per thread, over an odd number of steps so that both AA phases run.
-    With walls or a solid mask the option is a no-op, which this checks as well.
-    (One and two nodes per thread are compared with each other for FP32 only:
-    in FP16 and FP64 the compiler may contract a product into a different add
-    when it schedules two nodes together, a last-bit difference.)"""
+    With walls or a solid mask, waves without a bounced link take the periodic
+    addresses and the others select full 32-bit offsets.
+
+    FP16 storage: the compiler may fuse an FP16 decode product (h_j w_j) into
+    the first add of the moment transform in one code form and round it
+    separately in the other, so the forms can differ by an FP16 rounding of a
+    few stored values; they are held to 2e-4 of max |f| (a half rounding of a
+    deviation is 4.9e-4 of the deviation, itself at most ~0.1 of f).  (One and
+    two nodes per thread are compared with each other for FP32 only, in the
+    test above: in FP16 and FP64 the compiler may contract a product into a
+    different add when it schedules two nodes together.)"""
     say(f"[buffer offsets] {case} {pattern} {storage}")
     B, W = rmrt.LAUNCH_BUFFER_OFFSETS, rmrt.LAUNCH_WIDE_TILES
     out = {}
@@ -169,7 +176,12 @@ def test_buffer_offsets_are_bitwise_identical(rmrt, case, pattern, storage):
         out[fl] = dom.populations().cpu().numpy()[:, m.fluid]
         dom.close()
     for ref, buf in ((0, B), (W, B | W)):
-        assert np.array_equal(out[buf], out[ref]), (buf, ref)
+        if storage == "f16dev":
+            err = rel_err(out[buf], out[ref])
+            say(f"   f16 flags {buf} vs {ref}: max |df| / max |f| = {err:.2e}")
+            assert err < 2e-4, (buf, ref)
+        else:
+            assert np.array_equal(out[buf], out[ref]), (buf, ref)
 
 
 @pytest.mark.parametrize("storage,tol", [("f32dev", 1e-5), ("f16dev", 3e-3)])
