@@ -73,6 +73,19 @@ struct Lat {
   static constexpr bool absent(int s) {
     return (L == LAT_Q19 && off_centre(s) == 3) || (linear && off_centre(s) >= 2);
   }
+  // the same as bit masks over the 3^D tensor slots
+  static constexpr uint32_t absent_mask() {
+    uint32_t m = 0;
+    for (int s = 0; s < NS; ++s)
+      if (absent(s)) m |= 1u << s;
+    return m;
+  }
+  static constexpr uint32_t dropped_mask() {
+    uint32_t m = 0;
+    for (int n = 0; n < NS; ++n)
+      if (dropped(n)) m |= 1u << n;
+    return m;
+  }
 };
 
 // Reciprocal in the working precision instead of the ~10-instruction IEEE
@@ -138,38 +151,118 @@ template <>
 __device__ __forceinline__ const Coef<float>& coef<float>(const DomainDev& D) { return D.cf; }
 
 // ----------------------------------------------------------------------------
-// Per-axis factorised transforms on 3^D tensor slots
+// Per-axis factorised transforms on 3^D tensor slots.  Z is the mask of slots
+// that are zero on entry (absent velocities before the forward transform,
+// dropped monomials before the inverse); zeros are tracked through the axes
+// so that no instruction adds a known zero (x + 0 cannot be folded by the
+// compiler because of the sign of zero).
 // ----------------------------------------------------------------------------
-template <int D, typename T, int NS>
+constexpr int axis_stride(int ax) { return ax == 0 ? 1 : (ax == 1 ? 3 : 9); }
+constexpr bool zbit(uint32_t z, int s) { return (z >> s) & 1u; }
+
+// zero mask after forward-transforming axis ax of a mask z
+constexpr uint32_t fwd_zero_after(uint32_t z, int ax, int NS) {
+  const int st = axis_stride(ax);
+  uint32_t out = z;
+  for (int b = 0; b < NS; ++b) {
+    if ((b / st) % 3 != 0) continue;
+    const bool zm = zbit(z, b), zz = zbit(z, b + st), zp = zbit(z, b + 2 * st);
+    out &= ~((1u << b) | (1u << (b + st)) | (1u << (b + 2 * st)));
+    if (zm && zz && zp) out |= 1u << b;
+    if (zm && zp) out |= (1u << (b + st)) | (1u << (b + 2 * st));
+  }
+  return out;
+}
+constexpr uint32_t inv_zero_after(uint32_t z, int ax, int NS) {
+  const int st = axis_stride(ax);
+  uint32_t out = z;
+  for (int b = 0; b < NS; ++b) {
+    if ((b / st) % 3 != 0) continue;
+    const bool z0 = zbit(z, b), z1 = zbit(z, b + st), z2 = zbit(z, b + 2 * st);
+    out &= ~((1u << b) | (1u << (b + st)) | (1u << (b + 2 * st)));
+    if (z1 && z2) out |= (1u << b) | (1u << (b + 2 * st));
+    if (z0 && z2) out |= 1u << (b + st);
+  }
+  return out;
+}
+template <bool FWD>
+constexpr uint32_t zero_before_axis(uint32_t z, int ax, int NS) {
+  for (int a = 0; a < ax; ++a) z = FWD ? fwd_zero_after(z, a, NS) : inv_zero_after(z, a, NS);
+  return z;
+}
+
+// (f-, f0, f+) -> (f- + f0 + f+, f+ - f-, f+ + f-) along each axis
+template <int D, uint32_t Z, typename T, int NS>
 __device__ __forceinline__ void moments_fwd(T (&t)[NS]) {
   static_for<0, D>([&](auto ax_) {
     constexpr int ax = decltype(ax_)::value;
-    constexpr int st = ax == 0 ? 1 : (ax == 1 ? 3 : 9);
+    constexpr int st = axis_stride(ax);
+    constexpr uint32_t z = zero_before_axis<true>(Z, ax, NS);
     static_for<0, NS>([&](auto b_) {
       constexpr int b = decltype(b_)::value;
       if constexpr ((b / st) % 3 == 0) {
-        const T m = t[b], z = t[b + st], p = t[b + 2 * st];
-        const T s = m + p;
-        t[b] = s + z;
-        t[b + st] = p - m;
+        constexpr bool zm = zbit(z, b), zz = zbit(z, b + st), zp = zbit(z, b + 2 * st);
+        const T m = t[b], c = t[b + st], p = t[b + 2 * st];
+        T s, d;
+        if constexpr (zm && zp) {
+          s = T(0);
+          d = T(0);
+        } else if constexpr (zm) {
+          s = p;
+          d = p;
+        } else if constexpr (zp) {
+          s = m;
+          d = -m;
+        } else {
+          s = m + p;
+          d = p - m;
+        }
+        if constexpr (zm && zp)
+          t[b] = c;
+        else if constexpr (zz)
+          t[b] = s;
+        else
+          t[b] = s + c;
+        t[b + st] = d;
         t[b + 2 * st] = s;
       }
     });
   });
 }
 
-template <int D, typename T, int NS>
+// (m0, m1, m2) -> ((m2 - m1)/2, m0 - m2, (m2 + m1)/2) along each axis
+template <int D, uint32_t Z, typename T, int NS>
 __device__ __forceinline__ void moments_inv(T (&t)[NS]) {
   static_for<0, D>([&](auto ax_) {
     constexpr int ax = decltype(ax_)::value;
-    constexpr int st = ax == 0 ? 1 : (ax == 1 ? 3 : 9);
+    constexpr int st = axis_stride(ax);
+    constexpr uint32_t z = zero_before_axis<false>(Z, ax, NS);
     static_for<0, NS>([&](auto b_) {
       constexpr int b = decltype(b_)::value;
       if constexpr ((b / st) % 3 == 0) {
+        constexpr bool z0 = zbit(z, b), z1 = zbit(z, b + st), z2 = zbit(z, b + 2 * st);
         const T m0 = t[b], m1 = t[b + st], m2 = t[b + 2 * st];
-        t[b] = T(0.5) * (m2 - m1);
-        t[b + st] = m0 - m2;
-        t[b + 2 * st] = T(0.5) * (m2 + m1);
+        if constexpr (z1 && z2) {
+          t[b] = T(0);
+          t[b + 2 * st] = T(0);
+        } else if constexpr (z1) {
+          t[b] = T(0.5) * m2;
+          t[b + 2 * st] = T(0.5) * m2;
+        } else if constexpr (z2) {
+          t[b] = T(-0.5) * m1;
+          t[b + 2 * st] = T(0.5) * m1;
+        } else {
+          t[b] = T(0.5) * (m2 - m1);
+          t[b + 2 * st] = T(0.5) * (m2 + m1);
+        }
+        if constexpr (z0 && z2)
+          t[b + st] = T(0);
+        else if constexpr (z2)
+          t[b + st] = m0;
+        else if constexpr (z0)
+          t[b + st] = -m2;
+        else
+          t[b + st] = m0 - m2;
       }
     });
   });
@@ -222,7 +315,7 @@ template <int L, int EQ, bool FORCE, typename T, int NS>
 __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, T phi_prev = T(0),
                                         T* phi_out = nullptr) {
   constexpr int D = Lat<L>::D;
-  moments_fwd<D>(t);
+  moments_fwd<D, Lat<L>::absent_mask()>(t);
 
   // slots of the first and second moments
   constexpr int sx = 1, sy = 3, sz = 9;
@@ -381,7 +474,7 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, T phi_prev
     }
   });
 
-  moments_inv<D>(t);
+  moments_inv<D, Lat<L>::dropped_mask()>(t);
 }
 
 }  // namespace rmrt
