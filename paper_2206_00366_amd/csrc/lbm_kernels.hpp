@@ -661,7 +661,7 @@ __global__ void __launch_bounds__(256)
           if constexpr (e1 * e2 != 0) m2[1][2] += (double)(e1 * e2) * d[J];
         });
         const double ru = C.hl ? C.rho0 : r;   // He-Luo: f_eq = g_eq(rho, rho0 u, rho0 u u)
-        const double ir = 1.0 / ru;
+        const double ir = recip(ru);
         double u[3];
         for (int a = 0; a < 3; ++a) u[a] = (m1[a] + C.half_force[a]) * ir;
         // v = m_2^ne + dt/2 (u F + F u + (cs2 I - u u) S) on the 2nd-order rows
@@ -687,22 +687,19 @@ __global__ void __launch_bounds__(256)
             for (int b = a; b < 3; ++b) o[a][b] = tau[a][b];
         } else {
           // eq. 4-28 with the tensors of eq. 4-29: tau_ab = 2 K_ab E_ab (a != b),
-          // tau_aa = K_aa (2 E_aa - (2/d) tr E) + Kb_a tr E, K = rho nu_entry
-          double num = 0.0, den = 1.0;
-          for (int a = 0; a < D; ++a) {
-            const double Kd = ru * Dm.ic.nu_diag[a], Kb = ru * Dm.ic.nu_b_ax[a];
-            num += tau[a][a] / (2.0 * Kd);
-            den += (Kb - 2.0 * Kd / D) / (2.0 * Kd);
-          }
-          const double trE = num / den;
+          // tau_aa = K_aa (2 E_aa - (2/d) tr E) + Kb_a tr E, K = rho nu_entry.
+          // Summing tau_aa / (2 K_aa) gives tr E (1 + sum_a (Kb_a - 2 K_aa / d) /
+          // (2 K_aa)), whose factor is rho-free and precomputed.
+          const InitCoef& I = Dm.ic;
+          double num = 0.0;
+          for (int a = 0; a < D; ++a) num += tau[a][a] * I.inv2nu_diag[a];
+          const double trE = num * ir * I.inv_trace_den;
           for (int a = 0; a < 3; ++a) o[a][a] = 0.0;
-          for (int a = 0; a < D; ++a) {
-            const double Kd = ru * Dm.ic.nu_diag[a], Kb = ru * Dm.ic.nu_b_ax[a];
-            o[a][a] = (tau[a][a] - (Kb - 2.0 * Kd / D) * trE) / (2.0 * Kd);
-          }
-          o[0][1] = tau[0][1] / (2.0 * ru * Dm.ic.nu_pair[0]);
-          o[0][2] = tau[0][2] / (2.0 * ru * Dm.ic.nu_pair[1]);
-          o[1][2] = tau[1][2] / (2.0 * ru * Dm.ic.nu_pair[2]);
+          for (int a = 0; a < D; ++a)
+            o[a][a] = (tau[a][a] - ru * I.bulk_excess[a] * trE) * ir * I.inv2nu_diag[a];
+          o[0][1] = tau[0][1] * ir * I.inv2nu_pair[0];
+          o[0][2] = tau[0][2] * ir * I.inv2nu_pair[1];
+          o[1][2] = tau[1][2] * ir * I.inv2nu_pair[2];
         }
         res[0] = o[0][0];
         res[1] = o[1][1];
@@ -716,14 +713,15 @@ __global__ void __launch_bounds__(256)
         }
       } else {
         const double Dphi = C.D0 * (1.0 + C.D2 * r * r);
-        const double s1 = 1.0 / (0.5 + Dphi * C.inv_cs2_dt);
+        const double s1 = recip(0.5 + Dphi * C.inv_cs2_dt);
+        const double iD = recip(Dphi);
         double X = C.source;
         if constexpr (Lat<L>::linear) {
           const double prev = (ST == ST_F64) ? ((const double*)Dm.hist)[idx] : (double)((const float*)Dm.hist)[idx];
           X = (r - prev) * C.inv_dt;
         }
         for (int a = 0; a < D; ++a)
-          res[a] = -(1.0 - 0.5 * s1) * (m1[a] - r * C.adv[a] + 0.5 * C.dt * C.adv_g[a] * X) / Dphi;
+          res[a] = -(1.0 - 0.5 * s1) * (m1[a] - r * C.adv[a] + 0.5 * C.dt * C.adv_g[a] * X) * iD;
       }
     }
     for (int k = 0; k < NC; ++k) {

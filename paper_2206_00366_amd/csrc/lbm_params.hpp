@@ -45,6 +45,10 @@ struct InitCoef {
   double k_off[3];   // 1 / (1 - s_off/2)
   double nu, nu_b;
   double nu_diag[3], nu_pair[3], nu_b_ax[3];   // viscosity tensor entries (eq. 4-29)
+  // strain rate from the stress (eq. 4-28 inverted with the tensors of eq. 4-29),
+  // per axis a < d: 1 / (2 nu_aa) and nu_b,a - 2 nu_aa / d; 1 / (1 + sum of
+  // their products); 1 / (2 nu_ab) per pair
+  double inv2nu_diag[3], bulk_excess[3], inv_trace_den, inv2nu_pair[3];
 };
 
 struct DomainDev {

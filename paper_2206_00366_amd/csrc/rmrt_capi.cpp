@@ -372,6 +372,15 @@ void fill_domain(const rmrt_params* p, const Derived& v, DomainDev& D, void* fa,
     D.ic.nu_pair[k] = v.nu_pair[k];
     D.ic.nu_b_ax[k] = v.nu_b_ax[k];
   }
+  double den = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    const bool axis = k < v.d, pair = (v.d == 3) || k == 0;
+    D.ic.inv2nu_diag[k] = axis ? 0.5 / v.nu_diag[k] : 0.0;
+    D.ic.bulk_excess[k] = axis ? v.nu_b_ax[k] - 2.0 * v.nu_diag[k] / v.d : 0.0;
+    D.ic.inv2nu_pair[k] = pair ? 0.5 / v.nu_pair[k] : 0.0;
+    den += D.ic.bulk_excess[k] * D.ic.inv2nu_diag[k];
+  }
+  D.ic.inv_trace_den = 1.0 / den;
   D.nx = p->n[0];
   D.ny = p->n[1];
   D.nz = p->n[2];
