@@ -236,6 +236,10 @@ def main():
     if "q19local" in only:
         log("[bench] rD3Q19 strain-rate output")
         per["rD3Q19_strain_rate_output"] = bench_local(torch, R, prm_h, rho_h, u_h, N_h)
+        fused = bench_step_local(torch, R, prm_h, rho_h, u_h, N_h)
+        sep = per["rD3Q19_strain_rate_output"]["us_per_call"] + 1e3 * head["ms_per_step"]
+        fused["speedup_vs_step_plus_on_demand"] = round(sep / fused["us_per_step"], 3)
+        per["rD3Q19_step_fused_strain"] = fused
     ceiling = None
     if "copy" in only:
         log("[bench] HBM copy ceiling")
@@ -364,6 +368,31 @@ def bench_local(torch, R, prm, rho, u, N, reps=50):
     us = ev_ms / reps * 1e3
     return {"workload": "rmrt_local_gradients(GRAD_STRAIN) on the rD3Q19 256x256x128 FP32-dev state, FP32 output",
             "us_per_call": round(us, 1), "bytes_per_node": bpn,
+            "kernel_GBps": round(bpn * N / (us * 1e-6) / 1e9, 1),
+            "pct_hbm_peak": round(100 * bpn * N / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 1)}
+
+
+def bench_step_local(torch, R, prm, rho, u, N, reps=50):
+    """rmrt_step_local on the headline domain: one step fused with the FP32
+    strain-rate output of the state it starts from (HIP-event time per call;
+    bytes: q populations read and written, six components written)."""
+    dom = R.Domain(R.make_params(**prm), rho, u)
+    dom.step(2)
+    out = torch.empty(6 * N, dtype=torch.float32, device="cuda")
+    lib = R.lib()
+    def call(n):
+        for _ in range(n):
+            R._check(lib.rmrt_step_local(dom._ctx, R.GRAD_STRAIN, R._ptr(out), R.OUT_F32, R._stream()),
+                     "rmrt_step_local")
+    wall, ev_ms = timed_steps(torch, call, reps, 4)
+    dom.close()
+    del out
+    torch.cuda.empty_cache()
+    bpn = 2 * 19 * 4 + 6 * 4
+    us = ev_ms / reps * 1e3
+    return {"workload": "rmrt_step_local(GRAD_STRAIN): one rD3Q19 256x256x128 FP32-dev AA step fused with its "
+                        "FP32 strain-rate output",
+            "us_per_step": round(us, 1), "MLUPS": round(N / (us * 1e-6) / 1e6, 1), "bytes_per_node": bpn,
             "kernel_GBps": round(bpn * N / (us * 1e-6) / 1e9, 1),
             "pct_hbm_peak": round(100 * bpn * N / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 1)}
 

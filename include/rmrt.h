@@ -243,6 +243,20 @@ int rmrt_populations(rmrt_ctx* ctx, double* f_out, void* stream);
 int rmrt_local_gradients(rmrt_ctx* ctx, int kind, void* out, int out_dtype, void* stream);
 
 /*
+ * One step fused with the local outputs of rmrt_local_gradients (same kinds,
+ * layout, errors and zeros at solid nodes): out receives the output of the
+ * state the step starts from, computed from the deviations the step has
+ * loaded, in the step's working precision (FP64 for FP64 storage, FP32
+ * otherwise), so the second non-equilibrium moment carries the FP32 rounding
+ * of the collision.  Costs one step plus the output writes (no second read of
+ * the state).  Advances the context by one step (one workgroup per tile, the
+ * context's residency cap, 64-bit addressing; no health check).  RMRT_EINVAL
+ * for a domain of a batch.  For the coupling loops of eq. 4-28 (a strain-rate
+ * dependent viscosity) and eq. 4-13.
+ */
+int rmrt_step_local(rmrt_ctx* ctx, int kind, void* out, int out_dtype, void* stream);
+
+/*
  * FP64 sums over fluid nodes: out[0] = sum rho (or phi), out[1..3] = sum rho u
  * (eq. 2-4-2; the mass and momentum that eq. 4-18-1 conserves).  Synchronises
  * stream.  Returns RMRT_ENONFINITE if any sum is NaN or Inf.

@@ -205,6 +205,104 @@ __device__ __forceinline__ size_t read_elem(const DomainDev& Dm, const Geo<D>& g
 // node ranges of a domain); a null tile list means one domain split into
 // tiles of `tile_nodes` nodes with one tile per workgroup.
 // ----------------------------------------------------------------------------
+// kinds of local output (stress / strain rate of the NSE, grad phi of the NCDE)
+enum { GRAD_STRAIN = 0, GRAD_STRESS = 1, GRAD_PHI = 2 };
+
+// The local outputs of one node from its deviations d_j (paper order), in the
+// working precision T: FP64 in the on-demand kernel, the step's precision in
+// the fused step.  prev: phi of the previous step (rD2Q5 / rD3Q7).
+template <int L, int EQ, typename T>
+__device__ __forceinline__ void local_node(const DomainDev& Dm, const Coef<T>& C, const T (&d)[Lat<L>::Q], T prev,
+                                           int kind, T (&res)[6]) {
+  constexpr int D = Lat<L>::D;
+  T drho = T(0), m1[3] = {T(0), T(0), T(0)};
+  static_for<0, Lat<L>::Q>([&](auto j_) {
+    constexpr int J = decltype(j_)::value;
+    drho += d[J];
+    if constexpr (Lat<L>::e(J, 0) != 0) m1[0] += (T)Lat<L>::e(J, 0) * d[J];
+    if constexpr (Lat<L>::e(J, 1) != 0) m1[1] += (T)Lat<L>::e(J, 1) * d[J];
+    if constexpr (Lat<L>::e(J, 2) != 0) m1[2] += (T)Lat<L>::e(J, 2) * d[J];
+  });
+  m1[0] *= C.c[0];
+  m1[1] *= C.c[1];
+  m1[2] *= C.c[2];
+  const T r = C.rho0 + drho + C.half_source;
+  if constexpr (EQ == EQ_NSE) {
+    // second moments of the deviations: sum c_a c_b d_j (the rest part
+    // w_j rho0 contributes rho0 cs2 I)
+    T m2[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+    static_for<0, Lat<L>::Q>([&](auto j_) {
+      constexpr int J = decltype(j_)::value;
+      constexpr int e0 = Lat<L>::e(J, 0), e1 = Lat<L>::e(J, 1), e2 = Lat<L>::e(J, 2);
+      if constexpr (e0 != 0) m2[0][0] += d[J];
+      if constexpr (e1 != 0) m2[1][1] += d[J];
+      if constexpr (e2 != 0) m2[2][2] += d[J];
+      if constexpr (e0 * e1 != 0) m2[0][1] += (T)(e0 * e1) * d[J];
+      if constexpr (e0 * e2 != 0) m2[0][2] += (T)(e0 * e2) * d[J];
+      if constexpr (e1 * e2 != 0) m2[1][2] += (T)(e1 * e2) * d[J];
+    });
+    const T ru = C.hl ? C.rho0 : r;   // He-Luo: f_eq = g_eq(rho, rho0 u, rho0 u u)
+    const T ir = recip(ru);
+    T u[3];
+    for (int a = 0; a < 3; ++a) u[a] = (m1[a] + C.half_force[a]) * ir;
+    // v = m_2^ne + dt/2 (u F + F u + (cs2 I - u u) S) on the 2nd-order rows
+    T v[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        const T m2ab = (a <= b ? m2[a][b] : m2[b][a]) * C.c[a] * C.c[b] + (a == b ? C.rho0 * C.cs2 : T(0));
+        v[a][b] = m2ab - (a == b ? r * C.cs2 : T(0)) - ru * u[a] * u[b] + u[a] * C.half_force[b] +
+                  C.half_force[a] * u[b] + (a == b ? C.half_cs2_source : T(0)) - u[a] * u[b] * C.half_source;
+      }
+    T tau[3][3];
+    for (int a = 0; a < 3; ++a) {
+      T sum = T(0);
+      for (int b = 0; b < D; ++b) sum += C.IhS[a][b] * v[b][b];
+      tau[a][a] = -sum;
+    }
+    tau[0][1] = -C.ihs_off[0] * v[0][1];
+    tau[0][2] = -C.ihs_off[1] * v[0][2];
+    tau[1][2] = -C.ihs_off[2] * v[1][2];
+    T o[3][3];
+    if (kind == GRAD_STRESS) {
+      for (int a = 0; a < 3; ++a)
+        for (int b = a; b < 3; ++b) o[a][b] = tau[a][b];
+    } else {
+      // eq. 4-28 with the tensors of eq. 4-29: tau_ab = 2 K_ab E_ab (a != b),
+      // tau_aa = K_aa (2 E_aa - (2/d) tr E) + Kb_a tr E, K = rho nu_entry.
+      // Summing tau_aa / (2 K_aa) gives tr E (1 + sum_a (Kb_a - 2 K_aa / d) /
+      // (2 K_aa)), whose factor is rho-free and precomputed.
+      const InitCoef& I = Dm.ic;
+      T num = T(0);
+      for (int a = 0; a < D; ++a) num += tau[a][a] * (T)I.inv2nu_diag[a];
+      const T trE = num * ir * (T)I.inv_trace_den;
+      for (int a = 0; a < 3; ++a) o[a][a] = T(0);
+      for (int a = 0; a < D; ++a)
+        o[a][a] = (tau[a][a] - ru * (T)I.bulk_excess[a] * trE) * ir * (T)I.inv2nu_diag[a];
+      o[0][1] = tau[0][1] * ir * (T)I.inv2nu_pair[0];
+      o[0][2] = tau[0][2] * ir * (T)I.inv2nu_pair[1];
+      o[1][2] = tau[1][2] * ir * (T)I.inv2nu_pair[2];
+    }
+    res[0] = o[0][0];
+    res[1] = o[1][1];
+    if constexpr (D == 2) {
+      res[2] = o[0][1];
+    } else {
+      res[2] = o[2][2];
+      res[3] = o[0][1];
+      res[4] = o[0][2];
+      res[5] = o[1][2];
+    }
+  } else {
+    const T Dphi = C.D0 * (T(1) + C.D2 * r * r);
+    const T s1 = recip(T(0.5) + Dphi * C.inv_cs2_dt);
+    const T iD = recip(Dphi);
+    T X = C.source;
+    if constexpr (Lat<L>::linear) X = (r - prev) * C.inv_dt;
+    for (int a = 0; a < D; ++a)
+      res[a] = -(T(1) - T(0.5) * s1) * (m1[a] - r * C.adv[a] + T(0.5) * C.dt * C.adv_g[a] * X) * iD;
+  }
+}
+
 // BUF: buffer addressing (buffers below 4 GiB).
 template <int L, int ST, int EQ, bool FORCE, int BC, int PH, bool BUF>
 struct NodeStep {
@@ -346,6 +444,32 @@ struct NodeStep {
     });
   }
 
+  // Local outputs of the state this node's update starts from (the loaded
+  // deviations, before the collision), in the working precision; zero at
+  // solid nodes.  Component k of node idx at out[k N + idx].
+  __device__ __forceinline__ void local_out(const DomainDev& Dm, const Coef<T>& C, void* out, int kind,
+                                            int out_f32) const {
+    constexpr int NC = (EQ == EQ_NSE) ? D * (D + 1) / 2 : D;
+    T res[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    if (live) {
+      T d[Q];
+      static_for<0, Q>([&](auto j_) {
+        constexpr int J = decltype(j_)::value;
+        d[J] = t[Lat<L>::slot(J)];
+      });
+      T prev = T(0);
+      if constexpr (Lat<L>::linear) prev = phi_prev;
+      local_node<L, EQ, T>(Dm, C, d, prev, kind, res);
+    }
+    const size_t N = Dm.N;
+    for (int k = 0; k < NC; ++k) {
+      if (out_f32)
+        to_global((float*)out)[(size_t)k * N + idx] = (float)res[k];
+      else
+        to_global((double*)out)[(size_t)k * N + idx] = (double)res[k];
+    }
+  }
+
   // Collide and write the q post-collision populations.
   __device__ __forceinline__ void finish(const DomainDev& Dm, const Coef<T>& C, gmem<S>* fout, R rout) {
     if (!live) return;
@@ -479,6 +603,35 @@ __global__ void __launch_bounds__(256)
         a.finish(Dm, C, fout, rout);
       }
     }
+  }
+}
+
+// One step of a single domain fused with its local outputs (stress / strain
+// rate or grad phi of the state the step starts from, computed from the loaded
+// deviations in the step's working precision).  One workgroup per tile, one
+// node per thread, 64-bit addressing.
+template <int L, int ST, int EQ, bool FORCE, int BC, int PH>
+__global__ void __launch_bounds__(256)
+    k_step_local(const DomainDev* __restrict__ doms, uint32_t tile_nodes, uint32_t parity, void* out, int kind,
+                 int out_f32) {
+  using SS = Store<ST>;
+  using S = typename SS::S;
+  using T = typename SS::T;
+  const DomainDev& Dm = doms[0];
+  const Coef<T>& C = coef<T>(Dm);
+  const uint32_t N = Dm.N, start = blockIdx.x * tile_nodes;
+  if (start >= N) return;
+  const uint32_t count = (N - start < tile_nodes) ? N - start : tile_nodes;
+  gmem<S>* fa = to_global((S*)Dm.fa);
+  gmem<S>* fb = to_global((S*)Dm.fb);
+  gmem<S>* fin = (PH == PH_AB && parity) ? fb : fa;
+  gmem<S>* fout = (PH == PH_AB) ? (parity ? fa : fb) : fa;
+  using NSp = NodeStep<L, ST, EQ, FORCE, BC, PH, false>;
+  for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) {
+    NSp a;
+    a.load(Dm, C, fin, 0, start + i, true);
+    a.local_out(Dm, C, out, kind, out_f32);
+    a.finish(Dm, C, fout, 0);
   }
 }
 
@@ -626,7 +779,6 @@ __global__ void __launch_bounds__(256)
 // Output component k of node i at out[k N + i]: (xx, yy, [zz,] xy, [xz, yz])
 // for tau / E, (x, y[, z]) for grad phi; zero at solid nodes.
 // ----------------------------------------------------------------------------
-enum { GRAD_STRAIN = 0, GRAD_STRESS = 1, GRAD_PHI = 2 };
 
 template <int L, int ST, int EQ, int BC, bool SWAPPED>
 __global__ void __launch_bounds__(256)
@@ -643,86 +795,10 @@ __global__ void __launch_bounds__(256)
     if (!(BC == 1 && Dm.has_solid && Dm.solid[idx])) {
       double d[Lat<L>::Q];
       gather64<L, ST, BC, SWAPPED>(Dm, f, idx, d);
-      double drho, m1[3];
-      first_moments<L>(Dm, d, drho, m1);
-      const double r = C.rho0 + drho + C.half_source;
-      if constexpr (EQ == EQ_NSE) {
-        // second moments of the deviations: sum c_a c_b d_j (the rest part
-        // w_j rho0 contributes rho0 cs2 I)
-        double m2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        static_for<0, Lat<L>::Q>([&](auto j_) {
-          constexpr int J = decltype(j_)::value;
-          constexpr int e0 = Lat<L>::e(J, 0), e1 = Lat<L>::e(J, 1), e2 = Lat<L>::e(J, 2);
-          if constexpr (e0 != 0) m2[0][0] += d[J];
-          if constexpr (e1 != 0) m2[1][1] += d[J];
-          if constexpr (e2 != 0) m2[2][2] += d[J];
-          if constexpr (e0 * e1 != 0) m2[0][1] += (double)(e0 * e1) * d[J];
-          if constexpr (e0 * e2 != 0) m2[0][2] += (double)(e0 * e2) * d[J];
-          if constexpr (e1 * e2 != 0) m2[1][2] += (double)(e1 * e2) * d[J];
-        });
-        const double ru = C.hl ? C.rho0 : r;   // He-Luo: f_eq = g_eq(rho, rho0 u, rho0 u u)
-        const double ir = recip(ru);
-        double u[3];
-        for (int a = 0; a < 3; ++a) u[a] = (m1[a] + C.half_force[a]) * ir;
-        // v = m_2^ne + dt/2 (u F + F u + (cs2 I - u u) S) on the 2nd-order rows
-        double v[3][3];
-        for (int a = 0; a < 3; ++a)
-          for (int b = 0; b < 3; ++b) {
-            const double m2ab = (a <= b ? m2[a][b] : m2[b][a]) * C.c[a] * C.c[b] + (a == b ? C.rho0 * C.cs2 : 0.0);
-            v[a][b] = m2ab - (a == b ? r * C.cs2 : 0.0) - ru * u[a] * u[b] + u[a] * C.half_force[b] +
-                      C.half_force[a] * u[b] + (a == b ? C.half_cs2_source : 0.0) - u[a] * u[b] * C.half_source;
-          }
-        double tau[3][3];
-        for (int a = 0; a < 3; ++a) {
-          double s = 0.0;
-          for (int b = 0; b < D; ++b) s += C.IhS[a][b] * v[b][b];
-          tau[a][a] = -s;
-        }
-        tau[0][1] = -C.ihs_off[0] * v[0][1];
-        tau[0][2] = -C.ihs_off[1] * v[0][2];
-        tau[1][2] = -C.ihs_off[2] * v[1][2];
-        double o[3][3];
-        if (kind == GRAD_STRESS) {
-          for (int a = 0; a < 3; ++a)
-            for (int b = a; b < 3; ++b) o[a][b] = tau[a][b];
-        } else {
-          // eq. 4-28 with the tensors of eq. 4-29: tau_ab = 2 K_ab E_ab (a != b),
-          // tau_aa = K_aa (2 E_aa - (2/d) tr E) + Kb_a tr E, K = rho nu_entry.
-          // Summing tau_aa / (2 K_aa) gives tr E (1 + sum_a (Kb_a - 2 K_aa / d) /
-          // (2 K_aa)), whose factor is rho-free and precomputed.
-          const InitCoef& I = Dm.ic;
-          double num = 0.0;
-          for (int a = 0; a < D; ++a) num += tau[a][a] * I.inv2nu_diag[a];
-          const double trE = num * ir * I.inv_trace_den;
-          for (int a = 0; a < 3; ++a) o[a][a] = 0.0;
-          for (int a = 0; a < D; ++a)
-            o[a][a] = (tau[a][a] - ru * I.bulk_excess[a] * trE) * ir * I.inv2nu_diag[a];
-          o[0][1] = tau[0][1] * ir * I.inv2nu_pair[0];
-          o[0][2] = tau[0][2] * ir * I.inv2nu_pair[1];
-          o[1][2] = tau[1][2] * ir * I.inv2nu_pair[2];
-        }
-        res[0] = o[0][0];
-        res[1] = o[1][1];
-        if constexpr (D == 2) {
-          res[2] = o[0][1];
-        } else {
-          res[2] = o[2][2];
-          res[3] = o[0][1];
-          res[4] = o[0][2];
-          res[5] = o[1][2];
-        }
-      } else {
-        const double Dphi = C.D0 * (1.0 + C.D2 * r * r);
-        const double s1 = recip(0.5 + Dphi * C.inv_cs2_dt);
-        const double iD = recip(Dphi);
-        double X = C.source;
-        if constexpr (Lat<L>::linear) {
-          const double prev = (ST == ST_F64) ? ((const double*)Dm.hist)[idx] : (double)((const float*)Dm.hist)[idx];
-          X = (r - prev) * C.inv_dt;
-        }
-        for (int a = 0; a < D; ++a)
-          res[a] = -(1.0 - 0.5 * s1) * (m1[a] - r * C.adv[a] + 0.5 * C.dt * C.adv_g[a] * X) * iD;
-      }
+      double prev = 0.0;
+      if constexpr (Lat<L>::linear)
+        prev = (ST == ST_F64) ? ((const double*)Dm.hist)[idx] : (double)((const float*)Dm.hist)[idx];
+      local_node<L, EQ, double>(Dm, C, d, prev, kind, res);
     }
     for (int k = 0; k < NC; ++k) {
       if (out_f32)
@@ -993,6 +1069,9 @@ struct StepLaunch {
   int eq, force, bc, phase;
   unsigned grid, block;
   hipStream_t stream;
+  // fused local outputs (k_step_local) when local_out is set
+  void* local_out;
+  int local_kind, local_f32;
 };
 struct AuxLaunch {
   const DomainDev* doms;

@@ -18,6 +18,11 @@ void do_step_npt(const StepLaunch& a) {
 // clears it otherwise).
 template <int L, int ST, int EQ, bool F, int BC, int PH>
 hipError_t do_step(const StepLaunch& a) {
+  if (a.local_out) {
+    hipLaunchKernelGGL((k_step_local<L, ST, EQ, F, BC, PH>), dim3(a.ntiles), dim3(a.block), a.lds_bytes, a.stream,
+                       a.doms, a.tile_nodes, a.parity, a.local_out, a.local_kind, a.local_f32);
+    return hipGetLastError();
+  }
   if (a.flags & STEP_BUFFER_OFFSETS)
     do_step_npt<L, ST, EQ, F, BC, PH, true>(a);
   else

@@ -903,7 +903,10 @@ int rmrt_moments(rmrt_ctx* c, void* rho_out, void* u_out, int out_dtype, void* s
   return RMRT_OK;
 }
 
-int rmrt_local_gradients(rmrt_ctx* c, int kind, void* out, int out_dtype, void* stream) {
+}  // extern "C"
+
+namespace {
+int check_local_args(const rmrt_ctx* c, int kind, const void* out, int out_dtype) {
   if (!c || !out) return fail(RMRT_EINVAL, "ctx or out is NULL");
   if (out_dtype != RMRT_OUT_F64 && out_dtype != RMRT_OUT_F32) return fail(RMRT_EINVAL, "bad out_dtype");
   const bool nse = c->p.equation == RMRT_NSE;
@@ -914,12 +917,51 @@ int rmrt_local_gradients(rmrt_ctx* c, int kind, void* out, int out_dtype, void* 
   } else {
     return fail(RMRT_EINVAL, "unknown kind %d", kind);
   }
+  return RMRT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int rmrt_local_gradients(rmrt_ctx* c, int kind, void* out, int out_dtype, void* stream) {
+  int rc = check_local_args(c, kind, out, out_dtype);
+  if (rc != RMRT_OK) return rc;
   AuxLaunch a = aux_of(c, (hipStream_t)stream);
   a.out0 = out;
   a.flag = out_dtype == RMRT_OUT_F32;
   a.kind = kind;
   hipError_t e = dispatch_local(c->p.lattice, c->p.storage, a);
   if (e != hipSuccess) return fail(RMRT_EHIP, "local gradients launch: %s", hipGetErrorString(e));
+  return RMRT_OK;
+}
+
+int rmrt_step_local(rmrt_ctx* c, int kind, void* out, int out_dtype, void* stream) {
+  int rc = check_local_args(c, kind, out, out_dtype);
+  if (rc != RMRT_OK) return rc;
+  if (c->batch) return fail(RMRT_EINVAL, "domain belongs to a batch");
+  hipStream_t s = (hipStream_t)stream;
+  StepLaunch a;
+  std::memset(&a, 0, sizeof(a));
+  a.doms = c->ddoms + c->dom;
+  a.tiles = nullptr;
+  a.tile_nodes = 256;
+  a.ntiles = (c->hdom.N + a.tile_nodes - 1) / a.tile_nodes;
+  a.flags = 0;
+  a.parity = (uint32_t)(c->steps & 1);
+  a.eq = c->p.equation;
+  a.force = has_force(&c->p);
+  a.bc = c->step_bc;
+  a.phase = c->p.pattern == RMRT_AB ? PH_AB : ((c->steps & 1) ? PH_AA_ODD : PH_AA_EVEN);
+  a.grid = a.ntiles;
+  a.lds_bytes = (c->flags & STEP_PERSISTENT) ? 0u : residency_lds(c->blocks_per_cu, 0u);
+  a.block = 256;
+  a.stream = s;
+  a.local_out = out;
+  a.local_kind = kind;
+  a.local_f32 = out_dtype == RMRT_OUT_F32;
+  hipError_t e = dispatch_step(c->p.lattice, c->p.storage, a);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "fused step launch failed: %s", hipGetErrorString(e));
+  c->steps += 1;
   return RMRT_OK;
 }
 

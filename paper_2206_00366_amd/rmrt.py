@@ -92,6 +92,7 @@ _sig = {
     "rmrt_batch_config_info": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                           C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "rmrt_local_gradients": (C.c_int, [_vp, C.c_int, _vp, C.c_int, _vp]),
+    "rmrt_step_local": (C.c_int, [_vp, C.c_int, _vp, C.c_int, _vp]),
     "rmrt_batch_step": (C.c_int, [_vp, C.c_int, _vp]),
     "rmrt_batch_residual": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
     "rmrt_batch_free": (C.c_int, [_vp]),
@@ -260,6 +261,15 @@ class Domain:
         out = torch.empty(nc * self.N, dtype=dt, device=self.f0.device)
         _check(_lib.rmrt_local_gradients(self._ctx, int(kind), _ptr(out), int(out_dtype), _stream()),
                "rmrt_local_gradients")
+        return out.view(nc, self.N)
+
+    def step_local(self, kind=GRAD_STRAIN, out_dtype=OUT_F32):
+        """One step fused with the local outputs of the state it starts from, shape (ncomp, N)."""
+        import torch
+        dt = torch.float64 if out_dtype == OUT_F64 else torch.float32
+        nc = self.d if kind == GRAD_PHI else self.d * (self.d + 1) // 2
+        out = torch.empty(nc * self.N, dtype=dt, device=self.f0.device)
+        _check(_lib.rmrt_step_local(self._ctx, int(kind), _ptr(out), int(out_dtype), _stream()), "rmrt_step_local")
         return out.view(nc, self.N)
 
     def populations(self):

@@ -152,3 +152,106 @@ def test_strain_rate_full_size_sampled(rmrt):
     err = np.abs(got - ref).max() / np.abs(ref).max()
     say(f"   sampled max rel err {err:.2e}")
     assert err < 1e-9
+
+
+def _kinds(m):
+    return (0, 1) if m.nse else (2,)
+
+
+@pytest.mark.parametrize("pattern", ["AB", "AA"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_fused_step_local_fp64(rmrt, case, pattern):
+    """rmrt_step_local with FP64 storage: over two consecutive steps (both AA
+    phases) its outputs equal the on-demand outputs of the states the steps
+    start from (same FP64 arithmetic on the same deviations), and the stepped
+    populations equal those of rmrt_step."""
+    say(f"[fused step + local outputs f64] {case} {pattern}")
+    for kind in _kinds(CASES_MODEL(case)):
+        m, a, _, _ = _run(rmrt, case, "f64", pattern)
+        _, b, _, _ = _run(rmrt, case, "f64", pattern)
+        fl = m.fluid
+        for _ in range(2):
+            ref = a.local_gradients(kind).cpu().numpy()
+            a.step(1)
+            got = b.step_local(kind, rmrt.OUT_F64).cpu().numpy()
+            err = np.abs(got[:, fl] - ref[:, fl]).max() / np.abs(ref[:, fl]).max()
+            say(f"   kind {kind}: max rel |fused - on demand| = {err:.2e}")
+            assert err < 1e-13
+            assert np.all(got[:, ~fl] == 0.0)
+        assert b.steps_taken() == a.steps_taken()
+        assert np.array_equal(a.populations().cpu().numpy()[:, fl], b.populations().cpu().numpy()[:, fl])
+        a.close()
+        b.close()
+
+
+def CASES_MODEL(case):
+    prm, solid_fn, _ = CASES[case]
+    return O.Model(prm, solid=None if solid_fn is None else solid_fn(prm["n"]))
+
+
+def _fp32_bound(prm, kind, f_full, w_rho0, rho_min):
+    """Absolute bound on the FP32 rounding of a fused output: the moment sums
+    of q deviations of size at most max|d| round to within q 2^-24 max|d| each
+    (times c_a c_b for the second moments), and the output is linear in them
+    with gain at most 1 (stress: entries of I - S/2 lie in (0, 1]), 3 / (2
+    rho nu_min) (strain rate: eq. 4-28 with the trace coupling of eq. 4-29) or
+    1 / D0 (grad phi, D(phi) >= D0); a factor 8 covers the few further FP32
+    operations of each path."""
+    q = f_full.shape[0]
+    d = np.abs(f_full - w_rho0[:, None]).max()
+    c2 = max(x * x for x in prm["dx"])
+    if kind == 1:
+        gain = 1.0
+    elif kind == 0:
+        nus = [prm["nu"]] + [x for x in prm.get("nu_tensor", ()) if x > 0] + \
+              [x for x in prm.get("nu_b_axis", ()) if x > 0] + ([prm["nu_b"]] if prm.get("nu_b", -1) > 0 else [])
+        gain = 3.0 / (2.0 * rho_min * min(nus))
+    else:
+        gain = 1.0 / prm["D0"]
+    return 8.0 * q * 2.0**-24 * d * c2 * gain
+
+
+@pytest.mark.parametrize("storage", ["f32dev", "f16dev"])
+@pytest.mark.parametrize("case", ["q9_full_block", "q19_channel_force", "q27_tensor_heluo", "q9_ncde_source",
+                                  "q7_ncde"])
+def test_fused_step_local_reduced_precision(rmrt, case, storage):
+    """rmrt_step_local with FP32 / FP16 storage computes in FP32, against the
+    FP64 on-demand output of the same stored state, held to the rounding bound
+    of _fp32_bound; populations equal those of rmrt_step (bitwise in FP32,
+    within one FP16 rounding of a few values in FP16)."""
+    say(f"[fused step + local outputs {storage}] {case}")
+    prm = CASES[case][0]
+    for kind in _kinds(CASES_MODEL(case)):
+        m, a, _, _ = _run(rmrt, case, storage, "AA")
+        _, b, _, _ = _run(rmrt, case, storage, "AA")
+        fl = m.fluid
+        w_rho0 = m.w * (m.rho0 if m.nse else 0.0)
+        for _ in range(2):
+            ref = a.local_gradients(kind).cpu().numpy()
+            f_full = a.populations().cpu().numpy()[:, fl]
+            rho_min = float(a.moments()[0].cpu().numpy()[fl].min()) if m.nse else 1.0
+            bound = _fp32_bound(prm, kind, f_full, w_rho0, rho_min)
+            a.step(1)
+            got = b.step_local(kind, rmrt.OUT_F64).cpu().numpy()
+            err = np.abs(got[:, fl] - ref[:, fl]).max()
+            say(f"   kind {kind}: max |fused FP32 - on demand FP64| = {err:.2e} (bound {bound:.2e}, "
+                f"{err / np.abs(ref[:, fl]).max():.1e} of max |out|)")
+            assert err < bound
+        fa, fb = a.populations().cpu().numpy()[:, fl], b.populations().cpu().numpy()[:, fl]
+        if storage == "f32dev":
+            assert np.array_equal(fa, fb)
+        else:
+            assert np.abs(fa - fb).max() / np.abs(fa).max() < 2e-4
+        a.close()
+        b.close()
+
+
+def test_fused_step_local_argument_errors(rmrt):
+    m, dom, f, h = _run(rmrt, "q9_full_block", "f64", "AA")
+    n0 = dom.steps_taken()
+    for kind in (rmrt.GRAD_PHI, 7):
+        with pytest.raises(rmrt.RMRTError) as ei:
+            dom.step_local(kind)
+        assert ei.value.code == rmrt.EINVAL
+    assert dom.steps_taken() == n0          # a rejected call does not step
+    dom.close()
