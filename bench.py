@@ -149,6 +149,21 @@ def cpu_baseline():
     rec = {"value": round(m.N * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
            "sample": f"rD3Q19 NSE Taylor-Green 32x32x32 (dz = 2 dx, nu = 0.005), {steps} steps of the dense "
                      f"FP64 numpy oracle ({dt:.1f} s); numpy BLAS threads = {threads}"}
+    # the same oracle on one host thread (BLAS limited to 1), a shorter sample
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            g = m.init(rho, u)
+            s1 = 0
+            t1 = time.perf_counter()
+            while time.perf_counter() - t1 < 5.0 or s1 < 5:
+                g = m.step(g, 5)
+                s1 += 5
+            d1 = time.perf_counter() - t1
+        rec["single_thread"] = {"value": round(m.N * s1 / d1 / 1e6, 4), "unit": "MLUPS", "cores": 1,
+                                "sample": f"the same case, {s1} steps ({d1:.1f} s)"}
+    except ImportError:
+        pass
     r_o, u_o = m.macroscopic(f)
     return rec, dict(prm=prm, rho=rho, u=u, steps=steps, rho_o=r_o, u_o=u_o)
 
