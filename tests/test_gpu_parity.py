@@ -513,16 +513,18 @@ def test_byte_offsets_beyond_4_gib(rmrt, lat, n, storage, buffer_offsets):
     assert err < (2e-6 if storage == "f32dev" else 1e-13)
 
 
-def test_full_size_taylor_green_decay_rate(rmrt):
-    """The benchmark's rD3Q19 256 x 256 x 128 FP32-dev AA configuration run for
-    2000 steps at U0 = 1e-3 (Re ~ 50, so the vortex stays in its linear decay):
-    the kinetic energy decays at 2 nu (kx^2 + ky^2 + kz^2) within 1%, a
-    property of the recovered Navier-Stokes equations at any size."""
-    say("[full size TG decay] Q19 256x256x128 f32dev")
+@pytest.mark.parametrize("lat,storage", [("Q19", "f32dev"), ("Q19", "f16dev"), ("Q27", "f32dev"), ("Q27", "f16dev")])
+def test_full_size_taylor_green_decay_rate(rmrt, lat, storage):
+    """The benchmark's 256 x 256 x 128, dz = 2 dx, AA configuration (and its
+    rD3Q27 / FP16 siblings) run for 2000 steps at U0 = 1e-3 (Re ~ 50, so the
+    vortex stays in its linear decay): the kinetic energy decays at
+    2 nu (kx^2 + ky^2 + kz^2) within 1%, a property of the recovered
+    Navier-Stokes equations at any size."""
+    say(f"[full size TG decay] {lat} 256x256x128 {storage}")
     n, dx, nu, U0 = (256, 256, 128), (1.0, 1.0, 2.0), 0.005, 1e-3
-    prm = dict(lattice="Q19", n=n, dx=dx, nu=nu, cs2=1.0 / 3.0)
+    prm = dict(lattice=lat, n=n, dx=dx, nu=nu, cs2=1.0 / 3.0)
     rho, u, (kx, ky, kz) = taylor_green_3d(n, dx, U0, 1.0 / 3.0)
-    dom = rmrt.Domain(rmrt.make_params(**prm, storage="f32dev", pattern="AA"), rho, u)
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage=storage, pattern="AA"), rho, u)
     del rho, u
     ts, es = [], []
     for t in range(0, 2001, 250):
