@@ -185,7 +185,7 @@ __global__ void k_bgrad_part(const uint16_t* __restrict__ dy, float* __restrict_
     for (long p = (long)blockIdx.x * lanes + slot; p < P; p += (long)gridDim.x * lanes) s += bf2f(dy[p * Cout + co]);
   sh[threadIdx.x] = s;
   __syncthreads();
-  if (threadIdx.x < Cout) {
+  if ((int)threadIdx.x < Cout) {
     float t = 0.f;
     for (int k = 0; k < lanes; ++k) t += sh[k * Cout + threadIdx.x];
     part[(long)blockIdx.x * Cout + threadIdx.x] = t;

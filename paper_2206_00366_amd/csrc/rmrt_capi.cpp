@@ -39,6 +39,15 @@ int fail(int code, const char* fmt, ...) {
       return fail(RMRT_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
   } while (0)
 
+// The two timing events of the tuners, destroyed on every return path.
+struct EventPair {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~EventPair() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Lattice and parameter derivation (Sec. III, Sec. IV, Sec. V)
 // ---------------------------------------------------------------------------
@@ -581,17 +590,19 @@ int ctx_alloc_scratch(rmrt_ctx* c) {
   return RMRT_OK;
 }
 
+// Release paths ignore the runtime's return codes: there is nothing left to
+// recover and the first error has already been reported.
 void ctx_release(rmrt_ctx* c) {
-  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
-  if (c->cap) hipStreamDestroy(c->cap);
-  if (c->partials) hipFree(c->partials);
-  if (c->dres) hipFree(c->dres);
-  if (c->hres) hipHostFree(c->hres);
-  if (c->uprev) hipFree(c->uprev);
-  if (c->links) hipFree(c->links);
-  if (c->hist) hipFree(c->hist);
-  if (c->owns_ddoms && c->ddoms) hipFree(c->ddoms);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  if (c->partials) (void)hipFree(c->partials);
+  if (c->dres) (void)hipFree(c->dres);
+  if (c->hres) (void)hipHostFree(c->hres);
+  if (c->uprev) (void)hipFree(c->uprev);
+  if (c->links) (void)hipFree(c->links);
+  if (c->hist) (void)hipFree(c->hist);
+  if (c->owns_ddoms && c->ddoms) (void)hipFree(c->ddoms);
 }
 
 // Allocate the link bits of a context (hdom.links set); the caller uploads
@@ -666,16 +677,16 @@ int run_graph(rmrt_ctx* c, int n, hipStream_t s) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap, &g);
     if (rc != RMRT_OK) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return rc;
     }
     if (e != hipSuccess) return fail(RMRT_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
     hipGraphExec_t ge = nullptr;
     e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(RMRT_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     if (c->graphs.size() >= 16) {
-      for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+      for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
       c->graphs.clear();
     }
     it = c->graphs.emplace(key, ge).first;
@@ -1023,7 +1034,7 @@ int rmrt_set_launch(rmrt_ctx* c, int blocks_per_cu, int flags) {
     return fail(RMRT_EINVAL, "a residency cap of 1 workgroup per CU is not supported (use >= 2)");
   c->blocks_per_cu = blocks_per_cu;
   c->flags = (uint32_t)flags;
-  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
   return RMRT_OK;
 }
@@ -1041,9 +1052,10 @@ int rmrt_tune(rmrt_ctx* c, int steps, void* stream, int* blocks_per_cu) {
   if (steps < 1) return fail(RMRT_EINVAL, "steps must be >= 1");
   hipStream_t s = (hipStream_t)stream;
   const int cands[] = {0, 2, 3, 4, 5, 6, 8};
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
+  EventPair ev;
+  HIP_TRY(hipEventCreate(&ev.e0));
+  HIP_TRY(hipEventCreate(&ev.e1));
+  hipEvent_t e0 = ev.e0, e1 = ev.e1;
   int best = kDefaultBlocksPerCU, best_flags = 0;
   float best_ms = 1e30f;
   const int nbuf = buffer_offsets_apply(c) ? 2 : 1;
@@ -1054,11 +1066,7 @@ int rmrt_tune(rmrt_ctx* c, int steps, void* stream, int* blocks_per_cu) {
     int rc = rmrt_set_launch(c, k, fl);
     if (rc == RMRT_OK) rc = step_impl(c, 2, s);
     if (rc == RMRT_OK) rc = step_impl(c, steps, s);
-    if (rc != RMRT_OK) {
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
-      return rc;
-    }
+    if (rc != RMRT_OK) return rc;
     HIP_TRY(hipEventRecord(e0, s));
     rc = step_impl(c, steps, s);
     HIP_TRY(hipEventRecord(e1, s));
@@ -1072,8 +1080,6 @@ int rmrt_tune(rmrt_ctx* c, int steps, void* stream, int* blocks_per_cu) {
       best_flags = fl;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   if (blocks_per_cu) *blocks_per_cu = best;
   return rmrt_set_launch(c, best, best_flags);
 }
@@ -1153,7 +1159,7 @@ int batch_build_tiles(rmrt_batch* b, int cfg, hipStream_t s) {
   HIP_TRY(hipStreamSynchronize(s));
   b->ntiles = (uint32_t)tiles.size();
   b->cfg = cfg;
-  for (auto& kv : b->graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
   b->graphs.clear();
   return RMRT_OK;
 }
@@ -1202,16 +1208,16 @@ int batch_graph(rmrt_batch* b, int n, hipStream_t s) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap, &g);
     if (rc != RMRT_OK) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return rc;
     }
     if (e != hipSuccess) return fail(RMRT_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
     hipGraphExec_t ge = nullptr;
     e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(RMRT_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     if (b->graphs.size() >= 16) {
-      for (auto& kv : b->graphs) hipGraphExecDestroy(kv.second);
+      for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
       b->graphs.clear();
     }
     it = b->graphs.emplace(key, ge).first;
@@ -1238,9 +1244,9 @@ int batch_step_impl(rmrt_batch* b, int nsteps, hipStream_t s) {
 }
 
 void batch_release(rmrt_batch* b) {
-  for (auto& kv : b->graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
   b->graphs.clear();
-  if (b->cap) hipStreamDestroy(b->cap);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
   for (auto* c : b->ctxs) {
     if (!c) continue;
     c->batch = nullptr;
@@ -1248,10 +1254,10 @@ void batch_release(rmrt_batch* b) {
     delete c;
   }
   b->ctxs.clear();
-  if (b->dtiles) hipFree(b->dtiles);
-  if (b->ddoms) hipFree(b->ddoms);
-  if (b->dres_all) hipFree(b->dres_all);
-  if (b->hres_all) hipHostFree(b->hres_all);
+  if (b->dtiles) (void)hipFree(b->dtiles);
+  if (b->ddoms) (void)hipFree(b->ddoms);
+  if (b->dres_all) (void)hipFree(b->dres_all);
+  if (b->hres_all) (void)hipHostFree(b->hres_all);
 }
 
 }  // namespace
@@ -1371,20 +1377,17 @@ int rmrt_batch_autotune(rmrt_batch* b, int steps, void* stream, int* chosen) {
   if (!b) return fail(RMRT_EINVAL, "batch is NULL");
   if (steps < 1) return fail(RMRT_EINVAL, "steps must be >= 1");
   hipStream_t s = (hipStream_t)stream;
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
+  EventPair ev;
+  HIP_TRY(hipEventCreate(&ev.e0));
+  HIP_TRY(hipEventCreate(&ev.e1));
+  hipEvent_t e0 = ev.e0, e1 = ev.e1;
   int best = -1;
   float best_ms = 1e30f;
   for (int cfg = 0; cfg < kNumTileShapes; ++cfg) {
     int rc = batch_build_tiles(b, cfg, s);
     if (rc == RMRT_OK) rc = batch_step_impl(b, 2, s);  // warm-up (and graph capture)
     if (rc == RMRT_OK) rc = batch_step_impl(b, steps, s);  // captures the timed graph
-    if (rc != RMRT_OK) {
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
-      return rc;
-    }
+    if (rc != RMRT_OK) return rc;
     HIP_TRY(hipEventRecord(e0, s));
     rc = batch_step_impl(b, steps, s);
     HIP_TRY(hipEventRecord(e1, s));
@@ -1397,8 +1400,6 @@ int rmrt_batch_autotune(rmrt_batch* b, int steps, void* stream, int* chosen) {
       best = cfg;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   int rc = batch_build_tiles(b, best, s);
   if (rc != RMRT_OK) return rc;
   if (chosen) *chosen = best;
