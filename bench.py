@@ -334,6 +334,8 @@ def main():
     if "q27batch" in only:
         log("[bench] rD3Q27 batch of 64 channels f32dev")
         per["rD3Q27_batch64_f32dev"] = bench_batch(torch, R, max(K // 10, 20), W)
+        log("[bench] rD3Q27 batch of 512 small channels f32dev")
+        per["rD3Q27_batch512_small_f32dev"] = bench_batch(torch, R, K, W, nd=512, nmin=16, nmax=48)
 
     out = {"metric": METRIC, "value": head["MLUPS"], "unit": "MLUPS", "n_gpus": 1, "steps": K, "warmup": W,
            "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -412,9 +414,14 @@ def bench_step_local(torch, R, prm, rho, u, N, reps=50):
             "pct_hbm_peak": round(100 * bpn * N / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 1)}
 
 
-def bench_batch(torch, R, steps, warmup):
+def bench_batch(torch, R, steps, warmup, nd=64, nmin=32, nmax=256, seq_steps=20):
+    """One graph-captured persistent launch per step over nd force-driven rD3Q27
+    channels (sizes U{nmin..nmax} per axis, seed 4), autotuned; then the same
+    domains as nd separate contexts stepped one after the other (each with its
+    default launch and graph replay), the plain path the batch replaces."""
+    import numpy as np
     from inputs import channel_batch
-    doms = channel_batch(seed=4, nd=64)
+    doms = channel_batch(seed=4, nd=nd, nmin=nmin, nmax=nmax)
     params = []
     total = 0
     for d in doms:
@@ -428,13 +435,30 @@ def bench_batch(torch, R, steps, warmup):
     wall, ev_ms = timed_steps(torch, b.step, steps, warmup)
     red = b.domains[0].reduce()
     fin = all(math.isfinite(v) for v in red)
-    e = lattice_entry(f"rD3Q27 batch of 64 force-driven channels (seed 4), {total} nodes, FP32-dev AA, "
-                      f"one persistent launch per step", 27, "f32dev", total, steps, wall, ev_ms)
+    e = lattice_entry(f"rD3Q27 batch of {nd} force-driven channels (seed 4, {nmin}..{nmax} nodes per axis), "
+                      f"{total} nodes, FP32-dev AA, one persistent launch per step", 27, "f32dev", total, steps,
+                      wall, ev_ms)
     e["autotuned_config"] = dict(zip(CONFIG_KEYS, R.Batch.configs()[cfg]))
     e["finite"] = fin
     b.close()
     del b
     torch.cuda.empty_cache()
+    ctxs = []
+    for prm, d in zip(params, doms):
+        N = d["n"][0] * d["n"][1] * d["n"][2]
+        ctxs.append(R.Domain(prm, np.ones(N), np.zeros((3, N))))
+    def seq(n):
+        for c in ctxs:
+            c.step(n)
+    seq_wall, _ = timed_steps(torch, seq, seq_steps, 2)
+    for c in ctxs:
+        c.close()
+    del ctxs
+    torch.cuda.empty_cache()
+    seq_mlups = total * seq_steps / seq_wall / 1e6
+    e["sequential_contexts"] = {"MLUPS": round(seq_mlups, 1), "steps": seq_steps,
+                                "note": f"the {nd} domains as separate contexts, stepped one after the other"}
+    e["speedup_vs_sequential"] = round(e["MLUPS"] / seq_mlups, 3)
     return e
 
 
