@@ -250,7 +250,7 @@ int rmrt_local_gradients(rmrt_ctx* ctx, int kind, void* out, int out_dtype, void
  * otherwise), so the second non-equilibrium moment carries the FP32 rounding
  * of the collision.  Costs one step plus the output writes (no second read of
  * the state).  Advances the context by one step (one workgroup per tile, the
- * context's residency cap, 64-bit addressing; no health check).  RMRT_EINVAL
+ * context's residency cap and tile order, 64-bit addressing; no health check).  RMRT_EINVAL
  * for a domain of a batch.  For the coupling loops of eq. 4-28 (a strain-rate
  * dependent viscosity) and eq. 4-13.
  */
@@ -280,7 +280,8 @@ int rmrt_steps_taken(const rmrt_ctx* ctx, long long* steps);
  * PERSISTENT: a persistent grid of blocks_per_cu workgroups per CU walks the
  * tiles, contiguously per XCD when flags & RMRT_LAUNCH_XCD_ORDER.
  * Default (measured on MI355X): one workgroup per tile with buffer addressing
- * (RMRT_LAUNCH_BUFFER_OFFSETS); a cap of 3 for rD3Q19 and rD3Q27 with
+ * and the alternating tile order (RMRT_LAUNCH_BUFFER_OFFSETS |
+ * RMRT_LAUNCH_ALTERNATE_ORDER); a cap of 3 for rD3Q19 and rD3Q27 with
  * FP32/FP64 storage and for rD3Q7 FP64; XCD order for rD2Q9, rD2Q5 and rD3Q7
  * FP32.  Invalidates the context's cached graphs.
  */
@@ -294,6 +295,12 @@ int rmrt_steps_taken(const rmrt_ctx* ctx, long long* steps);
  * no-op otherwise.  Results are bitwise those of the 64-bit form.  Part of
  * every default launch; batches use it whenever every domain qualifies. */
 #define RMRT_LAUNCH_BUFFER_OFFSETS 8
+/* Alternating tile order: odd steps walk the tiles backwards, so that every
+ * step starts on the nodes the previous step finished with, whose data the
+ * memory-side cache (MALL) and the L2 still hold.  Results are bitwise those
+ * of the forward order (nodes of one step are independent).  Part of every
+ * default launch; batches and rmrt_tune always use it. */
+#define RMRT_LAUNCH_ALTERNATE_ORDER 16
 int rmrt_set_launch(rmrt_ctx* ctx, int blocks_per_cu, int flags);
 int rmrt_get_launch(const rmrt_ctx* ctx, int* blocks_per_cu, int* flags);
 

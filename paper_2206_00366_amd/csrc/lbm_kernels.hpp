@@ -529,7 +529,16 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
 // so that the tiles resident at one time on an XCD are neighbours; the grid
 // size is the occupancy knob (fewer resident waves keep the q concurrent
 // address streams per wave from oversubscribing HBM).
-enum : uint32_t { STEP_XCD_ORDER = 1u, STEP_PERSISTENT = 2u, STEP_WIDE_TILES = 4u, STEP_BUFFER_OFFSETS = 8u };
+// STEP_ALTERNATE_ORDER walks the tiles backwards on odd steps, so that each
+// step starts on the tiles the previous one finished with, whose data the
+// memory-side cache (MALL) and the L2 still hold.
+enum : uint32_t {
+  STEP_XCD_ORDER = 1u,
+  STEP_PERSISTENT = 2u,
+  STEP_WIDE_TILES = 4u,
+  STEP_BUFFER_OFFSETS = 8u,
+  STEP_ALTERNATE_ORDER = 16u
+};
 
 // NPT nodes per thread per pass (1, or 2 with tiles of 2 blockDim nodes: both
 // nodes are read before either collides, so each wave keeps 2 q loads in
@@ -559,6 +568,7 @@ __global__ void __launch_bounds__(256)
       tt = blockIdx.x + it * G;
       if (tt >= ntiles) break;
     }
+    if ((flags & STEP_ALTERNATE_ORDER) && (parity & 1u)) tt = ntiles - 1u - tt;
     uint32_t dom, start, count;
     if (tiles != nullptr) {
       const Tile tl = tiles[tt];
@@ -613,13 +623,14 @@ __global__ void __launch_bounds__(256)
 template <int L, int ST, int EQ, bool FORCE, int BC, int PH>
 __global__ void __launch_bounds__(256)
     k_step_local(const DomainDev* __restrict__ doms, uint32_t tile_nodes, uint32_t parity, void* out, int kind,
-                 int out_f32) {
+                 int out_f32, int alternate) {
   using SS = Store<ST>;
   using S = typename SS::S;
   using T = typename SS::T;
   const DomainDev& Dm = doms[0];
   const Coef<T>& C = coef<T>(Dm);
-  const uint32_t N = Dm.N, start = blockIdx.x * tile_nodes;
+  const uint32_t tile = (alternate && (parity & 1u)) ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
+  const uint32_t N = Dm.N, start = tile * tile_nodes;
   if (start >= N) return;
   const uint32_t count = (N - start < tile_nodes) ? N - start : tile_nodes;
   gmem<S>* fa = to_global((S*)Dm.fa);

@@ -20,7 +20,8 @@ template <int L, int ST, int EQ, bool F, int BC, int PH>
 hipError_t do_step(const StepLaunch& a) {
   if (a.local_out) {
     hipLaunchKernelGGL((k_step_local<L, ST, EQ, F, BC, PH>), dim3(a.ntiles), dim3(a.block), a.lds_bytes, a.stream,
-                       a.doms, a.tile_nodes, a.parity, a.local_out, a.local_kind, a.local_f32);
+                       a.doms, a.tile_nodes, a.parity, a.local_out, a.local_kind, a.local_f32,
+                       (int)((a.flags & STEP_ALTERNATE_ORDER) != 0));
     return hipGetLastError();
   }
   if (a.flags & STEP_BUFFER_OFFSETS)

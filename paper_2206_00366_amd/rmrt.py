@@ -32,6 +32,7 @@ F64, F32DEV, F16DEV = 0, 1, 2
 AB, AA = 0, 1
 OUT_F64, OUT_F32 = 0, 1
 LAUNCH_XCD_ORDER, LAUNCH_PERSISTENT, LAUNCH_WIDE_TILES, LAUNCH_BUFFER_OFFSETS = 1, 2, 4, 8
+LAUNCH_ALTERNATE_ORDER = 16
 GRAD_STRAIN, GRAD_STRESS, GRAD_PHI = 0, 1, 2
 WALL_XM, WALL_XP, WALL_YM, WALL_YP, WALL_ZM, WALL_ZP = 1, 2, 4, 8, 16, 32
 

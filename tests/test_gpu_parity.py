@@ -184,6 +184,31 @@ def test_buffer_offsets_are_bitwise_identical(rmrt, case, pattern, storage):
             assert np.array_equal(out[buf], out[ref]), (buf, ref)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32dev", "f16dev"])
+@pytest.mark.parametrize("pattern", ["AB", "AA"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_alternating_tile_order_is_bitwise_identical(rmrt, case, pattern, storage):
+    """Walking the tiles backwards on odd steps (RMRT_LAUNCH_ALTERNATE_ORDER)
+    writes the same bits as the forward order: the nodes of one step are
+    independent.  Over an odd number of steps, with one and two nodes per
+    thread, buffer or 64-bit addressing, and a persistent grid."""
+    say(f"[alternating order] {case} {pattern} {storage}")
+    A, B, W, P = (rmrt.LAUNCH_ALTERNATE_ORDER, rmrt.LAUNCH_BUFFER_OFFSETS, rmrt.LAUNCH_WIDE_TILES,
+                  rmrt.LAUNCH_PERSISTENT)
+    out = {}
+    for bpc, fl in ((0, B), (0, B | A), (0, A), (0, B | W), (0, B | W | A), (2, B | P), (2, B | P | A)):
+        m, dom, rho, u, steps = _build(case, rmrt, storage, pattern)
+        dom.set_launch(bpc, fl)
+        dom.step(steps | 1)
+        out[(bpc, fl)] = dom.populations().cpu().numpy()[:, m.fluid]
+        dom.close()
+    for ref, alt in (((0, B), (0, B | A)), ((0, B), (0, A)), ((0, B | W), (0, B | W | A)), ((2, B | P), (2, B | P | A))):
+        if storage == "f64" or storage == "f32dev" or alt != (0, A):
+            assert np.array_equal(out[alt], out[ref]), (ref, alt)
+        else:   # FP16, 64-bit against buffer addressing: see the buffer-offsets test
+            assert rel_err(out[alt], out[ref]) < 2e-4
+
+
 @pytest.mark.parametrize("storage,tol", [("f32dev", 1e-5), ("f16dev", 3e-3)])
 @pytest.mark.parametrize("case", ["q9_periodic", "q9_channel_solid_force", "q9_ncde_nonlinear", "q19_periodic",
                                   "q19_channel_force", "q27_periodic", "q27_channel_solid_force", "q19_ncde"])
@@ -418,9 +443,10 @@ def test_launch_shapes_agree_and_match_oracle(rmrt):
     f_or = m.step(m.init(rho, u), 9)
     ref = None
     P, X, Wd = rmrt.LAUNCH_PERSISTENT, rmrt.LAUNCH_XCD_ORDER, rmrt.LAUNCH_WIDE_TILES
-    B = rmrt.LAUNCH_BUFFER_OFFSETS
+    B, A = rmrt.LAUNCH_BUFFER_OFFSETS, rmrt.LAUNCH_ALTERNATE_ORDER
     for bpc, fl in [(0, 0), (0, X), (3, 0), (8, 0), (1, P | X), (2, P | X), (3, P), (8, P | X), (0, Wd),
-                    (3, Wd | X), (2, Wd | P | X), (3, B), (0, B | X), (1, B | P | X), (2, B | Wd | P | X)]:
+                    (3, Wd | X), (2, Wd | P | X), (3, B), (0, B | X), (1, B | P | X), (2, B | Wd | P | X),
+                    (3, B | A), (0, A | X), (1, A | P | X), (3, A | P), (0, B | Wd | A), (2, B | Wd | P | X | A)]:
         dom = rmrt.Domain(rmrt.make_params(**prm, storage="f64", pattern="AA"), rho, u)
         dom.set_launch(bpc, fl)
         assert dom.get_launch() == (bpc, fl)
@@ -444,8 +470,8 @@ def test_tune_picks_a_valid_shape(rmrt):
     k = dom.tune(steps=4)
     assert k in (0, 2, 3, 4, 5, 6, 8)
     bpc, fl = dom.get_launch()
-    W, B = rmrt.LAUNCH_WIDE_TILES, rmrt.LAUNCH_BUFFER_OFFSETS
-    assert bpc == k and fl in (0, W, B, W | B)
+    W, B, A = rmrt.LAUNCH_WIDE_TILES, rmrt.LAUNCH_BUFFER_OFFSETS, rmrt.LAUNCH_ALTERNATE_ORDER
+    assert bpc == k and fl & A and (fl & ~A) in (0, W, B, W | B)
     r = dom.reduce()
     assert abs(r[0] - N) < 1e-6 * N
     dom.close()
