@@ -283,7 +283,7 @@ int rmrt_steps_taken(const rmrt_ctx* ctx, long long* steps);
  * and the alternating tile order (RMRT_LAUNCH_BUFFER_OFFSETS |
  * RMRT_LAUNCH_ALTERNATE_ORDER); a cap of 3 for rD3Q19 and rD3Q27 with
  * FP32/FP64 storage and for rD3Q7 FP64; XCD order for rD2Q9, rD2Q5 and rD3Q7
- * FP32.  Invalidates the context's cached graphs.
+ * FP32/FP16.  Invalidates the context's cached graphs.
  */
 #define RMRT_LAUNCH_XCD_ORDER 1
 #define RMRT_LAUNCH_PERSISTENT 2

@@ -515,20 +515,14 @@ struct NodeStep {
   }
 };
 
-__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
-  // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-  // contiguous range of tiles so neighbouring tiles share its L2
-  const uint32_t xcd = b & 7u, local = b >> 3;
-  const uint32_t per = G >> 3, rem = G & 7u;
-  return xcd * per + (xcd < rem ? xcd : rem) + local;
-}
-
-// Tile order.  With one workgroup per tile (gridDim == ntiles) tiles follow
-// xcd_remap.  With a persistent grid (gridDim < ntiles, a multiple of 8 when
-// XCD_ORDER is set) each XCD walks its own contiguous eighth of the tile list,
-// so that the tiles resident at one time on an XCD are neighbours; the grid
-// size is the occupancy knob (fewer resident waves keep the q concurrent
-// address streams per wave from oversubscribing HBM).
+// Tile order.  Workgroups are dealt round-robin to the 8 XCDs.  With
+// STEP_XCD_ORDER each XCD takes a contiguous range of the tile list instead, so
+// that neighbouring tiles share its L2: with one workgroup per tile (gridDim ==
+// ntiles) workgroup b of XCD b % 8 takes tile b / 8 of that XCD's range; with a
+// persistent grid (gridDim < ntiles, a multiple of 8 when XCD_ORDER is set)
+// each XCD walks its own contiguous eighth of the list.  The grid size is the
+// occupancy knob (fewer resident waves keep the q concurrent address streams
+// per wave from oversubscribing HBM).
 // STEP_ALTERNATE_ORDER walks the tiles backwards on odd steps, so that each
 // step starts on the tiles the previous one finished with, whose data the
 // memory-side cache (MALL) and the L2 still hold.
@@ -553,22 +547,33 @@ __global__ void __launch_bounds__(256)
   using T = typename SS::T;
   const uint32_t G = gridDim.x;
   const bool xcd = (flags & STEP_XCD_ORDER) != 0;
+  // odd steps of the alternating order walk backwards; with the XCD order each
+  // XCD reverses its own range, so that it keeps the tiles its L2 holds
+  const bool rev = (flags & STEP_ALTERNATE_ORDER) && (parity & 1u);
   const uint32_t per = (ntiles + 7u) >> 3;
   for (uint32_t it = 0;; ++it) {
     uint32_t tt;
     if (G >= ntiles) {
       if (it > 0 || blockIdx.x >= ntiles) break;
-      tt = xcd ? xcd_remap(blockIdx.x, ntiles) : blockIdx.x;
+      if (xcd) {
+        const uint32_t x = blockIdx.x & 7u, local = blockIdx.x >> 3;
+        const uint32_t q8 = ntiles >> 3, rem = ntiles & 7u;
+        const uint32_t first = x * q8 + (x < rem ? x : rem), cnt = q8 + (x < rem ? 1u : 0u);
+        tt = first + (rev ? cnt - 1u - local : local);
+      } else {
+        tt = rev ? ntiles - 1u - blockIdx.x : blockIdx.x;
+      }
     } else if (xcd) {
       const uint32_t local = (blockIdx.x >> 3) + it * (G >> 3);
-      if (local >= per) break;
-      tt = (blockIdx.x & 7u) * per + local;
-      if (tt >= ntiles) break;
+      const uint32_t first = (blockIdx.x & 7u) * per;
+      const uint32_t cnt = first < ntiles ? (ntiles - first < per ? ntiles - first : per) : 0u;
+      if (local >= cnt) break;
+      tt = first + (rev ? cnt - 1u - local : local);
     } else {
       tt = blockIdx.x + it * G;
       if (tt >= ntiles) break;
+      if (rev) tt = ntiles - 1u - tt;
     }
-    if ((flags & STEP_ALTERNATE_ORDER) && (parity & 1u)) tt = ntiles - 1u - tt;
     uint32_t dom, start, count;
     if (tiles != nullptr) {
       const Tile tl = tiles[tt];

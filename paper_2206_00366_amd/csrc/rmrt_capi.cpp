@@ -488,14 +488,15 @@ void default_launch(const rmrt_params& p, int& blocks_per_cu, uint32_t& flags) {
   // can get (rD3Q7 FP32: 7.0 TB/s uncapped, 6.1 with a cap of 3).
   // Alternating tile order everywhere: each step starts on the tiles the
   // previous one ended with, still held by the MALL and the L2 (rD3Q19 FP32
-  // 5.74 -> 6.45 TB/s of algorithmic traffic, FP16 +13%, rD3Q27 +10%).
+  // 5.74 -> 6.45 TB/s of algorithmic traffic, FP16 +11%, rD3Q27 +10%; the
+  // MALL-resident 2048 x 1024 rD2Q9 / rD2Q5 FP32 cases +14% / +20%).
   flags = STEP_BUFFER_OFFSETS | STEP_ALTERNATE_ORDER;
   if (p.lattice == RMRT_Q9 || p.lattice == RMRT_Q5) {
     flags |= STEP_XCD_ORDER;
   } else if (p.lattice == RMRT_Q7) {
     if (p.storage == RMRT_F64)
       blocks_per_cu = 3;
-    else if (p.storage == RMRT_F32DEV)
+    else
       flags |= STEP_XCD_ORDER;
   } else if (p.storage != RMRT_F16DEV) {
     blocks_per_cu = 3;

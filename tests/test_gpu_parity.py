@@ -191,18 +191,22 @@ def test_alternating_tile_order_is_bitwise_identical(rmrt, case, pattern, storag
     """Walking the tiles backwards on odd steps (RMRT_LAUNCH_ALTERNATE_ORDER)
     writes the same bits as the forward order: the nodes of one step are
     independent.  Over an odd number of steps, with one and two nodes per
-    thread, buffer or 64-bit addressing, and a persistent grid."""
+    thread, buffer or 64-bit addressing, a persistent grid and the XCD order
+    (whose ranges, ragged when the tile count is not a multiple of 8, each
+    XCD reverses on its own)."""
     say(f"[alternating order] {case} {pattern} {storage}")
-    A, B, W, P = (rmrt.LAUNCH_ALTERNATE_ORDER, rmrt.LAUNCH_BUFFER_OFFSETS, rmrt.LAUNCH_WIDE_TILES,
-                  rmrt.LAUNCH_PERSISTENT)
+    A, B, W, P, X = (rmrt.LAUNCH_ALTERNATE_ORDER, rmrt.LAUNCH_BUFFER_OFFSETS, rmrt.LAUNCH_WIDE_TILES,
+                     rmrt.LAUNCH_PERSISTENT, rmrt.LAUNCH_XCD_ORDER)
     out = {}
-    for bpc, fl in ((0, B), (0, B | A), (0, A), (0, B | W), (0, B | W | A), (2, B | P), (2, B | P | A)):
+    for bpc, fl in ((0, B), (0, B | A), (0, A), (0, B | W), (0, B | W | A), (2, B | P), (2, B | P | A),
+                    (0, B | X | A), (2, B | P | X | A)):
         m, dom, rho, u, steps = _build(case, rmrt, storage, pattern)
         dom.set_launch(bpc, fl)
         dom.step(steps | 1)
         out[(bpc, fl)] = dom.populations().cpu().numpy()[:, m.fluid]
         dom.close()
-    for ref, alt in (((0, B), (0, B | A)), ((0, B), (0, A)), ((0, B | W), (0, B | W | A)), ((2, B | P), (2, B | P | A))):
+    for ref, alt in (((0, B), (0, B | A)), ((0, B), (0, A)), ((0, B | W), (0, B | W | A)), ((2, B | P), (2, B | P | A)),
+                     ((0, B), (0, B | X | A)), ((0, B), (2, B | P | X | A))):
         if storage == "f64" or storage == "f32dev" or alt != (0, A):
             assert np.array_equal(out[alt], out[ref]), (ref, alt)
         else:   # FP16, 64-bit against buffer addressing: see the buffer-offsets test
