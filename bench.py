@@ -436,9 +436,11 @@ def bench_batch(torch, R, steps, warmup, nd=64, nmin=32, nmax=256, seq_steps=20)
     red = b.domains[0].reduce()
     fin = all(math.isfinite(v) for v in red)
     e = lattice_entry(f"rD3Q27 batch of {nd} force-driven channels (seed 4, {nmin}..{nmax} nodes per axis), "
-                      f"{total} nodes, FP32-dev AA, one persistent launch per step", 27, "f32dev", total, steps,
-                      wall, ev_ms)
+                      f"{total} nodes, FP32-dev AA, graph-captured launches over a tile list (one per step, or "
+                      f"one per domain group and step)", 27, "f32dev", total, steps, wall, ev_ms)
     e["autotuned_config"] = dict(zip(CONFIG_KEYS, R.Batch.configs()[cfg]))
+    gbytes, ngroups = b.group_bytes()
+    e["autotuned_groups"] = {"group_bytes": gbytes, "groups": ngroups}
     e["finite"] = fin
     b.close()
     del b

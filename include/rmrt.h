@@ -338,10 +338,26 @@ int rmrt_batch_domain(rmrt_batch* b, int d, rmrt_ctx** out);
 /*
  * Time every tile configuration of the built-in candidate list over `steps`
  * steps each (HIP events on stream), keep the fastest and return its index in
- * *chosen (may be NULL).  The timing runs advance the state; call
+ * *chosen (may be NULL); then time the domain groups of
+ * rmrt_batch_set_group_bytes (none, 128, 192 or 256 MiB) with that
+ * configuration and keep the fastest.  The timing runs advance the state; call
  * rmrt_set_fields afterwards when the initial state matters.
  */
 int rmrt_batch_autotune(rmrt_batch* b, int steps, void* stream, int* chosen);
+
+/*
+ * Domain groups: consecutive domains whose population buffers add up to at
+ * most `bytes` (a larger domain alone) form a group, and rmrt_batch_step(n)
+ * advances each group through its n steps before the next group starts, so
+ * that a group that fits in the memory-side cache (MALL, 256 MB) keeps its
+ * populations there from step to step.  The domains are independent, so the
+ * results are bitwise those of stepping all domains together.  bytes = 0 (the
+ * default): one group, one launch per step for the whole batch; otherwise one
+ * launch per group and step.  rmrt_batch_get_group_bytes returns the setting
+ * and the number of groups.
+ */
+int rmrt_batch_set_group_bytes(rmrt_batch* b, size_t bytes);
+int rmrt_batch_get_group_bytes(const rmrt_batch* b, size_t* bytes, int* ngroups);
 
 /* Select tile configuration `cfg` (0 .. rmrt_batch_num_configs()-1) explicitly. */
 int rmrt_batch_set_config(rmrt_batch* b, int cfg);

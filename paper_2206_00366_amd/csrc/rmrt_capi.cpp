@@ -1134,11 +1134,42 @@ struct rmrt_batch {
   int lattice = 0, storage = 0, equation = 0, pattern = 0, force = 0, bc = 0;
   std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
   hipStream_t cap = nullptr;
+  // domain groups: consecutive domains whose population buffers add up to at
+  // most group_bytes (0: one group) as (first tile, tile count); a stepping
+  // call advances each group through all its steps before the next group
+  size_t group_bytes = 0;
+  std::vector<std::pair<uint32_t, uint32_t>> groups;
   double* dres_all = nullptr;  // 2 * nd residual sums (device)
   double* hres_all = nullptr;  // pinned host copy
 };
 
 namespace {
+
+// Group consecutive domains (tiles are in domain order) up to group_bytes of
+// population buffers each; a larger domain forms a group of its own.
+void batch_make_groups(rmrt_batch* b) {
+  b->groups.clear();
+  const uint32_t tn = (uint32_t)kTileShapes[b->cfg].tile_nodes;
+  uint32_t first = 0, count = 0;
+  size_t bytes = 0;
+  for (int d = 0; d < b->nd; ++d) {
+    const rmrt_ctx* c = b->ctxs[d];
+    const uint32_t nt = (c->hdom.N + tn - 1) / tn;
+    const size_t db = (size_t)lattice_q(c->p.lattice) * c->hdom.ld * elem_size(c->p.storage) *
+                      (c->p.pattern == RMRT_AB ? 2u : 1u);
+    if (b->group_bytes > 0 && count > 0 && bytes + db > b->group_bytes) {
+      b->groups.emplace_back(first, count);
+      first += count;
+      count = 0;
+      bytes = 0;
+    }
+    count += nt;
+    bytes += db;
+  }
+  if (count > 0) b->groups.emplace_back(first, count);
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+}
 
 int batch_build_tiles(rmrt_batch* b, int cfg, hipStream_t s) {
   const TileConfig& tc = kTileShapes[cfg];
@@ -1164,18 +1195,17 @@ int batch_build_tiles(rmrt_batch* b, int cfg, hipStream_t s) {
   HIP_TRY(hipStreamSynchronize(s));
   b->ntiles = (uint32_t)tiles.size();
   b->cfg = cfg;
-  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
-  b->graphs.clear();
+  batch_make_groups(b);
   return RMRT_OK;
 }
 
-int batch_launch(rmrt_batch* b, long long step_index, hipStream_t s) {
+int batch_launch(rmrt_batch* b, long long step_index, hipStream_t s, size_t group) {
   const TileConfig& tc = kTileShapes[b->cfg];
   StepLaunch a;
   std::memset(&a, 0, sizeof(a));
   a.doms = b->ddoms;
-  a.tiles = b->dtiles;
-  a.ntiles = b->ntiles;
+  a.tiles = b->dtiles + b->groups[group].first;
+  a.ntiles = b->groups[group].second;
   a.tile_nodes = (uint32_t)tc.tile_nodes;
   a.parity = (uint32_t)(step_index & 1);
   a.eq = b->equation;
@@ -1189,7 +1219,7 @@ int batch_launch(rmrt_batch* b, long long step_index, hipStream_t s) {
   for (const rmrt_ctx* c : b->ctxs) buf = buf && buffer_offsets_apply(c);
   if (buf) a.flags |= STEP_BUFFER_OFFSETS;
   a.flags |= STEP_ALTERNATE_ORDER;
-  a.grid = persistent_grid(b->ntiles, b->cus, tc.blocks_per_cu, a.flags);
+  a.grid = persistent_grid(a.ntiles, b->cus, tc.blocks_per_cu, a.flags);
   a.lds_bytes = residency_lds(tc.blocks_per_cu, a.flags);
   a.block = (unsigned)tc.threads;
   a.stream = s;
@@ -1210,7 +1240,8 @@ int batch_graph(rmrt_batch* b, int n, hipStream_t s) {
     if (!b->cap) HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     int rc = RMRT_OK;
-    for (int i = 0; i < n && rc == RMRT_OK; ++i) rc = batch_launch(b, b->steps + i, b->cap);
+    for (size_t gi = 0; gi < b->groups.size() && rc == RMRT_OK; ++gi)
+      for (int i = 0; i < n && rc == RMRT_OK; ++i) rc = batch_launch(b, b->steps + i, b->cap, gi);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap, &g);
     if (rc != RMRT_OK) {
@@ -1242,9 +1273,11 @@ int batch_step_impl(rmrt_batch* b, int nsteps, hipStream_t s) {
   }
   if (left > 1) return batch_graph(b, left, s);
   if (left == 1) {
-    int rc = batch_launch(b, b->steps, s);
-    if (rc == RMRT_OK) batch_advance(b, 1);
-    return rc;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      int rc = batch_launch(b, b->steps, s, gi);
+      if (rc != RMRT_OK) return rc;
+    }
+    batch_advance(b, 1);
   }
   return RMRT_OK;
 }
@@ -1408,7 +1441,47 @@ int rmrt_batch_autotune(rmrt_batch* b, int steps, void* stream, int* chosen) {
   }
   int rc = batch_build_tiles(b, best, s);
   if (rc != RMRT_OK) return rc;
+  // then domain groups for the chosen shape: none, or groups of up to 128, 192
+  // or 256 MiB of populations (the MALL holds 256 MB)
+  const size_t group_cands[] = {0, (size_t)128 << 20, (size_t)192 << 20, (size_t)256 << 20};
+  const size_t keep = b->group_bytes;
+  size_t best_group = keep;
+  best_ms = 1e30f;
+  for (size_t gb : group_cands) {
+    b->group_bytes = gb;
+    batch_make_groups(b);
+    rc = batch_step_impl(b, 2, s);
+    if (rc == RMRT_OK) rc = batch_step_impl(b, steps, s);
+    if (rc != RMRT_OK) return rc;
+    HIP_TRY(hipEventRecord(e0, s));
+    rc = batch_step_impl(b, steps, s);
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    if (rc != RMRT_OK) return rc;
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_group = gb;
+    }
+  }
+  b->group_bytes = best_group;
+  batch_make_groups(b);
   if (chosen) *chosen = best;
+  return RMRT_OK;
+}
+
+int rmrt_batch_set_group_bytes(rmrt_batch* b, size_t bytes) {
+  if (!b) return fail(RMRT_EINVAL, "batch is NULL");
+  b->group_bytes = bytes;
+  batch_make_groups(b);
+  return RMRT_OK;
+}
+
+int rmrt_batch_get_group_bytes(const rmrt_batch* b, size_t* bytes, int* ngroups) {
+  if (!b) return fail(RMRT_EINVAL, "batch is NULL");
+  if (bytes) *bytes = b->group_bytes;
+  if (ngroups) *ngroups = (int)b->groups.size();
   return RMRT_OK;
 }
 

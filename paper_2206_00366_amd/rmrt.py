@@ -89,6 +89,8 @@ _sig = {
     "rmrt_batch_domain": (C.c_int, [_vp, C.c_int, C.POINTER(_vp)]),
     "rmrt_batch_autotune": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(C.c_int)]),
     "rmrt_batch_set_config": (C.c_int, [_vp, C.c_int]),
+    "rmrt_batch_set_group_bytes": (C.c_int, [_vp, C.c_size_t]),
+    "rmrt_batch_get_group_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_int)]),
     "rmrt_batch_num_configs": (C.c_int, []),
     "rmrt_batch_config_info": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                           C.POINTER(C.c_int), C.POINTER(C.c_int)]),
@@ -359,6 +361,16 @@ class Batch:
 
     def set_config(self, cfg):
         _check(_lib.rmrt_batch_set_config(self._b, int(cfg)), "rmrt_batch_set_config")
+
+    def set_group_bytes(self, nbytes):
+        """Domain groups of at most nbytes of populations stepped one after the other (0: one group)."""
+        _check(_lib.rmrt_batch_set_group_bytes(self._b, C.c_size_t(int(nbytes))), "rmrt_batch_set_group_bytes")
+
+    def group_bytes(self):
+        """(group size limit in bytes, number of groups)."""
+        nb, ng = C.c_size_t(), C.c_int()
+        _check(_lib.rmrt_batch_get_group_bytes(self._b, C.byref(nb), C.byref(ng)), "rmrt_batch_get_group_bytes")
+        return nb.value, ng.value
 
     def residuals(self):
         n = len(self.domains)

@@ -230,3 +230,37 @@ def test_batch_with_solid_masks_matches_oracle(rmrt, pattern):
             say(f"   domain {k}: max rel |f - f_oracle| = {err:.2e}")
             assert err < 1e-12
         b.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+@pytest.mark.parametrize("pattern", ["AB", "AA"])
+def test_domain_groups_are_bitwise_identical(rmrt, small_oracle, pattern, storage):
+    """Domain groups (each group advanced through all its steps before the next)
+    give the bits of the one-group batch: graph chunks and single steps, odd
+    totals, one-workgroup-per-tile and persistent shapes; FP64 also against the
+    oracle."""
+    nbytes = [rmrt.population_bytes(rmrt.make_params(**p, storage=storage, pattern=pattern))
+              * (2 if pattern == "AB" else 1) for p in SMALL]
+    configs = rmrt.Batch.configs()
+    persistent = next(i for i, c in enumerate(configs) if c[3])
+    for cfg in (0, persistent):
+        out = {}
+        for gb in (0, 1, max(nbytes[0], nbytes[1]) + min(nbytes)):
+            b = rmrt.Batch([rmrt.make_params(**p, storage=storage, pattern=pattern) for p in SMALL])
+            b.set_config(cfg)
+            b.set_group_bytes(gb)
+            lim, ng = b.group_bytes()
+            assert lim == gb and (ng == 1 if gb == 0 else 1 < ng <= len(SMALL))
+            for k, (m, rho, u, _) in enumerate(small_oracle):
+                b.domains[k].set_fields(rho, u)
+            b.step(20)
+            b.step(1)
+            out[gb] = [b.domains[k].populations().cpu().numpy() for k in range(len(SMALL))]
+            b.close()
+        say(f"[batch groups] {pattern} {storage} config {cfg}: group counts checked")
+        for gb, res in out.items():
+            for k in range(len(SMALL)):
+                assert np.array_equal(res[k], out[0][k]), (gb, k)
+        if storage == "f64":
+            for k, (m, rho, u, f_or) in enumerate(small_oracle):
+                assert rel_err(out[0][k], f_or) < 1e-12
