@@ -324,7 +324,8 @@ class Domain:
 
 
 class Batch:
-    """Many domains stepped by one persistent kernel per step (graph replay)."""
+    """Many domains stepped through one tile list: one launch per step, or one per domain group
+    and step (rmrt_batch_set_group_bytes), graph-replayed."""
 
     def __init__(self, params_list, solids=None, device="cuda"):
         import torch
