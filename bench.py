@@ -496,9 +496,11 @@ def warmstart_study(torch, args):
         b = S.make_batch(geoms)
         if cfg is None:
             cfg = b.autotune(steps=20)
-            record("autotune", config=dict(zip(CONFIG_KEYS, b.configs()[cfg])))
+            group_bytes = b.group_bytes()[0]
+            record("autotune", config=dict(zip(CONFIG_KEYS, b.configs()[cfg])), group_bytes=group_bytes)
         else:
             b.set_config(cfg)
+            b.set_group_bytes(group_bytes)
         rho, u = S.initial_fields(geoms)
         S.apply_initial(b, rho, u)
         steps, conv, wall, n = S.run_to_steady(b, tol=args.ws_train_tol, max_steps=args.ws_max_steps, log=log,
@@ -532,6 +534,7 @@ def warmstart_study(torch, args):
             geoms = test[s0:s0 + 50]
             b = S.make_batch(geoms)
             b.set_config(cfg)
+            b.set_group_bytes(group_bytes)
             t_inf = 0.0
             if mode != "cold":
                 torch.cuda.synchronize()
