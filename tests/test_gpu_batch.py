@@ -232,6 +232,39 @@ def test_batch_with_solid_masks_matches_oracle(rmrt, pattern):
         b.close()
 
 
+@pytest.mark.parametrize("storage", ["f32dev", "f16dev"])
+@pytest.mark.parametrize("pattern", ["AB", "AA"])
+def test_batch_graph_replays_match_single_steps(rmrt, small_oracle, pattern, storage):
+    """Batch graphs replayed several times, with eager work (per-domain moments
+    and the batch residuals) and host synchronisations between the replays,
+    leave the bits of the same number of eagerly launched single steps; with
+    domain groups too."""
+    for gb in (0, 1):
+        bs = []
+        for _ in range(2):
+            b = rmrt.Batch([rmrt.make_params(**p, storage=storage, pattern=pattern) for p in SMALL])
+            b.set_config(0)
+            b.set_group_bytes(gb)
+            for k, (m, rho, u, _) in enumerate(small_oracle):
+                b.domains[k].set_fields(rho, u)
+            bs.append(b)
+        g, e = bs
+        for it, n in enumerate((4, 4, 4, 3, 3)):
+            g.step(n)
+            for _ in range(n):
+                e.step(1)
+            g.domains[0].moments()
+            g.residuals()
+            torch.cuda.synchronize()
+            for k in range(len(SMALL)):
+                fg = g.domains[k].populations().cpu().numpy()
+                fe = e.domains[k].populations().cpu().numpy()
+                assert np.array_equal(fg, fe), (gb, it, n, k)
+        say(f"[batch graph replay] {pattern} {storage} group bytes {gb}: bitwise")
+        g.close()
+        e.close()
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32dev"])
 @pytest.mark.parametrize("pattern", ["AB", "AA"])
 def test_domain_groups_are_bitwise_identical(rmrt, small_oracle, pattern, storage):
