@@ -537,7 +537,7 @@ enum : uint32_t {
 // NPT nodes per thread per pass (1, or 2 with tiles of 2 blockDim nodes: both
 // nodes are read before either collides, so each wave keeps 2 q loads in
 // flight).  BUF selects buffer addressing of the population streams (the host
-// sets it only for periodic domains whose buffers are below 4 GiB).
+// sets it only where every population buffer is below 4 GiB).
 template <int L, int ST, int EQ, bool FORCE, int BC, int PH, int NPT, bool BUF>
 __global__ void __launch_bounds__(256)
     k_step(const DomainDev* __restrict__ doms, const Tile* __restrict__ tiles, uint32_t ntiles,
