@@ -394,6 +394,49 @@ def test_q19_256x256x128_one_step_sampled(rmrt, storage, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("lat,storage,tol", [("Q19", "f32dev", 1e-7), ("Q19", "f16dev", 5e-5), ("Q27", "f32dev", 1e-7)])
+def test_full_size_odd_phase_sampled(rmrt, lat, storage, tol):
+    """256 x 256 x 128, dz = 2 dx, the benchmark's default launch (AA, alternating tile
+    order, buffer addressing): the second step, the odd AA phase, at full size.  The
+    GPU's own state after the first step is the input: the oracle collides it at the
+    upstream nodes of 2048 sampled outputs (plus both ends), and the second step must
+    have pulled exactly those values.  Taylor-Green fields with seeded density noise, so
+    that neighbouring nodes differ.  With the GPU's own input the only difference is one
+    collision in working precision and one store: 3e-9 (FP32) and 4e-6 (FP16) of
+    max |f| observed."""
+    say(f"[{lat} 256x256x128 odd phase sampled] {storage}")
+    n, dx = (256, 256, 128), (1.0, 1.0, 2.0)
+    prm = dict(lattice=lat, n=n, dx=dx, nu=0.005, cs2=1.0 / 3.0)
+    rho, u, _ = taylor_green_3d(n, dx, 0.02, 1.0 / 3.0)
+    rho = rho + 1e-4 * np.random.default_rng(11).uniform(-1, 1, rho.size)
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage=storage, pattern="AA"), rho, u)
+    cap, flags = dom.get_launch()
+    assert flags & rmrt.LAUNCH_ALTERNATE_ORDER and flags & rmrt.LAUNCH_BUFFER_OFFSETS
+    dom.step(1)
+    f1 = dom.populations()                                   # (q, N) FP64 on the GPU
+    dom.step(1)
+    f2 = dom.populations()
+    nx, ny, nz = n
+    N = nx * ny * nz
+    idx = np.concatenate([np.random.default_rng(12).integers(0, N, 2048), [0, N - 1]])
+    E = O.unit_offsets(lat)
+    q = E.shape[0]
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    ups = np.stack([((x - E[j, 0]) % nx) + nx * (((y - E[j, 1]) % ny) + ny * ((z - E[j, 2]) % nz))
+                    for j in range(q)])                      # (q, S) upstream node of population j
+    flat = ups.reshape(-1)
+    fin = f1[:, torch.as_tensor(flat, device=f1.device)].cpu().numpy()
+    got = f2[:, torch.as_tensor(idx, device=f2.device)].cpu().numpy()
+    dom.close()
+    sub = dict(prm, n=(flat.size, 1, 1))
+    fstar = O.Model(sub).collide(fin)                        # (q, q S)
+    S = idx.size
+    expect = np.stack([fstar[j, j * S:(j + 1) * S] for j in range(q)])
+    err = np.abs(got - expect).max() / np.abs(expect).max()
+    say(f"   launch cap {cap} flags {flags}: sampled max rel err {err:.2e}")
+    assert err < tol
+
+
 def test_ncde_2048x1024_one_step_sampled(rmrt):
     say("[ncde 2048x1024 sampled] f32dev")
     nx, ny, dx, dy = 2048, 1024, 1.0, 0.5
