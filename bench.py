@@ -169,8 +169,27 @@ def cpu_baseline():
                                 "sample": f"the same case, {s1} steps ({d1:.1f} s)"}
     except ImportError:
         pass
+    rec["host_cpu"] = host_cpu()
     r_o, u_o = m.macroscopic(f)
     return rec, dict(prm=prm, rho=rho, u=u, steps=steps, rho_o=r_o, u_o=u_o)
+
+
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"model": model, "cores_available": avail}
 
 
 def accuracy_vs_oracle(torch, R, ref):
