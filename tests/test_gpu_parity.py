@@ -394,21 +394,30 @@ def test_q19_256x256x128_one_step_sampled(rmrt, storage, tol):
     assert err < tol
 
 
-@pytest.mark.parametrize("lat,storage,tol", [("Q19", "f32dev", 1e-7), ("Q19", "f16dev", 5e-5), ("Q27", "f32dev", 1e-7)])
+@pytest.mark.parametrize("lat,storage,tol", [("Q19", "f32dev", 1e-7), ("Q19", "f16dev", 5e-5), ("Q27", "f32dev", 1e-7),
+                                             ("Q9", "f32dev", 1e-7)])
 def test_full_size_odd_phase_sampled(rmrt, lat, storage, tol):
-    """256 x 256 x 128, dz = 2 dx, the benchmark's default launch (AA, alternating tile
-    order, buffer addressing): the second step, the odd AA phase, at full size.  The
-    GPU's own state after the first step is the input: the oracle collides it at the
-    upstream nodes of 2048 sampled outputs (plus both ends), and the second step must
-    have pulled exactly those values.  Taylor-Green fields with seeded density noise, so
-    that neighbouring nodes differ.  With the GPU's own input the only difference is one
-    collision in working precision and one store: 3e-9 (FP32) and 4e-6 (FP16) of
-    max |f| observed."""
-    say(f"[{lat} 256x256x128 odd phase sampled] {storage}")
-    n, dx = (256, 256, 128), (1.0, 1.0, 2.0)
-    prm = dict(lattice=lat, n=n, dx=dx, nu=0.005, cs2=1.0 / 3.0)
-    rho, u, _ = taylor_green_3d(n, dx, 0.02, 1.0 / 3.0)
-    rho = rho + 1e-4 * np.random.default_rng(11).uniform(-1, 1, rho.size)
+    """The second step, the odd AA phase, at full size in the benchmark's default launch
+    (alternating tile order, buffer addressing): rD3Q19 / rD3Q27 Taylor-Green at
+    256 x 256 x 128 with dz = 2 dx, and the rD2Q9 NCDE Gaussian hill at 2048 x 1024 with
+    dy = dx / 2, each with seeded noise so that neighbouring nodes differ.  The GPU's own
+    state after the first step is the input: the oracle collides it at the upstream nodes
+    of 2048 sampled outputs (plus both ends), and the second step must have pulled exactly
+    those values.  With the GPU's own input the only difference is one collision in
+    working precision and one store: 3e-9 (FP32) and 4e-6 (FP16) of max |f| observed."""
+    rng = np.random.default_rng(11)
+    if lat == "Q9":
+        n, dx = (2048, 1024, 1), (1.0, 0.5, 1.0)
+        prm = dict(lattice="Q9", equation="NCDE", n=n, dx=dx, D0=0.01, D2=1.0, adv=(0.05, 0.02, 0.0), rho0=0.0)
+        rho = gaussian_hill_field(n[0], n[1], dx[0], dx[1], 40.0, 1024.0, 256.0)
+        rho = rho + 1e-4 * rng.uniform(-1, 1, rho.size)
+        u = None
+    else:
+        n, dx = (256, 256, 128), (1.0, 1.0, 2.0)
+        prm = dict(lattice=lat, n=n, dx=dx, nu=0.005, cs2=1.0 / 3.0)
+        rho, u, _ = taylor_green_3d(n, dx, 0.02, 1.0 / 3.0)
+        rho = rho + 1e-4 * rng.uniform(-1, 1, rho.size)
+    say(f"[{lat} {n} odd phase sampled] {storage}")
     dom = rmrt.Domain(rmrt.make_params(**prm, storage=storage, pattern="AA"), rho, u)
     cap, flags = dom.get_launch()
     assert flags & rmrt.LAUNCH_ALTERNATE_ORDER and flags & rmrt.LAUNCH_BUFFER_OFFSETS
@@ -421,8 +430,10 @@ def test_full_size_odd_phase_sampled(rmrt, lat, storage, tol):
     idx = np.concatenate([np.random.default_rng(12).integers(0, N, 2048), [0, N - 1]])
     E = O.unit_offsets(lat)
     q = E.shape[0]
+    E3 = np.zeros((q, 3), dtype=np.int64)
+    E3[:, : E.shape[1]] = E
     x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
-    ups = np.stack([((x - E[j, 0]) % nx) + nx * (((y - E[j, 1]) % ny) + ny * ((z - E[j, 2]) % nz))
+    ups = np.stack([((x - E3[j, 0]) % nx) + nx * (((y - E3[j, 1]) % ny) + ny * ((z - E3[j, 2]) % nz))
                     for j in range(q)])                      # (q, S) upstream node of population j
     flat = ups.reshape(-1)
     fin = f1[:, torch.as_tensor(flat, device=f1.device)].cpu().numpy()
