@@ -354,7 +354,8 @@ int rmrt_batch_autotune(rmrt_batch* b, int steps, void* stream, int* chosen);
  * results are bitwise those of stepping all domains together.  bytes = 0 (the
  * default): one group, one launch per step for the whole batch; otherwise one
  * launch per group and step.  rmrt_batch_get_group_bytes returns the setting
- * and the number of groups.
+ * and the number of groups (either pointer may be NULL).  RMRT_EINVAL for a
+ * NULL batch.  Changing the setting drops the batch's cached graphs.
  */
 int rmrt_batch_set_group_bytes(rmrt_batch* b, size_t bytes);
 int rmrt_batch_get_group_bytes(const rmrt_batch* b, size_t* bytes, int* ngroups);

@@ -594,11 +594,21 @@ int ctx_alloc_scratch(rmrt_ctx* c) {
   return RMRT_OK;
 }
 
+// Destroy cached graph executables.  A graph launched by an earlier call may
+// still run on some stream, so the device is drained first (graphs are dropped
+// only on a launch-shape change, a cache eviction or a release).
+template <class Map>
+void drop_graphs(Map& graphs) {
+  if (graphs.empty()) return;
+  (void)hipDeviceSynchronize();
+  for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  graphs.clear();
+}
+
 // Release paths ignore the runtime's return codes: there is nothing left to
 // recover and the first error has already been reported.
 void ctx_release(rmrt_ctx* c) {
-  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-  c->graphs.clear();
+  drop_graphs(c->graphs);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   if (c->partials) (void)hipFree(c->partials);
   if (c->dres) (void)hipFree(c->dres);
@@ -689,10 +699,7 @@ int run_graph(rmrt_ctx* c, int n, hipStream_t s) {
     e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(RMRT_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    if (c->graphs.size() >= 16) {
-      for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-      c->graphs.clear();
-    }
+    if (c->graphs.size() >= 16) drop_graphs(c->graphs);
     it = c->graphs.emplace(key, ge).first;
   }
   HIP_TRY(hipGraphLaunch(it->second, s));
@@ -1038,8 +1045,7 @@ int rmrt_set_launch(rmrt_ctx* c, int blocks_per_cu, int flags) {
     return fail(RMRT_EINVAL, "a residency cap of 1 workgroup per CU is not supported (use >= 2)");
   c->blocks_per_cu = blocks_per_cu;
   c->flags = (uint32_t)flags;
-  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-  c->graphs.clear();
+  drop_graphs(c->graphs);
   return RMRT_OK;
 }
 
@@ -1167,8 +1173,7 @@ void batch_make_groups(rmrt_batch* b) {
     bytes += db;
   }
   if (count > 0) b->groups.emplace_back(first, count);
-  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
-  b->graphs.clear();
+  drop_graphs(b->graphs);
 }
 
 int batch_build_tiles(rmrt_batch* b, int cfg, hipStream_t s) {
@@ -1253,10 +1258,7 @@ int batch_graph(rmrt_batch* b, int n, hipStream_t s) {
     e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(RMRT_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    if (b->graphs.size() >= 16) {
-      for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
-      b->graphs.clear();
-    }
+    if (b->graphs.size() >= 16) drop_graphs(b->graphs);
     it = b->graphs.emplace(key, ge).first;
   }
   HIP_TRY(hipGraphLaunch(it->second, s));
@@ -1283,8 +1285,7 @@ int batch_step_impl(rmrt_batch* b, int nsteps, hipStream_t s) {
 }
 
 void batch_release(rmrt_batch* b) {
-  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
-  b->graphs.clear();
+  drop_graphs(b->graphs);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   for (auto* c : b->ctxs) {
     if (!c) continue;

@@ -158,6 +158,32 @@ def test_graph_replays_match_single_steps(rmrt, case, pattern, storage):
 
 
 @pytest.mark.parametrize("pattern", ["AB", "AA"])
+def test_graph_cache_eviction_mid_flight(rmrt, pattern):
+    """More distinct step counts than the graph cache holds, issued back to back
+    with no host synchronisation, so that cached graphs are dropped while earlier
+    ones may still run; then a launch-shape change, which drops them again.  The
+    result must be the bits of eager single steps."""
+    _, g, _, _, _ = _build("q19_channel_force", rmrt, "f32dev", pattern)
+    _, e, _, _, _ = _build("q19_channel_force", rmrt, "f32dev", pattern)
+    total = 0
+    for n in list(range(2, 22)) + [2, 3]:
+        g.step(n)
+        total += n
+    cap, flags = g.get_launch()
+    g.set_launch(0 if cap else 3, flags)
+    g.step(7)
+    total += 7
+    for _ in range(total):
+        e.step(1)
+    torch.cuda.synchronize()
+    assert g.steps_taken() == e.steps_taken() == total
+    assert np.array_equal(g.populations().cpu().numpy(), e.populations().cpu().numpy())
+    say(f"[graph eviction] {pattern}: {total} steps bitwise")
+    g.close()
+    e.close()
+
+
+@pytest.mark.parametrize("pattern", ["AB", "AA"])
 @pytest.mark.parametrize("case", list(CASES))
 def test_two_nodes_per_thread_is_bitwise_identical(rmrt, case, pattern):
     """The paired-node launch (both nodes read before either collides, ragged
