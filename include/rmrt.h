@@ -314,7 +314,8 @@ int rmrt_get_launch(const rmrt_ctx* ctx, int* blocks_per_cu, int* flags);
  */
 int rmrt_tune(rmrt_ctx* ctx, int steps, void* stream, int* blocks_per_cu);
 
-/* Release the context (does not free the caller's buffers). */
+/* Release the context (does not free the caller's buffers).  Waits for the
+ * device's outstanding work first, since it may still use the context. */
 int rmrt_free(rmrt_ctx* ctx);
 
 /*
@@ -385,6 +386,8 @@ int rmrt_batch_step(rmrt_batch* b, int nsteps, void* stream);
  */
 int rmrt_batch_residual(rmrt_batch* b, double* r, void* stream);
 
+/* Release the batch and its domain contexts (not the caller's buffers); waits
+ * for the device's outstanding work first. */
 int rmrt_batch_free(rmrt_batch* b);
 
 /* ===========================================================================

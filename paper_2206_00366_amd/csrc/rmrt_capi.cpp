@@ -608,6 +608,7 @@ void drop_graphs(Map& graphs) {
 // Release paths ignore the runtime's return codes: there is nothing left to
 // recover and the first error has already been reported.
 void ctx_release(rmrt_ctx* c) {
+  (void)hipDeviceSynchronize();  // work issued on any stream may still use the buffers
   drop_graphs(c->graphs);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   if (c->partials) (void)hipFree(c->partials);
@@ -1191,7 +1192,8 @@ int batch_build_tiles(rmrt_batch* b, int cfg, hipStream_t s) {
     }
   }
   if (b->dtiles) {
-    HIP_TRY(hipStreamSynchronize(s));
+    // a step launched earlier on any stream may still read the old tile list
+    HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipFree(b->dtiles));
     b->dtiles = nullptr;
   }
@@ -1285,6 +1287,7 @@ int batch_step_impl(rmrt_batch* b, int nsteps, hipStream_t s) {
 }
 
 void batch_release(rmrt_batch* b) {
+  (void)hipDeviceSynchronize();  // work issued on any stream may still use the buffers
   drop_graphs(b->graphs);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   for (auto* c : b->ctxs) {
