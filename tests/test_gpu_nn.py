@@ -59,6 +59,33 @@ def test_conv_forward_matches_oracle(R, cin, cout, dil, shape):
     assert np.abs(host(a) - silu).max() <= 2.0**-7 * np.abs(silu).max() + 1e-6
 
 
+@pytest.mark.parametrize("cin,cout,dil", [(16, 32, 1), (32, 32, 2), (32, 32, 4), (32, 16, 8)])
+def test_conv_at_the_surrogate_shape(R, cin, cout, dil):
+    """The four layers of the warm-start network at the shape it runs at: batches of
+    16 images of 64 x 128 coarse cells (obstacle channels of 512 x 256 nodes coarsened
+    4x).  Forward and weight gradient against the oracle on the whole output."""
+    say(f"[nn surrogate shape] cin={cin} cout={cout} dil={dil}")
+    B, H, W = 16, 64, 128
+    rng = np.random.default_rng(31 * dil + cin)
+    x = C.to_bf16(rng.standard_normal((B, H, W, cin)))
+    w = C.to_bf16(rng.standard_normal((cout, 3, 3, cin)) / np.sqrt(9 * cin))
+    b = rng.standard_normal(cout).astype(np.float32).astype(np.float64)
+    y_or = C.conv_forward(x, w, b, dil)
+    y = torch.empty((B, H, W, cout), dtype=torch.float32, device="cuda")
+    a = torch.empty((B, H, W, cout), dtype=torch.bfloat16, device="cuda")
+    R.nn_conv_forward(bf16_dev(x), bf16_dev(w), f32_dev(b), y, a, None, dil, R.NN_EPI_SILU)
+    assert np.abs(host(y) - y_or).max() < 1e-5 * np.abs(y_or).max()
+    dy = C.to_bf16(rng.standard_normal((B, H, W, cout)))
+    dW_or, db_or = C.conv_backward_weight(x, dy, dil)
+    dW = torch.empty((cout, 3, 3, cin), dtype=torch.float32, device="cuda")
+    db = torch.empty(cout, dtype=torch.float32, device="cuda")
+    scr = torch.empty(R.nn_wgrad_scratch_floats(B, H, W, cin, cout), dtype=torch.float32, device="cuda")
+    R.nn_conv_backward_weight(bf16_dev(x), bf16_dev(dy), dil, dW, db, scr)
+    # sums of B H W = 131072 bf16 products: fp32 accumulation in another order
+    assert np.abs(host(dW) - dW_or).max() < 1e-5 * np.abs(dW_or).max() + 1e-4
+    assert np.abs(host(db) - db_or).max() < 1e-5 * np.abs(db_or).max() + 1e-4
+
+
 @pytest.mark.parametrize("cin,cout,dil", [(32, 32, 4), (16, 32, 1), (32, 16, 2)])
 def test_backward_data_with_silu_grad(R, cin, cout, dil):
     say(f"[nn bwd data] cin={cin} cout={cout} dil={dil}")
