@@ -76,8 +76,10 @@ enum { RMRT_OUT_F64 = 0, RMRT_OUT_F32 = 1 };                       /* macroscopi
 #define RMRT_WALL_ZP 32u
 
 /*
- * Parameters of one rectangular domain.  Zero or negative values of the
- * "default" fields select the documented defaults.
+ * Parameters of one rectangular domain.  The notes below give, per field, the
+ * values that select its documented default: dt, cs2 and s_hi take theirs at
+ * zero, nu_b and w_corner only when negative (a zero bulk viscosity is
+ * rejected, a zero corner weight is valid).
  *
  *   lattice, equation, storage, pattern : enumerations above (FP16
  *             deviation storage needs every weight > 0)

@@ -52,7 +52,28 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")
+    build_examples(verbose)
     return LIB
+
+
+EXAMPLES = os.path.join(HERE, "examples")
+
+
+def build_examples(verbose: bool = True) -> None:
+    """Plain-C programs that use the C ABI of librmrt.so (host code, gcc)."""
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    for src in sorted(f for f in os.listdir(EXAMPLES) if f.endswith(".c")):
+        exe = os.path.join(EXAMPLES, src[:-2])
+        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+               "-I", os.path.join(HERE, "..", "include"), "-I", os.path.join(rocm, "include"),
+               os.path.join(EXAMPLES, src), "-o", exe, "-L", HERE, "-lrmrt",
+               "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-lm",
+               "-Wl,-rpath,$ORIGIN/..", "-Wl,-rpath," + os.path.join(rocm, "lib")]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"gcc failed for {src}:\n{res.stderr[-4000:]}")
+        if verbose:
+            print(f"built {exe}")
 
 
 if __name__ == "__main__":
