@@ -229,10 +229,10 @@ def test_batch_with_solid_masks_matches_oracle(rmrt, pattern):
         fields.append((rho, u))
         solids.append(None if sol is None else sol.astype(np.uint8))
         refs.append(m.step(m.init(rho, u), 21))
-    configs = rmrt.Batch.configs()
-    picks = [0, next(i for i, c in enumerate(configs) if c[3]), next(i for i, c in enumerate(configs) if c[4] == 2)]
+    shapes = rmrt.Batch.configs()
+    picks = [0, next(i for i, c in enumerate(shapes) if c[3]), next(i for i, c in enumerate(shapes) if c[4] == 2)]
     for cfg in picks:
-        say(f"[batch f64 solids] {pattern} config {cfg} {configs[cfg]}")
+        say(f"[batch f64 solids] {pattern} tile shape {cfg} {shapes[cfg]}")
         b = rmrt.Batch([rmrt.make_params(**p, storage="f64", pattern=pattern) for p, _ in SOLID_MIX], solids=solids)
         b.set_config(cfg)
         for k, (rho, u) in enumerate(fields):
@@ -288,8 +288,8 @@ def test_domain_groups_are_bitwise_identical(rmrt, small_oracle, pattern, storag
     oracle."""
     nbytes = [rmrt.population_bytes(rmrt.make_params(**p, storage=storage, pattern=pattern))
               * (2 if pattern == "AB" else 1) for p in SMALL]
-    configs = rmrt.Batch.configs()
-    persistent = next(i for i, c in enumerate(configs) if c[3])
+    shapes = rmrt.Batch.configs()
+    persistent = next(i for i, c in enumerate(shapes) if c[3])
     for cfg in (0, persistent):
         out = {}
         for gb in (0, 1, max(nbytes[0], nbytes[1]) + min(nbytes)):
