@@ -1,0 +1,104 @@
+"""Seeded sweep of random parameter sets through the C ABI against the FP64
+oracle: lattice (rD2Q9 / rD3Q19 / rD3Q27), equation (NSE / NCDE), ragged grid
+sizes, grid spacings, c_s^2, viscosities, higher-order rate, wall pairs, random
+solid nodes, body force and mass source, He-Luo equilibrium, viscosity tensors,
+the NCDE variants, AA or AB pattern, odd and even step counts.  FP64 storage:
+every fluid population within 1e-12 of max |f|.  Draws that the library rejects
+as invalid (rmrt_derive) are redrawn."""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_util import WALLS, random_fields, rel_err
+from oracle import rmrt_oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NCASES = 48
+
+
+@pytest.fixture(scope="module")
+def rmrt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_00366_amd import rmrt as R
+    return R
+
+
+def _draw(rng):
+    lat = str(rng.choice(["Q9", "Q19", "Q27"]))
+    d = 2 if lat == "Q9" else 3
+    nse = rng.random() < 0.7
+    n = [int(rng.integers(3, 14)) for _ in range(d)] + ([1] if d == 2 else [])
+    dx = [1.0] + [float(rng.choice([0.5, 1.0, 2.0])) for _ in range(d - 1)] + ([1.0] if d == 2 else [])
+    prm = dict(lattice=lat, equation="NSE" if nse else "NCDE", n=tuple(n), dx=tuple(dx))
+    if rng.random() < 0.3:
+        prm["cs2"] = float(rng.uniform(0.15, 0.33)) * min(v * v for v in dx[:d])
+    if rng.random() < 0.4:
+        prm["s_hi"] = float(rng.uniform(0.8, 1.7))
+    axes = [a for a in range(d) if rng.random() < 0.35]
+    prm["wall_faces"] = sum((3 << (2 * a)) for a in axes)
+    if nse:
+        prm["nu"] = float(rng.uniform(0.01, 0.1))
+        if rng.random() < 0.5:
+            prm["nu_b"] = float(rng.uniform(0.01, 0.2))
+        if rng.random() < 0.5:
+            prm["force"] = tuple(float(v) for v in rng.uniform(-2e-5, 2e-5, 3) * ([1, 1, 1] if d == 3 else [1, 1, 0]))
+        if rng.random() < 0.25:
+            prm["source"] = float(rng.choice([-1.0, 1.0]) * 1e-6)
+        if rng.random() < 0.2:
+            prm["incompressible"] = True
+        if rng.random() < 0.2:
+            prm["nu_tensor"] = tuple(float(v) for v in rng.uniform(0.01, 0.1, 6))
+    else:
+        prm["D0"] = float(rng.uniform(0.01, 0.1))
+        prm["D2"] = float(rng.choice([0.0, rng.uniform(0.0, 1.0)]))
+        prm["adv"] = tuple(float(v) for v in rng.uniform(-0.05, 0.05, 3) * ([1, 1, 1] if d == 3 else [1, 1, 0]))
+        prm["rho0"] = 0.0
+        if rng.random() < 0.4:
+            prm["source"] = float(rng.uniform(-1e-3, 1e-3))
+        variant = rng.random()
+        if variant < 0.2:
+            prm["gamma0"] = True
+        elif variant < 0.35:
+            prm["diffusive"] = True
+    N = int(np.prod(n))
+    solid = (rng.random(N) < 0.08) if rng.random() < 0.3 else None
+    pattern = str(rng.choice(["AA", "AB"]))
+    steps = int(rng.integers(5, 16))
+    return prm, solid, pattern, steps
+
+
+def _valid(R, prm):
+    try:
+        R.derive(R.make_params(**prm))
+        return True
+    except R.RMRTError:
+        return False
+
+
+@pytest.mark.parametrize("k", range(NCASES))
+def test_random_configuration_matches_oracle(rmrt, k):
+    rng = np.random.default_rng(1000 + k)
+    while True:
+        prm, solid, pattern, steps = _draw(rng)
+        if _valid(rmrt, prm):
+            break
+    print(f"[random {k}] {prm} solid={solid is not None} {pattern} {steps} steps", flush=True)
+    sys.stdout.flush()
+    m = O.Model(prm, solid=solid)
+    rho, u = random_fields(m, seed=k, du=0.02 if m.nse else 0.0)
+    if not m.nse:
+        u = None
+    f_or = m.step(m.init(rho, u), steps)
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage="f64", pattern=pattern), rho, u,
+                      solid=None if solid is None else solid.astype(np.uint8))
+    dom.step(steps)
+    g = dom.populations().cpu().numpy()
+    dom.close()
+    fl = m.fluid
+    err = rel_err(g[:, fl], f_or[:, fl])
+    print(f"   max rel |f - f_oracle| = {err:.2e}", flush=True)
+    assert err < 1e-12
