@@ -102,3 +102,35 @@ def test_random_configuration_matches_oracle(rmrt, k):
     err = rel_err(g[:, fl], f_or[:, fl])
     print(f"   max rel |f - f_oracle| = {err:.2e}", flush=True)
     assert err < 1e-12
+
+
+@pytest.mark.parametrize("k", range(0, NCASES, 2))
+def test_random_configuration_fp32_storage(rmrt, k):
+    """The same draws in FP32 deviation storage: rho (or phi) within 1e-5 of rho0
+    (of the peak phi) and u within 1e-5 of its maximum, at every fluid node."""
+    rng = np.random.default_rng(1000 + k)
+    while True:
+        prm, solid, pattern, steps = _draw(rng)
+        if _valid(rmrt, prm):
+            break
+    print(f"[random fp32 {k}] {prm['lattice']} {prm['equation']} {pattern} {steps} steps", flush=True)
+    m = O.Model(prm, solid=solid)
+    rho, u = random_fields(m, seed=k, du=0.02 if m.nse else 0.0)
+    if not m.nse:
+        u = None
+    f_or = m.step(m.init(rho, u), steps)
+    r_o, u_o = m.macroscopic(f_or)
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage="f32dev", pattern=pattern), rho, u,
+                      solid=None if solid is None else solid.astype(np.uint8))
+    dom.step(steps)
+    r_g, u_g = dom.moments()
+    dom.close()
+    fl = m.fluid
+    scale = m.rho0 if m.nse else np.abs(r_o[fl]).max()
+    err_r = np.abs(r_g.cpu().numpy()[fl] - r_o[fl]).max() / scale
+    print(f"   rho/phi err {err_r:.2e}", flush=True)
+    assert err_r < 1e-5
+    if m.nse:
+        err_u = rel_err(u_g.cpu().numpy()[:, fl], u_o[:, fl])
+        print(f"   u err {err_u:.2e}", flush=True)
+        assert err_u < 1e-5
