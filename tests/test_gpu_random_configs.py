@@ -134,3 +134,56 @@ def test_random_configuration_fp32_storage(rmrt, k):
         err_u = rel_err(u_g.cpu().numpy()[:, fl], u_o[:, fl])
         print(f"   u err {err_u:.2e}", flush=True)
         assert err_u < 1e-5
+
+
+def _draw_batch(rng):
+    """3..7 random domains sharing lattice, equation and pattern (what a batch
+    requires); everything else per domain."""
+    lat = str(rng.choice(["Q9", "Q19", "Q27"]))
+    nse = rng.random() < 0.75
+    pattern = str(rng.choice(["AA", "AB"]))
+    doms = []
+    while len(doms) < int(rng.integers(3, 8)):
+        prm, solid, _, _ = _draw(rng)
+        if prm["lattice"] != lat or (prm["equation"] == "NSE") != nse:
+            continue
+        doms.append((prm, solid))
+    return doms, pattern
+
+
+@pytest.mark.parametrize("k", range(12))
+def test_random_batch_matches_oracle(rmrt, k):
+    """Random batches in FP64: every domain within 1e-12 of the oracle after an odd
+    number of steps split over a graph chunk and a single step, in a random tile
+    shape, with or without domain groups."""
+    rng = np.random.default_rng(5000 + k)
+    while True:
+        doms, pattern = _draw_batch(rng)
+        if all(_valid(rmrt, p) for p, _ in doms):
+            break
+    shape = int(rng.integers(0, len(rmrt.Batch.configs())))
+    groups = int(rng.choice([0, 1, 20000]))
+    print(f"[random batch {k}] {len(doms)} x {doms[0][0]['lattice']} {doms[0][0]['equation']} {pattern} "
+          f"tile shape {shape} group bytes {groups}", flush=True)
+    models, fields, refs = [], [], []
+    for j, (prm, solid) in enumerate(doms):
+        m = O.Model(prm, solid=solid)
+        rho, u = random_fields(m, seed=100 * k + j, du=0.02 if m.nse else 0.0)
+        if not m.nse:
+            u = None
+        models.append(m)
+        fields.append((rho, u))
+        refs.append(m.step(m.init(rho, u), 13))
+    b = rmrt.Batch([rmrt.make_params(**p, storage="f64", pattern=pattern) for p, _ in doms],
+                   solids=[None if s is None else s.astype(np.uint8) for _, s in doms])
+    b.set_config(shape)
+    b.set_group_bytes(groups)
+    for d, (rho, u) in zip(b.domains, fields):
+        d.set_fields(rho, u)
+    b.step(12)
+    b.step(1)
+    for j, (d, m, f_or) in enumerate(zip(b.domains, models, refs)):
+        g = d.populations().cpu().numpy()
+        err = rel_err(g[:, m.fluid], f_or[:, m.fluid])
+        assert err < 1e-12, (j, err)
+    b.close()
