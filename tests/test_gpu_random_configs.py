@@ -187,3 +187,51 @@ def test_random_batch_matches_oracle(rmrt, k):
         err = rel_err(g[:, m.fluid], f_or[:, m.fluid])
         assert err < 1e-12, (j, err)
     b.close()
+
+
+def _draw_reduced(rng):
+    lat = str(rng.choice(["Q5", "Q7"]))
+    d = 2 if lat == "Q5" else 3
+    n = [int(rng.integers(3, 16)) for _ in range(d)] + ([1] if d == 2 else [])
+    dx = [1.0] + [float(rng.choice([0.5, 1.0, 2.0])) for _ in range(d - 1)] + ([1.0] if d == 2 else [])
+    prm = dict(lattice=lat, equation="NCDE", n=tuple(n), dx=tuple(dx), rho0=0.0,
+               D0=float(rng.uniform(0.01, 0.1)), D2=float(rng.choice([0.0, rng.uniform(0.0, 1.0)])),
+               adv=tuple(float(v) for v in rng.uniform(-0.05, 0.05, 3) * ([1, 1, 1] if d == 3 else [1, 1, 0])))
+    if rng.random() < 0.3:
+        prm["cs2"] = float(rng.uniform(0.15, 0.33)) * min(v * v for v in dx[:d])
+    if rng.random() < 0.3:
+        prm["s_hi"] = float(rng.uniform(0.8, 1.7))
+    if rng.random() < 0.5:
+        prm["source"] = float(rng.uniform(-1e-3, 1e-3))
+    variant = rng.random()
+    if variant < 0.2:
+        prm["gamma0"] = True
+    elif variant < 0.35:
+        prm["diffusive"] = True
+    prm["wall_faces"] = sum((3 << (2 * a)) for a in range(d) if rng.random() < 0.35)
+    N = int(np.prod(n))
+    solid = (rng.random(N) < 0.08) if rng.random() < 0.3 else None
+    return prm, solid, str(rng.choice(["AA", "AB"])), int(rng.integers(5, 16))
+
+
+@pytest.mark.parametrize("k", range(16))
+def test_random_reduced_lattice_matches_oracle(rmrt, k):
+    """Random rD2Q5 / rD3Q7 NCDE parameter sets (with the previous-step phi that
+    the library keeps): FP64 populations within 1e-12 of max |f|."""
+    rng = np.random.default_rng(7000 + k)
+    while True:
+        prm, solid, pattern, steps = _draw_reduced(rng)
+        if _valid(rmrt, prm):
+            break
+    print(f"[random reduced {k}] {prm} solid={solid is not None} {pattern} {steps} steps", flush=True)
+    m = O.Model(prm, solid=solid)
+    phi, _ = random_fields(m, seed=k, du=0.0)
+    f_or, _ = m.step(m.init(phi, None), steps, m.init_history(phi))
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage="f64", pattern=pattern), phi, None,
+                      solid=None if solid is None else solid.astype(np.uint8))
+    dom.step(steps)
+    g = dom.populations().cpu().numpy()
+    dom.close()
+    err = rel_err(g[:, m.fluid], f_or[:, m.fluid])
+    print(f"   max rel |f - f_oracle| = {err:.2e}", flush=True)
+    assert err < 1e-12
