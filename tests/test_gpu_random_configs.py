@@ -235,3 +235,39 @@ def test_random_reduced_lattice_matches_oracle(rmrt, k):
     err = rel_err(g[:, m.fluid], f_or[:, m.fluid])
     print(f"   max rel |f - f_oracle| = {err:.2e}", flush=True)
     assert err < 1e-12
+
+
+@pytest.mark.parametrize("k", range(0, NCASES, 3))
+def test_random_configuration_local_outputs(rmrt, k):
+    """Local outputs (strain rate and stress for the NSE, grad phi for the NCDE) of
+    the random draws after their steps, FP64 storage, against the oracle's formulas
+    on its own state: within 1e-11 of the output's magnitude; zero at solid nodes."""
+    rng = np.random.default_rng(1000 + k)
+    while True:
+        prm, solid, pattern, steps = _draw(rng)
+        if _valid(rmrt, prm):
+            break
+    print(f"[random local {k}] {prm['lattice']} {prm['equation']} {pattern} {steps} steps", flush=True)
+    m = O.Model(prm, solid=solid)
+    rho, u = random_fields(m, seed=k, du=0.02 if m.nse else 0.0)
+    if not m.nse:
+        u = None
+    f_or = m.step(m.init(rho, u), steps)
+    dom = rmrt.Domain(rmrt.make_params(**prm, storage="f64", pattern=pattern), rho, u,
+                      solid=None if solid is None else solid.astype(np.uint8))
+    dom.step(steps)
+    fl = m.fluid
+    if m.nse:
+        tau, E = m.local_gradients(f_or[:, fl])
+        pairs = [(a, a) for a in range(m.d)] + [(a, b) for a in range(m.d) for b in range(a + 1, m.d)]
+        refs = {rmrt.GRAD_STRAIN: np.stack([E[a, b] for a, b in pairs]),
+                rmrt.GRAD_STRESS: np.stack([tau[a, b] for a, b in pairs])}
+    else:
+        refs = {rmrt.GRAD_PHI: m.local_gradients(f_or[:, fl])}
+    for kind, ref in refs.items():
+        got = dom.local_gradients(kind).cpu().numpy()
+        err = np.abs(got[:, fl] - ref).max() / np.abs(ref).max()
+        print(f"   kind {kind}: max rel err {err:.2e}", flush=True)
+        assert err < 1e-11
+        assert np.all(got[:, ~fl] == 0.0)
+    dom.close()
