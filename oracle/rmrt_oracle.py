@@ -13,11 +13,11 @@ time step is eq. 2-2-3 followed by propagation (eq. 2-2, second line).
 Arrays: populations have shape (q, N) with N = nx*ny*nz nodes in x-fastest
 order (node index = x + nx*(y + ny*z)); all arithmetic is float64.
 
-Parity unpinned: the nonlinear diffusivity D(phi) = D0 (1 + D2 phi^2) of the
-NCDE (eq. 4-10 with reading A14) has no closed-form solution; beyond this file
-it is pinned only by exact phi conservation and its D2 -> 0 limit (the
-constant-D Gaussian hill).  Every other part is pinned by the tests listed in
-the design notes.
+Every part is pinned by tests that check it against something other than
+this file (closed forms, printed values, invariants, limits), listed in the
+design notes.  The nonlinear diffusivity D(phi) = D0 (1 + D2 phi^2) of the
+NCDE (eq. 4-10 with reading A14) is pinned by the linearised decay of a small
+mode on uniform backgrounds, whose rate is D(phibar) |k|^2 (eq. 4-15).
 
 Readings of the paper where it is silent or garbled (kept in one place so the
 GPU side can take the same ones; numbering as in the design notes):

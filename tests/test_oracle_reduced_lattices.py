@@ -139,8 +139,9 @@ def test_dropping_g_leaves_the_uu_diffusion_error():
 
 
 def test_nonlinear_diffusivity_conserves_mass():
-    """D(phi) = D0 (1 + D2 phi^2): parity beyond the oracle is unpinned; the
-    total phi is conserved without a source and grows by N dt S with one."""
+    """D(phi) = D0 (1 + D2 phi^2) (its phi dependence is pinned by the linearised
+    decay in test_oracle_nonlinear_diffusion.py): the total phi is conserved
+    without a source and grows by N dt S with one."""
     for S in (0.0, 1e-4):
         m = _model("Q5", n=(20, 16, 1), dx=(1.0, 0.5, 1.0), D0=0.02, D2=2.0, adv=(0.03, -0.02, 0.0), source=S)
         phi = 0.5 + 0.3 * np.random.default_rng(9).random(m.N)
