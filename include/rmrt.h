@@ -266,6 +266,26 @@ int rmrt_step_local(rmrt_ctx* ctx, int kind, void* out, int out_dtype, void* str
 int rmrt_reduce(rmrt_ctx* ctx, double out[4], void* stream);
 
 /*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the sums of rmrt_reduce
+ * (same kernels, same summation order, same values) written to out[0..3],
+ * caller-owned DEVICE memory (4 doubles), asynchronously on stream, with no
+ * host synchronisation, no allocation and no memset, so the call can be
+ * captured into a graph.  The block partial sums live in one fixed file-scope
+ * device array of the library (2048 x 5 doubles = 80 KiB per GPU, held until
+ * the process ends); the reduction launches at most 2048 workgroups whatever
+ * the domain size, and RMRT_EINVAL reports a launch that would need more.
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (concurrent streams, or host threads) race and must be serialised by the
+ * caller; consecutive calls on one stream are safe.  Like every captured
+ * launch of this library, a captured call reads the state in the layout of
+ * the step count at capture time (the AA parity).  Finiteness is not
+ * checked (the host never sees the values); RMRT_EINVAL for a NULL argument,
+ * RMRT_EHIP if the array's device address cannot be obtained.
+ */
+int rmrt_reduce_noalloc(rmrt_ctx* ctx, double* out, void* stream);
+
+/*
  * Steady-state residual r = ||u^n - u^prev||_2 / ||u^n||_2 (FP64, fluid nodes)
  * against the velocity stored by the previous call on this context; the first
  * call stores u and returns r = +inf.  Synchronises stream.

@@ -11,6 +11,26 @@ hipError_t launch_reduce_final(const double* partials, uint32_t nb, double* out,
   return hipGetLastError();
 }
 
+// The mass and momentum of k_reduce's partials [sum rho', sum j, fluid count]:
+// out = [count rho0 + sum rho', sum j_x, sum j_y, sum j_z], the values the host
+// forms from k_reduce_final's sums (the product and the sum rounded separately).
+__global__ void k_reduce_final_mass(const double* __restrict__ partials, uint32_t nb, double rho0, double* out) {
+  double res[5];
+  sum_partials<5>(partials, nb, res);
+  if (threadIdx.x == 0) {
+#pragma clang fp contract(off)
+    out[0] = res[4] * rho0 + res[0];
+    out[1] = res[1];
+    out[2] = res[2];
+    out[3] = res[3];
+  }
+}
+
+hipError_t launch_reduce_final_mass(const double* partials, uint32_t nb, double rho0, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_final_mass, dim3(1), dim3(256), 0, s, partials, nb, rho0, out);
+  return hipGetLastError();
+}
+
 }  // namespace rmrt
 
 namespace rmrt {

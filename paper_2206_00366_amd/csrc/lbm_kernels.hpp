@@ -901,9 +901,10 @@ __global__ void __launch_bounds__(256)
   block_reduce_store<2>(acc, partials);
 }
 
-// sums nb x K partials in a fixed order (deterministic)
+// Sum of nb x K partials in a fixed order (deterministic); the result is
+// valid in thread 0 of a single 256-thread workgroup.
 template <int K>
-__global__ void k_reduce_final(const double* __restrict__ partials, uint32_t nb, double* out) {
+__device__ __forceinline__ void sum_partials(const double* __restrict__ partials, uint32_t nb, double (&res)[K]) {
   __shared__ double sh[K][256];
   double v[K];
   for (int k = 0; k < K; ++k) v[k] = 0.0;
@@ -915,10 +916,19 @@ __global__ void k_reduce_final(const double* __restrict__ partials, uint32_t nb,
     for (int k = 0; k < K; ++k) {
       double s = 0.0;
       for (uint32_t t = 0; t < blockDim.x; ++t) s += sh[k][t];
-      out[k] = s;
+      res[k] = s;
     }
   }
 }
+
+template <int K>
+__global__ void k_reduce_final(const double* __restrict__ partials, uint32_t nb, double* out) {
+  double res[K];
+  sum_partials<K>(partials, nb, res);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < K; ++k) out[k] = res[k];
+}
+
 
 // ----------------------------------------------------------------------------
 // Initialisation: fbar = g_eq(A, B, M) in velocity space (eq. 3-3) with
@@ -1121,6 +1131,7 @@ hipError_t launch_local(const AuxLaunch& a);
 template <int L>
 hipError_t launch_links(const DomainDev* doms, uint32_t dom, void* out, unsigned grid, hipStream_t s);
 hipError_t launch_reduce_final(const double* partials, uint32_t nb, double* out, int K, hipStream_t s);
+hipError_t launch_reduce_final_mass(const double* partials, uint32_t nb, double rho0, double* out, hipStream_t s);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 }  // namespace rmrt

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -507,6 +508,46 @@ constexpr unsigned kMaxAuxGrid = 2048;
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free reduction (rmrt_reduce_noalloc): the block
+// partial sums of k_reduce (5 doubles per workgroup, at most kMaxAuxGrid
+// workgroups: 80 KiB per GPU, held until the process ends).  Host code never
+// passes `scratch` itself to a kernel (in host code it names a host-side
+// stand-in); it passes the device address that hipGetSymbolAddress returns
+// for the GPU, looked up once per device at context creation with that device
+// current.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr uint32_t kNoAllocBlocks = kMaxAuxGrid;
+constexpr size_t kNoAllocDoubles = (size_t)kNoAllocBlocks * 5;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (the current device), looked up on
+// the first call for that device and cached.
+int noalloc_scratch(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(RMRT_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      g_scratch_err[dev] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+      return fail(RMRT_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(g_scratch_err[dev]));
+    }
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RMRT_OK;
+}
+static_assert(kMaxAuxGrid <= kNoAllocBlocks, "the reduction grid must fit the scratch");
+}  // namespace
+
 // shared error channel for the surrogate kernels' ABI (nn_capi.cpp)
 int rmrt_set_error_(int code, const char* msg) {
   g_last_error = msg;
@@ -538,6 +579,7 @@ struct rmrt_ctx {
   int step_bc = 0;             // 0 periodic, 1 walls from coordinates, 2 link bits
   int blocks_per_cu = kDefaultBlocksPerCU;  // resident workgroups per CU (0: hardware limit)
   uint32_t flags = kDefaultFlags;
+  int device = 0;              // the device current at creation
 };
 
 namespace {
@@ -843,6 +885,13 @@ static int ctx_create(rmrt_ctx** out, const rmrt_params* p, void* f0, void* f1, 
     c->hdom.hist = c->hist;
   }
   c->cus = device_cus();
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
+  {
+    // set-up of the allocation-free reduction's scratch on this device; a
+    // failure here is reported by rmrt_reduce_noalloc, the only user
+    double* unused = nullptr;
+    if (noalloc_scratch(c->device, &unused) != RMRT_OK) g_last_error.clear();
+  }
   default_launch(*p, c->blocks_per_cu, c->flags);
   c->step_bc = c->hdom.walls != 0 ? 1 : 0;
   if (c->hdom.has_solid) {
@@ -1003,6 +1052,24 @@ int rmrt_populations(rmrt_ctx* c, double* f_out, void* stream) {
 int rmrt_reduce(rmrt_ctx* c, double out[4], void* stream) {
   if (!c || !out) return fail(RMRT_EINVAL, "ctx or out is NULL");
   return reduce_impl(c, out, (hipStream_t)stream);
+}
+
+int rmrt_reduce_noalloc(rmrt_ctx* c, double* out, void* stream) {
+  if (!c || !out) return fail(RMRT_EINVAL, "ctx or out is NULL");
+  double* part = nullptr;
+  int rc = noalloc_scratch(c->device, &part);
+  if (rc != RMRT_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  AuxLaunch a = aux_of(c, s);
+  if (a.grid > kNoAllocBlocks)
+    return fail(RMRT_EINVAL, "the reduction needs %u partial blocks; the allocation-free scratch holds %u",
+                a.grid, kNoAllocBlocks);
+  a.out0 = part;
+  hipError_t e = dispatch_reduce(c->p.lattice, c->p.storage, a);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "reduce launch: %s", hipGetErrorString(e));
+  e = launch_reduce_final_mass(part, a.grid, c->p.rho0, out, s);
+  if (e != hipSuccess) return fail(RMRT_EHIP, "reduce final: %s", hipGetErrorString(e));
+  return RMRT_OK;
 }
 
 int rmrt_residual(rmrt_ctx* c, double* r, void* stream) {

@@ -78,6 +78,7 @@ _sig = {
     "rmrt_moments": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
     "rmrt_populations": (C.c_int, [_vp, _vp, _vp]),
     "rmrt_reduce": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
+    "rmrt_reduce_noalloc": (C.c_int, [_vp, _vp, _vp]),
     "rmrt_residual": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
     "rmrt_steps_taken": (C.c_int, [_vp, C.POINTER(C.c_longlong)]),
     "rmrt_set_launch": (C.c_int, [_vp, C.c_int, C.c_int]),
