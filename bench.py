@@ -58,10 +58,14 @@ def sizeof(storage):
     return {"f64": 8, "f32dev": 4, "f16dev": 2}[storage]
 
 
-def timed_steps(torch, step_fn, steps, warmup):
+def timed_steps(torch, step_fn, steps, warmup, prepare=None):
     """Warm up, then time exactly `steps` steps: wall clock between two
-    synchronisations and HIP events on the current stream (where the kernels run)."""
+    synchronisations and HIP events on the current stream (where the kernels run).
+    prepare(steps), when given, captures the HIP graphs of the timed call before
+    the clock starts (graph capture is set-up, not part of a step)."""
     step_fn(warmup)
+    if prepare is not None:
+        prepare(steps)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -75,16 +79,37 @@ def timed_steps(torch, step_fn, steps, warmup):
     return wall, ev_ms
 
 
+def settle(torch, R, seconds=0.3, nbytes=1 << 30):
+    """Keep the GPU busy with plain copies for `seconds`, so that a leg's warm-up
+    starts at the GPU's working clocks.  Measured on MI355X: after 2 s idle the
+    first 50 rD3Q19 256 x 256 x 128 steps take 208-216 us each and the rate
+    reaches 201 us only after about 100 steps; right after a 1 s busy period
+    it is 201 us from the first step (20-step graph: 211.8 against 199.0 us)."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            R.stream_copy(dst, src)
+        torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+
+
 def tg3d_fields(n, dx, U0, cs2):
     from inputs import taylor_green_3d
     rho, u, _ = taylor_green_3d(n, dx, U0, cs2)
     return rho, u
 
 
-def run_single(torch, R, prm, rho, u, steps, warmup, solid=None, launch=None):
+def run_single(torch, R, prm, rho, u, steps, warmup, solid=None, launch=None, settle_s=0.3):
+    """One domain: W warm-up steps, then exactly `steps` timed steps; with
+    settle_s > 0 the GPU is kept busy for that long first (settle())."""
     dom = R.Domain(R.make_params(**prm), rho, u, solid=solid)
     torch.cuda.synchronize()
-    wall, ev_ms = timed_steps(torch, dom.step, steps, warmup)
+    if settle_s > 0:
+        settle(torch, R, settle_s)
+    wall, ev_ms = timed_steps(torch, dom.step, steps, warmup, prepare=dom.prepare)
     red = dom.reduce()
     finite = all(math.isfinite(v) for v in red)
     if launch is not None:
@@ -131,44 +156,48 @@ def copy_ceiling(torch, R, nbytes=2 << 30, reps=20):
 
 def cpu_baseline():
     """The FP64 oracle as it stands, on a bounded sample of the headline workload.
-    Returns the baseline record and the oracle's final state for the accuracy check."""
+    The primary figure runs numpy's BLAS on one thread (cores = 1, the threads
+    the oracle keeps busy: its dense products are small and most of its time is
+    single-threaded numpy work); a second, shorter figure lets BLAS use its
+    whole pool, for comparison.  Returns the baseline record and the oracle's
+    final state for the accuracy check."""
     import numpy as np
     from oracle import rmrt_oracle as O
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
-    except Exception:
-        threads = 1
+        from threadpoolctl import threadpool_info, threadpool_limits
+        pool = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
+    except ImportError:
+        threadpool_limits, pool = None, 1
     n, dx = (32, 32, 32), (1.0, 1.0, 2.0)
     prm = dict(lattice="Q19", n=n, dx=dx, nu=0.005, cs2=1.0 / 3.0)
     m = O.Model(prm)
     rho, u = tg3d_fields(n, dx, 0.02, m.cs2)
-    f = m.init(rho, u)
-    steps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < 12.0 or steps < 10:
-        f = m.step(f, 5)
-        steps += 5
-    dt = time.perf_counter() - t0
-    assert np.isfinite(f).all()
-    rec = {"value": round(m.N * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-           "sample": f"rD3Q19 NSE Taylor-Green 32x32x32 (dz = 2 dx, nu = 0.005), {steps} steps of the dense "
-                     f"FP64 numpy oracle ({dt:.1f} s); numpy BLAS threads = {threads}"}
-    # the same oracle on one host thread (BLAS limited to 1), a shorter sample
-    try:
-        from threadpoolctl import threadpool_limits
+
+    def run(seconds, min_steps):
+        f = m.init(rho, u)
+        steps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds or steps < min_steps:
+            f = m.step(f, 5)
+            steps += 5
+        return f, steps, time.perf_counter() - t0
+
+    if threadpool_limits is not None:
         with threadpool_limits(limits=1):
-            g = m.init(rho, u)
-            s1 = 0
-            t1 = time.perf_counter()
-            while time.perf_counter() - t1 < 5.0 or s1 < 5:
-                g = m.step(g, 5)
-                s1 += 5
-            d1 = time.perf_counter() - t1
-        rec["single_thread"] = {"value": round(m.N * s1 / d1 / 1e6, 4), "unit": "MLUPS", "cores": 1,
-                                "sample": f"the same case, {s1} steps ({d1:.1f} s)"}
-    except ImportError:
-        pass
+            f, steps, dt = run(12.0, 10)
+        cores = 1
+    else:
+        f, steps, dt = run(12.0, 10)
+        cores = pool
+    assert np.isfinite(f).all()
+    rec = {"value": round(m.N * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": f"rD3Q19 NSE Taylor-Green 32x32x32 (dz = 2 dx, nu = 0.005), {steps} steps of the dense "
+                     f"FP64 numpy oracle ({dt:.1f} s), numpy BLAS limited to {cores} thread(s)"}
+    if threadpool_limits is not None and pool > 1:
+        _, s2, d2 = run(5.0, 5)
+        rec["blas_pool"] = {"value": round(m.N * s2 / d2 / 1e6, 4), "unit": "MLUPS", "blas_threads": pool,
+                            "sample": f"the same case, {s2} steps ({d2:.1f} s) with BLAS free to use {pool} "
+                                      f"threads; the oracle's small products keep few of them busy"}
     rec["host_cpu"] = host_cpu()
     r_o, u_o = m.macroscopic(f)
     return rec, dict(prm=prm, rho=rho, u=u, steps=steps, rho_o=r_o, u_o=u_o)
@@ -253,8 +282,12 @@ def main():
     N_h = n_h[0] * n_h[1] * n_h[2]
     prm_h = dict(lattice="Q19", equation="NSE", n=n_h, dx=dx_h, nu=0.005, cs2=1.0 / 3.0, rho0=1.0,
                 storage="f32dev", pattern="AA")
-    log("[bench] headline rD3Q19 256x256x128 f32dev AA")
+    log("[bench] headline rD3Q19 256x256x128 f32dev AA, on the GPU as it comes")
     rho_h, u_h = tg3d_fields(n_h, dx_h, 0.02, 1.0 / 3.0)
+    wall_c, ev_c, _ = run_single(torch, R, prm_h, rho_h, u_h, K, W, settle_s=0.0)
+    log("[bench] HBM copy ceiling")
+    ceiling = copy_ceiling(torch, R)
+    log("[bench] headline rD3Q19 256x256x128 f32dev AA")
     launch = {}
     wall, ev_ms, finite = run_single(torch, R, prm_h, rho_h, u_h, K, W, launch=launch)
     head = lattice_entry("rD3Q19 NSE TG 256x256x128 dz=2dx FP32-dev AA", 19, "f32dev", N_h, K, wall, ev_ms)
@@ -271,6 +304,11 @@ def main():
                 "avg_launch_us": round(avg_launch_s * 1e6, 2),
                 "launch": dict(launch, workgroup=256, tile_nodes=256)}
 
+    head["cold_gpu"] = {"MLUPS": round(N_h * K / wall_c / 1e6, 1), "ms_per_step": round(wall_c / K * 1e3, 4),
+                        "avg_launch_us": round(ev_c / K * 1e3, 2),
+                        "note": "the same K steps after the same W warm-up steps, timed first on a GPU idle "
+                                "before (its clocks rise during the first ~100 steps); value and every other "
+                                "leg are timed after 0.3 s of plain copies that bring the clocks up"}
     per = {"rD3Q19_f32dev": head}
     if "q19local" in only:
         log("[bench] rD3Q19 strain-rate output")
@@ -279,10 +317,6 @@ def main():
         sep = per["rD3Q19_strain_rate_output"]["us_per_call"] + 1e3 * head["ms_per_step"]
         fused["speedup_vs_step_plus_on_demand"] = round(sep / fused["us_per_step"], 3)
         per["rD3Q19_step_fused_strain"] = fused
-    ceiling = None
-    if "copy" in only:
-        log("[bench] HBM copy ceiling")
-        ceiling = copy_ceiling(torch, R)
     if "q19f16" in only:
         log("[bench] rD3Q19 f16dev")
         prm = dict(prm_h, storage="f16dev")
@@ -389,7 +423,9 @@ def main():
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"], ref = cpu_baseline()
         out["accuracy_vs_fp64_oracle"] = accuracy_vs_oracle(torch, R, ref)
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
 
 def bench_local(torch, R, prm, rho, u, N, reps=50):
@@ -404,6 +440,7 @@ def bench_local(torch, R, prm, rho, u, N, reps=50):
         for _ in range(n):
             R._check(lib.rmrt_local_gradients(dom._ctx, R.GRAD_STRAIN, R._ptr(out), R.OUT_F32, R._stream()),
                      "rmrt_local_gradients")
+    settle(torch, R)
     wall, ev_ms = timed_steps(torch, call, reps, 3)
     dom.close()
     del out
@@ -428,6 +465,7 @@ def bench_step_local(torch, R, prm, rho, u, N, reps=50):
         for _ in range(n):
             R._check(lib.rmrt_step_local(dom._ctx, R.GRAD_STRAIN, R._ptr(out), R.OUT_F32, R._stream()),
                      "rmrt_step_local")
+    settle(torch, R)
     wall, ev_ms = timed_steps(torch, call, reps, 4)
     dom.close()
     del out
@@ -459,7 +497,8 @@ def bench_batch(torch, R, steps, warmup, nd=64, nmin=32, nmax=256, seq_steps=20)
     b = R.Batch(params)
     torch.cuda.synchronize()
     cfg = b.autotune(steps=4)
-    wall, ev_ms = timed_steps(torch, b.step, steps, warmup)
+    settle(torch, R)
+    wall, ev_ms = timed_steps(torch, b.step, steps, warmup, prepare=b.prepare)
     red = b.domains[0].reduce()
     fin = all(math.isfinite(v) for v in red)
     e = lattice_entry(f"rD3Q27 batch of {nd} force-driven channels (seed 4, {nmin}..{nmax} nodes per axis), "
@@ -479,7 +518,12 @@ def bench_batch(torch, R, steps, warmup, nd=64, nmin=32, nmax=256, seq_steps=20)
     def seq(n):
         for c in ctxs:
             c.step(n)
-    seq_wall, _ = timed_steps(torch, seq, seq_steps, 2)
+
+    def seq_prepare(n):
+        for c in ctxs:
+            c.prepare(n)
+    settle(torch, R)
+    seq_wall, _ = timed_steps(torch, seq, seq_steps, 2, prepare=seq_prepare)
     for c in ctxs:
         c.close()
     del ctxs

@@ -211,6 +211,16 @@ int rmrt_set_fields(rmrt_ctx* ctx, const double* rho, const double* u, int with_
 int rmrt_step(rmrt_ctx* ctx, int nsteps, void* stream);
 
 /*
+ * Capture, instantiate and upload (on stream) the graphs that
+ * rmrt_step(ctx, nsteps) will replay from the context's current step count,
+ * without running them or advancing the state.  Optional: rmrt_step captures
+ * a graph on its first use; calling this first keeps the capture out of a
+ * timed region or a latency-sensitive loop.  RMRT_EINVAL for a domain of a
+ * batch or nsteps < 0.
+ */
+int rmrt_step_prepare(rmrt_ctx* ctx, int nsteps, void* stream);
+
+/*
  * Macroscopic fields of the current state (eq. 2-4-1 / eq. 2-4-2):
  * rho (or phi) into rho_out[N]; u into u_out[d*N] SoA (may be NULL).
  * out_dtype RMRT_OUT_F64 or RMRT_OUT_F32.  Solid nodes are written as rho0, 0.
@@ -399,6 +409,11 @@ int rmrt_batch_config_info(int cfg, int* threads, int* tile_nodes, int* blocks_p
 
 /* Advance every domain nsteps steps (graph replay of persistent launches). */
 int rmrt_batch_step(rmrt_batch* b, int nsteps, void* stream);
+
+/* rmrt_step_prepare for a batch: capture, instantiate and upload the graphs
+ * of rmrt_batch_step(b, nsteps) for the current tile configuration and
+ * domain groups, without running them. */
+int rmrt_batch_step_prepare(rmrt_batch* b, int nsteps, void* stream);
 
 /*
  * rmrt_residual for every domain of the batch with one host synchronisation:

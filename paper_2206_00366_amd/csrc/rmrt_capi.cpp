@@ -722,15 +722,17 @@ int launch_one_step(rmrt_ctx* c, long long step_index, hipStream_t s) {
 
 constexpr int kGraphChunk = 256;
 
-// steps n launches as a cached graph keyed by (n, parity of the first step)
-int run_graph(rmrt_ctx* c, int n, hipStream_t s) {
-  const auto key = std::make_pair(n, (int)(c->steps & 1));
+// The graph of n launches starting at step `first`, cached by (n, parity of
+// the first step): captured and instantiated on first use, and uploaded to
+// stream s when one is given (rmrt_step_prepare).
+int graph_for(rmrt_ctx* c, int n, long long first, hipGraphExec_t* out, hipStream_t upload) {
+  const auto key = std::make_pair(n, (int)(first & 1));
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
     if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     int rc = RMRT_OK;
-    for (int i = 0; i < n && rc == RMRT_OK; ++i) rc = launch_one_step(c, c->steps + i, c->cap);
+    for (int i = 0; i < n && rc == RMRT_OK; ++i) rc = launch_one_step(c, first + i, c->cap);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap, &g);
     if (rc != RMRT_OK) {
@@ -744,9 +746,39 @@ int run_graph(rmrt_ctx* c, int n, hipStream_t s) {
     if (e != hipSuccess) return fail(RMRT_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     if (c->graphs.size() >= 16) drop_graphs(c->graphs);
     it = c->graphs.emplace(key, ge).first;
+    if (upload) HIP_TRY(hipGraphUpload(ge, upload));
   }
-  HIP_TRY(hipGraphLaunch(it->second, s));
+  *out = it->second;
+  return RMRT_OK;
+}
+
+// steps n launches as a cached graph keyed by (n, parity of the first step)
+int run_graph(rmrt_ctx* c, int n, hipStream_t s) {
+  hipGraphExec_t ge = nullptr;
+  int rc = graph_for(c, n, c->steps, &ge, nullptr);
+  if (rc != RMRT_OK) return rc;
+  HIP_TRY(hipGraphLaunch(ge, s));
   c->steps += n;
+  return RMRT_OK;
+}
+
+// The graphs rmrt_step(n) would replay from step `first` (chunks of
+// kGraphChunk, then the rest; a single step runs without a graph); returns
+// the step count after them.
+int prepare_graphs(rmrt_ctx* c, int n, long long first, hipStream_t s, long long* after) {
+  hipGraphExec_t ge = nullptr;
+  int left = n;
+  while (left >= kGraphChunk) {
+    int rc = graph_for(c, kGraphChunk, first, &ge, s);
+    if (rc != RMRT_OK) return rc;
+    first += kGraphChunk;
+    left -= kGraphChunk;
+  }
+  if (left > 1) {
+    int rc = graph_for(c, left, first, &ge, s);
+    if (rc != RMRT_OK) return rc;
+  }
+  *after = first + left;
   return RMRT_OK;
 }
 
@@ -961,6 +993,25 @@ int rmrt_step(rmrt_ctx* c, int nsteps, void* stream) {
     return RMRT_OK;
   }
   return step_impl(c, nsteps, s);
+}
+
+int rmrt_step_prepare(rmrt_ctx* c, int nsteps, void* stream) {
+  if (!c) return fail(RMRT_EINVAL, "ctx is NULL");
+  if (c->batch) return fail(RMRT_EINVAL, "domain belongs to a batch: use rmrt_batch_step_prepare");
+  if (nsteps < 0) return fail(RMRT_EINVAL, "nsteps < 0");
+  hipStream_t s = (hipStream_t)stream;
+  long long at = c->steps;
+  if (c->p.check_every > 0) {
+    int left = nsteps;
+    while (left > 0) {
+      const int k = std::min(left, c->p.check_every);
+      int rc = prepare_graphs(c, k, at, s, &at);
+      if (rc != RMRT_OK) return rc;
+      left -= k;
+    }
+    return RMRT_OK;
+  }
+  return prepare_graphs(c, nsteps, at, s, &at);
 }
 
 int rmrt_moments(rmrt_ctx* c, void* rho_out, void* u_out, int out_dtype, void* stream) {
@@ -1307,15 +1358,17 @@ void batch_advance(rmrt_batch* b, int n) {
   for (auto* c : b->ctxs) c->steps = b->steps;
 }
 
-int batch_graph(rmrt_batch* b, int n, hipStream_t s) {
-  const auto key = std::make_tuple(n, (int)(b->steps & 1), b->cfg);
+// The graph of n steps of every group from step `first`, cached by (n,
+// parity, tile configuration); uploaded to stream `upload` when given.
+int batch_graph_for(rmrt_batch* b, int n, long long first, hipGraphExec_t* out, hipStream_t upload) {
+  const auto key = std::make_tuple(n, (int)(first & 1), b->cfg);
   auto it = b->graphs.find(key);
   if (it == b->graphs.end()) {
     if (!b->cap) HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     int rc = RMRT_OK;
     for (size_t gi = 0; gi < b->groups.size() && rc == RMRT_OK; ++gi)
-      for (int i = 0; i < n && rc == RMRT_OK; ++i) rc = batch_launch(b, b->steps + i, b->cap, gi);
+      for (int i = 0; i < n && rc == RMRT_OK; ++i) rc = batch_launch(b, first + i, b->cap, gi);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap, &g);
     if (rc != RMRT_OK) {
@@ -1329,8 +1382,17 @@ int batch_graph(rmrt_batch* b, int n, hipStream_t s) {
     if (e != hipSuccess) return fail(RMRT_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     if (b->graphs.size() >= 16) drop_graphs(b->graphs);
     it = b->graphs.emplace(key, ge).first;
+    if (upload) HIP_TRY(hipGraphUpload(ge, upload));
   }
-  HIP_TRY(hipGraphLaunch(it->second, s));
+  *out = it->second;
+  return RMRT_OK;
+}
+
+int batch_graph(rmrt_batch* b, int n, hipStream_t s) {
+  hipGraphExec_t ge = nullptr;
+  int rc = batch_graph_for(b, n, b->steps, &ge, nullptr);
+  if (rc != RMRT_OK) return rc;
+  HIP_TRY(hipGraphLaunch(ge, s));
   batch_advance(b, n);
   return RMRT_OK;
 }
@@ -1481,6 +1543,23 @@ int rmrt_batch_step(rmrt_batch* b, int nsteps, void* stream) {
   if (!b) return fail(RMRT_EINVAL, "batch is NULL");
   if (nsteps < 0) return fail(RMRT_EINVAL, "nsteps < 0");
   return batch_step_impl(b, nsteps, (hipStream_t)stream);
+}
+
+int rmrt_batch_step_prepare(rmrt_batch* b, int nsteps, void* stream) {
+  if (!b) return fail(RMRT_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(RMRT_EINVAL, "nsteps < 0");
+  hipStream_t s = (hipStream_t)stream;
+  hipGraphExec_t ge = nullptr;
+  long long first = b->steps;
+  int left = nsteps;
+  while (left >= kGraphChunk) {
+    int rc = batch_graph_for(b, kGraphChunk, first, &ge, s);
+    if (rc != RMRT_OK) return rc;
+    first += kGraphChunk;
+    left -= kGraphChunk;
+  }
+  if (left > 1) return batch_graph_for(b, left, first, &ge, s);
+  return RMRT_OK;
 }
 
 int rmrt_batch_autotune(rmrt_batch* b, int steps, void* stream, int* chosen) {

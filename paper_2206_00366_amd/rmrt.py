@@ -75,6 +75,7 @@ _sig = {
     "rmrt_init": (C.c_int, [C.POINTER(_vp), C.POINTER(Params), _vp, _vp, _vp, _vp, _vp, C.c_int, _vp]),
     "rmrt_set_fields": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
     "rmrt_step": (C.c_int, [_vp, C.c_int, _vp]),
+    "rmrt_step_prepare": (C.c_int, [_vp, C.c_int, _vp]),
     "rmrt_moments": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
     "rmrt_populations": (C.c_int, [_vp, _vp, _vp]),
     "rmrt_reduce": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
@@ -98,6 +99,7 @@ _sig = {
     "rmrt_local_gradients": (C.c_int, [_vp, C.c_int, _vp, C.c_int, _vp]),
     "rmrt_step_local": (C.c_int, [_vp, C.c_int, _vp, C.c_int, _vp]),
     "rmrt_batch_step": (C.c_int, [_vp, C.c_int, _vp]),
+    "rmrt_batch_step_prepare": (C.c_int, [_vp, C.c_int, _vp]),
     "rmrt_batch_residual": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
     "rmrt_batch_free": (C.c_int, [_vp]),
     "rmrt_nn_conv_forward": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
@@ -249,6 +251,10 @@ class Domain:
     def step(self, n=1):
         _check(_lib.rmrt_step(self._ctx, int(n), _stream()), "rmrt_step")
 
+    def prepare(self, n):
+        """Capture the graphs of step(n) now (no steps are taken)."""
+        _check(_lib.rmrt_step_prepare(self._ctx, int(n), _stream()), "rmrt_step_prepare")
+
     def moments(self, out_dtype=OUT_F64, with_u=True):
         import torch
         dt = torch.float64 if out_dtype == OUT_F64 else torch.float32
@@ -355,6 +361,10 @@ class Batch:
 
     def step(self, n=1):
         _check(_lib.rmrt_batch_step(self._b, int(n), _stream()), "rmrt_batch_step")
+
+    def prepare(self, n):
+        """Capture the graphs of step(n) now (no steps are taken)."""
+        _check(_lib.rmrt_batch_step_prepare(self._b, int(n), _stream()), "rmrt_batch_step_prepare")
 
     def autotune(self, steps=10):
         ch = C.c_int()

@@ -264,6 +264,12 @@ def test_batch_graph_replays_match_single_steps(rmrt, small_oracle, pattern, sto
             bs.append(b)
         g, e = bs
         for it, n in enumerate((4, 4, 4, 3, 3)):
+            if it == 3:
+                # prepared graphs (captured ahead, no steps taken) replay the same bits
+                before = g.domains[0].populations().cpu().numpy()
+                g.prepare(n)
+                torch.cuda.synchronize()
+                assert np.array_equal(g.domains[0].populations().cpu().numpy(), before)
             g.step(n)
             for _ in range(n):
                 e.step(1)

@@ -157,6 +157,38 @@ def test_graph_replays_match_single_steps(rmrt, case, pattern, storage):
     e.close()
 
 
+@pytest.mark.parametrize("check_every", [0, 7])
+@pytest.mark.parametrize("pattern", ["AB", "AA"])
+def test_prepared_graphs_take_no_steps_and_replay_bitwise(rmrt, pattern, check_every):
+    """rmrt_step_prepare captures the graphs of a later rmrt_step without
+    running them: the step count and the state do not move, and the prepared
+    call then leaves the bits of eager single steps (chunks of 256 and a
+    remainder, both parities, with and without the health-check split)."""
+    prm, _, _ = CASES["q19_channel_force"]
+    prm = dict(prm, check_every=check_every)
+    m = O.Model(prm)
+    rho, u = random_fields(m, seed=11)
+    g = rmrt.Domain(rmrt.make_params(**prm, storage="f32dev", pattern=pattern), rho, u)
+    e = rmrt.Domain(rmrt.make_params(**prm, storage="f32dev", pattern=pattern), rho, u)
+    g.step(1)
+    e.step(1)
+    before = g.populations().cpu().numpy()
+    for n in (300, 5, 6):
+        g.prepare(n)
+        torch.cuda.synchronize()
+        assert g.steps_taken() == e.steps_taken()
+        assert np.array_equal(g.populations().cpu().numpy(), before)
+        g.step(n)
+        for _ in range(n):
+            e.step(1)
+        torch.cuda.synchronize()
+        before = g.populations().cpu().numpy()
+        assert np.array_equal(before, e.populations().cpu().numpy()), n
+    say(f"[prepared graphs] {pattern} check_every={check_every}: {g.steps_taken()} steps bitwise")
+    g.close()
+    e.close()
+
+
 @pytest.mark.parametrize("pattern", ["AB", "AA"])
 def test_graph_cache_eviction_mid_flight(rmrt, pattern):
     """More distinct step counts than the graph cache holds, issued back to back
