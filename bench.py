@@ -571,7 +571,7 @@ def warmstart_study(torch, args):
             b.set_group_bytes(group_bytes)
         rho, u = S.initial_fields(geoms)
         S.apply_initial(b, rho, u)
-        steps, conv, wall, n = S.run_to_steady(b, tol=args.ws_train_tol, max_steps=args.ws_max_steps, log=log,
+        steps, conv, wall, n, _ = S.run_to_steady(b, tol=args.ws_train_tol, max_steps=args.ws_max_steps, log=log,
                                                label=f"train batch {s0 // nb}")
         tgt, wgt = S.steady_targets(b, geoms)
         x0, _ = S.features(geoms)
@@ -598,6 +598,7 @@ def warmstart_study(torch, args):
     results = {}
     for mode in ("cold", "prior", "warm"):
         all_steps, all_conv, all_time, wall_tot, inf_tot = [], [], [], 0.0, 0.0
+        restarts = 0
         for s0 in range(0, len(test), 50):
             geoms = test[s0:s0 + 50]
             b = S.make_batch(geoms)
@@ -612,8 +613,9 @@ def warmstart_study(torch, args):
                 S.apply_initial(b, rho, u)
                 torch.cuda.synchronize()
                 t_inf = time.perf_counter() - ti
-            steps, conv, wall, n = S.run_to_steady(b, tol=1e-6, max_steps=args.ws_max_steps, log=log,
-                                                   label=f"{mode} batch {s0 // 50}")
+            steps, conv, wall, n, rst = S.run_to_steady(b, tol=1e-6, max_steps=args.ws_max_steps, log=log,
+                                                        label=f"{mode} batch {s0 // 50}", fallback=mode != "cold")
+            restarts += int(rst.sum())
             all_steps.append(steps)
             all_conv.append(conv)
             # per-domain time: its steps at the batch's cost per domain-step, plus its share of the init
@@ -632,6 +634,7 @@ def warmstart_study(torch, args):
                          "mean_time_s": float(tm[cv].mean()) if ok.size else None,
                          "median_time_s": float(np.median(tm[cv])) if ok.size else None,
                          "batch_wall_s": round(wall_tot, 1), "init_s": round(inf_tot, 3),
+                         "cold_restarts": restarts,
                          "steps_per_domain": st.tolist()}
         record("eval", mode=mode, **{k: v for k, v in results[mode].items() if k != "steps_per_domain"})
     cold = np.array(results["cold"]["steps_per_domain"], dtype=float)

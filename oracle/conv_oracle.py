@@ -14,6 +14,11 @@ convolutions whose definitions are written out here literally:
   pooling       mean over non-overlapping k x k blocks
   upsampling    bilinear, sample positions (i + 1/2) / k - 1/2 in coarse units,
                 clamped to the edge cells
+  storage       the network keeps its weights, its stored activations silu(y)
+                and the gradients it propagates between layers (the loss
+                gradient dL/dout and dL/dy of every hidden layer) in bf16, and
+                pre-activations y in fp32; network_forward / network_backward
+                take that rounding as `store` (to_bf16), or none (FP64 mode)
 """
 from __future__ import annotations
 
@@ -69,14 +74,20 @@ def silu_grad(y):
     return s * (1.0 + y * (1.0 - s))
 
 
-def network_forward(x, Ws, bs, dils):
-    """Returns the output and the per-layer (input, pre-activation) pairs."""
+def _identity(v):
+    return v
+
+
+def network_forward(x, Ws, bs, dils, store=None):
+    """Returns the output and the per-layer (input, pre-activation) pairs.
+    store: rounding of the stored activations silu(y) (None: exact)."""
+    store = store or _identity
     a = x
     cache = []
     for l, (W, b, d) in enumerate(zip(Ws, bs, dils)):
         y = conv_forward(a, W, b, d)
         cache.append((a, y))
-        a = silu(y) if l < len(Ws) - 1 else y
+        a = store(silu(y)) if l < len(Ws) - 1 else y
     return a, cache
 
 
@@ -88,16 +99,19 @@ def masked_mse(out, target, mask):
     return loss, dout
 
 
-def network_backward(dout, cache, Ws, dils):
+def network_backward(dout, cache, Ws, dils, store=None):
+    """Per-layer (dW, db) from dL/dout.  store: rounding of the propagated
+    gradients dL/dout and dL/dy (None: exact)."""
+    store = store or _identity
     grads = [None] * len(Ws)
-    g = dout
+    g = store(dout)
     for l in range(len(Ws) - 1, -1, -1):
         a, y = cache[l]
         dW, db = conv_backward_weight(a, g, dils[l])
         grads[l] = (dW, db)
         if l > 0:
             da = conv_backward_data(g, Ws[l], dils[l])
-            g = da * silu_grad(cache[l - 1][1])
+            g = store(da * silu_grad(cache[l - 1][1]))
     return grads
 
 

@@ -118,13 +118,36 @@ def make_batch(geoms, storage="f32dev"):
     return R.Batch([channel_params(g, storage) for g in geoms], solids=[g["solid"].astype(np.uint8) for g in geoms])
 
 
-def run_to_steady(batch, tol=1e-6, check=50, max_steps=400_000, log=None, label=""):
+def cold_start(batch, k):
+    """Re-initialise domain k of a batch at rest (rho = 1, u = 0)."""
+    d = batch.domains[k]
+    d.set_fields(torch.ones(d.N, dtype=torch.float64, device="cuda"),
+                 torch.zeros((d.d, d.N), dtype=torch.float64, device="cuda"))
+
+
+def run_to_steady(batch, tol=1e-6, check=50, max_steps=400_000, log=None, label="", fallback=False,
+                  stall_checks=200):
     """Step every domain until its residual (checked every `check` steps, as
-    ||u^n - u^(n-check)|| / ||u^n||) falls below tol.  Returns the step count
-    at convergence per domain (max_steps + check where not converged), the
-    converged flags and the wall time."""
+    ||u^n - u^(n-check)|| / ||u^n||) falls below tol.
+
+    With fallback=True a domain that was started from a prediction restarts
+    cold (rho = 1, u = 0) once, when its residual is not finite or has made no
+    new minimum for `stall_checks` consecutive checks; its step count includes
+    the steps spent before the restart.  The window must span several sound
+    periods of the channel: a start from a predicted field excites sound waves
+    that keep the residual from setting a new minimum for a while (the default
+    200 checks of 50 steps are over five periods across 512 nodes; 40 checks
+    restarted 9 of 16 good warm starts).  Without fallback a non-finite
+    residual raises FloatingPointError.
+
+    Returns the step count at convergence per domain (the last step count where
+    not converged), the converged flags, the wall time, the total steps, and the
+    number of cold restarts per domain."""
     nd = len(batch.domains)
     steps = np.full(nd, -1, dtype=np.int64)
+    restarts = np.zeros(nd, dtype=np.int64)
+    best = np.full(nd, np.inf)
+    since_best = np.zeros(nd, dtype=np.int64)
     batch.residuals()                       # stores the initial velocity
     n = 0
     t0 = time.perf_counter()
@@ -133,19 +156,37 @@ def run_to_steady(batch, tol=1e-6, check=50, max_steps=400_000, log=None, label=
         batch.step(check)
         n += check
         r = np.array(batch.residuals())
-        newly = (steps < 0) & (r < tol)
+        bad = ~np.isfinite(r)
+        if bad.any() and not fallback:
+            raise FloatingPointError(f"non-finite residual in domains {np.where(bad)[0].tolist()}")
+        newly = (steps < 0) & ~bad & (r < tol)
         steps[newly] = n
-        if not np.all(np.isfinite(r)):
-            bad = np.where(~np.isfinite(r))[0]
-            raise FloatingPointError(f"non-finite residual in domains {bad.tolist()}")
+        improved = ~bad & (r < best)
+        best[improved] = r[improved]
+        since_best[improved] = 0
+        since_best[~improved] += 1
+        if fallback:
+            # a first residual after a (re)start is +inf: it neither improves nor stalls
+            stalled = (steps < 0) & (restarts == 0) & (bad | (since_best >= stall_checks))
+            for k in np.where(stalled)[0]:
+                cold_start(batch, int(k))
+                restarts[k] += 1
+                best[k] = np.inf
+                since_best[k] = 0
+            if stalled.any():
+                batch.residuals()           # the restarted domains store their new velocity
+                if log:
+                    log(f"{label} step {n}: cold restart of domains {np.where(stalled)[0].tolist()}")
         if log and time.perf_counter() - last_log > 20.0:
             last_log = time.perf_counter()
-            log(f"{label} step {n}: {int((steps >= 0).sum())}/{nd} converged, max r = {r.max():.2e}")
+            fin = r[np.isfinite(r)]
+            log(f"{label} step {n}: {int((steps >= 0).sum())}/{nd} converged, "
+                f"max r = {fin.max() if fin.size else float('nan'):.2e}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     conv = steps >= 0
     steps[~conv] = n
-    return steps, conv, wall, n
+    return steps, conv, wall, n, restarts
 
 
 def geometry_tensors(geoms, device="cuda"):

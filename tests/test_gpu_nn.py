@@ -211,28 +211,41 @@ def test_features_targets_and_warm_fields(R):
 
 
 def test_network_gradients_match_oracle(R):
-    """Full 4-layer forward + backward through the driver against the oracle."""
-    say("[nn] network forward/backward vs oracle")
+    """Full 4-layer forward + backward through the driver against the oracle in
+    the network's own storage mode (bf16 stored activations and propagated
+    gradients, the rest exact), every dW and db entry compared.  What remains
+    is the fp32 accumulation of the GPU against the oracle's fp64: a few
+    1e-7 relative per sum, plus an occasional bf16 rounding of a stored value
+    that the two accumulations put on different sides of a rounding boundary."""
+    say("[nn] network forward/backward vs oracle (bf16 storage mode)")
     from paper_2206_00366_amd.surrogate import Surrogate
     B, H, W = 2, 16, 32
     net = Surrogate(seed=1, B=B, H=H, W=W)
     rng = np.random.default_rng(2)
     x = C.to_bf16(np.concatenate([rng.standard_normal((B, H, W, 3)), np.zeros((B, H, W, 13))], -1))
-    tgt = rng.standard_normal((B, H, W, 3)) * 0.1
-    wgt = rng.uniform(0, 1, (B, H, W))
+    # fp32-representable targets and weights, the values the GPU sees
+    tgt = (rng.standard_normal((B, H, W, 3)) * 0.1).astype(np.float32).astype(np.float64)
+    wgt = rng.uniform(0, 1, (B, H, W)).astype(np.float32).astype(np.float64)
     loss = net.loss_and_grads(bf16_dev(x), f32_dev(tgt), f32_dev(wgt))
     Ws = [C.to_bf16(host(w)) for w in net.w32]
     bs = [host(b) for b in net.b32]
-    out, cache = C.network_forward(x, Ws, bs, net.dils)
+    out, cache = C.network_forward(x, Ws, bs, net.dils, store=C.to_bf16)
     loss_or, dout = C.masked_mse(out[..., :3], tgt, wgt)
     dout_full = np.zeros_like(out)
     dout_full[..., :3] = dout
-    grads = C.network_backward(dout_full, cache, Ws, net.dils)
-    say(f"   loss gpu {loss:.6e} oracle {loss_or:.6e}")
-    assert abs(loss - loss_or) < 2e-2 * loss_or
+    grads = C.network_backward(dout_full, cache, Ws, net.dils, store=C.to_bf16)
+    say(f"   loss gpu {loss:.9e} oracle {loss_or:.9e}")
+    assert abs(loss - loss_or) < 1e-5 * loss_or
+    stats = []
     for l in range(4):
-        gw = host(net.gw[l])
-        ref = grads[l][0]
-        rel = np.linalg.norm(gw - ref) / np.linalg.norm(ref)
-        say(f"   layer {l}: |dW - dW_oracle| / |dW_oracle| = {rel:.3e}")
-        assert rel < 3e-2
+        for name, got, ref in (("dW", host(net.gw[l]), grads[l][0]), ("db", host(net.gb[l]), grads[l][1])):
+            scale = np.abs(ref).max()
+            err = np.abs(got - ref)
+            norm = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            frac = float((err <= 1e-5 * scale).mean())
+            say(f"   layer {l} {name}: max |d - d_oracle| / max |d_oracle| = {err.max() / scale:.3e}, "
+                f"norm {norm:.3e}, entries within 1e-5: {frac:.3f} of {err.size}")
+            stats.append((l, name, err.max() / scale, norm, frac))
+    for l, name, emax, norm, frac in stats:
+        assert emax <= 2e-3, (l, name, emax)
+        assert norm <= 5e-4, (l, name, norm)

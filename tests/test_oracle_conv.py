@@ -119,3 +119,55 @@ def test_bf16_rounding_matches_torch():
                         [1.0, 1.0 + 2.0**-8, 1.0 + 3 * 2.0**-8, -2.5, 0.0]])
     ref = torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
     np.testing.assert_array_equal(C.to_bf16(a), ref)
+
+
+def test_bf16_storage_mode_matches_torch_autograd():
+    """The oracle's bf16-storage mode (stored activations and propagated
+    gradients rounded to bf16, everything else exact) against the same network
+    built from torch's float64 conv2d and autograd on the CPU: a rounding op
+    whose gradient passes straight through stores the activations, and
+    gradient hooks round dL/dout and every hidden dL/dy."""
+    torch = pytest.importorskip("torch")
+    p = conv_problem(seed=8, B=2, H=6, W=7, cin=4, chid=8, cout=3)
+    dils = (1, 2, 1, 3)
+    Ws = [C.to_bf16(w) for w in p["W"]]
+    x = C.to_bf16(p["x"])
+
+    class Store(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, v):
+            return torch.from_numpy(C.to_bf16(v.detach().numpy()))
+
+        @staticmethod
+        def backward(ctx, g):
+            return g
+
+    def round_grad(g):
+        return torch.from_numpy(C.to_bf16(g.numpy()))
+
+    a = torch.tensor(x).permute(0, 3, 1, 2)
+    tw = [torch.tensor(w).permute(0, 3, 1, 2).requires_grad_(True) for w in Ws]
+    tb = [torch.tensor(b).requires_grad_(True) for b in p["b"]]
+    for l in range(4):
+        y = torch.nn.functional.conv2d(a, tw[l], tb[l], padding=dils[l], dilation=dils[l])
+        y.register_hook(round_grad)
+        a = Store.apply(torch.nn.functional.silu(y)) if l < 3 else y
+    out_t = a.permute(0, 2, 3, 1)
+    m = torch.tensor(p["mask"])
+    loss_t = (m[..., None] * (out_t - torch.tensor(p["target"])) ** 2).sum() / m.sum()
+    loss_t.backward()
+
+    out, cache = C.network_forward(x, Ws, p["b"], dils, store=C.to_bf16)
+    loss, dout = C.masked_mse(out, p["target"], p["mask"])
+    grads = C.network_backward(dout, cache, Ws, dils, store=C.to_bf16)
+    assert abs(loss - loss_t.item()) < 1e-13 * loss
+    for l in range(4):
+        gw = tw[l].grad.permute(0, 2, 3, 1).numpy()
+        assert np.abs(grads[l][0] - gw).max() < 1e-12 * np.abs(gw).max(), l
+        assert np.abs(grads[l][1] - tb[l].grad.numpy()).max() < 1e-12 * np.abs(gw).max(), l
+    # the stored activations are bf16 numbers; without rounding the mode is the FP64 network
+    for a_l, _ in cache[1:]:
+        np.testing.assert_array_equal(a_l, C.to_bf16(a_l))
+    out64, _ = C.network_forward(x, Ws, p["b"], dils)
+    out_id, _ = C.network_forward(x, Ws, p["b"], dils, store=lambda v: v)
+    np.testing.assert_array_equal(out64, out_id)
