@@ -59,6 +59,17 @@ GPU side can take the same ones; numbering as in the design notes):
       (the history field); at t = 0 it is the initial phi, so the first step
       sees dB/dt = 0.  Moment rows are the monomials with at most one non-zero
       exponent; rates of order 2 default to 1 as in A5.
+  A23 the same C = 0 form of eq. 4-16 as an option (c_zero) on rD2Q9, rD3Q19
+      and rD3Q27: f_eq = g_eq(phi, phi u_adv, 0), G from the first-order
+      difference of B = phi u_adv with the history field, rates of order >= 2
+      as in A5.
+  A24 source fields: the mass source, the NCDE source and the body force may
+      vary from node to node and from step to step (set_sources /
+      update_sources); every formula takes the node's value at the current
+      step.  In the gamma = 0 form the dt^2/2 dF/dt term is the explicit
+      difference dt (F(t) - F(t - dt)) / 2 with F(t - dt) the source the
+      previous step used; at the first step after the fields are set it is
+      taken equal to F(t).
 """
 from __future__ import annotations
 
@@ -238,7 +249,7 @@ DEFAULTS = dict(lattice="Q9", equation="NSE", n=(8, 8, 1), dx=(1.0, 1.0, 1.0), d
                 cs2=-1.0, nu=0.1, nu_b=-1.0, s_hi=-1.0, w_corner=-1.0,
                 D0=0.0, D2=0.0, adv=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0),
                 source=0.0, rho0=1.0, wall_faces=0, incompressible=False, nu_tensor=None, nu_b_axis=None,
-                gamma0=False, diffusive=False)
+                gamma0=False, diffusive=False, c_zero=False)
 
 
 class Model:
@@ -253,6 +264,10 @@ class Model:
         self.linear = self.lattice in LINEAR_LATTICES                          # A18
         if self.linear and self.nse:
             raise ValueError("rD2Q5 / rD3Q7 carry the NCDE only (linear equilibrium)")
+        # the C = 0 form of eq. 4-16 (G from dB/dt, history of phi): always on the
+        # reduced lattices (A18), an option on the others (A23)
+        self.c_zero = bool(p["c_zero"]) and not self.nse
+        self.hist_form = self.linear or self.c_zero
         E = unit_offsets(self.lattice)
         self.E = E
         self.q, self.d = E.shape
@@ -347,6 +362,40 @@ class Model:
         for r in self.rows1:
             self.P1[r, r] = 1.0
         self._build_streaming(solid)
+        self.S_node = self.F_node = self.S_prev = None
+
+    # ------------------------------------------------------------------ sources
+    def set_sources(self, S=None, F=None):
+        """Per-node source fields in place of the parameter set's constant source
+        and force (eq. NSE, eq. NCDE): S (N,) the NSE mass source Sbar or the NCDE
+        source S, F (d, N) the NSE body-force density Fbar; None for one of them
+        means zero, None for both returns to the constants.  The previous-step
+        source of the gamma = 0 form starts equal to S, so the first step sees no
+        difference (A24)."""
+        if S is None and F is None:
+            self.S_node = self.F_node = self.S_prev = None
+            return
+        self.S_node = np.zeros(self.N) if S is None else np.array(S, dtype=np.float64).reshape(self.N)
+        self.F_node = (np.zeros((self.d, self.N)) if F is None
+                       else np.array(F, dtype=np.float64).reshape(self.d, self.N))
+        self.S_prev = self.S_node.copy()
+
+    def update_sources(self, S=None, F=None):
+        """New values of the per-node fields for the following steps; the
+        previous-step source keeps the values the last step used."""
+        if S is not None:
+            self.S_node = np.array(S, dtype=np.float64).reshape(self.N)
+        if F is not None:
+            self.F_node = np.array(F, dtype=np.float64).reshape(self.d, self.N)
+
+    def _sources(self, n, sel):
+        """Source, force and previous-step source of n nodes (the nodes `sel` of
+        the domain, all when None): (S (n,), F (d, n), S_prev (n,))."""
+        if self.S_node is None:
+            S = np.full(n, self.source)
+            return S, np.repeat(self.force[:, None], n, axis=1), S
+        idx = slice(None) if sel is None else sel
+        return self.S_node[idx], self.F_node[:, idx], self.S_prev[idx]
 
     # ---------------------------------------------------------------- geometry
     def _build_streaming(self, solid):
@@ -382,14 +431,16 @@ class Model:
             self.bounce[j] = out_wall | self.solid[lin]
 
     # -------------------------------------------------------------- equilibria
-    def macroscopic(self, fbar):
-        """rho (or phi) and u from fbar, eq. 2-4-1 / eq. 2-4-2."""
+    def macroscopic(self, fbar, sel=None):
+        """rho (or phi) and u from fbar, eq. 2-4-1 / eq. 2-4-2 (sel: the nodes of
+        fbar when they are not all the domain's)."""
+        S, F, _ = self._sources(fbar.shape[1], sel)
         if self.nse:
-            rho = fbar.sum(axis=0) + self.dt * self.source / 2.0
+            rho = fbar.sum(axis=0) + self.dt * S / 2.0
             den = self.rho0 if self.hl else rho[None, :]                         # A19: rho0 u = j
-            u = (self.C.T @ fbar + self.dt * self.force[:, None] / 2.0) / den
+            u = (self.C.T @ fbar + self.dt * F / 2.0) / den
             return rho, u
-        phi = fbar.sum(axis=0) + self.half_src * self.dt * self.source
+        phi = fbar.sum(axis=0) + self.half_src * self.dt * S
         return phi, np.repeat(self.adv[:, None], fbar.shape[1], axis=1)
 
     def s1_ncde(self, phi):
@@ -397,43 +448,51 @@ class Model:
         D = self.p["D0"] * (1.0 + self.p["D2"] * phi**2)
         return 1.0 / (0.5 + D / (self.cs2 * self.dt))
 
-    def distributions(self, fbar, phi_prev=None):
+    def distributions(self, fbar, phi_prev=None, sel=None):
         """f_eq, F and G of the node states in fbar (eq. NSEfeq/NSEFeq/NSEGeq,
-        eq. 4-14/4-14-1, or eq. 4-16 on the reduced lattices, which need the
-        previous step's phi in phi_prev)."""
+        eq. 4-14/4-14-1, or eq. 4-16 in the C = 0 form, which needs the previous
+        step's phi in phi_prev); sel: the nodes of fbar (all when None)."""
         d, n = self.d, fbar.shape[1]
         I = np.eye(d)[:, :, None]
+        Sn, Fn, _ = self._sources(n, sel)
         if self.nse:
-            rho, u = self.macroscopic(fbar)
+            rho, u = self.macroscopic(fbar, sel)
             rr = np.full_like(rho, self.rho0) if self.hl else rho                 # A19
             feq = g_eq(self.C, self.w, self.c, self.cs2, rho, rr[None] * u,
                        rr[None, None] * np.einsum("an,bn->abn", u, u))
-            Sb, Fb = self.source, self.force
-            F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, Sb),
-                     np.repeat(Fb[:, None], n, axis=1), -self.cs2 * Sb * np.repeat(I, n, axis=2))
-            T = (np.einsum("an,b->abn", u, Fb) + np.einsum("a,bn->abn", Fb, u)
-                 + self.cs2 * Sb * np.repeat(I, n, axis=2))
+            F = g_eq(self.C, self.w, self.c, self.cs2, Sn, Fn, -self.cs2 * Sn[None, None] * I)
+            T = (np.einsum("an,bn->abn", u, Fn) + np.einsum("an,bn->abn", Fn, u)
+                 + self.cs2 * Sn[None, None] * I)
             M2G = self._apply_I_minus_half_S2(T)
             G = g_eq(self.C, self.w, self.c, self.cs2, np.zeros(n), np.zeros((d, n)), M2G)
             return feq, F, G, None
-        phi, u = self.macroscopic(fbar)
+        phi, u = self.macroscopic(fbar, sel)
         B = phi[None] * u
-        S = self.source
-        F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, S), np.zeros((d, n)), np.zeros((d, d, n)))
+        F = g_eq(self.C, self.w, self.c, self.cs2, Sn, np.zeros((d, n)), np.zeros((d, d, n)))
         s1 = self.s1_ncde(phi)
         if self.diffusive:
             feq = g_eq(self.C, self.w, self.c, self.cs2, phi, B, np.zeros((d, d, n)))   # eq. 4-17
             M1G = np.zeros((d, n))
-        elif self.linear:
+        elif self.hist_form:
             feq = g_eq(self.C, self.w, self.c, self.cs2, phi, B, np.zeros((d, d, n)))   # eq. 4-16a
             dBdt = u * (phi - phi_prev)[None] / self.dt                        # first-order difference
             M1G = (1.0 - s1[None] / 2.0) * dBdt                                # eq. 4-16b
         else:
             feq = g_eq(self.C, self.w, self.c, self.cs2, phi, B,
                        phi[None, None] * np.einsum("an,bn->abn", u, u))
-            M1G = (1.0 - s1[None] / 2.0) * u * S                               # eq. 4-11, B' = u_adv
+            M1G = (1.0 - s1[None] / 2.0) * u * Sn[None]                        # eq. 4-11, B' = u_adv
         G = g_eq(self.C, self.w, self.c, self.cs2, np.zeros(n), M1G, np.zeros((d, d, n)))
         return feq, F, G, s1
+
+    def source_difference(self, n, sel=None):
+        """dt/2 times the explicit difference F(t) - F(t - dt) of the NCDE source
+        distribution F_j = w_j S (eq. 4-14-1): the dt^2/2 dF/dt term of eq. 2-1
+        with gamma = 0 (A21, A24); zero in the gamma = 1 form."""
+        if not self.gamma0:
+            return np.zeros((self.q, n))
+        S, _, Sp = self._sources(n, sel)
+        d = self.d
+        return 0.5 * g_eq(self.C, self.w, self.c, self.cs2, S - Sp, np.zeros((d, n)), np.zeros((d, d, n)))
 
     def _second_order_vec(self, T):
         """Symmetric tensor -> vector over the second-order rows (diagonal then off-diagonal)."""
@@ -461,25 +520,29 @@ class Model:
         return y
 
     # --------------------------------------------------------------- collision
-    def collide(self, fbar, phi_prev=None):
+    def collide(self, fbar, phi_prev=None, sel=None):
         """Post-collision fbar* in moment space, eq. 2-2-3 (before propagation)."""
-        feq, F, G, s1 = self.distributions(fbar, phi_prev)
+        feq, F, G, s1 = self.distributions(fbar, phi_prev, sel)
         m = self.M @ fbar
         meq = self.M @ feq
         mF = self.M @ F
         mG = self.M @ G
-        # gamma = 1 (eq. 2-3): dt (G + (I - Lambda/2) F); gamma = 0 (eq. 2-1, A21): dt (G + F)
-        mstar = m - self.apply_S(m - meq, s1) + self.dt * (mG + mF - self.half_src * self.apply_S(mF, s1))
+        mD = self.M @ self.source_difference(fbar.shape[1], sel)
+        # gamma = 1 (eq. 2-3): dt (G + (I - Lambda/2) F); gamma = 0 (eq. 2-1, A21):
+        # dt (G + F + (F(t) - F(t - dt)) / 2)
+        mstar = (m - self.apply_S(m - meq, s1) + self.dt * (mG + mF - self.half_src * self.apply_S(mF, s1))
+                 + self.dt * mD)
         return np.linalg.solve(self.M, mstar)
 
-    def collide_velocity_space(self, fbar, phi_prev=None):
+    def collide_velocity_space(self, fbar, phi_prev=None, sel=None):
         """Same collision written in velocity space with Lambda = M^-1 S M (eq. 2-3, eq. 5-1)."""
-        feq, F, G, s1 = self.distributions(fbar, phi_prev)
+        feq, F, G, s1 = self.distributions(fbar, phi_prev, sel)
 
         def Lam(x):
             return self.Minv @ self.apply_S(self.M @ x, s1)
 
-        return fbar - Lam(fbar - feq) + self.dt * (G + F - self.half_src * Lam(F))
+        return (fbar - Lam(fbar - feq) + self.dt * (G + F - self.half_src * Lam(F))
+                + self.dt * self.source_difference(fbar.shape[1], sel))
 
     # ------------------------------------------------------------- propagation
     def stream(self, fstar, fprev):
@@ -498,27 +561,31 @@ class Model:
         return out
 
     def step(self, fbar, nsteps=1, hist=None):
-        """nsteps collide-and-stream steps.  On the reduced lattices (A18) hist
-        is the previous step's phi per node (init_history gives it at t = 0)
-        and the call returns (fbar, hist); otherwise it returns fbar."""
-        if self.linear != (hist is not None):
-            raise ValueError("hist is required on rD2Q5 / rD3Q7 and meaningless elsewhere")
+        """nsteps collide-and-stream steps.  In the C = 0 form (the reduced
+        lattices, A18, or the c_zero option, A23) hist is the previous step's
+        phi per node (init_history gives it at t = 0) and the call returns
+        (fbar, hist); otherwise it returns fbar."""
+        if self.hist_form != (hist is not None):
+            raise ValueError("hist is required in the C = 0 form and meaningless elsewhere")
         fl = self.fluid
+        sel = np.flatnonzero(fl)
         if hist is not None:
             hist = np.array(hist, dtype=np.float64).reshape(self.N)
         for _ in range(nsteps):
             fstar = fbar.copy()
-            if self.linear:
-                phi, _ = self.macroscopic(fbar[:, fl])
-                fstar[:, fl] = self.collide(fbar[:, fl], hist[fl])
+            if self.hist_form:
+                phi, _ = self.macroscopic(fbar[:, fl], sel)
+                fstar[:, fl] = self.collide(fbar[:, fl], hist[fl], sel)
                 hist[fl] = phi
             else:
-                fstar[:, fl] = self.collide(fbar[:, fl])
+                fstar[:, fl] = self.collide(fbar[:, fl], sel=sel)
             fbar = self.stream(fstar, fbar)
+            if self.S_node is not None:
+                self.S_prev = self.S_node.copy()                               # F(t - dt) of the next step
         return fbar if hist is None else (fbar, hist)
 
     def init_history(self, phi):
-        """phi(t - dt) at t = 0 for the reduced lattices: the initial phi (A18)."""
+        """phi(t - dt) at t = 0 in the C = 0 form: the initial phi (A18, A23)."""
         return np.array(phi, dtype=np.float64).reshape(self.N)
 
     # ------------------------------------------------------- local gradients
@@ -542,13 +609,13 @@ class Model:
         n = fbar.shape[1]
         feq, F, G, s1 = self.distributions(fbar, hist)
         fne = fbar + self.half_src * self.dt * F - feq
+        Sn, Fn, _ = self._sources(n, None)
         if self.nse:
             rho, u = self.macroscopic(fbar)
             I = np.eye(d)[:, :, None]
             m2ne = np.einsum("ja,jb,jn->abn", self.C, self.C, fne)
-            Sb, Fb = self.source, self.force
-            T = (np.einsum("an,b->abn", u, Fb) + np.einsum("a,bn->abn", Fb, u)
-                 + (self.cs2 * I - np.einsum("an,bn->abn", u, u)) * Sb)
+            T = (np.einsum("an,bn->abn", u, Fn) + np.einsum("an,bn->abn", Fn, u)
+                 + (self.cs2 * I - np.einsum("an,bn->abn", u, u)) * Sn[None, None])
             tau = -self._apply_I_minus_half_S2(m2ne + 0.5 * self.dt * T)
             rr = np.full_like(rho, self.rho0) if self.hl else rho
             # invert eq. 4-28 with the tensors of eq. 4-29:
@@ -569,10 +636,10 @@ class Model:
         m1ne = self.C.T @ fne
         if self.diffusive:
             X = np.zeros_like(u)
-        elif self.linear:
+        elif self.hist_form:
             X = u * (phi - hist)[None] / self.dt
         else:
-            X = u * self.source
+            X = u * Sn[None]
         D = self.p["D0"] * (1.0 + self.p["D2"] * phi**2)
         return -(1.0 - 0.5 * s1)[None] * (m1ne + 0.5 * self.dt * X) / D[None]
 
@@ -585,6 +652,7 @@ class Model:
         d = self.d
         rho = np.asarray(rho, dtype=np.float64).reshape(n)
         I = np.eye(d)[:, :, None]
+        Sn, Fn, _ = self._sources(n, None)
         if self.nse:
             u = np.asarray(u, dtype=np.float64).reshape(d, n)
             rr = np.full_like(rho, self.rho0) if self.hl else rho                 # A19
@@ -592,16 +660,13 @@ class Model:
             if with_fne:
                 Mt = Mt + self.m2_ne(rr, u)
             feq = g_eq(self.C, self.w, self.c, self.cs2, rho, rr[None] * u, Mt)
-            Sb, Fb = self.source, self.force
-            F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, Sb),
-                     np.repeat(Fb[:, None], n, axis=1), -self.cs2 * Sb * np.repeat(I, n, axis=2))
+            F = g_eq(self.C, self.w, self.c, self.cs2, Sn, Fn, -self.cs2 * Sn[None, None] * I)
         else:
             u = np.repeat(self.adv[:, None], n, axis=1)
-            Mt = (np.zeros((d, d, n)) if (self.linear or self.diffusive)
+            Mt = (np.zeros((d, d, n)) if (self.hist_form or self.diffusive)
                   else rho[None, None] * np.einsum("an,bn->abn", u, u))
             feq = g_eq(self.C, self.w, self.c, self.cs2, rho, rho[None] * u, Mt)
-            F = g_eq(self.C, self.w, self.c, self.cs2, np.full(n, self.source),
-                     np.zeros((d, n)), np.zeros((d, d, n)))
+            F = g_eq(self.C, self.w, self.c, self.cs2, Sn, np.zeros((d, n)), np.zeros((d, d, n)))
         return feq - self.half_src * self.dt * F
 
     def velocity_gradient(self, u):
@@ -660,9 +725,9 @@ class Model:
         for k, (a, b) in enumerate(self.pairs):
             out[a, b] = -v[d + k]
             out[b, a] = -v[d + k]
-        Fb, Sb = self.force, self.source
-        out -= 0.5 * self.dt * (np.einsum("an,b->abn", u, Fb) + np.einsum("a,bn->abn", Fb, u)
-                                + self.cs2 * Sb * I)
+        Sn, Fn, _ = self._sources(n, None)
+        out -= 0.5 * self.dt * (np.einsum("an,bn->abn", u, Fn) + np.einsum("an,bn->abn", Fn, u)
+                                + self.cs2 * Sn[None, None] * I)
         return out
 
 

@@ -98,8 +98,8 @@ def _hill(lat, n, dx, D, adv, sigma, steps, drop_g=False):
         # planted omission: the dB/dt auxiliary distribution G set to zero
         full = m.distributions
 
-        def without_g(fbar, phi_prev=None):
-            feq, F, G, s1 = full(fbar, phi_prev)
+        def without_g(fbar, phi_prev=None, sel=None):
+            feq, F, G, s1 = full(fbar, phi_prev, sel)
             return feq, F, np.zeros_like(G), s1
         m.distributions = without_g
     d = m.d
