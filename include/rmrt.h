@@ -122,6 +122,12 @@ enum { RMRT_OUT_F64 = 0, RMRT_OUT_F32 = 1 };                       /* macroscopi
  *   nu_b_axis[3]  NSE: per-axis bulk viscosities K_mu_b,aa = rho nu_b_axis[a]
  *             of eq. 4-29 (set s_b,a); entries <= 0 take nu_b (a zero-initialised
  *             struct is the isotropic model)
+ *   c_zero    NCDE on rD2Q9 / rD3Q19 / rD3Q27: 1 selects the C = 0 form of
+ *             eq. 4-16 (the second branch of eq. 4-11): f_eq = g_eq(phi, phi adv, 0)
+ *             and G_j = g_eq(0, (1 - s_1/2) dB/dt, 0) with dB/dt = adv (phi -
+ *             phi_prev) / dt from the previous step's phi, kept in a
+ *             library-owned field as on rD2Q5 / rD3Q7 (which always take
+ *             this form); 0 = C = phi adv adv (the first branch)
  */
 typedef struct rmrt_params {
   int lattice, equation, storage, pattern;
@@ -143,6 +149,7 @@ typedef struct rmrt_params {
   double nu_b_axis[3];
   int gamma0;
   int diffusive;
+  int c_zero;
 } rmrt_params;
 
 /* Values the library derives from a parameter set (host only, no GPU). */
@@ -202,6 +209,35 @@ int rmrt_init(rmrt_ctx** out, const rmrt_params* p, void* f0, void* f1, const ui
 
 /* Re-initialise the populations of an existing context (same meaning as in rmrt_init). */
 int rmrt_set_fields(rmrt_ctx* ctx, const double* rho, const double* u, int with_fne, void* stream);
+
+/*
+ * Source and force fields that vary from node to node (eq. NSE: mass source
+ * Sbar(x) and body-force density Fbar(x); eq. NCDE: source S(x)), in place of
+ * the constant source and force of the parameter set, which are then ignored.
+ *   S  device array of N values: Sbar (NSE) or S (NCDE); NULL = zero
+ *   F  device array of d*N values, SoA (component a of node i at a*N + i):
+ *      Fbar (NSE only; RMRT_EINVAL for the NCDE); NULL = zero
+ * Element type: double for RMRT_F64 storage, float otherwise.  Both NULL
+ * detaches the fields (the constants apply again).  The arrays are borrowed:
+ * every step reads the values they hold when it runs, so the caller may
+ * change them between steps (stream-ordered) for sources that vary in time;
+ * the steps of one multi-step call (one graph) see the same values.
+ * Every formula takes the node's value: rho = sum fbar + dt Sbar/2, u =
+ * (sum c fbar + dt Fbar/2) / rho (eq. 2-4-2), F_j = g_eq(Sbar, Fbar, -cs2 Sbar
+ * I) and M_2G (eq. NSEFeq, M2GComput a); phi = sum fbar + dt S/2 (eq. 2-4-1),
+ * F_j = w_j S (eq. 4-14-1).  In the gamma = 0 NCDE form (gamma0 = 1, eq. 2-1)
+ * the step adds dt (F(t) - F(t - dt)) / 2 with F(t - dt) the source the
+ * previous step read, kept by the library in a field of N values that this
+ * call allocates and sets to S (the first step sees no difference).  The
+ * initial state of rmrt_init / rmrt_set_fields (fbar = f_eq - dt F/2) takes
+ * the fields attached at that time: attach, then (re)initialise.
+ * Extra algorithmic bytes per update: one read of S (and d of F for the NSE)
+ * in the working precision; with gamma = 0 one more read and one write.
+ * Local outputs (rmrt_local_gradients, rmrt_step_local) return
+ * RMRT_EUNSUPPORTED while fields are attached; RMRT_EINVAL on a domain of a
+ * batch.  Drops the context's cached graphs; synchronises stream.
+ */
+int rmrt_set_source_fields(rmrt_ctx* ctx, const void* S, const void* F, void* stream);
 
 /*
  * Advance nsteps >= 0 time steps (eq. 2-2-3 then propagation with halfway

@@ -297,6 +297,45 @@ __device__ __forceinline__ T gmom(const Coef<T>& C, T A, const T (&B)[3], const 
   }
 }
 
+// Source terms of one node: the parameter set's constants (F_CONST) or the
+// node's field values (F_FIELD), in the form the collision uses (every term
+// carries its factor dt; half_* are the half-step corrections of eq. 2-4).
+// diff is dt/2 times the explicit difference S(t) - S(t - dt) of the gamma = 0
+// NCDE form (eq. 2-1), zero otherwise.
+template <typename T>
+struct NodeSrc {
+  T source, half_source, cs2_source, half_cs2_source, force[3], half_force[3], diff;
+};
+template <typename T>
+__device__ __forceinline__ NodeSrc<T> const_sources(const Coef<T>& C) {
+  NodeSrc<T> s;
+  s.source = C.source;
+  s.half_source = C.half_source;
+  s.cs2_source = C.cs2_source;
+  s.half_cs2_source = C.half_cs2_source;
+  for (int a = 0; a < 3; ++a) {
+    s.force[a] = C.force[a];
+    s.half_force[a] = C.half_force[a];
+  }
+  s.diff = T(0);
+  return s;
+}
+// from the node's source S, previous-step source Sp and body force F
+template <typename T>
+__device__ __forceinline__ NodeSrc<T> field_sources(const Coef<T>& C, T S, T Sp, const T (&F)[3]) {
+  NodeSrc<T> s;
+  s.source = C.dt * S;
+  s.half_source = C.half_src_factor * S;
+  s.cs2_source = C.dt_cs2 * S;
+  s.half_cs2_source = C.half_dt_cs2 * S;
+  for (int a = 0; a < 3; ++a) {
+    s.force[a] = C.dt * F[a];
+    s.half_force[a] = C.half_dt * F[a];
+  }
+  s.diff = C.half_dt * (S - Sp);
+  return s;
+}
+
 // ----------------------------------------------------------------------------
 // Collision of one node in deviation variables (eq. 2-2-3):
 //   m* = m - S (m - m_eq') + (m_G + m_F),  m_eq' = m_eq - m_F / 2,
@@ -304,17 +343,19 @@ __device__ __forceinline__ T gmom(const Coef<T>& C, T A, const T (&B)[3], const 
 // and m_G + m_F = g_eq(Sbar, Fbar, M_2G - cs2 Sbar I) for the NSE
 // (eq. NSEfeq, NSEFeq, NSEGeq, M2GComput a), or
 // m_eq' = g_eq(phi - S/2, phi u, phi u u), m_G + m_F = g_eq(S, M_1G, 0) with
-// M_1G = (1 - s1/2) u S for the NCDE (eq. 4-14, 4-14-1, 4-11).  On rD2Q5 /
-// rD3Q7 (C = 0 form, eq. 4-16) m_eq' = g_eq(phi - S/2, phi u, 0) and
-// M_1G = (1 - s1/2) u (phi - phi_prev) / dt, with phi_prev the previous
-// step's phi of the node; phi is returned in phi_out for the next step.
+// M_1G = (1 - s1/2) u S for the NCDE (eq. 4-14, 4-14-1, 4-11).  In the C = 0
+// form (eq. 4-16: rD2Q5 / rD3Q7, or EQ_NCDE_C0) m_eq' = g_eq(phi - S/2, phi u, 0)
+// and M_1G = (1 - s1/2) u (phi - phi_prev) / dt, with phi_prev the previous
+// step's phi of the node; phi is returned in phi_out for the next step.  The
+// gamma = 0 NCDE form adds dt (F(t) - F(t - dt)) / 2 = g_eq(src.diff, 0, 0).
 // t[] holds the deviation populations in tensor slots on entry and the
-// post-collision deviations on exit.
+// post-collision deviations on exit; src holds the node's source terms.
 // ----------------------------------------------------------------------------
-template <int L, int EQ, bool FORCE, typename T, int NS>
-__device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, T phi_prev = T(0),
-                                        T* phi_out = nullptr) {
+template <int L, int EQ, int FORCE, typename T, int NS>
+__device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, const NodeSrc<T>& src,
+                                        T phi_prev = T(0), T* phi_out = nullptr) {
   constexpr int D = Lat<L>::D;
+  constexpr bool HIST = Lat<L>::linear || EQ == EQ_NCDE_C0;
   moments_fwd<D, Lat<L>::absent_mask()>(t);
 
   // slots of the first and second moments
@@ -332,10 +373,10 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, T phi_prev
   if constexpr (EQ == EQ_NSE) {
     // eq. 2-4-2; without forcing the host guarantees Fbar = 0 and Sbar = 0, so
     // the kernel does not hold the half-step corrections at all
-    const T rho = FORCE ? C.rho0 + drho + C.half_source : C.rho0 + drho;
-    const T jx = FORCE ? m1[0] + C.half_force[0] : m1[0];
-    const T jy = FORCE ? m1[1] + C.half_force[1] : m1[1];
-    const T jz = FORCE ? m1[2] + C.half_force[2] : m1[2];
+    const T rho = FORCE ? C.rho0 + drho + src.half_source : C.rho0 + drho;
+    const T jx = FORCE ? m1[0] + src.half_force[0] : m1[0];
+    const T jy = FORCE ? m1[1] + src.half_force[1] : m1[1];
+    const T jz = FORCE ? m1[2] + src.half_force[2] : m1[2];
     // u = j / rho, or j / rho0 with the He-Luo equilibrium g_eq(rho, rho0 u, rho0 u u)
     const T ir = recip(C.hl ? C.rho0 : rho);
     const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
@@ -350,40 +391,41 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, T phi_prev
     eMo[1] = jx * uz;
     eMo[2] = jy * uz;
     if constexpr (FORCE) {
-      const T hs = C.half_cs2_source;
+      const T hs = src.half_cs2_source;
       eMd[0] += hs;
       eMd[1] += hs;
       eMd[2] += hs;
       // M_2G = (I - S2/2)(u F + F u + cs2 Sbar I)   (eq. M2GComput a)
-      const T Txx = T(2) * ux * C.force[0] + C.cs2_source;
-      const T Tyy = T(2) * uy * C.force[1] + C.cs2_source;
-      const T Tzz = T(2) * uz * C.force[2] + C.cs2_source;
-      sA = C.source;
-      sB[0] = C.force[0];
-      sB[1] = C.force[1];
-      sB[2] = C.force[2];
-      sMd[0] = C.IhS[0][0] * Txx + C.IhS[0][1] * Tyy + C.IhS[0][2] * Tzz - C.cs2_source;
-      sMd[1] = C.IhS[1][0] * Txx + C.IhS[1][1] * Tyy + C.IhS[1][2] * Tzz - C.cs2_source;
-      sMd[2] = C.IhS[2][0] * Txx + C.IhS[2][1] * Tyy + C.IhS[2][2] * Tzz - C.cs2_source;
-      sMo[0] = C.ihs_off[0] * (ux * C.force[1] + uy * C.force[0]);
-      sMo[1] = C.ihs_off[1] * (ux * C.force[2] + uz * C.force[0]);
-      sMo[2] = C.ihs_off[2] * (uy * C.force[2] + uz * C.force[1]);
+      const T Txx = T(2) * ux * src.force[0] + src.cs2_source;
+      const T Tyy = T(2) * uy * src.force[1] + src.cs2_source;
+      const T Tzz = T(2) * uz * src.force[2] + src.cs2_source;
+      sA = src.source;
+      sB[0] = src.force[0];
+      sB[1] = src.force[1];
+      sB[2] = src.force[2];
+      sMd[0] = C.IhS[0][0] * Txx + C.IhS[0][1] * Tyy + C.IhS[0][2] * Tzz - src.cs2_source;
+      sMd[1] = C.IhS[1][0] * Txx + C.IhS[1][1] * Tyy + C.IhS[1][2] * Tzz - src.cs2_source;
+      sMd[2] = C.IhS[2][0] * Txx + C.IhS[2][1] * Tyy + C.IhS[2][2] * Tzz - src.cs2_source;
+      sMo[0] = C.ihs_off[0] * (ux * src.force[1] + uy * src.force[0]);
+      sMo[1] = C.ihs_off[1] * (ux * src.force[2] + uz * src.force[0]);
+      sMo[2] = C.ihs_off[2] * (uy * src.force[2] + uz * src.force[1]);
     }
   } else {
-    const T phi = FORCE ? C.rho0 + drho + C.half_source : C.rho0 + drho;   // eq. 2-4-1
+    const T phi = FORCE ? C.rho0 + drho + src.half_source : C.rho0 + drho;   // eq. 2-4-1
     const T Dphi = C.D0 * (T(1) + C.D2 * phi * phi);
     s1 = recip(T(0.5) + Dphi * C.inv_cs2_dt);                          // eq. 4-10
     eA = drho;
     eB[0] = phi * C.adv[0];
     eB[1] = phi * C.adv[1];
     eB[2] = phi * C.adv[2];
-    if constexpr (Lat<L>::linear) {
+    if constexpr (HIST) {
       for (int k = 0; k < 3; ++k) eMd[k] = eMo[k] = T(0);
       if (phi_out) *phi_out = phi;
       if constexpr (FORCE) {
         // G from dB/dt = u (phi - phi_prev) / dt, first-order difference (eq. 4-16)
         const T g = (T(1) - T(0.5) * s1) * (phi - phi_prev) * C.inv_dt;
-        sA = C.source;
+        sA = src.source;
+        if constexpr (FORCE == F_FIELD) sA += src.diff;
         sB[0] = g * C.adv_g[0];
         sB[1] = g * C.adv_g[1];
         sB[2] = g * C.adv_g[2];
@@ -397,8 +439,9 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, T phi_prev
       eMo[1] = eB[0] * C.adv_c[2];
       eMo[2] = eB[1] * C.adv_c[2];
       if constexpr (FORCE) {
-        const T g = (T(1) - T(0.5) * s1) * C.source;                    // eq. 4-11
-        sA = C.source;
+        const T g = (T(1) - T(0.5) * s1) * src.source;                  // eq. 4-11
+        sA = src.source;
+        if constexpr (FORCE == F_FIELD) sA += src.diff;
         sB[0] = g * C.adv_g[0];
         sB[1] = g * C.adv_g[1];
         sB[2] = g * C.adv_g[2];
@@ -465,7 +508,7 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, T phi_prev
       T cA, cB[3], cMd[3], cMo[3];
       combine(C.s_off[pr], cA, cB, cMd, cMo);
       t[n] = (T(1) - C.s_off[pr]) * t[n] + gmom<L, n>(C, cA, cB, cMd, cMo);
-    } else if constexpr (EQ == EQ_NCDE && ord == 1) {
+    } else if constexpr (EQ != EQ_NSE && ord == 1) {
       T cA, cB[3], cMd[3], cMo[3];
       combine(s1, cA, cB, cMd, cMo);
       t[n] = (T(1) - s1) * t[n] + gmom<L, n>(C, cA, cB, cMd, cMo);

@@ -297,14 +297,15 @@ __device__ __forceinline__ void local_node(const DomainDev& Dm, const Coef<T>& C
     const T s1 = recip(T(0.5) + Dphi * C.inv_cs2_dt);
     const T iD = recip(Dphi);
     T X = C.source;
-    if constexpr (Lat<L>::linear) X = (r - prev) * C.inv_dt;
+    if (C.hist_g) X = (r - prev) * C.inv_dt;   // C = 0 form: dB/dt = u (phi - phi_prev) / dt
     for (int a = 0; a < D; ++a)
       res[a] = -(T(1) - T(0.5) * s1) * (m1[a] - r * C.adv[a] + T(0.5) * C.dt * C.adv_g[a] * X) * iD;
   }
 }
 
-// BUF: buffer addressing (buffers below 4 GiB).
-template <int L, int ST, int EQ, bool FORCE, int BC, int PH, bool BUF>
+// BUF: buffer addressing (buffers below 4 GiB).  FORCE: F_NONE, F_CONST or
+// F_FIELD (the node's source terms read from the domain's field arrays).
+template <int L, int ST, int EQ, int FORCE, int BC, int PH, bool BUF>
 struct NodeStep {
   using R = typename StreamRes<BUF>::type;
   using SS = Store<ST>;
@@ -312,6 +313,7 @@ struct NodeStep {
   using T = typename SS::T;
   using LW = typename LinkBits<L>::W;
   static constexpr int Q = Lat<L>::Q, NS = Lat<L>::NS, D = Lat<L>::D;
+  static constexpr bool HIST = Lat<L>::linear || EQ == EQ_NCDE_C0;   // C = 0 form: previous phi
 
   T t[NS];
   Geo<D> g;
@@ -319,7 +321,9 @@ struct NodeStep {
   uint32_t idx;
   bool live;   // a fluid node to update
   bool edge;   // buffer addressing with walls: some lane of the wave has a bounced link
-  T phi_prev;  // rD2Q5 / rD3Q7: phi of the previous step
+  T phi_prev;  // C = 0 form: phi of the previous step
+  T src_s;     // F_FIELD: the node's source S (kept for the gamma = 0 previous-step field)
+  NodeSrc<T> src;
 
   // Boundary modes: 0 periodic; 1 wall faces from the coordinates (the host
   // never pairs it with a solid mask: a mask selects mode 2); 2 link words.
@@ -350,7 +354,22 @@ struct NodeStep {
       }
     }
     if (!live) return;
-    if constexpr (Lat<L>::linear) phi_prev = to_global((const T*)Dm.hist)[idx];
+    if constexpr (HIST) phi_prev = to_global((const T*)Dm.hist)[idx];
+    if constexpr (FORCE == F_FIELD) {
+      // field values of this node (null arrays are zero; every node of a
+      // domain takes the same branch)
+      const T Sn = Dm.src ? to_global((const T*)Dm.src)[idx] : T(0);
+      T F[3] = {T(0), T(0), T(0)};
+      if constexpr (EQ == EQ_NSE) {
+        if (Dm.frc)
+          for (int a = 0; a < D; ++a) F[a] = to_global((const T*)Dm.frc)[(size_t)a * Dm.N + idx];
+      }
+      const T Sp = Dm.sprev ? to_global((const T*)Dm.sprev)[idx] : Sn;
+      src_s = Sn;
+      src = field_sources<T>(C, Sn, Sp, F);
+    } else {
+      src = const_sources<T>(C);
+    }
     if constexpr (PH != PH_AA_EVEN) g.make(Dm, idx);
     edge = false;
     if constexpr (BUF && BC != 0 && PH != PH_AA_EVEN) {
@@ -458,8 +477,8 @@ struct NodeStep {
         d[J] = t[Lat<L>::slot(J)];
       });
       T prev = T(0);
-      if constexpr (Lat<L>::linear) prev = phi_prev;
-      local_node<L, EQ, T>(Dm, C, d, prev, kind, res);
+      if constexpr (HIST) prev = phi_prev;
+      local_node<L, (EQ == EQ_NSE ? EQ_NSE : EQ_NCDE), T>(Dm, C, d, prev, kind, res);
     }
     const size_t N = Dm.N;
     for (int k = 0; k < NC; ++k) {
@@ -473,12 +492,15 @@ struct NodeStep {
   // Collide and write the q post-collision populations.
   __device__ __forceinline__ void finish(const DomainDev& Dm, const Coef<T>& C, gmem<S>* fout, R rout) {
     if (!live) return;
-    if constexpr (Lat<L>::linear) {
+    if constexpr (HIST) {
       T phi;
-      collide<L, EQ, FORCE>(t, C, phi_prev, &phi);
+      collide<L, EQ, FORCE>(t, C, src, phi_prev, &phi);
       to_global((T*)Dm.hist)[idx] = phi;
     } else {
-      collide<L, EQ, FORCE>(t, C);
+      collide<L, EQ, FORCE>(t, C, src);
+    }
+    if constexpr (FORCE == F_FIELD) {
+      if (Dm.sprev) to_global((T*)Dm.sprev)[idx] = src_s;   // F(t - dt) of the next step
     }
     const uint32_t LD = Dm.ld;   // stream stride
     if constexpr (BUF && BC != 0 && PH != PH_AA_EVEN) {
@@ -538,7 +560,7 @@ enum : uint32_t {
 // nodes are read before either collides, so each wave keeps 2 q loads in
 // flight).  BUF selects buffer addressing of the population streams (the host
 // sets it only where every population buffer is below 4 GiB).
-template <int L, int ST, int EQ, bool FORCE, int BC, int PH, int NPT, bool BUF>
+template <int L, int ST, int EQ, int FORCE, int BC, int PH, int NPT, bool BUF>
 __global__ void __launch_bounds__(256)
     k_step(const DomainDev* __restrict__ doms, const Tile* __restrict__ tiles, uint32_t ntiles,
            uint32_t tile_nodes, uint32_t parity, uint32_t flags) {
@@ -625,7 +647,7 @@ __global__ void __launch_bounds__(256)
 // rate or grad phi of the state the step starts from, computed from the loaded
 // deviations in the step's working precision).  One workgroup per tile, one
 // node per thread, 64-bit addressing.
-template <int L, int ST, int EQ, bool FORCE, int BC, int PH>
+template <int L, int ST, int EQ, int FORCE, int BC, int PH>
 __global__ void __launch_bounds__(256)
     k_step_local(const DomainDev* __restrict__ doms, uint32_t tile_nodes, uint32_t parity, void* out, int kind,
                  int out_f32, int alternate) {
@@ -709,6 +731,34 @@ __device__ __forceinline__ void first_moments(const DomainDev& Dm, const double 
   m1[2] *= Dm.cd.c[2];
 }
 
+// Half-step source corrections of node idx in FP64 (eq. 2-4): dt S / 2 (0 in
+// the gamma = 0 form and at the diffusive scaling), dt F / 2 and dt cs2 S / 2,
+// from the parameter set or, when fields are attached, from the node's values.
+struct HalfSrc {
+  double source, force[3], cs2_source;
+};
+__device__ __forceinline__ HalfSrc half_sources(const DomainDev& Dm, uint32_t idx) {
+  const Coef<double>& C = Dm.cd;
+  HalfSrc h;
+  if (!Dm.src_field) {
+    h.source = C.half_source;
+    for (int a = 0; a < 3; ++a) h.force[a] = C.half_force[a];
+    h.cs2_source = C.half_cs2_source;
+    return h;
+  }
+  const bool dbl = Dm.storage == ST_F64;
+  auto at = [&](const void* p, size_t i) {
+    return dbl ? ((const double*)p)[i] : (double)((const float*)p)[i];
+  };
+  const double S = Dm.src ? at(Dm.src, idx) : 0.0;
+  h.source = C.half_src_factor * S;
+  h.cs2_source = C.half_dt_cs2 * S;
+  const int d = (Dm.lattice == LAT_Q9 || Dm.lattice == LAT_Q5) ? 2 : 3;
+  for (int a = 0; a < 3; ++a)
+    h.force[a] = (Dm.frc && Dm.equation == EQ_NSE && a < d) ? C.half_dt * at(Dm.frc, (size_t)a * Dm.N + idx) : 0.0;
+  return h;
+}
+
 // rho (or phi) and u of node idx (eq. 2-4-1 / eq. 2-4-2)
 template <int L, int ST, int EQ, int BC, bool SWAPPED>
 __device__ __forceinline__ void macro_node(const DomainDev& Dm, const typename Store<ST>::S* f,
@@ -719,13 +769,14 @@ __device__ __forceinline__ void macro_node(const DomainDev& Dm, const typename S
   double drho, m1[3];
   first_moments<L>(Dm, d, drho, m1);
   const Coef<double>& C = Dm.cd;
-  rho = C.rho0 + drho + C.half_source;
-  drho_out = drho + C.half_source;
+  const HalfSrc h = half_sources(Dm, idx);
+  rho = C.rho0 + drho + h.source;
+  drho_out = drho + h.source;
   if constexpr (EQ == EQ_NSE) {
     const double ir = 1.0 / (C.hl ? C.rho0 : rho);   // He-Luo: rho0 u = j
-    u[0] = (m1[0] + C.half_force[0]) * ir;
-    u[1] = (m1[1] + C.half_force[1]) * ir;
-    u[2] = (m1[2] + C.half_force[2]) * ir;
+    u[0] = (m1[0] + h.force[0]) * ir;
+    u[1] = (m1[1] + h.force[1]) * ir;
+    u[2] = (m1[2] + h.force[2]) * ir;
   } else {
     u[0] = C.adv[0];
     u[1] = C.adv[1];
@@ -812,7 +863,7 @@ __global__ void __launch_bounds__(256)
       double d[Lat<L>::Q];
       gather64<L, ST, BC, SWAPPED>(Dm, f, idx, d);
       double prev = 0.0;
-      if constexpr (Lat<L>::linear)
+      if (Dm.hist)   // C = 0 form
         prev = (ST == ST_F64) ? ((const double*)Dm.hist)[idx] : (double)((const float*)Dm.hist)[idx];
       local_node<L, EQ, double>(Dm, C, d, prev, kind, res);
     }
@@ -863,11 +914,12 @@ __global__ void __launch_bounds__(256)
     gather64<L, ST, BC, SWAPPED>(Dm, f, idx, d);
     double drho, m1[3];
     first_moments<L>(Dm, d, drho, m1);
-    acc[0] += drho + Dm.cd.half_source;
+    const HalfSrc h = half_sources(Dm, idx);
+    acc[0] += drho + h.source;
     if constexpr (EQ == EQ_NSE) {
-      acc[1] += m1[0] + Dm.cd.half_force[0];
-      acc[2] += m1[1] + Dm.cd.half_force[1];
-      acc[3] += m1[2] + Dm.cd.half_force[2];
+      acc[1] += m1[0] + h.force[0];
+      acc[2] += m1[1] + h.force[1];
+      acc[3] += m1[2] + h.force[2];
     }
     acc[4] += 1.0;
   }
@@ -982,15 +1034,16 @@ __global__ void __launch_bounds__(256)
     g.make(Dm, idx);
     const double r = rho_in ? rho_in[idx] : C.rho0;
     double A, B[3] = {0, 0, 0}, M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    const HalfSrc h = half_sources(Dm, idx);
     if constexpr (EQ == EQ_NSE) {
       double u[3] = {0, 0, 0};
       if (u_in)
         for (int a = 0; a < D; ++a) u[a] = u_in[(size_t)a * N + idx];
       const double ru = C.hl ? C.rho0 : r;   // He-Luo: g_eq(rho, rho0 u, rho0 u u)
-      A = r - C.rho0 - C.half_source;
-      for (int a = 0; a < 3; ++a) B[a] = ru * u[a] - C.half_force[a];
+      A = r - C.rho0 - h.source;
+      for (int a = 0; a < 3; ++a) B[a] = ru * u[a] - h.force[a];
       for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) M[a][b] = ru * u[a] * u[b] + (a == b ? C.half_cs2_source : 0.0);
+        for (int b = 0; b < 3; ++b) M[a][b] = ru * u[a] * u[b] + (a == b ? h.cs2_source : 0.0);
       if (with_fne && u_in && !(Dm.has_solid && Dm.solid[idx])) {
         // m_2^ne = -(I - S2/2)^-1 tau - dt/2 (u F + F u + cs2 Sbar I)   (eq. 4-34)
         double G[3][3];
@@ -1013,19 +1066,18 @@ __global__ void __launch_bounds__(256)
         mne[0][1] = mne[1][0] = -Dm.ic.k_off[0] * tau[0][1];
         mne[0][2] = mne[2][0] = -Dm.ic.k_off[1] * tau[0][2];
         mne[1][2] = mne[2][1] = -Dm.ic.k_off[2] * tau[1][2];
-        // (C.half_force and C.half_cs2_source already carry the factor dt / 2)
+        // (the half-step corrections already carry the factor dt / 2)
         for (int a = 0; a < 3; ++a)
           for (int b = 0; b < 3; ++b)
-            M[a][b] += mne[a][b] - (u[a] * C.half_force[b] + C.half_force[a] * u[b] +
-                                    (a == b ? C.half_cs2_source : 0.0));
+            M[a][b] += mne[a][b] - (u[a] * h.force[b] + h.force[a] * u[b] + (a == b ? h.cs2_source : 0.0));
       }
     } else {
-      A = r - C.rho0 - C.half_source;
+      A = r - C.rho0 - h.source;
       for (int a = 0; a < 3; ++a) B[a] = r * C.adv[a];
       if constexpr (!Lat<L>::linear)
         for (int a = 0; a < 3; ++a)
-          for (int b = 0; b < 3; ++b) M[a][b] = r * C.adv_c[a] * C.adv_c[b];   // 0 at the diffusive scaling
-      else if (!(Dm.has_solid && Dm.solid[idx]))
+          for (int b = 0; b < 3; ++b) M[a][b] = r * C.adv_c[a] * C.adv_c[b];   // 0 in the C = 0 forms
+      if (Dm.hist && !(Dm.has_solid && Dm.solid[idx]))
         ((typename Store<ST>::T*)Dm.hist)[idx] = (typename Store<ST>::T)r;   // dB/dt = 0 at the first step
     }
     // g_eq_j = w_j (A + c_j.B / cs2 + sum_a M_aa (c_ja^2 - cs2) / (cs2 (c_a^2 - cs2))

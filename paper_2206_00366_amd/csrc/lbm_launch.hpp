@@ -5,9 +5,14 @@
 
 namespace rmrt {
 
-template <int L, int ST, int EQ, bool F, int BC, int PH, bool BUF>
+// Field sources and the C = 0 NCDE form have a one-node-per-thread kernel
+// only: with STEP_WIDE_TILES it walks each 512-node tile in two passes.
+template <int L, int ST, int EQ, int F, int BC, int PH, bool BUF>
 void do_step_npt(const StepLaunch& a) {
-  if (a.flags & STEP_WIDE_TILES)
+  if constexpr (F == F_FIELD || EQ == EQ_NCDE_C0)
+    hipLaunchKernelGGL((k_step<L, ST, EQ, F, BC, PH, 1, BUF>), dim3(a.grid), dim3(a.block), a.lds_bytes, a.stream,
+                       a.doms, a.tiles, a.ntiles, a.tile_nodes, a.parity, a.flags);
+  else if (a.flags & STEP_WIDE_TILES)
     hipLaunchKernelGGL((k_step<L, ST, EQ, F, BC, PH, 2, BUF>), dim3(a.grid), dim3(a.block), a.lds_bytes, a.stream,
                        a.doms, a.tiles, a.ntiles, a.tile_nodes, a.parity, a.flags);
   else
@@ -16,13 +21,17 @@ void do_step_npt(const StepLaunch& a) {
 }
 // STEP_BUFFER_OFFSETS reaches here only for buffers below 4 GiB (the host
 // clears it otherwise).
-template <int L, int ST, int EQ, bool F, int BC, int PH>
+template <int L, int ST, int EQ, int F, int BC, int PH>
 hipError_t do_step(const StepLaunch& a) {
   if (a.local_out) {
-    hipLaunchKernelGGL((k_step_local<L, ST, EQ, F, BC, PH>), dim3(a.ntiles), dim3(a.block), a.lds_bytes, a.stream,
-                       a.doms, a.tile_nodes, a.parity, a.local_out, a.local_kind, a.local_f32,
-                       (int)((a.flags & STEP_ALTERNATE_ORDER) != 0));
-    return hipGetLastError();
+    if constexpr (F == F_FIELD) {
+      return hipErrorInvalidValue;   // local outputs take the constant sources only (host-checked)
+    } else {
+      hipLaunchKernelGGL((k_step_local<L, ST, EQ, F, BC, PH>), dim3(a.ntiles), dim3(a.block), a.lds_bytes,
+                         a.stream, a.doms, a.tile_nodes, a.parity, a.local_out, a.local_kind, a.local_f32,
+                         (int)((a.flags & STEP_ALTERNATE_ORDER) != 0));
+      return hipGetLastError();
+    }
   }
   if (a.flags & STEP_BUFFER_OFFSETS)
     do_step_npt<L, ST, EQ, F, BC, PH, true>(a);
@@ -30,7 +39,7 @@ hipError_t do_step(const StepLaunch& a) {
     do_step_npt<L, ST, EQ, F, BC, PH, false>(a);
   return hipGetLastError();
 }
-template <int L, int ST, int EQ, bool F, int BC>
+template <int L, int ST, int EQ, int F, int BC>
 hipError_t step_ph(const StepLaunch& a) {
   switch (a.phase) {
     case PH_AB: return do_step<L, ST, EQ, F, BC, PH_AB>(a);
@@ -39,7 +48,7 @@ hipError_t step_ph(const StepLaunch& a) {
   }
   return hipErrorInvalidValue;
 }
-template <int L, int ST, int EQ, bool F>
+template <int L, int ST, int EQ, int F>
 hipError_t step_bc(const StepLaunch& a) {
   switch (a.bc) {
     case 0: return step_ph<L, ST, EQ, F, 0>(a);
@@ -50,14 +59,25 @@ hipError_t step_bc(const StepLaunch& a) {
 }
 template <int L, int ST, int EQ>
 hipError_t step_f(const StepLaunch& a) {
-  return a.force ? step_bc<L, ST, EQ, true>(a) : step_bc<L, ST, EQ, false>(a);
+  switch (a.force) {
+    case F_NONE: return step_bc<L, ST, EQ, F_NONE>(a);
+    case F_CONST: return step_bc<L, ST, EQ, F_CONST>(a);
+    case F_FIELD: return step_bc<L, ST, EQ, F_FIELD>(a);
+  }
+  return hipErrorInvalidValue;
 }
 template <int L, int ST>
 hipError_t launch_step(const StepLaunch& a) {
-  if constexpr (Lat<L>::linear)   // rD2Q5 / rD3Q7 carry the NCDE only
-    return a.eq == EQ_NCDE ? step_f<L, ST, EQ_NCDE>(a) : hipErrorInvalidValue;
-  else
-    return a.eq == EQ_NCDE ? step_f<L, ST, EQ_NCDE>(a) : step_f<L, ST, EQ_NSE>(a);
+  if constexpr (Lat<L>::linear) {   // rD2Q5 / rD3Q7 carry the NCDE only, always in the C = 0 form
+    return (a.eq == EQ_NCDE || a.eq == EQ_NCDE_C0) ? step_f<L, ST, EQ_NCDE>(a) : hipErrorInvalidValue;
+  } else {
+    switch (a.eq) {
+      case EQ_NSE: return step_f<L, ST, EQ_NSE>(a);
+      case EQ_NCDE: return step_f<L, ST, EQ_NCDE>(a);
+      case EQ_NCDE_C0: return step_f<L, ST, EQ_NCDE_C0>(a);
+    }
+    return hipErrorInvalidValue;
+  }
 }
 
 // ---- companions: dispatch over (eq, bc, swapped) ----

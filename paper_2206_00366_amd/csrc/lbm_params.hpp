@@ -7,7 +7,12 @@
 namespace rmrt {
 
 enum { LAT_Q9 = 0, LAT_Q19 = 1, LAT_Q27 = 2, LAT_Q5 = 3, LAT_Q7 = 4 };
-enum { EQ_NSE = 0, EQ_NCDE = 1 };
+// EQ_NCDE_C0: the NCDE in the C = 0 form of eq. 4-16 on the full lattices
+// (rD2Q5 / rD3Q7 always take that form under EQ_NCDE)
+enum { EQ_NSE = 0, EQ_NCDE = 1, EQ_NCDE_C0 = 2 };
+// source terms of a step: none, the parameter set's constants, or per-node
+// fields (mass or NCDE source, body force; read per node and step)
+enum { F_NONE = 0, F_CONST = 1, F_FIELD = 2 };
 enum { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2 };
 enum { PH_AB = 0, PH_AA_EVEN = 1, PH_AA_ODD = 2 };
 
@@ -36,7 +41,13 @@ struct Coef {
   T adv[3], D0, D2, inv_cs2_dt, inv_dt;
   T adv_c[3];               // NCDE: adv in C = phi u u (0 at the diffusive scaling, eq. 4-17)
   T adv_g[3];               // NCDE: adv in M_1G (0 at the diffusive scaling: G = 0)
+  // per-node source fields: source = dt S, half_source = half_src_factor S
+  // (0.5 dt, or 0 in the gamma = 0 form and at the diffusive scaling),
+  // cs2_source = dt_cs2 S, half_cs2_source = half_dt_cs2 S, force = dt F,
+  // half_force = half_dt F
+  T half_dt, dt_cs2, half_dt_cs2, half_src_factor;
   uint32_t hl;              // He-Luo equilibrium (1) or eq. NSEfeq (0)
+  uint32_t hist_g;          // NCDE: G from dB/dt with the previous step's phi (C = 0 form of eq. 4-16)
 };
 
 // Initialisation-only quantities (always FP64).
@@ -67,8 +78,16 @@ struct DomainDev {
   const uint8_t* solid;     // 1 byte per node or null
   const void* links;        // per-node link bits (uint16 for q <= 15, uint32 otherwise) or null:
                             // bit j = link x -> x + e_j hits a wall or solid; top bit = solid node
-  void* hist;               // rD2Q5 / rD3Q7: phi of the previous step per node (double for FP64
-                            // storage, float otherwise); null on the other lattices
+  void* hist;               // C = 0 NCDE form: phi of the previous step per node (double for FP64
+                            // storage, float otherwise); null otherwise
+  // per-node source fields (working precision: double for FP64 storage, float
+  // otherwise), used when src_field is set: S (N values; null = 0), F (d x N
+  // SoA body force, NSE; null = 0), and in the gamma = 0 NCDE form the
+  // source of the previous step (N values, library-owned; null otherwise)
+  const void* src;
+  const void* frc;
+  void* sprev;
+  uint32_t src_field;
 };
 
 // One unit of persistent-kernel work: nodes [start, start + count) of a domain.

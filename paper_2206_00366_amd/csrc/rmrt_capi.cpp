@@ -221,6 +221,8 @@ int derive(const rmrt_params* p, Derived& v) {
     if (p->incompressible) return fail(RMRT_EINVAL, "the He-Luo equilibrium is an NSE option");
   }
   if (p->equation == RMRT_NSE && p->gamma0) return fail(RMRT_EINVAL, "gamma = 0 is an NCDE option (eq. 2-1)");
+  if (p->equation == RMRT_NSE && p->c_zero) return fail(RMRT_EINVAL, "the C = 0 form is an NCDE option (eq. 4-16)");
+  if (p->c_zero && p->diffusive) return fail(RMRT_EINVAL, "c_zero and diffusive are different NCDE models");
   if (p->equation == RMRT_NSE && p->diffusive) return fail(RMRT_EINVAL, "the diffusive scaling is an NCDE option");
   if (p->equation != RMRT_NSE) {
     if (!(p->D0 > 0)) return fail(RMRT_EINVAL, "D0 must be > 0 for the NCDE");
@@ -349,11 +351,20 @@ void fill_coef(const rmrt_params* p, const Derived& v, Coef<T>& C) {
   // no dt S / 2 shift (eq. 2-1 without the dt^2/2 D F term)
   const bool no_shift = p->equation == RMRT_NCDE && (p->gamma0 || p->diffusive);
   C.half_source = no_shift ? (T)0 : (T)(0.5 * dt * p->source);
+  // C = 0 form (eq. 4-16: the reduced lattices, or the c_zero option): no
+  // C = phi u u in the equilibrium, G from dB/dt with the history field
+  const bool c0 = p->equation == RMRT_NCDE && (lattice_linear(p->lattice) || p->c_zero);
   for (int a = 0; a < 3; ++a) {
     const bool diff = p->equation == RMRT_NCDE && p->diffusive;
-    C.adv_c[a] = diff ? (T)0 : C.adv[a];   // eq. 4-17: C = 0 and G = 0
-    C.adv_g[a] = diff ? (T)0 : C.adv[a];
+    C.adv_c[a] = (diff || c0) ? (T)0 : C.adv[a];   // eq. 4-17 and eq. 4-16: C = 0
+    C.adv_g[a] = diff ? (T)0 : C.adv[a];           // eq. 4-17: G = 0
   }
+  C.hist_g = c0 ? 1u : 0u;
+  // factors of the per-node source fields
+  C.half_dt = (T)(0.5 * dt);
+  C.dt_cs2 = (T)(dt * cs2);
+  C.half_dt_cs2 = (T)(0.5 * dt * cs2);
+  C.half_src_factor = no_shift ? (T)0 : (T)(0.5 * dt);
   C.cs2_source = (T)(dt * cs2 * p->source);
   C.half_cs2_source = (T)(0.5 * dt * cs2 * p->source);
   C.D0 = (T)p->D0;
@@ -410,9 +421,13 @@ void fill_domain(const rmrt_params* p, const Derived& v, DomainDev& D, void* fa,
   D.solid = solid;
 }
 
+bool c_zero_form(const rmrt_params* p) {
+  return p->equation == RMRT_NCDE && (lattice_linear(p->lattice) || p->c_zero);
+}
+
 bool has_force(const rmrt_params* p) {
   if (p->source != 0.0) return true;
-  if (lattice_linear(p->lattice))   // the dB/dt term G of eq. 4-16
+  if (c_zero_form(p))   // the dB/dt term G of eq. 4-16
     for (int a = 0; a < 3; ++a)
       if (p->adv[a] != 0.0) return true;
   if (p->equation == RMRT_NSE)
@@ -580,6 +595,7 @@ struct rmrt_ctx {
   int blocks_per_cu = kDefaultBlocksPerCU;  // resident workgroups per CU (0: hardware limit)
   uint32_t flags = kDefaultFlags;
   int device = 0;              // the device current at creation
+  void* sprev = nullptr;       // gamma = 0 NCDE with source fields: the previous step's source (library-owned)
 };
 
 namespace {
@@ -659,6 +675,7 @@ void ctx_release(rmrt_ctx* c) {
   if (c->uprev) (void)hipFree(c->uprev);
   if (c->links) (void)hipFree(c->links);
   if (c->hist) (void)hipFree(c->hist);
+  if (c->sprev) (void)hipFree(c->sprev);
   if (c->owns_ddoms && c->ddoms) (void)hipFree(c->ddoms);
 }
 
@@ -690,6 +707,16 @@ int launch_init_fields(rmrt_ctx* c, const double* rho, const double* u, int with
   return RMRT_OK;
 }
 
+// Equation and source mode of a context's step kernel.
+int step_eq(const rmrt_ctx* c) {
+  if (c->p.equation == RMRT_NCDE && c->p.c_zero && !lattice_linear(c->p.lattice)) return EQ_NCDE_C0;
+  return c->p.equation;
+}
+int step_force(const rmrt_ctx* c) {
+  if (c->hdom.src_field) return F_FIELD;
+  return has_force(&c->p) ? F_CONST : F_NONE;
+}
+
 // Buffer addressing takes 32-bit byte offsets: it serves domains whose
 // population buffer is below 4 GiB.  Elsewhere the flag is a no-op.
 bool buffer_offsets_apply(const rmrt_ctx* c) {
@@ -707,8 +734,8 @@ int launch_one_step(rmrt_ctx* c, long long step_index, hipStream_t s) {
   a.flags = c->flags;
   if (!buffer_offsets_apply(c)) a.flags &= ~STEP_BUFFER_OFFSETS;
   a.parity = (uint32_t)(step_index & 1);
-  a.eq = c->p.equation;
-  a.force = has_force(&c->p);
+  a.eq = step_eq(c);
+  a.force = step_force(c);
   a.bc = c->step_bc;
   a.phase = c->p.pattern == RMRT_AB ? PH_AB : ((step_index & 1) ? PH_AA_ODD : PH_AA_EVEN);
   a.grid = persistent_grid(a.ntiles, c->cus, c->blocks_per_cu, c->flags);
@@ -907,7 +934,7 @@ static int ctx_create(rmrt_ctx** out, const rmrt_params* p, void* f0, void* f1, 
     delete c;
     return rc;
   }
-  if (lattice_linear(p->lattice)) {
+  if (c_zero_form(p)) {
     hipError_t e = hipMalloc(&c->hist, (p->storage == RMRT_F64 ? 8 : 4) * (size_t)c->hdom.N);
     if (e != hipSuccess) {
       ctx_release(c);
@@ -974,6 +1001,39 @@ int rmrt_set_fields(rmrt_ctx* c, const double* rho, const double* u, int with_fn
   return launch_init_fields(c, rho, u, with_fne, (hipStream_t)stream);
 }
 
+int rmrt_set_source_fields(rmrt_ctx* c, const void* S, const void* F, void* stream) {
+  if (!c) return fail(RMRT_EINVAL, "ctx is NULL");
+  if (c->batch) return fail(RMRT_EINVAL, "source fields are not offered on the domains of a batch");
+  if (F && c->p.equation != RMRT_NSE) return fail(RMRT_EINVAL, "a body-force field is an NSE input");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t es = c->p.storage == RMRT_F64 ? 8 : 4;
+  const size_t N = c->hdom.N;
+  drop_graphs(c->graphs);   // cached graphs were captured for the previous source mode
+  if (!S && !F) {
+    c->hdom.src_field = 0;
+    c->hdom.src = c->hdom.frc = nullptr;
+    c->hdom.sprev = nullptr;
+  } else {
+    c->hdom.src_field = 1;
+    c->hdom.src = S;
+    c->hdom.frc = F;
+    if (c->p.equation == RMRT_NCDE && c->p.gamma0) {
+      // F(t - dt) of the gamma = 0 form: the attached source (no difference at the first step)
+      if (!c->sprev) HIP_TRY(hipMalloc(&c->sprev, es * N));
+      if (S)
+        HIP_TRY(hipMemcpyAsync(c->sprev, S, es * N, hipMemcpyDeviceToDevice, s));
+      else
+        HIP_TRY(hipMemsetAsync(c->sprev, 0, es * N, s));
+      c->hdom.sprev = c->sprev;
+    } else {
+      c->hdom.sprev = nullptr;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(c->ddoms + c->dom, &c->hdom, sizeof(DomainDev), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return RMRT_OK;
+}
+
 int rmrt_step(rmrt_ctx* c, int nsteps, void* stream) {
   if (!c) return fail(RMRT_EINVAL, "ctx is NULL");
   if (c->batch) return fail(RMRT_EINVAL, "domain belongs to a batch: use rmrt_batch_step");
@@ -1031,6 +1091,8 @@ int rmrt_moments(rmrt_ctx* c, void* rho_out, void* u_out, int out_dtype, void* s
 namespace {
 int check_local_args(const rmrt_ctx* c, int kind, const void* out, int out_dtype) {
   if (!c || !out) return fail(RMRT_EINVAL, "ctx or out is NULL");
+  if (c->hdom.src_field)
+    return fail(RMRT_EUNSUPPORTED, "local outputs take the parameter set's constant sources (fields attached)");
   if (out_dtype != RMRT_OUT_F64 && out_dtype != RMRT_OUT_F32) return fail(RMRT_EINVAL, "bad out_dtype");
   const bool nse = c->p.equation == RMRT_NSE;
   if (kind == RMRT_GRAD_STRAIN || kind == RMRT_GRAD_STRESS) {
@@ -1074,8 +1136,8 @@ int rmrt_step_local(rmrt_ctx* c, int kind, void* out, int out_dtype, void* strea
   a.ntiles = (c->hdom.N + a.tile_nodes - 1) / a.tile_nodes;
   a.flags = c->flags & STEP_ALTERNATE_ORDER;
   a.parity = (uint32_t)(c->steps & 1);
-  a.eq = c->p.equation;
-  a.force = has_force(&c->p);
+  a.eq = step_eq(c);
+  a.force = step_force(c);
   a.bc = c->step_bc;
   a.phase = c->p.pattern == RMRT_AB ? PH_AB : ((c->steps & 1) ? PH_AA_ODD : PH_AA_EVEN);
   a.grid = a.ntiles;
@@ -1458,8 +1520,8 @@ int rmrt_batch_create(rmrt_batch** out, int nd, const rmrt_params* params, void*
   for (int d = 1; d < nd; ++d) {
     const rmrt_params& p = params[d];
     if (p.lattice != p0.lattice || p.equation != p0.equation || p.storage != p0.storage ||
-        p.pattern != p0.pattern)
-      return fail(RMRT_EINVAL, "domain %d differs in lattice/equation/storage/pattern", d);
+        p.pattern != p0.pattern || (p.c_zero != 0) != (p0.c_zero != 0))
+      return fail(RMRT_EINVAL, "domain %d differs in lattice/equation/storage/pattern/c_zero", d);
   }
   hipStream_t s = (hipStream_t)stream;
   rmrt_batch* b = new (std::nothrow) rmrt_batch();
@@ -1490,6 +1552,7 @@ int rmrt_batch_create(rmrt_batch** out, int nd, const rmrt_params* params, void*
     }
     c->batch = b;
     b->ctxs.push_back(c);
+    b->equation = step_eq(c);
     b->force |= has_force(&params[d]) ? 1 : 0;
     b->bc = std::max(b->bc, c->step_bc);
   }

@@ -52,7 +52,7 @@ class Params(C.Structure):
         ("D0", C.c_double), ("D2", C.c_double), ("adv", C.c_double * 3), ("force", C.c_double * 3),
         ("source", C.c_double), ("rho0", C.c_double), ("wall_faces", C.c_uint), ("check_every", C.c_int),
         ("incompressible", C.c_int), ("nu_tensor", C.c_double * 6), ("nu_b_axis", C.c_double * 3),
-        ("gamma0", C.c_int), ("diffusive", C.c_int),
+        ("gamma0", C.c_int), ("diffusive", C.c_int), ("c_zero", C.c_int),
     ]
 
 
@@ -74,6 +74,7 @@ _sig = {
     "rmrt_population_bytes": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_size_t)]),
     "rmrt_init": (C.c_int, [C.POINTER(_vp), C.POINTER(Params), _vp, _vp, _vp, _vp, _vp, C.c_int, _vp]),
     "rmrt_set_fields": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
+    "rmrt_set_source_fields": (C.c_int, [_vp, _vp, _vp, _vp]),
     "rmrt_step": (C.c_int, [_vp, C.c_int, _vp]),
     "rmrt_step_prepare": (C.c_int, [_vp, C.c_int, _vp]),
     "rmrt_moments": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
@@ -157,7 +158,7 @@ def make_params(lattice="Q9", equation="NSE", storage="f64", pattern="AB", n=(8,
                 dx=(1.0, 1.0, 1.0), dt=1.0, cs2=-1.0, nu=0.1, nu_b=-1.0, s_hi=-1.0, w_corner=-1.0,
                 D0=0.0, D2=0.0, adv=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0), source=0.0, rho0=1.0,
                 wall_faces=0, check_every=0, incompressible=False, nu_tensor=None, nu_b_axis=None,
-                gamma0=False, diffusive=False, **_ignored) -> Params:
+                gamma0=False, diffusive=False, c_zero=False, **_ignored) -> Params:
     def pad3(v, fill):
         v = list(v) + [fill] * 3
         return v[:3]
@@ -179,6 +180,7 @@ def make_params(lattice="Q9", equation="NSE", storage="f64", pattern="AB", n=(8,
     p.incompressible = int(bool(incompressible))
     p.gamma0 = int(bool(gamma0))
     p.diffusive = int(bool(diffusive))
+    p.c_zero = int(bool(c_zero))
     p.nu_tensor[:] = [float(v) for v in (nu_tensor if nu_tensor is not None else [-1.0] * 6)]
     p.nu_b_axis[:] = [float(v) for v in (nu_b_axis if nu_b_axis is not None else [-1.0] * 3)]
     return p
@@ -254,6 +256,28 @@ class Domain:
     def prepare(self, n):
         """Capture the graphs of step(n) now (no steps are taken)."""
         _check(_lib.rmrt_step_prepare(self._ctx, int(n), _stream()), "rmrt_step_prepare")
+
+    def source_dtype(self):
+        import torch
+        return torch.float64 if self.params.storage == F64 else torch.float32
+
+    def set_source_fields(self, S=None, F=None):
+        """Attach per-node source fields (device tensors of source_dtype(); S: N
+        values, F: (d, N)) or detach with both None.  The tensors are kept
+        referenced; update them in place between steps for time-varying sources."""
+        import torch
+        dt = self.source_dtype()
+
+        def dev(a, shape):
+            if a is None:
+                return None
+            t = torch.as_tensor(a, device=self.f0.device)
+            if t.dtype != dt or not t.is_contiguous():
+                raise ValueError(f"source fields must be contiguous {dt} tensors")
+            return t.view(shape)
+        self._src = (dev(S, (self.N,)), dev(F, (self.d, self.N)))
+        _check(_lib.rmrt_set_source_fields(self._ctx, _ptr(self._src[0]), _ptr(self._src[1]), _stream()),
+               "rmrt_set_source_fields")
 
     def moments(self, out_dtype=OUT_F64, with_u=True):
         import torch
