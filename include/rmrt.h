@@ -342,6 +342,29 @@ int rmrt_residual(rmrt_ctx* ctx, double* r, void* stream);
 int rmrt_steps_taken(const rmrt_ctx* ctx, long long* steps);
 
 /*
+ * Checkpoints of a context's state: a header (lattice, equation, storage,
+ * pattern, sizes, step count), the stored populations of the current state in
+ * their stored layout, and the library-held fields the next steps read (the
+ * previous step's phi of the C = 0 form; the previous-step source of the
+ * gamma = 0 form with source fields).  A context restored from a checkpoint
+ * continues bit for bit as the saved context would have (same kernels, same
+ * parity).  Caller-owned inputs (solid mask, source fields) are not part of
+ * the checkpoint.
+ *   rmrt_checkpoint_bytes   size of the checkpoint of ctx (host only)
+ *   rmrt_checkpoint_save    writes it to dst (device or host memory of that
+ *                           size); synchronises stream
+ *   rmrt_checkpoint_restore reads it from src into ctx, which must have the
+ *                           same lattice, equation, storage, pattern, size and
+ *                           c_zero, and the same previous-step source field
+ *                           (attached, or not); sets the step count and restarts
+ *                           the residual; synchronises stream.  RMRT_EINVAL for
+ *                           a mismatch, a foreign buffer or a domain of a batch.
+ */
+int rmrt_checkpoint_bytes(const rmrt_ctx* ctx, size_t* bytes);
+int rmrt_checkpoint_save(rmrt_ctx* ctx, void* dst, void* stream);
+int rmrt_checkpoint_restore(rmrt_ctx* ctx, const void* src, void* stream);
+
+/*
  * Launch shape of rmrt_step.  flags = 0: one workgroup per 256-node tile
  * (hardware scheduling); blocks_per_cu > 0 then caps the resident workgroups
  * per compute unit through dynamic LDS (0 = no cap).  flags & RMRT_LAUNCH_

@@ -1218,6 +1218,109 @@ int rmrt_steps_taken(const rmrt_ctx* c, long long* steps) {
   return RMRT_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Checkpoints: a header, then the stored populations of the current state in
+// their stored layout (one buffer: the AA buffer, or the AB buffer the step
+// count selects), then the C = 0 history field and the gamma = 0
+// previous-step source when the context has them.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr uint64_t kCkptMagic = 0x3150434b54524d52ull;   // "RMRTCKP1"
+struct CkptHeader {
+  uint64_t magic;
+  int32_t lattice, equation, storage, pattern, n[3], c_zero;
+  uint32_t ld, has_hist, has_sprev, pad;
+  int64_t steps;
+  uint64_t pop_bytes, field_bytes;
+};
+static_assert(sizeof(CkptHeader) % 16 == 0, "checkpoint payload stays 16-byte aligned");
+
+CkptHeader ckpt_header(const rmrt_ctx* c) {
+  CkptHeader h;
+  std::memset(&h, 0, sizeof(h));
+  h.magic = kCkptMagic;
+  h.lattice = c->p.lattice;
+  h.equation = c->p.equation;
+  h.storage = c->p.storage;
+  h.pattern = c->p.pattern;
+  for (int a = 0; a < 3; ++a) h.n[a] = c->p.n[a];
+  h.c_zero = c->p.c_zero ? 1 : 0;
+  h.ld = c->hdom.ld;
+  h.has_hist = c->hist != nullptr;
+  h.has_sprev = c->hdom.sprev != nullptr;
+  h.steps = c->steps;
+  h.pop_bytes = (uint64_t)lattice_q(c->p.lattice) * c->hdom.ld * elem_size(c->p.storage);
+  h.field_bytes = (uint64_t)c->hdom.N * (c->p.storage == RMRT_F64 ? 8 : 4);
+  return h;
+}
+size_t ckpt_bytes(const CkptHeader& h) {
+  return sizeof(CkptHeader) + h.pop_bytes + (h.has_hist + h.has_sprev) * h.field_bytes;
+}
+void* current_population_buffer(const rmrt_ctx* c) {
+  return (c->p.pattern == RMRT_AB && (c->steps & 1)) ? c->hdom.fb : c->hdom.fa;
+}
+}  // namespace
+
+extern "C" {
+
+int rmrt_checkpoint_bytes(const rmrt_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(RMRT_EINVAL, "NULL argument");
+  *bytes = ckpt_bytes(ckpt_header(c));
+  return RMRT_OK;
+}
+
+int rmrt_checkpoint_save(rmrt_ctx* c, void* dst, void* stream) {
+  if (!c || !dst) return fail(RMRT_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const CkptHeader h = ckpt_header(c);
+  char* out = (char*)dst;
+  HIP_TRY(hipMemcpyAsync(out, &h, sizeof(h), hipMemcpyDefault, s));
+  size_t off = sizeof(h);
+  HIP_TRY(hipMemcpyAsync(out + off, current_population_buffer(c), h.pop_bytes, hipMemcpyDefault, s));
+  off += h.pop_bytes;
+  if (h.has_hist) {
+    HIP_TRY(hipMemcpyAsync(out + off, c->hist, h.field_bytes, hipMemcpyDefault, s));
+    off += h.field_bytes;
+  }
+  if (h.has_sprev) HIP_TRY(hipMemcpyAsync(out + off, c->hdom.sprev, h.field_bytes, hipMemcpyDefault, s));
+  HIP_TRY(hipStreamSynchronize(s));   // the header copy reads a host local
+  return RMRT_OK;
+}
+
+int rmrt_checkpoint_restore(rmrt_ctx* c, const void* src, void* stream) {
+  if (!c || !src) return fail(RMRT_EINVAL, "NULL argument");
+  if (c->batch) return fail(RMRT_EINVAL, "domain belongs to a batch: its step count is the batch's");
+  hipStream_t s = (hipStream_t)stream;
+  CkptHeader h;
+  HIP_TRY(hipMemcpyAsync(&h, src, sizeof(h), hipMemcpyDefault, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const CkptHeader mine = ckpt_header(c);
+  if (h.magic != kCkptMagic) return fail(RMRT_EINVAL, "not a checkpoint of this library");
+  if (h.lattice != mine.lattice || h.equation != mine.equation || h.storage != mine.storage ||
+      h.pattern != mine.pattern || h.n[0] != mine.n[0] || h.n[1] != mine.n[1] || h.n[2] != mine.n[2] ||
+      h.c_zero != mine.c_zero || h.ld != mine.ld)
+    return fail(RMRT_EINVAL, "checkpoint of a different lattice, equation, storage, pattern or size");
+  if (h.has_hist != mine.has_hist || h.has_sprev != mine.has_sprev)
+    return fail(RMRT_EINVAL, "checkpoint %s a previous-step source field the context %s",
+                h.has_sprev ? "holds" : "lacks", mine.has_sprev ? "has" : "has not");
+  if (h.steps < 0) return fail(RMRT_EINVAL, "checkpoint step count %lld < 0", (long long)h.steps);
+  const char* in = (const char*)src;
+  size_t off = sizeof(h);
+  c->steps = h.steps;   // selects the layout (AA) or the buffer (AB) written next
+  HIP_TRY(hipMemcpyAsync(current_population_buffer(c), in + off, h.pop_bytes, hipMemcpyDefault, s));
+  off += h.pop_bytes;
+  if (h.has_hist) {
+    HIP_TRY(hipMemcpyAsync(c->hist, in + off, h.field_bytes, hipMemcpyDefault, s));
+    off += h.field_bytes;
+  }
+  if (h.has_sprev) HIP_TRY(hipMemcpyAsync(c->hdom.sprev, in + off, h.field_bytes, hipMemcpyDefault, s));
+  c->have_prev = false;   // the residual restarts from the restored state
+  HIP_TRY(hipStreamSynchronize(s));
+  return RMRT_OK;
+}
+
 int rmrt_set_launch(rmrt_ctx* c, int blocks_per_cu, int flags) {
   if (!c) return fail(RMRT_EINVAL, "ctx is NULL");
   if (blocks_per_cu < 0 || blocks_per_cu > 32) return fail(RMRT_EINVAL, "blocks_per_cu must be in [0, 32]");

@@ -83,6 +83,9 @@ _sig = {
     "rmrt_reduce_noalloc": (C.c_int, [_vp, _vp, _vp]),
     "rmrt_residual": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
     "rmrt_steps_taken": (C.c_int, [_vp, C.POINTER(C.c_longlong)]),
+    "rmrt_checkpoint_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
+    "rmrt_checkpoint_save": (C.c_int, [_vp, _vp, _vp]),
+    "rmrt_checkpoint_restore": (C.c_int, [_vp, _vp, _vp]),
     "rmrt_set_launch": (C.c_int, [_vp, C.c_int, C.c_int]),
     "rmrt_get_launch": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "rmrt_tune": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(C.c_int)]),
@@ -321,6 +324,18 @@ class Domain:
         r = C.c_double()
         _check(_lib.rmrt_residual(self._ctx, C.byref(r), _stream()), "rmrt_residual")
         return r.value
+
+    def checkpoint(self, device="cuda"):
+        """The context's checkpoint in a new uint8 tensor (device or "cpu")."""
+        import torch
+        n = C.c_size_t()
+        _check(_lib.rmrt_checkpoint_bytes(self._ctx, C.byref(n)), "rmrt_checkpoint_bytes")
+        buf = torch.empty(n.value, dtype=torch.uint8, device=device)
+        _check(_lib.rmrt_checkpoint_save(self._ctx, _ptr(buf), _stream()), "rmrt_checkpoint_save")
+        return buf
+
+    def restore(self, buf):
+        _check(_lib.rmrt_checkpoint_restore(self._ctx, _ptr(buf), _stream()), "rmrt_checkpoint_restore")
 
     def steps_taken(self):
         s = C.c_longlong()

@@ -1,0 +1,91 @@
+"""Checkpoints (rmrt_checkpoint_save / rmrt_checkpoint_restore): a context
+stepped N1 steps, saved, and stepped N2 more must equal, bit for bit, a fresh
+context restored from the save and stepped N2 (odd N1 exercises the AA
+parity; the C = 0 form carries its previous-step phi, the gamma = 0 form with
+source fields its previous-step source), from device and from host memory;
+mismatched contexts are refused."""
+import numpy as np
+import pytest
+
+from gpu_util import WALLS, circle_mask, random_fields
+from oracle import rmrt_oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_00366_amd import rmrt
+    return rmrt
+
+
+CASES = {
+    "q19_f32_aa": (dict(lattice="Q19", n=(21, 13, 9), dx=(1.0, 0.5, 2.0), nu=0.03), "f32dev", "AA"),
+    "q9_f64_ab_solid_force": (dict(lattice="Q9", n=(40, 21, 1), dx=(1.0, 0.5, 1.0), nu=0.05, force=(2e-5, 0.0, 0.0),
+                                   wall_faces=WALLS["y"]), "f64", "AB"),
+    "q27_f16_aa_walls": (dict(lattice="Q27", n=(11, 9, 8), dx=(1.0, 2.0, 1.0), nu=0.05, wall_faces=WALLS["yz"]),
+                         "f16dev", "AA"),
+    "q7_history": (dict(lattice="Q7", equation="NCDE", n=(11, 9, 7), dx=(1.0, 1.0, 2.0), D0=0.02, D2=0.5,
+                        adv=(0.03, 0.01, -0.02), rho0=0.0, source=1e-4), "f32dev", "AA"),
+    "q9_czero_gamma0_fields": (dict(lattice="Q9", equation="NCDE", n=(33, 17, 1), dx=(1.0, 0.5, 1.0), D0=0.01,
+                                    D2=1.0, adv=(0.05, 0.02, 0.0), rho0=0.0, gamma0=True, c_zero=True),
+                               "f64", "AA"),
+}
+
+
+def _make(R, case, seed):
+    prm, storage, pattern = CASES[case]
+    solid = circle_mask(prm["n"], (12, 10), 4) if "solid" in case else None
+    m = O.Model(prm, solid=solid)
+    rho, u = random_fields(m, seed, du=0.02 if m.nse else 0.0)
+    dom = R.Domain(R.make_params(**prm, storage=storage, pattern=pattern), rho, u if m.nse else None,
+                   solid=None if solid is None else solid.astype(np.uint8))
+    if "fields" in case:
+        S = torch.tensor(1e-4 * np.random.default_rng(3).uniform(-1, 1, m.N), dtype=dom.source_dtype(),
+                         device="cuda")
+        dom.set_source_fields(S)
+        dom.set_fields(rho)
+    return dom
+
+
+@pytest.mark.parametrize("where", ["cuda", "cpu"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_n_plus_restore_plus_n_equals_2n(R, case, where):
+    a = _make(R, case, seed=1)
+    b = _make(R, case, seed=2)          # a different state, overwritten by the restore
+    n1, n2 = 7, 300                     # odd first leg; a graph chunk and a remainder after
+    a.step(n1)
+    ckpt = a.checkpoint(device=where)
+    a.step(n2)
+    b.restore(ckpt)
+    assert b.steps_taken() == n1
+    b.step(n2)
+    torch.cuda.synchronize()
+    assert a.steps_taken() == b.steps_taken() == n1 + n2
+    fa, fb = a.populations().cpu().numpy(), b.populations().cpu().numpy()
+    assert np.array_equal(fa, fb), np.abs(fa - fb).max()
+    # restoring into the context itself rewinds it
+    a.restore(ckpt)
+    a.step(n2)
+    assert np.array_equal(a.populations().cpu().numpy(), fb)
+    a.close()
+    b.close()
+
+
+def test_mismatched_restore_is_refused(R):
+    a = _make(R, "q19_f32_aa", 1)
+    ckpt = a.checkpoint()
+    prm, storage, pattern = CASES["q19_f32_aa"]
+    other = R.Domain(R.make_params(**dict(prm, n=(21, 13, 8)), storage=storage, pattern=pattern),
+                     np.ones(21 * 13 * 8), np.zeros((3, 21 * 13 * 8)))
+    with pytest.raises(R.RMRTError) as e:
+        other.restore(ckpt)
+    assert e.value.code == R.EINVAL
+    junk = torch.zeros_like(ckpt)
+    with pytest.raises(R.RMRTError):
+        a.restore(junk)
+    a.close()
+    other.close()
