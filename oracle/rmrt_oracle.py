@@ -70,8 +70,18 @@ GPU side can take the same ones; numbering as in the design notes):
       difference dt (F(t) - F(t - dt)) / 2 with F(t - dt) the source the
       previous step used; at the first step after the fields are set it is
       taken equal to F(t).
+  A25 central-moment (cascaded) collision (option central, NSE on rD2Q9 and
+      rD3Q27, whose moment sets are closed under the shift): the moments are
+      kappa = N(u) M fbar with N(u) the binomial shift of eq. 5-1-1 at the
+      node's u, and the relaxation matrix in that basis has the blocks of the
+      raw-moment model (the full second-order block from nu and nu_b, s_ab on
+      the off-diagonal second moments, s_hi above); equilibrium, auxiliary and
+      source moments are N(u) times the raw ones, so the step is eq. 2-2-3 with
+      Lambda = M^-1 N^-1 S N M (eq. 5-1-2).
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -249,7 +259,7 @@ DEFAULTS = dict(lattice="Q9", equation="NSE", n=(8, 8, 1), dx=(1.0, 1.0, 1.0), d
                 cs2=-1.0, nu=0.1, nu_b=-1.0, s_hi=-1.0, w_corner=-1.0,
                 D0=0.0, D2=0.0, adv=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0),
                 source=0.0, rho0=1.0, wall_faces=0, incompressible=False, nu_tensor=None, nu_b_axis=None,
-                gamma0=False, diffusive=False, c_zero=False)
+                gamma0=False, diffusive=False, c_zero=False, central=False)
 
 
 class Model:
@@ -268,6 +278,10 @@ class Model:
         # reduced lattices (A18), an option on the others (A23)
         self.c_zero = bool(p["c_zero"]) and not self.nse
         self.hist_form = self.linear or self.c_zero
+        # central-moment (cascaded) collision, eq. 5-1-1 / 5-1-2 (A25)
+        self.central = bool(p["central"])
+        if self.central and not (self.nse and self.lattice in ("Q9", "Q27")):
+            raise ValueError("the central-moment collision is built for the NSE on rD2Q9 and rD3Q27")
         E = unit_offsets(self.lattice)
         self.E = E
         self.q, self.d = E.shape
@@ -363,6 +377,7 @@ class Model:
             self.P1[r, r] = 1.0
         self._build_streaming(solid)
         self.S_node = self.F_node = self.S_prev = None
+        self.S_central = None      # a relaxation matrix for the central moments other than S (tests only)
 
     # ------------------------------------------------------------------ sources
     def set_sources(self, S=None, F=None):
@@ -512,6 +527,21 @@ class Model:
             out[b, a] = v2[self.d + k]
         return out
 
+    def shift_matrix(self, u):
+        """N(u) of eq. 5-1-1 for the central moments: row i (exponents a) holds
+        prod_axis binom(a, b) (-u)^(a - b) at column k (exponents b <= a), so that
+        N(u) M f = sum_j prod_axis (c_j - u)^a f_j.  u: (d, n); returns (q, q, n)."""
+        q, n = self.q, u.shape[1]
+        N = np.zeros((q, q, n))
+        for i, ea in enumerate(self.exps):
+            for k, eb in enumerate(self.exps):
+                if all(b <= a for a, b in zip(ea, eb)):
+                    v = np.ones(n)
+                    for ax, (a, b) in enumerate(zip(ea, eb)):
+                        v = v * math.comb(a, b) * (-u[ax]) ** (a - b)
+                    N[i, k] = v
+        return N
+
     def apply_S(self, x, s1=None):
         """S x with S the block relaxation matrix; NCDE adds s_1(phi) on the first-order rows."""
         y = self.S @ x
@@ -527,6 +557,16 @@ class Model:
         meq = self.M @ feq
         mF = self.M @ F
         mG = self.M @ G
+        if self.central:
+            # the same step in the central moments kappa = N(u) m (eq. 5-1-1), whose
+            # relaxation matrix Sbar has this model's blocks (eq. 5-1-2, A25)
+            _, u = self.macroscopic(fbar, sel)
+            N = self.shift_matrix(u)
+            k, keq, kF, kG = (np.einsum("ikn,kn->in", N, v) for v in (m, meq, mF, mG))
+            Sb = self.S_central if self.S_central is not None else self.S
+            kstar = k - Sb @ (k - keq) + self.dt * (kG + kF - 0.5 * (Sb @ kF))
+            mstar = np.stack([np.linalg.solve(N[:, :, j], kstar[:, j]) for j in range(kstar.shape[1])], axis=1)
+            return np.linalg.solve(self.M, mstar)
         mD = self.M @ self.source_difference(fbar.shape[1], sel)
         # gamma = 1 (eq. 2-3): dt (G + (I - Lambda/2) F); gamma = 0 (eq. 2-1, A21):
         # dt (G + F + (F(t) - F(t - dt)) / 2)
@@ -537,9 +577,19 @@ class Model:
     def collide_velocity_space(self, fbar, phi_prev=None, sel=None):
         """Same collision written in velocity space with Lambda = M^-1 S M (eq. 2-3, eq. 5-1)."""
         feq, F, G, s1 = self.distributions(fbar, phi_prev, sel)
+        if self.central:
+            _, u = self.macroscopic(fbar, sel)
+            N = self.shift_matrix(u)
+            Sb = self.S_central if self.S_central is not None else self.S
+            # per node: Lambda = M^-1 N^-1 Sbar N M (eq. 5-1-2)
+            Lam_n = np.stack([self.Minv @ np.linalg.solve(N[:, :, j], Sb @ N[:, :, j]) @ self.M
+                              for j in range(fbar.shape[1])], axis=2)
 
-        def Lam(x):
-            return self.Minv @ self.apply_S(self.M @ x, s1)
+            def Lam(x):
+                return np.einsum("jkn,kn->jn", Lam_n, x)
+        else:
+            def Lam(x):
+                return self.Minv @ self.apply_S(self.M @ x, s1)
 
         return (fbar - Lam(fbar - feq) + self.dt * (G + F - self.half_src * Lam(F))
                 + self.dt * self.source_difference(fbar.shape[1], sel))
