@@ -128,6 +128,15 @@ enum { RMRT_OUT_F64 = 0, RMRT_OUT_F32 = 1 };                       /* macroscopi
  *             phi_prev) / dt from the previous step's phi, kept in a
  *             library-owned field as on rD2Q5 / rD3Q7 (which always take
  *             this form); 0 = C = phi adv adv (the first branch)
+ *   central   NSE on rD2Q9 / rD3Q27: 1 relaxes in the central moments
+ *             kappa = N(u) M fbar (the cascaded basis of eq. 5-1-1, N(u) the
+ *             binomial shift by the node's u) with the same relaxation blocks
+ *             as the raw-moment model (full second-order block from nu, nu_b;
+ *             s_ab; s_hi above) and the equilibrium, auxiliary and source
+ *             moments shifted alike, so Lambda = M^-1 N^-1 S N M (eq. 5-1-2);
+ *             the recovered NSE is the same, the higher moments relax in the
+ *             frame moving with the fluid.  RMRT_EUNSUPPORTED on the other
+ *             lattices; local outputs are refused with it.
  */
 typedef struct rmrt_params {
   int lattice, equation, storage, pattern;
@@ -150,6 +159,7 @@ typedef struct rmrt_params {
   int gamma0;
   int diffusive;
   int c_zero;
+  int central;
 } rmrt_params;
 
 /* Values the library derives from a parameter set (host only, no GPU). */

@@ -268,6 +268,42 @@ __device__ __forceinline__ void moments_inv(T (&t)[NS]) {
   });
 }
 
+// Central-moment shift (eq. 5-1-1) in the scaled basis: along each axis the
+// line (m0, m1, m2) becomes (m0, m1 - v m0, m2 - 2 v m1 + v^2 m0) with
+// v = u_a / c_a (the binomial shift of c_a^k m~_k by u_a), and back with -v.
+template <int D, typename T, int NS>
+__device__ __forceinline__ void central_shift(T (&t)[NS], const T (&v)[3]) {
+  static_for<0, D>([&](auto ax_) {
+    constexpr int ax = decltype(ax_)::value;
+    constexpr int st = axis_stride(ax);
+    const T w = v[ax];
+    static_for<0, NS>([&](auto b_) {
+      constexpr int b = decltype(b_)::value;
+      if constexpr ((b / st) % 3 == 0) {
+        const T m0 = t[b], m1 = t[b + st], m2 = t[b + 2 * st];
+        t[b + st] = m1 - w * m0;
+        t[b + 2 * st] = m2 - w * (T(2) * m1 - w * m0);
+      }
+    });
+  });
+}
+template <int D, typename T, int NS>
+__device__ __forceinline__ void central_unshift(T (&t)[NS], const T (&v)[3]) {
+  static_for<0, D>([&](auto ax_) {
+    constexpr int ax = decltype(ax_)::value;
+    constexpr int st = axis_stride(ax);
+    const T w = v[ax];
+    static_for<0, NS>([&](auto b_) {
+      constexpr int b = decltype(b_)::value;
+      if constexpr ((b / st) % 3 == 0) {
+        const T k0 = t[b], k1 = t[b + st], k2 = t[b + 2 * st];
+        t[b + st] = k1 + w * k0;
+        t[b + 2 * st] = k2 + w * (T(2) * k1 + w * k0);
+      }
+    });
+  });
+}
+
 // Scaled raw moment n of g_eq(A, B, M) (eq. 3-3): only the terms that the
 // lattice parity leaves non-zero are emitted.  Md = (Mxx, Myy, Mzz),
 // Mo = (Mxy, Mxz, Myz).
@@ -356,6 +392,9 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, const Node
                                         T phi_prev = T(0), T* phi_out = nullptr) {
   constexpr int D = Lat<L>::D;
   constexpr bool HIST = Lat<L>::linear || EQ == EQ_NCDE_C0;
+  constexpr bool NSE = EQ == EQ_NSE || EQ == EQ_NSE_CENTRAL;
+  static_assert(EQ != EQ_NSE_CENTRAL || L == LAT_Q9 || L == LAT_Q27,
+                "the central-moment collision needs a moment set closed under the shift");
   moments_fwd<D, Lat<L>::absent_mask()>(t);
 
   // slots of the first and second moments
@@ -370,7 +409,8 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, const Node
   T eA, eB[3], eMd[3], eMo[3];
   T sA = T(0), sB[3] = {T(0), T(0), T(0)}, sMd[3] = {T(0), T(0), T(0)}, sMo[3] = {T(0), T(0), T(0)};
   T s1 = T(0);
-  if constexpr (EQ == EQ_NSE) {
+  T vc[3] = {T(0), T(0), T(0)};   // u_a / c_a of the central-moment shift
+  if constexpr (NSE) {
     // eq. 2-4-2; without forcing the host guarantees Fbar = 0 and Sbar = 0, so
     // the kernel does not hold the half-step corrections at all
     const T rho = FORCE ? C.rho0 + drho + src.half_source : C.rho0 + drho;
@@ -380,6 +420,11 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, const Node
     // u = j / rho, or j / rho0 with the He-Luo equilibrium g_eq(rho, rho0 u, rho0 u u)
     const T ir = recip(C.hl ? C.rho0 : rho);
     const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    if constexpr (EQ == EQ_NSE_CENTRAL) {
+      vc[0] = ux * C.inv_c[0];
+      vc[1] = uy * C.inv_c[1];
+      vc[2] = uz * C.inv_c[2];
+    }
     eA = drho;
     eB[0] = m1[0];
     eB[1] = m1[1];
@@ -449,7 +494,49 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, const Node
     }
   }
 
-  if constexpr (EQ == EQ_NSE) {
+  if constexpr (EQ == EQ_NSE_CENTRAL) {
+    // kappa* = kappa - Sbar (kappa - kappa_eq') + kappa_s with kappa = N(u) m and
+    // the equilibrium and source moments shifted the same way (eq. 5-1-2); Sbar
+    // has the raw model's blocks.  Conserved central moments are at their
+    // equilibrium (kappa_0 = rho', kappa_1 = j - rho u = -dt F / 2), so only the
+    // source is added to them.
+    T e[NS], sv[NS];
+    static_for<0, NS>([&](auto n_) {
+      constexpr int n = decltype(n_)::value;
+      e[n] = gmom<L, n>(C, eA, eB, eMd, eMo);
+      if constexpr (FORCE) sv[n] = gmom<L, n>(C, sA, sB, sMd, sMo);
+    });
+    central_shift<D>(t, vc);
+    central_shift<D>(e, vc);
+    if constexpr (FORCE) central_shift<D>(sv, vc);
+    T nd[3] = {t[sxx] - e[sxx], t[syy] - e[syy], D == 3 ? t[szz] - e[szz] : T(0)};
+    static_for<0, NS>([&](auto n_) {
+      constexpr int n = decltype(n_)::value;
+      constexpr int a = n % 3, b = (n / 3) % 3, p = n / 9;
+      constexpr int ord = a + b + p;
+      constexpr bool diag2 = (n == sxx || n == syy || n == szz);
+      T r;
+      if constexpr (ord <= 1) {
+        r = T(0);
+      } else if constexpr (diag2) {
+        constexpr int ax = (n == sxx) ? 0 : (n == syy ? 1 : 2);
+        r = C.Sd[ax][0] * nd[0] + C.Sd[ax][1] * nd[1];
+        if constexpr (D == 3) r += C.Sd[ax][2] * nd[2];
+      } else if constexpr (ord == 2) {
+        constexpr int pr = (p == 0) ? 0 : ((a == 1) ? 1 : 2);
+        r = C.s_off[pr] * (t[n] - e[n]);
+      } else {
+        r = C.s_hi * (t[n] - e[n]);
+      }
+      t[n] -= r;
+      if constexpr (FORCE) t[n] += sv[n];
+    });
+    central_unshift<D>(t, vc);
+    moments_inv<D, Lat<L>::dropped_mask()>(t);
+    return;
+  }
+
+  if constexpr (NSE) {
     // second-order diagonal block: full (D x D) relaxation matrix, scaled basis
     T nd[3];
     nd[0] = t[sxx] - gmom<L, sxx>(C, eA, eB, eMd, eMo);
@@ -499,16 +586,16 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, const Node
     constexpr bool diag2 = (n == sxx || n == syy || n == szz);
     if constexpr (Lat<L>::dropped(n)) {
       t[n] = T(0);
-    } else if constexpr (ord == 0 || (EQ == EQ_NSE && (ord == 1 || diag2))) {
+    } else if constexpr (ord == 0 || (NSE && (ord == 1 || diag2))) {
       // conserved (eq. 4-18-1), or NSE momentum (its rate is irrelevant), or
       // the diagonal second moments relaxed above: only the source is added
       if constexpr (FORCE) t[n] += gmom<L, n>(C, sA, sB, sMd, sMo);
-    } else if constexpr (EQ == EQ_NSE && ord == 2) {
+    } else if constexpr (NSE && ord == 2) {
       constexpr int pr = (p == 0) ? 0 : ((a == 1) ? 1 : 2);
       T cA, cB[3], cMd[3], cMo[3];
       combine(C.s_off[pr], cA, cB, cMd, cMo);
       t[n] = (T(1) - C.s_off[pr]) * t[n] + gmom<L, n>(C, cA, cB, cMd, cMo);
-    } else if constexpr (EQ != EQ_NSE && ord == 1) {
+    } else if constexpr (!NSE && ord == 1) {
       T cA, cB[3], cMd[3], cMo[3];
       combine(s1, cA, cB, cMd, cMo);
       t[n] = (T(1) - s1) * t[n] + gmom<L, n>(C, cA, cB, cMd, cMo);

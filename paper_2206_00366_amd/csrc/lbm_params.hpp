@@ -9,7 +9,9 @@ namespace rmrt {
 enum { LAT_Q9 = 0, LAT_Q19 = 1, LAT_Q27 = 2, LAT_Q5 = 3, LAT_Q7 = 4 };
 // EQ_NCDE_C0: the NCDE in the C = 0 form of eq. 4-16 on the full lattices
 // (rD2Q5 / rD3Q7 always take that form under EQ_NCDE)
-enum { EQ_NSE = 0, EQ_NCDE = 1, EQ_NCDE_C0 = 2 };
+// EQ_NSE_CENTRAL: the NSE with the central-moment collision of eq. 5-1-1 /
+// 5-1-2 (rD2Q9 and rD3Q27)
+enum { EQ_NSE = 0, EQ_NCDE = 1, EQ_NCDE_C0 = 2, EQ_NSE_CENTRAL = 3 };
 // source terms of a step: none, the parameter set's constants, or per-node
 // fields (mass or NCDE source, body force; read per node and step)
 enum { F_NONE = 0, F_CONST = 1, F_FIELD = 2 };
@@ -22,7 +24,7 @@ enum { PH_AB = 0, PH_AA_EVEN = 1, PH_AA_ODD = 2 };
 template <typename T>
 struct Coef {
   T rho0, cs2, inv_cs2, dt;
-  T c[3];
+  T c[3], inv_c[3];
   T w[27], iw[27];          // weights in paper order and their reciprocals
   // the same by weight class (0 rest, 1-3 x/y/z axes, 4-6 xy/xz/yz edges, 7
   // corners): every velocity of a class has the same weight (Sec. III), so

@@ -223,6 +223,12 @@ int derive(const rmrt_params* p, Derived& v) {
   if (p->equation == RMRT_NSE && p->gamma0) return fail(RMRT_EINVAL, "gamma = 0 is an NCDE option (eq. 2-1)");
   if (p->equation == RMRT_NSE && p->c_zero) return fail(RMRT_EINVAL, "the C = 0 form is an NCDE option (eq. 4-16)");
   if (p->c_zero && p->diffusive) return fail(RMRT_EINVAL, "c_zero and diffusive are different NCDE models");
+  if (p->central) {
+    if (p->equation != RMRT_NSE) return fail(RMRT_EINVAL, "the central-moment collision is an NSE option");
+    if (p->lattice != RMRT_Q9 && p->lattice != RMRT_Q27)
+      return fail(RMRT_EUNSUPPORTED, "the central-moment collision is built for rD2Q9 and rD3Q27 (moment sets "
+                                     "closed under the shift)");
+  }
   if (p->equation == RMRT_NSE && p->diffusive) return fail(RMRT_EINVAL, "the diffusive scaling is an NCDE option");
   if (p->equation != RMRT_NSE) {
     if (!(p->D0 > 0)) return fail(RMRT_EINVAL, "D0 must be > 0 for the NCDE");
@@ -281,7 +287,10 @@ void fill_coef(const rmrt_params* p, const Derived& v, Coef<T>& C) {
   C.cs2 = (T)v.cs2;
   C.inv_cs2 = (T)(1.0 / v.cs2);
   C.dt = (T)dt;
-  for (int a = 0; a < 3; ++a) C.c[a] = (T)v.c[a];
+  for (int a = 0; a < 3; ++a) {
+    C.c[a] = (T)v.c[a];
+    C.inv_c[a] = (T)(1.0 / v.c[a]);
+  }
   for (int j = 0; j < 27; ++j) {
     C.w[j] = (T)v.w[j];
     C.iw[j] = v.w[j] > 0 ? (T)(1.0 / v.w[j]) : (T)0;
@@ -710,6 +719,7 @@ int launch_init_fields(rmrt_ctx* c, const double* rho, const double* u, int with
 // Equation and source mode of a context's step kernel.
 int step_eq(const rmrt_ctx* c) {
   if (c->p.equation == RMRT_NCDE && c->p.c_zero && !lattice_linear(c->p.lattice)) return EQ_NCDE_C0;
+  if (c->p.equation == RMRT_NSE && c->p.central) return EQ_NSE_CENTRAL;
   return c->p.equation;
 }
 int step_force(const rmrt_ctx* c) {
@@ -1093,6 +1103,7 @@ int check_local_args(const rmrt_ctx* c, int kind, const void* out, int out_dtype
   if (!c || !out) return fail(RMRT_EINVAL, "ctx or out is NULL");
   if (c->hdom.src_field)
     return fail(RMRT_EUNSUPPORTED, "local outputs take the parameter set's constant sources (fields attached)");
+  if (c->p.central) return fail(RMRT_EUNSUPPORTED, "local outputs are built for the raw-moment collision");
   if (out_dtype != RMRT_OUT_F64 && out_dtype != RMRT_OUT_F32) return fail(RMRT_EINVAL, "bad out_dtype");
   const bool nse = c->p.equation == RMRT_NSE;
   if (kind == RMRT_GRAD_STRAIN || kind == RMRT_GRAD_STRESS) {
@@ -1623,8 +1634,8 @@ int rmrt_batch_create(rmrt_batch** out, int nd, const rmrt_params* params, void*
   for (int d = 1; d < nd; ++d) {
     const rmrt_params& p = params[d];
     if (p.lattice != p0.lattice || p.equation != p0.equation || p.storage != p0.storage ||
-        p.pattern != p0.pattern || (p.c_zero != 0) != (p0.c_zero != 0))
-      return fail(RMRT_EINVAL, "domain %d differs in lattice/equation/storage/pattern/c_zero", d);
+        p.pattern != p0.pattern || (p.c_zero != 0) != (p0.c_zero != 0) || (p.central != 0) != (p0.central != 0))
+      return fail(RMRT_EINVAL, "domain %d differs in lattice/equation/storage/pattern/c_zero/central", d);
   }
   hipStream_t s = (hipStream_t)stream;
   rmrt_batch* b = new (std::nothrow) rmrt_batch();
