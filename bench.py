@@ -287,6 +287,7 @@ def main():
     wall_c, ev_c, _ = run_single(torch, R, prm_h, rho_h, u_h, K, W, settle_s=0.0)
     log("[bench] HBM copy ceiling")
     ceiling = copy_ceiling(torch, R)
+    mall_ceiling = copy_ceiling(torch, R, nbytes=96 << 20, reps=400)
     log("[bench] headline rD3Q19 256x256x128 f32dev AA")
     launch = {}
     wall, ev_ms, finite = run_single(torch, R, prm_h, rho_h, u_h, K, W, launch=launch)
@@ -404,6 +405,10 @@ def main():
            "roofline": roofline}
     if ceiling:
         out["hbm_copy_ceiling"] = ceiling
+        mall_ceiling["note"] = ("the same copy over 96 MiB source and destination, which stay in the 256 MB "
+                                "memory-side cache (MALL) from pass to pass: the most any reuse of data across "
+                                "steps through that cache could reach")
+        out["mall_copy_ceiling"] = mall_ceiling
         roofline["frac_of_copy_ceiling"] = round(achieved / ceiling["GBps"], 4)
         roofline["note"] = ("achieved = algorithmic bytes / kernel time; with the alternating tile order each step "
                             "starts on data the 256 MB MALL still holds from the previous step, so achieved can "
@@ -507,7 +512,25 @@ def bench_batch(torch, R, steps, warmup, nd=64, nmin=32, nmax=256, seq_steps=20)
     e["autotuned_config"] = dict(zip(CONFIG_KEYS, R.Batch.configs()[cfg]))
     gbytes, ngroups = b.group_bytes()
     e["autotuned_groups"] = {"group_bytes": gbytes, "groups": ngroups}
+    mode, nchunked = b.xcd_chunks()
+    e["autotuned_xcd_chunks"] = {"mode": mode, "groups_with_straddling_rows": nchunked}
     e["finite"] = fin
+    # the single persistent launch per step (one group): its best tile shape
+    b.set_group_bytes(0)
+    best = None
+    for k, shape in enumerate(R.Batch.configs()):
+        if not shape[3]:
+            continue
+        b.set_config(k)
+        w_k, ev_k = timed_steps(torch, b.step, min(steps, 20), 4, prepare=b.prepare)
+        if best is None or ev_k < best[1]:
+            best = (k, ev_k, min(steps, 20))
+    k, ev_k, n_k = best
+    e["persistent_single_launch"] = {
+        "MLUPS": round(total * n_k / (ev_k * 1e-3) / 1e6, 1),
+        "kernel_GBps": round(total * 2 * 27 * sizeof("f32dev") / (ev_k / n_k * 1e-3) / 1e9, 1),
+        "config": dict(zip(CONFIG_KEYS, R.Batch.configs()[k])), "steps": n_k,
+        "note": "best persistent tile shape with every domain in one launch per step (HIP events)"}
     b.close()
     del b
     torch.cuda.empty_cache()

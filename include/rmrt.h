@@ -382,9 +382,13 @@ int rmrt_checkpoint_restore(rmrt_ctx* ctx, const void* src, void* stream);
  * tiles, contiguously per XCD when flags & RMRT_LAUNCH_XCD_ORDER.
  * Default (measured on MI355X): one workgroup per tile with buffer addressing
  * and the alternating tile order (RMRT_LAUNCH_BUFFER_OFFSETS |
- * RMRT_LAUNCH_ALTERNATE_ORDER); a cap of 3 for rD3Q19 and rD3Q27 with
- * FP32/FP64 storage and for rD3Q7 FP64; XCD order for rD2Q9, rD2Q5 and rD3Q7
- * FP32/FP16.  Invalidates the context's cached graphs.
+ * RMRT_LAUNCH_ALTERNATE_ORDER); a cap of 4 for rD3Q19 FP32 and for rD3Q27
+ * FP32 with walls, a solid mask or a source / force, of 3 for the periodic,
+ * unforced rD3Q27 FP32 step, for rD3Q19 and rD3Q27 FP64 and for rD3Q7 FP64;
+ * XCD order for rD2Q9, rD2Q5 and rD3Q7 FP32/FP16; RMRT_LAUNCH_XCD_CHUNKS for
+ * the other cases whose rows (n[0] x the storage element size) are not a
+ * whole number of 128-byte cache lines.  Invalidates the context's cached
+ * graphs.
  */
 #define RMRT_LAUNCH_XCD_ORDER 1
 #define RMRT_LAUNCH_PERSISTENT 2
@@ -402,6 +406,13 @@ int rmrt_checkpoint_restore(rmrt_ctx* ctx, const void* src, void* stream);
  * of the forward order (nodes of one step are independent).  Part of every
  * default launch; batches and rmrt_tune always use it. */
 #define RMRT_LAUNCH_ALTERNATE_ORDER 16
+/* XCD chunks (one workgroup per tile; ignored by persistent grids): runs of
+ * 16 consecutive tiles go to one XCD, the eight XCDs' runs interleaved, so
+ * that cache lines straddling two tiles are mostly written through one L2
+ * (the odd AA step's neighbour offsets straddle tiles whenever a row is not a
+ * whole number of cache lines).  Results are bitwise those of the plain
+ * order. */
+#define RMRT_LAUNCH_XCD_CHUNKS 32
 int rmrt_set_launch(rmrt_ctx* ctx, int blocks_per_cu, int flags);
 int rmrt_get_launch(const rmrt_ctx* ctx, int* blocks_per_cu, int* flags);
 
@@ -409,7 +420,8 @@ int rmrt_get_launch(const rmrt_ctx* ctx, int* blocks_per_cu, int* flags);
  * Time rmrt_step over `steps` steps for one workgroup per tile with the
  * residency cap blocks_per_cu in {0 (none), 2, 3, 4, 5, 6, 8}, with 256- and
  * 512-node tiles, with and without RMRT_LAUNCH_BUFFER_OFFSETS where it
- * applies (HIP events on stream), keep the fastest and return its cap
+ * applies and RMRT_LAUNCH_XCD_CHUNKS where rows straddle cache lines (HIP
+ * events on stream), keep the fastest and return its cap
  * in *blocks_per_cu (may be NULL; rmrt_get_launch gives the flags).  The
  * timing runs advance the state.
  */
@@ -442,8 +454,11 @@ int rmrt_batch_domain(rmrt_batch* b, int d, rmrt_ctx** out);
  * steps each (HIP events on stream), keep the fastest and return its index in
  * *chosen (may be NULL); then time the domain groups of
  * rmrt_batch_set_group_bytes (none, 128, 192 or 256 MiB) with that
- * configuration and keep the fastest.  The timing runs advance the state; call
- * rmrt_set_fields afterwards when the initial state matters.
+ * configuration and keep the fastest; then, when a group holds a domain whose
+ * rows straddle cache lines and the chosen shape is not persistent, time
+ * rmrt_batch_set_xcd_chunks modes 1 and 0 and keep the faster.  The timing
+ * runs advance the state; call rmrt_set_fields afterwards when the initial
+ * state matters.
  */
 int rmrt_batch_autotune(rmrt_batch* b, int steps, void* stream, int* chosen);
 
@@ -461,6 +476,18 @@ int rmrt_batch_autotune(rmrt_batch* b, int steps, void* stream, int* chosen);
  */
 int rmrt_batch_set_group_bytes(rmrt_batch* b, size_t bytes);
 int rmrt_batch_get_group_bytes(const rmrt_batch* b, size_t* bytes, int* ngroups);
+
+/*
+ * XCD chunks for batches (see RMRT_LAUNCH_XCD_CHUNKS): mode 1 (the default)
+ * launches with them every group that holds a domain whose rows are not a
+ * whole number of 128-byte cache lines (n[0] x the storage element size), when
+ * the tile shape is one workgroup per tile; mode 0 never.  Results are
+ * bitwise the same either way.  rmrt_batch_get_xcd_chunks returns the mode
+ * and how many groups qualify (either pointer may be NULL).  RMRT_EINVAL for a
+ * NULL batch or another mode.  Changing the mode drops the cached graphs.
+ */
+int rmrt_batch_set_xcd_chunks(rmrt_batch* b, int mode);
+int rmrt_batch_get_xcd_chunks(const rmrt_batch* b, int* mode, int* chunked_groups);
 
 /* Select tile configuration `cfg` (0 .. rmrt_batch_num_configs()-1) explicitly. */
 int rmrt_batch_set_config(rmrt_batch* b, int cfg);

@@ -548,13 +548,33 @@ struct NodeStep {
 // STEP_ALTERNATE_ORDER walks the tiles backwards on odd steps, so that each
 // step starts on the tiles the previous one finished with, whose data the
 // memory-side cache (MALL) and the L2 still hold.
+// STEP_XCD_CHUNKS (one workgroup per tile only) deals runs of kXcdChunk
+// consecutive tiles to one XCD, the eight XCDs' runs interleaved: the chip
+// still sweeps the list in order, and only one tile boundary in kXcdChunk
+// lies between two XCDs' L2s.  The odd AA step reads and writes cache lines
+// that straddle tile boundaries whenever a neighbour offset is not a whole
+// number of lines (rows of nx % 32 != 0 nodes in FP32); a line written in
+// part by two XCDs reaches memory as two partial writes.
 enum : uint32_t {
   STEP_XCD_ORDER = 1u,
   STEP_PERSISTENT = 2u,
   STEP_WIDE_TILES = 4u,
   STEP_BUFFER_OFFSETS = 8u,
-  STEP_ALTERNATE_ORDER = 16u
+  STEP_ALTERNATE_ORDER = 16u,
+  STEP_XCD_CHUNKS = 32u
 };
+constexpr uint32_t kXcdChunk = 16;
+
+// Tile of workgroup b (on XCD b % 8) under STEP_XCD_CHUNKS; the ragged end of
+// the list (fewer than 8 kXcdChunk tiles) keeps the identity, so the map is a
+// bijection of [0, ntiles).
+__device__ __forceinline__ uint32_t xcd_chunk_tile(uint32_t b, uint32_t ntiles) {
+  constexpr uint32_t M = 8u * kXcdChunk;
+  const uint32_t full = ntiles / M * M;
+  if (b >= full) return b;
+  const uint32_t x = b & 7u, l = b >> 3;
+  return (l / kXcdChunk) * M + x * kXcdChunk + (l % kXcdChunk);
+}
 
 // NPT nodes per thread per pass (1, or 2 with tiles of 2 blockDim nodes: both
 // nodes are read before either collides, so each wave keeps 2 q loads in
@@ -582,6 +602,9 @@ __global__ void __launch_bounds__(256)
         const uint32_t q8 = ntiles >> 3, rem = ntiles & 7u;
         const uint32_t first = x * q8 + (x < rem ? x : rem), cnt = q8 + (x < rem ? 1u : 0u);
         tt = first + (rev ? cnt - 1u - local : local);
+      } else if (flags & STEP_XCD_CHUNKS) {
+        tt = xcd_chunk_tile(blockIdx.x, ntiles);
+        if (rev) tt = ntiles - 1u - tt;
       } else {
         tt = rev ? ntiles - 1u - blockIdx.x : blockIdx.x;
       }

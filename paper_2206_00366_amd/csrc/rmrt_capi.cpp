@@ -95,6 +95,13 @@ uint32_t stream_ld(uint32_t N, int storage) {
 }
 bool lattice_linear(int lat) { return lat == RMRT_Q5 || lat == RMRT_Q7; }
 
+// Do the rows of the population streams straddle 128-byte cache lines?  Then
+// the odd AA step's neighbour offsets along y (and z) are not whole lines and
+// its accesses share lines between neighbouring tiles.
+bool rows_straddle_lines(const rmrt_params& p) {
+  return ((uint64_t)p.n[0] * elem_size(p.storage)) % 128u != 0;
+}
+
 int derive(const rmrt_params* p, Derived& v) {
   if (!p) return fail(RMRT_EINVAL, "params is NULL");
   if (p->lattice < RMRT_Q9 || p->lattice > RMRT_Q7) return fail(RMRT_EINVAL, "unknown lattice %d", p->lattice);
@@ -498,13 +505,14 @@ constexpr unsigned kAuxBlock = 256;
 // Launch shape of the single-domain step.  Measured on MI355X: one workgroup
 // per 256-node tile with hardware scheduling beats persistent grids (whose
 // tile loop serialises loads behind the previous tile's stores).  For the 3D
-// lattices with 4- and 8-byte storage a cap of 3 resident workgroups per CU
-// (12 waves) raises the step from 5.2 to 5.5-5.65 TB/s: fewer waves issuing q
-// concurrent address streams keep HBM rows open longer.  FP16 storage and the
-// 2D lattices prefer no cap, rD2Q9 and rD2Q5 the XCD-contiguous tile order.
+// lattices with 4- and 8-byte storage a cap of 3-4 resident workgroups per CU
+// (12-16 waves) beats full occupancy (rD3Q19 FP32 forward order: 5.2 -> 5.65
+// TB/s): fewer waves issuing q concurrent address streams keep HBM rows open
+// longer.  FP16 storage and the 2D lattices prefer no cap, rD2Q9 and rD2Q5 the
+// XCD-contiguous tile order.
 constexpr int kDefaultBlocksPerCU = 0;
 constexpr uint32_t kDefaultFlags = 0u;
-void default_launch(const rmrt_params& p, int& blocks_per_cu, uint32_t& flags) {
+void default_launch(const rmrt_params& p, bool bounded, int& blocks_per_cu, uint32_t& flags) {
   blocks_per_cu = 0;
   // Buffer addressing everywhere it applies (graph replay at 256 x 256 x 128
   // or 2048 x 1024: rD3Q19 FP32 5.58 -> 5.73 TB/s, FP16 5.03 -> 5.31, rD3Q27
@@ -516,6 +524,16 @@ void default_launch(const rmrt_params& p, int& blocks_per_cu, uint32_t& flags) {
   // 5.74 -> 6.45 TB/s of algorithmic traffic, FP16 +11%, rD3Q27 +10%; the
   // MALL-resident 2048 x 1024 rD2Q9 / rD2Q5 FP32 cases +14% / +20%).
   flags = STEP_BUFFER_OFFSETS | STEP_ALTERNATE_ORDER;
+  // XCD chunks wherever rows straddle cache lines and the tiles are not
+  // already contiguous per XCD (500-1000-step graph replays, plain / chunked,
+  // us per step): rD3Q27 FP32 200 x 160 x 260 periodic 314.0 / 304.6, 223 x
+  // 116 x 100 periodic 98.9 / 91.7, with walls 102.5 / 95.3; rD3Q19 FP16
+  // 250 x 256 x 128 125.4 / 110.6, FP64 446.7 / 435.3, FP32 207.3 / 209.3,
+  // FP32 223 x 116 x 100 with walls and force 66.0 / 62.0.  Rows of whole
+  // lines (256 x 256 x 128) lose with them (rD3Q19 FP32 199.2 / 224.3).
+  if (rows_straddle_lines(p) && p.lattice != RMRT_Q9 && p.lattice != RMRT_Q5 &&
+      !(p.lattice == RMRT_Q7 && p.storage != RMRT_F64))
+    flags |= STEP_XCD_CHUNKS;
   if (p.lattice == RMRT_Q9 || p.lattice == RMRT_Q5) {
     flags |= STEP_XCD_ORDER;
   } else if (p.lattice == RMRT_Q7) {
@@ -523,8 +541,15 @@ void default_launch(const rmrt_params& p, int& blocks_per_cu, uint32_t& flags) {
       blocks_per_cu = 3;
     else
       flags |= STEP_XCD_ORDER;
-  } else if (p.storage != RMRT_F16DEV) {
-    blocks_per_cu = 3;
+  } else if (p.storage == RMRT_F32DEV) {
+    // Residency caps, 500-step graph replays on two MI355X (us per step, cap
+    // 3 / 4): rD3Q19 256 x 256 x 128 periodic 195.6 / 190.1 (the odd phase
+    // gains 5%), 256 x 128 x 128 with walls and force 118.3 / 104.6; rD3Q27
+    // periodic 291.7 / 297.5 (cap 2 ties cap 3), 223 x 116 x 100 and
+    // 144^3 with walls and force 106.6 / 103.4 and 121.3 / 115.4.
+    blocks_per_cu = (p.lattice == RMRT_Q19 || bounded || has_force(&p)) ? 4 : 3;
+  } else if (p.storage == RMRT_F64) {
+    blocks_per_cu = 3;   // rD3Q19 / rD3Q27 FP64: 440 / 642 us at caps 2 and 3, 460 / 667 at 4
   }
 }
 constexpr uint32_t kLdsPerCU = 160u * 1024u;  // gfx950 LDS per compute unit
@@ -961,7 +986,7 @@ static int ctx_create(rmrt_ctx** out, const rmrt_params* p, void* f0, void* f1, 
     double* unused = nullptr;
     if (noalloc_scratch(c->device, &unused) != RMRT_OK) g_last_error.clear();
   }
-  default_launch(*p, c->blocks_per_cu, c->flags);
+  default_launch(*p, c->hdom.walls != 0 || c->hdom.has_solid, c->blocks_per_cu, c->flags);
   c->step_bc = c->hdom.walls != 0 ? 1 : 0;
   if (c->hdom.has_solid) {
     rc = alloc_links(c);
@@ -1335,7 +1360,7 @@ int rmrt_checkpoint_restore(rmrt_ctx* c, const void* src, void* stream) {
 int rmrt_set_launch(rmrt_ctx* c, int blocks_per_cu, int flags) {
   if (!c) return fail(RMRT_EINVAL, "ctx is NULL");
   if (blocks_per_cu < 0 || blocks_per_cu > 32) return fail(RMRT_EINVAL, "blocks_per_cu must be in [0, 32]");
-  if (flags & ~31) return fail(RMRT_EINVAL, "unknown launch flags 0x%x", flags);
+  if (flags & ~63) return fail(RMRT_EINVAL, "unknown launch flags 0x%x", flags);
   if (blocks_per_cu == 1 && !(flags & STEP_PERSISTENT))
     return fail(RMRT_EINVAL, "a residency cap of 1 workgroup per CU is not supported (use >= 2)");
   c->blocks_per_cu = blocks_per_cu;
@@ -1364,11 +1389,13 @@ int rmrt_tune(rmrt_ctx* c, int steps, void* stream, int* blocks_per_cu) {
   int best = kDefaultBlocksPerCU, best_flags = 0;
   float best_ms = 1e30f;
   const int nbuf = buffer_offsets_apply(c) ? 2 : 1;
+  const int nchunk = rows_straddle_lines(c->p) ? 2 : 1;
+  for (int chunk = 0; chunk < nchunk; ++chunk)
   for (int buf = 0; buf < nbuf; ++buf)
   for (int wide = 0; wide < 2; ++wide)
   for (int k : cands) {
     const int fl = (wide ? (int)STEP_WIDE_TILES : 0) | (buf ? (int)STEP_BUFFER_OFFSETS : 0) |
-                   (int)STEP_ALTERNATE_ORDER;
+                   (chunk ? (int)STEP_XCD_CHUNKS : 0) | (int)STEP_ALTERNATE_ORDER;
     int rc = rmrt_set_launch(c, k, fl);
     if (rc == RMRT_OK) rc = step_impl(c, 2, s);
     if (rc == RMRT_OK) rc = step_impl(c, steps, s);
@@ -1440,6 +1467,11 @@ struct rmrt_batch {
   // call advances each group through all its steps before the next group
   size_t group_bytes = 0;
   std::vector<std::pair<uint32_t, uint32_t>> groups;
+  // XCD chunks (STEP_XCD_CHUNKS) for the one-workgroup-per-tile launches of
+  // the groups holding a domain whose rows straddle cache lines (mode 1, the
+  // default), or never (mode 0)
+  int xcd_chunks = 1;
+  std::vector<uint8_t> group_chunked;
   double* dres_all = nullptr;  // 2 * nd residual sums (device)
   double* hres_all = nullptr;  // pinned host copy
 };
@@ -1450,9 +1482,11 @@ namespace {
 // population buffers each; a larger domain forms a group of its own.
 void batch_make_groups(rmrt_batch* b) {
   b->groups.clear();
+  b->group_chunked.clear();
   const uint32_t tn = (uint32_t)kTileShapes[b->cfg].tile_nodes;
   uint32_t first = 0, count = 0;
   size_t bytes = 0;
+  bool straddle = false;
   for (int d = 0; d < b->nd; ++d) {
     const rmrt_ctx* c = b->ctxs[d];
     const uint32_t nt = (c->hdom.N + tn - 1) / tn;
@@ -1460,14 +1494,20 @@ void batch_make_groups(rmrt_batch* b) {
                       (c->p.pattern == RMRT_AB ? 2u : 1u);
     if (b->group_bytes > 0 && count > 0 && bytes + db > b->group_bytes) {
       b->groups.emplace_back(first, count);
+      b->group_chunked.push_back(straddle ? 1 : 0);
       first += count;
       count = 0;
       bytes = 0;
+      straddle = false;
     }
     count += nt;
     bytes += db;
+    straddle = straddle || rows_straddle_lines(c->p);
   }
-  if (count > 0) b->groups.emplace_back(first, count);
+  if (count > 0) {
+    b->groups.emplace_back(first, count);
+    b->group_chunked.push_back(straddle ? 1 : 0);
+  }
   drop_graphs(b->graphs);
 }
 
@@ -1520,6 +1560,7 @@ int batch_launch(rmrt_batch* b, long long step_index, hipStream_t s, size_t grou
   for (const rmrt_ctx* c : b->ctxs) buf = buf && buffer_offsets_apply(c);
   if (buf) a.flags |= STEP_BUFFER_OFFSETS;
   a.flags |= STEP_ALTERNATE_ORDER;
+  if (b->xcd_chunks && b->group_chunked[group] && !(a.flags & STEP_PERSISTENT)) a.flags |= STEP_XCD_CHUNKS;
   a.grid = persistent_grid(a.ntiles, b->cus, tc.blocks_per_cu, a.flags);
   a.lds_bytes = residency_lds(tc.blocks_per_cu, a.flags);
   a.block = (unsigned)tc.threads;
@@ -1794,7 +1835,47 @@ int rmrt_batch_autotune(rmrt_batch* b, int steps, void* stream, int* chosen) {
   }
   b->group_bytes = best_group;
   batch_make_groups(b);
+  // then XCD chunks for the groups whose rows straddle cache lines, or none
+  bool any_chunked = false;
+  for (uint8_t g : b->group_chunked) any_chunked = any_chunked || g;
+  if (any_chunked && !kTileShapes[best].persistent) {
+    float mode_ms[2] = {0.f, 0.f};
+    for (int mode = 0; mode < 2; ++mode) {
+      b->xcd_chunks = mode;
+      drop_graphs(b->graphs);
+      rc = batch_step_impl(b, 2, s);
+      if (rc == RMRT_OK) rc = batch_step_impl(b, steps, s);
+      if (rc != RMRT_OK) return rc;
+      HIP_TRY(hipEventRecord(e0, s));
+      rc = batch_step_impl(b, steps, s);
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      if (rc != RMRT_OK) return rc;
+      HIP_TRY(hipEventElapsedTime(&mode_ms[mode], e0, e1));
+    }
+    b->xcd_chunks = mode_ms[1] <= mode_ms[0] ? 1 : 0;
+    drop_graphs(b->graphs);
+  }
   if (chosen) *chosen = best;
+  return RMRT_OK;
+}
+
+int rmrt_batch_set_xcd_chunks(rmrt_batch* b, int mode) {
+  if (!b) return fail(RMRT_EINVAL, "batch is NULL");
+  if (mode != 0 && mode != 1) return fail(RMRT_EINVAL, "xcd chunk mode must be 0 or 1");
+  b->xcd_chunks = mode;
+  drop_graphs(b->graphs);
+  return RMRT_OK;
+}
+
+int rmrt_batch_get_xcd_chunks(const rmrt_batch* b, int* mode, int* chunked_groups) {
+  if (!b) return fail(RMRT_EINVAL, "batch is NULL");
+  if (mode) *mode = b->xcd_chunks;
+  if (chunked_groups) {
+    int n = 0;
+    for (uint8_t g : b->group_chunked) n += g ? 1 : 0;
+    *chunked_groups = n;
+  }
   return RMRT_OK;
 }
 

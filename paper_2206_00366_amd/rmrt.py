@@ -33,6 +33,7 @@ AB, AA = 0, 1
 OUT_F64, OUT_F32 = 0, 1
 LAUNCH_XCD_ORDER, LAUNCH_PERSISTENT, LAUNCH_WIDE_TILES, LAUNCH_BUFFER_OFFSETS = 1, 2, 4, 8
 LAUNCH_ALTERNATE_ORDER = 16
+LAUNCH_XCD_CHUNKS = 32
 GRAD_STRAIN, GRAD_STRESS, GRAD_PHI = 0, 1, 2
 WALL_XM, WALL_XP, WALL_YM, WALL_YP, WALL_ZM, WALL_ZP = 1, 2, 4, 8, 16, 32
 
@@ -97,6 +98,8 @@ _sig = {
     "rmrt_batch_set_config": (C.c_int, [_vp, C.c_int]),
     "rmrt_batch_set_group_bytes": (C.c_int, [_vp, C.c_size_t]),
     "rmrt_batch_get_group_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_int)]),
+    "rmrt_batch_set_xcd_chunks": (C.c_int, [_vp, C.c_int]),
+    "rmrt_batch_get_xcd_chunks": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "rmrt_batch_num_configs": (C.c_int, []),
     "rmrt_batch_config_info": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                           C.POINTER(C.c_int), C.POINTER(C.c_int)]),
@@ -423,6 +426,16 @@ class Batch:
         nb, ng = C.c_size_t(), C.c_int()
         _check(_lib.rmrt_batch_get_group_bytes(self._b, C.byref(nb), C.byref(ng)), "rmrt_batch_get_group_bytes")
         return nb.value, ng.value
+
+    def set_xcd_chunks(self, mode):
+        """1: XCD chunks for the groups whose rows straddle cache lines; 0: never."""
+        _check(_lib.rmrt_batch_set_xcd_chunks(self._b, int(mode)), "rmrt_batch_set_xcd_chunks")
+
+    def xcd_chunks(self):
+        """(mode, number of groups launched with XCD chunks under mode 1)."""
+        m, g = C.c_int(), C.c_int()
+        _check(_lib.rmrt_batch_get_xcd_chunks(self._b, C.byref(m), C.byref(g)), "rmrt_batch_get_xcd_chunks")
+        return m.value, g.value
 
     def residuals(self):
         n = len(self.domains)

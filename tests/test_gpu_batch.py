@@ -317,3 +317,47 @@ def test_domain_groups_are_bitwise_identical(rmrt, small_oracle, pattern, storag
         if storage == "f64":
             for k, (m, rho, u, f_or) in enumerate(small_oracle):
                 assert rel_err(out[0][k], f_or) < 1e-12
+
+
+def test_xcd_chunks_are_bitwise_identical(rmrt):
+    """rmrt_batch_set_xcd_chunks only permutes tiles among workgroups: modes 0
+    and 1 give the same bits, in one group and in one group per domain, with
+    256- and 512-node tiles; only the groups whose rows straddle cache lines
+    (n[0] x 4 B not a multiple of 128) qualify."""
+    W = rmrt.WALL_YM | rmrt.WALL_YP | rmrt.WALL_ZM | rmrt.WALL_ZP
+    dims = [(45, 37, 29), (64, 32, 40), (33, 50, 41)]
+    prms = [rmrt.make_params(lattice="Q27", n=n, nu=0.04, force=(1e-5, 0.0, 0.0), wall_faces=W,
+                             storage="f32dev", pattern="AA") for n in dims]
+    rng = np.random.default_rng(8)
+    init = []
+    for n in dims:
+        N = n[0] * n[1] * n[2]
+        init.append((1 + 0.01 * rng.standard_normal(N), 0.02 * rng.standard_normal((3, N))))
+    shapes = rmrt.Batch.configs()
+    wide = next(i for i, c in enumerate(shapes) if not c[3] and c[4] == 2)
+    for cfg in (0, wide):
+        ref = None
+        for gb, mode in ((0, 0), (0, 1), (1, 0), (1, 1)):
+            b = rmrt.Batch(prms)
+            b.set_config(cfg)
+            b.set_group_bytes(gb)
+            b.set_xcd_chunks(mode)
+            m, g = b.xcd_chunks()
+            assert m == mode and g == (1 if gb == 0 else 2)
+            for k, (rho, u) in enumerate(init):
+                b.domains[k].set_fields(rho, u)
+            b.step(6)
+            b.step(1)
+            out = [b.domains[k].populations().cpu().numpy() for k in range(len(dims))]
+            b.close()
+            if ref is None:
+                ref = out
+            else:
+                for k in range(len(dims)):
+                    assert np.array_equal(out[k], ref[k]), (cfg, gb, mode, k)
+        say(f"[batch xcd chunks] config {cfg}: modes and groups bitwise equal")
+    b = rmrt.Batch(prms)
+    with pytest.raises(rmrt.RMRTError) as e:
+        b.set_xcd_chunks(2)
+    assert e.value.code == rmrt.EINVAL
+    b.close()

@@ -587,10 +587,11 @@ def test_launch_shapes_agree_and_match_oracle(rmrt):
     f_or = m.step(m.init(rho, u), 9)
     ref = None
     P, X, Wd = rmrt.LAUNCH_PERSISTENT, rmrt.LAUNCH_XCD_ORDER, rmrt.LAUNCH_WIDE_TILES
-    B, A = rmrt.LAUNCH_BUFFER_OFFSETS, rmrt.LAUNCH_ALTERNATE_ORDER
+    B, A, Ch = rmrt.LAUNCH_BUFFER_OFFSETS, rmrt.LAUNCH_ALTERNATE_ORDER, rmrt.LAUNCH_XCD_CHUNKS
     for bpc, fl in [(0, 0), (0, X), (3, 0), (8, 0), (1, P | X), (2, P | X), (3, P), (8, P | X), (0, Wd),
                     (3, Wd | X), (2, Wd | P | X), (3, B), (0, B | X), (1, B | P | X), (2, B | Wd | P | X),
-                    (3, B | A), (0, A | X), (1, A | P | X), (3, A | P), (0, B | Wd | A), (2, B | Wd | P | X | A)]:
+                    (3, B | A), (0, A | X), (1, A | P | X), (3, A | P), (0, B | Wd | A), (2, B | Wd | P | X | A),
+                    (0, Ch), (4, B | A | Ch), (4, B | A | Wd | Ch), (2, B | A | P | Ch)]:
         dom = rmrt.Domain(rmrt.make_params(**prm, storage="f64", pattern="AA"), rho, u)
         dom.set_launch(bpc, fl)
         assert dom.get_launch() == (bpc, fl)
@@ -606,6 +607,32 @@ def test_launch_shapes_agree_and_match_oracle(rmrt):
             assert np.array_equal(g, ref), (bpc, fl)
 
 
+@pytest.mark.parametrize("n", [(45, 37, 29), (64, 32, 40)])
+def test_xcd_chunks_are_bitwise_the_plain_order(rmrt, n):
+    """RMRT_LAUNCH_XCD_CHUNKS only permutes tiles among workgroups: a walled,
+    forced rD3Q27 channel with a ragged tile count (189 tiles: 128 chunked, 61
+    in the identity tail; 320 tiles: 256 + 64) steps bitwise as in the plain
+    order, with 256- and 512-node tiles, both AA phases."""
+    say(f"[xcd chunks] Q27 {n} f32dev")
+    N = n[0] * n[1] * n[2]
+    rng = np.random.default_rng(5)
+    rho, u = 1 + 0.01 * rng.standard_normal(N), 0.02 * rng.standard_normal((3, N))
+    W = rmrt.WALL_YM | rmrt.WALL_YP | rmrt.WALL_ZM | rmrt.WALL_ZP
+    prm = rmrt.make_params(lattice="Q27", n=n, nu=0.05, force=(1e-5, 0.0, 0.0), wall_faces=W,
+                           storage="f32dev", pattern="AA")
+    B, A, Ch, Wd = (rmrt.LAUNCH_BUFFER_OFFSETS, rmrt.LAUNCH_ALTERNATE_ORDER, rmrt.LAUNCH_XCD_CHUNKS,
+                    rmrt.LAUNCH_WIDE_TILES)
+    out = []
+    for bpc, fl in [(4, B | A), (4, B | A | Ch), (0, Ch), (3, B | A | Wd | Ch), (3, B | A | Wd)]:
+        dom = rmrt.Domain(prm, rho, u)
+        dom.set_launch(bpc, fl)
+        dom.step(7)
+        out.append(dom.populations().cpu().numpy())
+        dom.close()
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    assert np.array_equal(out[3], out[4])
+
+
 def test_tune_picks_a_valid_shape(rmrt):
     say("[tune] Q19 64x64x64 f32dev")
     prm = dict(lattice="Q19", n=(64, 64, 64), dx=(1.0, 1.0, 2.0), nu=0.01)
@@ -615,7 +642,7 @@ def test_tune_picks_a_valid_shape(rmrt):
     assert k in (0, 2, 3, 4, 5, 6, 8)
     bpc, fl = dom.get_launch()
     W, B, A = rmrt.LAUNCH_WIDE_TILES, rmrt.LAUNCH_BUFFER_OFFSETS, rmrt.LAUNCH_ALTERNATE_ORDER
-    assert bpc == k and fl & A and (fl & ~A) in (0, W, B, W | B)
+    assert bpc == k and fl & A and (fl & ~A) in (0, W, B, W | B)   # 64-node rows: no XCD chunks
     r = dom.reduce()
     assert abs(r[0] - N) < 1e-6 * N
     dom.close()
