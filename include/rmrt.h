@@ -432,6 +432,26 @@ int rmrt_tune(rmrt_ctx* ctx, int steps, void* stream, int* blocks_per_cu);
 int rmrt_free(rmrt_ctx* ctx);
 
 /*
+ * Linear stability preflight of a parameter set (a check before a long run,
+ * not part of the method): the collide-and-stream step of eq. 2-2-3 with
+ * p's lattice, spacings, rates and variants, in FP64 on a periodic 16 x 16
+ * (x 16) domain without walls, solids, force or source, evolves a zero-mean
+ * pseudo-random perturbation (amplitude 1e-7 on every stored population) of
+ * the uniform state rho = p->rho0 (phi0 for the NCDE), u = u0 (NSE; double[3]
+ * host array, NULL for rest), renormalised to its first size after each of 8
+ * legs of about steps / 8 (even) steps: a power iteration of the linearised
+ * step.  *growth = the mean growth of the perturbation's 2-norm per step over
+ * the last 4 legs; it tends to the largest amplification factor |lambda(k)|
+ * of the linearised step over the domain's wave vectors (von Neumann
+ * analysis), so > 1 flags a parameter set whose small disturbances grow.
+ * INFINITY when the perturbation overflows within a leg.  steps in [16, 1e6]
+ * (a few thousand resolve growth rates of 1e-3 per step); RMRT_EINVAL for NULL
+ * pointers or steps out of range, and every error rmrt_derive returns for p.
+ * Allocates and frees its own device memory; synchronous on stream.
+ */
+int rmrt_preflight(const rmrt_params* p, const double* u0, int steps, double* growth, void* stream);
+
+/*
  * Batched persistent stepping of nd independent domains that share lattice,
  * equation, storage, pattern and forcing on/off, but not sizes, spacings,
  * viscosities or walls.  One persistent kernel per step processes a static

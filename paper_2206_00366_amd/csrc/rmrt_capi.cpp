@@ -1427,6 +1427,134 @@ int rmrt_free(rmrt_ctx* c) {
 
 }  // extern "C"
 
+namespace {
+struct DevMem {
+  void* p = nullptr;
+  ~DevMem() {
+    if (p) (void)hipFree(p);
+  }
+};
+struct CtxGuard {
+  rmrt_ctx* c = nullptr;
+  ~CtxGuard() {
+    if (c) (void)rmrt_free(c);
+  }
+};
+// uniform in [-1, 1) from a counter (splitmix64 finaliser)
+double noise(uint64_t k) {
+  uint64_t z = k + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+}  // namespace
+
+extern "C" {
+
+// Linear (von Neumann) stability preflight: the parameter set's own step
+// kernel, in FP64 on a periodic 16^d domain without walls, solids or
+// forcing, evolves a small zero-mean perturbation of the uniform state
+// (rho0, u0), renormalised to its initial size after every leg of an even
+// number of steps (a power iteration of the linearised collide-and-stream
+// operator; even legs end in the natural AA layout, so the stored values are
+// read and rescaled in place).  The mean growth per step over the second
+// half of the legs estimates the largest amplification factor |lambda(k)|
+// over the domain's wave vectors.
+int rmrt_preflight(const rmrt_params* p, const double* u0, int steps, double* growth, void* stream) {
+  if (!p || !growth) return fail(RMRT_EINVAL, "params or growth is NULL");
+  if (steps < 16 || steps > 1000000) return fail(RMRT_EINVAL, "steps must be in [16, 1000000]");
+  hipStream_t s = (hipStream_t)stream;
+  rmrt_params q = *p;
+  q.storage = RMRT_F64;
+  q.pattern = RMRT_AA;
+  q.wall_faces = 0;
+  q.check_every = 0;
+  q.source = 0.0;
+  for (int a = 0; a < 3; ++a) q.force[a] = 0.0;
+  q.n[0] = q.n[1] = 16;
+  q.n[2] = lattice_2d(q.lattice) ? 1 : 16;
+  Derived v;
+  int rc = derive(&q, v);
+  if (rc != RMRT_OK) return rc;
+  const size_t N = (size_t)q.n[0] * q.n[1] * q.n[2];
+  const int Q = v.q;
+  size_t bytes = 0;
+  rc = rmrt_population_bytes(&q, &bytes);
+  if (rc != RMRT_OK) return rc;
+  const size_t ld = bytes / (sizeof(double) * (size_t)Q);
+  DevMem f, rho_d, u_d;
+  HIP_TRY(hipMalloc(&f.p, bytes));
+  HIP_TRY(hipMalloc(&rho_d.p, N * sizeof(double)));
+  HIP_TRY(hipMalloc(&u_d.p, 3 * N * sizeof(double)));
+  std::vector<double> h_rho(N, q.rho0), h_u(3 * N, 0.0);
+  if (u0 && q.equation == RMRT_NSE)
+    for (int a = 0; a < v.d; ++a) std::fill(h_u.begin() + a * N, h_u.begin() + (a + 1) * N, u0[a]);
+  HIP_TRY(hipMemcpyAsync(rho_d.p, h_rho.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(u_d.p, h_u.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
+  CtxGuard g;
+  rc = rmrt_init(&g.c, &q, f.p, nullptr, nullptr, (const double*)rho_d.p, (const double*)u_d.p, 0, stream);
+  if (rc != RMRT_OK) return rc;
+  // state = stored populations [+ the C = 0 form's previous-step phi]
+  double* hist = (double*)g.c->hdom.hist;
+  const size_t nh = hist ? N : 0;
+  std::vector<double> base((size_t)Q * ld + nh), cur(base.size());
+  HIP_TRY(hipMemcpyAsync(base.data(), f.p, bytes, hipMemcpyDeviceToHost, s));
+  if (hist) HIP_TRY(hipMemcpyAsync(base.data() + (size_t)Q * ld, hist, nh * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  // the uniform state is a fixed point of the step; perturb every stored
+  // population by a zero-mean pseudo-random field of amplitude 1e-7
+  cur = base;
+  for (int j = 0; j < Q; ++j) {
+    double mean = 0;
+    for (size_t n = 0; n < N; ++n) mean += noise((uint64_t)j * N + n);
+    mean /= (double)N;
+    for (size_t n = 0; n < N; ++n) cur[(size_t)j * ld + n] += 1e-7 * (noise((uint64_t)j * N + n) - mean);
+  }
+  auto dev_norm = [&]() {
+    double acc = 0;
+    for (int j = 0; j < Q; ++j)
+      for (size_t n = 0; n < N; ++n) {
+        const double d = cur[(size_t)j * ld + n] - base[(size_t)j * ld + n];
+        acc += d * d;
+      }
+    for (size_t n = 0; n < nh; ++n) {
+      const double d = cur[(size_t)Q * ld + n] - base[(size_t)Q * ld + n];
+      acc += d * d;
+    }
+    return std::sqrt(acc);
+  };
+  const double norm0 = dev_norm();
+  const int legs = 8;
+  const int L = std::max(2, (steps / legs + 1) / 2 * 2);
+  double log_growth = 0;
+  for (int leg = 0; leg < legs; ++leg) {
+    HIP_TRY(hipMemcpyAsync(f.p, cur.data(), bytes, hipMemcpyHostToDevice, s));
+    if (hist) HIP_TRY(hipMemcpyAsync(hist, cur.data() + (size_t)Q * ld, nh * sizeof(double), hipMemcpyHostToDevice, s));
+    rc = rmrt_step(g.c, L, stream);
+    if (rc != RMRT_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(cur.data(), f.p, bytes, hipMemcpyDeviceToHost, s));
+    if (hist) HIP_TRY(hipMemcpyAsync(cur.data() + (size_t)Q * ld, hist, nh * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double nrm = dev_norm();
+    if (!std::isfinite(nrm)) {
+      *growth = INFINITY;
+      return RMRT_OK;
+    }
+    if (nrm == 0.0) {
+      *growth = 0.0;
+      return RMRT_OK;
+    }
+    if (leg >= legs / 2) log_growth += std::log(nrm / norm0);
+    const double scale = norm0 / nrm;
+    for (size_t i = 0; i < cur.size(); ++i) cur[i] = base[i] + (cur[i] - base[i]) * scale;
+  }
+  *growth = std::exp(log_growth / ((double)L * (legs - legs / 2)));
+  return RMRT_OK;
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------------------
 // Batched persistent stepping
 // ---------------------------------------------------------------------------

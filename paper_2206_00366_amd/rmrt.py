@@ -98,6 +98,7 @@ _sig = {
     "rmrt_batch_set_config": (C.c_int, [_vp, C.c_int]),
     "rmrt_batch_set_group_bytes": (C.c_int, [_vp, C.c_size_t]),
     "rmrt_batch_get_group_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_int)]),
+    "rmrt_preflight": (C.c_int, [_vp, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double), _vp]),
     "rmrt_batch_set_xcd_chunks": (C.c_int, [_vp, C.c_int]),
     "rmrt_batch_get_xcd_chunks": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "rmrt_batch_num_configs": (C.c_int, []),
@@ -203,6 +204,15 @@ def population_bytes(params: Params) -> int:
     b = C.c_size_t()
     _check(_lib.rmrt_population_bytes(C.byref(params), C.byref(b)), "rmrt_population_bytes")
     return b.value
+
+
+def preflight(params: Params, u0=None, steps=400) -> float:
+    """Largest per-step growth of a small perturbation of the uniform state
+    (rho0, u0) under the parameter set's step (rmrt_preflight); > 1: unstable."""
+    g = C.c_double()
+    uu = None if u0 is None else (C.c_double * 3)(*[float(x) for x in u0] + [0.0] * (3 - len(u0)))
+    _check(_lib.rmrt_preflight(C.byref(params), uu, int(steps), C.byref(g), _stream()), "rmrt_preflight")
+    return g.value
 
 
 def _ptr(t):

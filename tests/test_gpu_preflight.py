@@ -1,0 +1,78 @@
+"""rmrt_preflight (linear stability of a parameter set) against the von
+Neumann analysis of the oracle's step (tests/vn_reference.py) on the same
+16-node periodic grid: neutral or decaying parameter sets report a growth of
+at most 1, unstable ones (s_hi = 1 on the rD3Q19 / rD3Q27 benchmark
+spacings, reading A5; a fast flow on a rectangular rD2Q9 lattice; strong
+advection of a weakly diffusive NCDE) the oracle's largest amplification
+factor."""
+import sys
+
+import numpy as np
+import pytest
+
+from vn_reference import max_amplification
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_00366_amd import rmrt
+    return rmrt
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = {
+    # name: (params, rho0, u0, steps)
+    # (steps keep each leg's growth, max |lambda|^(steps / 8), far below 1e5:
+    # the perturbation of 1e-7 stays linear)
+    "q19_benchmark_rates": (dict(lattice="Q19", dx=(1.0, 1.0, 2.0), nu=0.005), 1.0, (0.02, 0.01, 0.0), 2000),
+    "q19_s_hi_one": (dict(lattice="Q19", dx=(1.0, 1.0, 2.0), nu=0.005, s_hi=1.0), 1.0, (0.0, 0.0, 0.0), 2000),
+    "q27_s_hi_one": (dict(lattice="Q27", dx=(1.0, 2.0, 1.0), nu=0.005, s_hi=1.0), 1.0, (0.0, 0.0, 0.0), 2000),
+    "q9_rect_fast_flow": (dict(lattice="Q9", dx=(1.0, 0.5, 1.0), nu=0.001), 1.0, (0.1, 0.05, 0.0), 400),
+    "q9_rect_rest": (dict(lattice="Q9", dx=(1.0, 0.5, 1.0), nu=0.001), 1.0, (0.0, 0.0, 0.0), 2000),
+    "q9_ncde_stable": (dict(lattice="Q9", equation="NCDE", dx=(1.0, 0.5, 1.0), D0=0.01, D2=1.0,
+                            adv=(0.05, 0.02, 0.0)), 1.0, None, 2000),
+    "q9_ncde_advection_unstable": (dict(lattice="Q9", equation="NCDE", dx=(1.0, 0.5, 1.0), D0=0.001, D2=0.0,
+                                        adv=(0.3, 0.2, 0.0)), 1.0, None, 320),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_preflight_matches_von_neumann(R, case):
+    prm, rho0, u0, steps = CASES[case]
+    d = 2 if prm["lattice"] == "Q9" else 3
+    grid = (16, 16, 16)[:d]
+    ref = max_amplification(prm, rho0, u0, grid)
+    p = R.make_params(**prm, n=(4, 4, 4) if d == 3 else (4, 4, 1), rho0=rho0, storage="f32dev",
+                      force=(1e-5, 0.0, 0.0) if prm.get("equation", "NSE") == "NSE" else (0.0, 0.0, 0.0),
+                      wall_faces=R.WALL_YM | R.WALL_YP)
+    g = R.preflight(p, u0, steps=steps)
+    say(f"[preflight] {case}: growth {g:.6f}, oracle max |lambda| {ref:.6f}")
+    if ref <= 1 + 1e-9:
+        # neutral or decaying: the perturbation never grows
+        assert g <= 1 + 1e-9
+        assert g > ref - 0.02
+    else:
+        assert g > 1 + 0.5 * (ref - 1)
+        assert abs(g - ref) < 0.1 * (ref - 1)
+
+
+def test_preflight_refuses_bad_input(R):
+    p = R.make_params(lattice="Q19", n=(8, 8, 8), nu=0.01)
+    with pytest.raises(R.RMRTError) as e:
+        R.preflight(p, None, steps=8)
+    assert e.value.code == R.EINVAL
+    bad = R.make_params(lattice="Q19", n=(8, 8, 8), nu=0.01)
+    bad.nu = -1.0
+    with pytest.raises(R.RMRTError) as e:
+        R.preflight(bad, None)
+    assert e.value.code == R.EINVAL
+    assert R.lib().rmrt_preflight(None, None, 100, None, None) == R.EINVAL
