@@ -147,6 +147,13 @@ int main(void) {
   CHECK(rmrt_batch_set_config(NULL, 0) == RMRT_EINVAL);
   CHECK(rmrt_batch_set_group_bytes(NULL, 0) == RMRT_EINVAL);
   CHECK(rmrt_batch_get_group_bytes(NULL, NULL, NULL) == RMRT_EINVAL);
+  CHECK(rmrt_batch_set_xcd_chunks(NULL, 1) == RMRT_EINVAL);
+  CHECK(rmrt_batch_get_xcd_chunks(NULL, NULL, NULL) == RMRT_EINVAL);
+  double growth = 0;
+  CHECK(rmrt_preflight(NULL, NULL, 100, &growth, NULL) == RMRT_EINVAL);
+  CHECK(rmrt_preflight(&p, NULL, 100, NULL, NULL) == RMRT_EINVAL);
+  CHECK(rmrt_preflight(&p, NULL, 8, &growth, NULL) == RMRT_EINVAL);
+  CHECK(rmrt_preflight(&p, NULL, 2000000, &growth, NULL) == RMRT_EINVAL);
   CHECK(rmrt_batch_domain(NULL, 0, &ctx) == RMRT_EINVAL);
   CHECK(rmrt_batch_residual(NULL, NULL, NULL) == RMRT_EINVAL);
   CHECK(rmrt_batch_free(NULL) == RMRT_OK);
