@@ -79,12 +79,16 @@ def timed_steps(torch, step_fn, steps, warmup, prepare=None):
     return wall, ev_ms
 
 
-def settle(torch, R, seconds=0.3, nbytes=1 << 30):
+def settle(torch, R, seconds=0.3, nbytes=64 << 20):
     """Keep the GPU busy with plain copies for `seconds`, so that a leg's warm-up
     starts at the GPU's working clocks.  Measured on MI355X: after 2 s idle the
     first 50 rD3Q19 256 x 256 x 128 steps take 208-216 us each and the rate
     reaches 201 us only after about 100 steps; right after a 1 s busy period
-    it is 201 us from the first step (20-step graph: 211.8 against 199.0 us)."""
+    it is 201 us from the first step (20-step graph: 211.8 against 199.0 us).
+    The copies stay in the memory-side cache (64 MiB source and destination):
+    on a box without that ramp, 0.3 s of 1 GiB copies left the next 20 steps
+    1.2% slower than after 2 s idle (202.5 against 200.0 us), 64 MiB copies
+    did not (199.6 us)."""
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     t0 = time.perf_counter()
