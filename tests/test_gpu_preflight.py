@@ -2,8 +2,9 @@
 Neumann analysis of the oracle's step (tests/vn_reference.py) on the same
 16-node periodic grid: neutral or decaying parameter sets report a growth of
 at most 1, unstable ones (s_hi = 1 on the rD3Q19 / rD3Q27 benchmark
-spacings, reading A5; a fast flow on a rectangular rD2Q9 lattice; strong
-advection of a weakly diffusive NCDE) the oracle's largest amplification
+spacings, reading A5; a fast flow on a rectangular rD2Q9 lattice or under the
+central-moment collision; strong advection of a weakly diffusive NCDE, also in
+the C = 0 form with its previous-step phi) the oracle's largest amplification
 factor."""
 import sys
 
@@ -42,13 +43,23 @@ CASES = {
                             adv=(0.05, 0.02, 0.0)), 1.0, None, 2000),
     "q9_ncde_advection_unstable": (dict(lattice="Q9", equation="NCDE", dx=(1.0, 0.5, 1.0), D0=0.001, D2=0.0,
                                         adv=(0.3, 0.2, 0.0)), 1.0, None, 320),
+    # the C = 0 form (state: populations and the previous step's phi)
+    "q7_c_zero": (dict(lattice="Q7", equation="NCDE", dx=(1.0, 1.0, 2.0), D0=0.02, D2=0.5,
+                       adv=(0.03, 0.01, -0.02)), 1.0, None, 2000),
+    "q7_c_zero_fast_advection": (dict(lattice="Q7", equation="NCDE", dx=(1.0, 1.0, 2.0), D0=0.002, D2=0.0,
+                                      adv=(0.4, 0.3, 0.0)), 1.0, None, 320),
+    "q9_c_zero_fast_advection": (dict(lattice="Q9", equation="NCDE", dx=(1.0, 0.5, 1.0), D0=0.001, D2=0.0,
+                                      adv=(0.3, 0.2, 0.0), c_zero=True), 1.0, None, 200),
+    # the central-moment collision in a fast flow
+    "q27_central_fast_flow": (dict(lattice="Q27", dx=(1.0, 2.0, 1.0), nu=0.005, central=True), 1.0,
+                              (0.1, 0.05, 0.0), 2000),
 }
 
 
 @pytest.mark.parametrize("case", list(CASES))
 def test_preflight_matches_von_neumann(R, case):
     prm, rho0, u0, steps = CASES[case]
-    d = 2 if prm["lattice"] == "Q9" else 3
+    d = 2 if prm["lattice"] in ("Q9", "Q5") else 3
     grid = (16, 16, 16)[:d]
     ref = max_amplification(prm, rho0, u0, grid)
     p = R.make_params(**prm, n=(4, 4, 4) if d == 3 else (4, 4, 1), rho0=rho0, storage="f32dev",

@@ -47,3 +47,19 @@ def test_default_rates_neutral_and_s_hi_one_unstable():
     base = dict(lattice="Q19", dx=(1.0, 1.0, 2.0), nu=0.005)
     assert max_amplification(base, 1.0, (0.0, 0.0, 0.0), (8, 8, 8)) < 1 + 1e-9
     assert max_amplification(dict(base, s_hi=1.0), 1.0, (0.0, 0.0, 0.0), (8, 8, 8)) > 1.01
+
+
+def test_c_zero_form_diffusion_mode():
+    """The C = 0 NCDE form carries phi of the previous step: its state is (f,
+    phi_prev), and its diffusion mode still decays at exp(-D k^2)."""
+    D0 = 0.02
+    for prm in (dict(lattice="Q7", equation="NCDE", dx=(1.0, 1.0, 2.0), D0=D0, D2=0.0, adv=(0.0, 0.0, 0.0)),
+                dict(lattice="Q9", equation="NCDE", dx=(1.0, 0.5, 1.0), D0=D0, D2=0.0, adv=(0.0, 0.0, 0.0),
+                     c_zero=True)):
+        m = O.Model(dict(prm, n=(1, 1, 1)))
+        J = jacobian(m, 1.0, None)
+        assert J.shape == (m.q + 1, m.q + 1)
+        k = [2 * np.pi / 16] + [0.0] * (m.d - 1)
+        lam = np.linalg.eigvals(amplification(m, J, k))
+        want = np.exp(-D0 * k[0] ** 2)
+        assert np.min(np.abs(np.abs(lam) - want)) < 2e-2 * (1 - want), prm["lattice"]
