@@ -406,10 +406,11 @@ int rmrt_checkpoint_restore(rmrt_ctx* ctx, const void* src, void* stream);
  * of the forward order (nodes of one step are independent).  Part of every
  * default launch; batches and rmrt_tune always use it. */
 #define RMRT_LAUNCH_ALTERNATE_ORDER 16
-/* XCD chunks (one workgroup per tile; ignored by persistent grids): runs of
- * 16 consecutive tiles go to one XCD, the eight XCDs' runs interleaved, so
- * that cache lines straddling two tiles are mostly written through one L2
- * (the odd AA step's neighbour offsets straddle tiles whenever a row is not a
+/* XCD chunks (one workgroup per tile; ignored by persistent grids; applied
+ * to the odd AA steps and to AB steps, the ones that access neighbours'
+ * slots): runs of 16 consecutive tiles go to one XCD, the eight XCDs' runs
+ * interleaved, so that cache lines straddling two tiles are mostly written
+ * through one L2 (neighbour offsets straddle tiles whenever a row is not a
  * whole number of cache lines).  Results are bitwise those of the plain
  * order. */
 #define RMRT_LAUNCH_XCD_CHUNKS 32

@@ -548,13 +548,15 @@ struct NodeStep {
 // STEP_ALTERNATE_ORDER walks the tiles backwards on odd steps, so that each
 // step starts on the tiles the previous one finished with, whose data the
 // memory-side cache (MALL) and the L2 still hold.
-// STEP_XCD_CHUNKS (one workgroup per tile only) deals runs of kXcdChunk
-// consecutive tiles to one XCD, the eight XCDs' runs interleaved: the chip
-// still sweeps the list in order, and only one tile boundary in kXcdChunk
-// lies between two XCDs' L2s.  The odd AA step reads and writes cache lines
-// that straddle tile boundaries whenever a neighbour offset is not a whole
-// number of lines (rows of nx % 32 != 0 nodes in FP32); a line written in
-// part by two XCDs reaches memory as two partial writes.
+// STEP_XCD_CHUNKS (one workgroup per tile only; odd AA and AB steps) deals
+// runs of kXcdChunk consecutive tiles to one XCD, the eight XCDs' runs
+// interleaved: the chip still sweeps the list in order, and only one tile
+// boundary in kXcdChunk lies between two XCDs' L2s.  The odd AA step (and the
+// AB step's pushes) read and write cache lines that straddle tile boundaries
+// whenever a neighbour offset is not a whole number of lines (rows of
+// nx % 32 != 0 nodes in FP32); a line written in part by two XCDs reaches
+// memory as two partial writes.  The even AA step touches only its own
+// nodes' slots and keeps the plain round-robin order.
 enum : uint32_t {
   STEP_XCD_ORDER = 1u,
   STEP_PERSISTENT = 2u,
@@ -602,7 +604,7 @@ __global__ void __launch_bounds__(256)
         const uint32_t q8 = ntiles >> 3, rem = ntiles & 7u;
         const uint32_t first = x * q8 + (x < rem ? x : rem), cnt = q8 + (x < rem ? 1u : 0u);
         tt = first + (rev ? cnt - 1u - local : local);
-      } else if (flags & STEP_XCD_CHUNKS) {
+      } else if (PH != PH_AA_EVEN && (flags & STEP_XCD_CHUNKS)) {
         tt = xcd_chunk_tile(blockIdx.x, ntiles);
         if (rev) tt = ntiles - 1u - tt;
       } else {
