@@ -453,6 +453,26 @@ int rmrt_free(rmrt_ctx* ctx);
 int rmrt_preflight(const rmrt_params* p, const double* u0, int steps, double* growth, void* stream);
 
 /*
+ * Index-checked build (librmrt_checked.so, the library compiled with
+ * RMRT_CHECKED=1 in its host code and FP64 kernels; not for production runs):
+ * every neighbour node index the kernels compute (streaming in the odd AA and
+ * the AB steps, swapped-layout reads of the companion kernels, solid-mask and
+ * velocity-gradient neighbours) is tested against the domain's node count;
+ * an index outside it is counted in a per-context device counter and
+ * replaced by the node's own index, so that no access leaves the buffers.
+ * rmrt_checked_build returns 1 in that build and 0 in the production one.
+ * rmrt_checked_violations copies the counter to *count (synchronous on
+ * stream).  rmrt_checked_set_limit lowers the bound the checks use to limit
+ * (in [1, N]) and clears the counter: a test of the checks themselves, whose
+ * nodes at and above limit then count as out of range while every access
+ * stays inside the buffers.  Both return RMRT_EUNSUPPORTED in the production
+ * build and RMRT_EINVAL for NULL pointers or a limit out of range.
+ */
+int rmrt_checked_build(void);
+int rmrt_checked_violations(rmrt_ctx* ctx, unsigned* count, void* stream);
+int rmrt_checked_set_limit(rmrt_ctx* ctx, unsigned limit, void* stream);
+
+/*
  * Batched persistent stepping of nd independent domains that share lattice,
  * equation, storage, pattern and forcing on/off, but not sizes, spacings,
  * viscosities or walls.  One persistent kernel per step processes a static

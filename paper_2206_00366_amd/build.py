@@ -14,6 +14,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librmrt.so")
+# The checked library: the same code with every neighbour node index tested
+# against the domain (RMRT_CHECKED = 1) in the FP64 kernels of every lattice
+# and in the host code; the FP32 / FP16 kernels, whose index code is the same
+# templates, are the production objects.
+CHECKED_LIB = os.path.join(HERE, "librmrt_checked.so")
+CHECKED_BUILD = os.path.join(BUILD, "checked")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -29,29 +35,47 @@ def sources():
     return [os.path.join(CSRC, s) for s in srcs]
 
 
-def compile_one(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", src, "-o", obj]
+def checked_unit(src: str) -> bool:
+    name = os.path.basename(src)
+    return name.endswith("_f64.hip") or name == "rmrt_capi.cpp"
+
+
+def compile_one(src: str, checked: bool = False) -> str:
+    out_dir = CHECKED_BUILD if checked else BUILD
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *FLAGS, *(["-DRMRT_CHECKED=1"] if checked else []), "-x", "hip", "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr[-4000:]}")
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = sources()
-    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
-    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(compile_one, srcs))
-    tmp = LIB + ".tmp"
+def link(objs, lib: str) -> None:
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr[-4000:]}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(jobs: int | None = None, verbose: bool = True) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    os.makedirs(CHECKED_BUILD, exist_ok=True)
+    srcs = sources()
+    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
+    checked_srcs = [s for s in srcs if checked_unit(s)]
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = [ex.submit(compile_one, s) for s in srcs]
+        cfuts = [ex.submit(compile_one, s, True) for s in checked_srcs]
+        objs = [f.result() for f in futs]
+        cobjs = {os.path.basename(s): f.result() for s, f in zip(checked_srcs, cfuts)}
+    link(objs, LIB)
     if verbose:
         print(f"built {LIB}")
+    link([cobjs.get(os.path.basename(s), o) for s, o in zip(srcs, objs)], CHECKED_LIB)
+    if verbose:
+        print(f"built {CHECKED_LIB}")
     build_examples(verbose)
     return LIB
 

@@ -112,6 +112,23 @@ __device__ __forceinline__ uint32_t fast_div(uint32_t n, uint32_t d, uint32_t m,
 }
 
 // Geometry of one node: neighbour offsets with periodic wrap and wall flags.
+#ifndef RMRT_CHECKED
+#define RMRT_CHECKED 0
+#endif
+// Neighbour node index n of node self.  The checked build (RMRT_CHECKED = 1,
+// librmrt_checked.so) tests it against Dm.oob_limit, counts an index outside
+// it in *Dm.oob and takes the node's own index instead, so that the access
+// stays inside the buffers; the production build compiles the test away.
+__device__ __forceinline__ uint32_t checked_node(const DomainDev& Dm, uint32_t n, uint32_t self) {
+  if constexpr (RMRT_CHECKED != 0) {
+    if (n >= Dm.oob_limit) {
+      atomicAdd(Dm.oob, 1u);
+      return self < Dm.oob_limit ? self : 0u;
+    }
+  }
+  return n;
+}
+
 template <int D>
 struct Geo {
   int32_t ox[3], oy[3], oz[3];
@@ -156,6 +173,11 @@ struct Geo {
     constexpr int ex = Lat<L>::e(J, 0), ey = Lat<L>::e(J, 1), ez = Lat<L>::e(J, 2);
     return ox[ex + 1] + oy[ey + 1] + oz[ez + 1];
   }
+  // the neighbour of node idx along e_J (periodic wrap included)
+  template <int L, int J>
+  __device__ __forceinline__ uint32_t nbr(const DomainDev& Dm, uint32_t idx) const {
+    return checked_node(Dm, (uint32_t)(idx + (uint32_t)off<L, J>()), idx);
+  }
   // does the link from this node along e_J hit a wall face (or, with SOLID, a
   // solid node of the byte mask)?
   template <int L, int J, bool SOLID = true>
@@ -170,7 +192,7 @@ struct Geo {
     if constexpr (ez < 0) b = b || lo[2];
     if constexpr (ez > 0) b = b || hi[2];
     if constexpr (SOLID)
-      if (Dm.has_solid) b = b || (to_global(Dm.solid)[idx + (uint32_t)off<L, J>()] != 0);
+      if (Dm.has_solid) b = b || (to_global(Dm.solid)[nbr<L, J>(Dm, idx)] != 0);
     return b;
   }
 };
@@ -196,7 +218,7 @@ __device__ __forceinline__ size_t read_elem(const DomainDev& Dm, const Geo<D>& g
     if constexpr (BC == 1) {
       if (g.template bounce<L, O>(Dm, idx)) return (size_t)J * LD + idx;
     }
-    return (size_t)O * LD + (uint32_t)(idx + (uint32_t)g.template off<L, O>());
+    return (size_t)O * LD + g.template nbr<L, O>(Dm, idx);
   }
 }
 
@@ -344,7 +366,7 @@ struct NodeStep {
   // Read the q populations of node idx_ (nothing for solid or invalid nodes).
   __device__ __forceinline__ void load(const DomainDev& Dm, const Coef<T>& C, const gmem<S>* fin, R rin,
                                        uint32_t idx_, bool valid) {
-    idx = idx_;
+    idx = valid ? checked_node(Dm, idx_, 0u) : idx_;
     live = valid;
     lb = 0;
     if constexpr (BC == 2) {
@@ -399,14 +421,14 @@ struct NodeStep {
         constexpr int O = Lat<L>::opp(J);
         constexpr uint32_t es = sizeof(S);
         if constexpr (PH == PH_AA_ODD)
-          v = buf_ld<S>(rin, (uint32_t)(idx + (uint32_t)g.template off<L, O>()) * es, (uint32_t)O * LD * es);
+          v = buf_ld<S>(rin, g.template nbr<L, O>(Dm, idx) * es, (uint32_t)O * LD * es);
         else
           v = buf_ld<S>(rin, idx * es, (uint32_t)J * LD * es);
       } else if constexpr (PH == PH_AA_ODD) {
         // swapped layout: the value for direction J sits in slot O of the
         // upstream node, or in this node's own slot J when that link bounced
         constexpr int O = Lat<L>::opp(J);
-        const gmem<S>* pu = fin + (size_t)O * LD + (uint32_t)(idx + (uint32_t)g.template off<L, O>());
+        const gmem<S>* pu = fin + (size_t)O * LD + g.template nbr<L, O>(Dm, idx);
         if constexpr (BC == 0) {
           v = *pu;
         } else {
@@ -433,7 +455,7 @@ struct NodeStep {
       constexpr int J = decltype(j_)::value;
       constexpr int O = Lat<L>::opp(J);
       constexpr uint32_t es = sizeof(S);
-      const uint32_t up = (uint32_t)(idx + (uint32_t)g.template off<L, O>());
+      const uint32_t up = g.template nbr<L, O>(Dm, idx);
       S v;
       if constexpr (EDGE) {
         const uint32_t full = bounced<O>(Dm) ? (uint32_t)J * LD + idx : (uint32_t)O * LD + up;
@@ -453,7 +475,7 @@ struct NodeStep {
       constexpr int O = Lat<L>::opp(J);
       constexpr uint32_t es = sizeof(S);
       const S v = SS::template enc<Lat<L>::wclass(J)>(t[Lat<L>::slot(J)], C);
-      const uint32_t down = (uint32_t)(idx + (uint32_t)g.template off<L, J>());
+      const uint32_t down = g.template nbr<L, J>(Dm, idx);
       if constexpr (EDGE) {
         const uint32_t full = bounced<J>(Dm) ? (uint32_t)O * LD + idx : (uint32_t)J * LD + down;
         buf_st<S>(rout, full * es, 0u, v);
@@ -518,18 +540,18 @@ struct NodeStep {
       if constexpr (BUF && PH == PH_AA_EVEN) {
         buf_st<S>(rout, idx * es, (uint32_t)O * LD * es, v);
       } else if constexpr (BUF) {
-        buf_st<S>(rout, (uint32_t)(idx + (uint32_t)g.template off<L, J>()) * es, (uint32_t)J * LD * es, v);
+        buf_st<S>(rout, g.template nbr<L, J>(Dm, idx) * es, (uint32_t)J * LD * es, v);
       } else if constexpr (PH == PH_AA_EVEN) {
         st_elem(fout + (size_t)O * LD, idx, v);
       } else if constexpr (BC == 0) {
-        st_elem(fout + (size_t)J * LD, (uint32_t)(idx + (uint32_t)g.template off<L, J>()), v);
+        st_elem(fout + (size_t)J * LD, g.template nbr<L, J>(Dm, idx), v);
       } else {
         bool b;
         if constexpr (BC == 2)
           b = (lb >> J) & 1;
         else
           b = g.template bounce<L, J, false>(Dm, idx);
-        gmem<S>* pd = fout + (size_t)J * LD + (uint32_t)(idx + (uint32_t)g.template off<L, J>());
+        gmem<S>* pd = fout + (size_t)J * LD + g.template nbr<L, J>(Dm, idx);
         gmem<S>* pb = fout + (size_t)O * LD + idx;
         *(b ? pb : pd) = v;
       }
@@ -1025,7 +1047,7 @@ __device__ __forceinline__ void velocity_gradient(const DomainDev& Dm, const dou
   for (int b = 0; b < D; ++b) {
     const int32_t op = (b == 0) ? g.ox[2] : (b == 1 ? g.oy[2] : g.oz[2]);
     const int32_t om = (b == 0) ? g.ox[0] : (b == 1 ? g.oy[0] : g.oz[0]);
-    const uint32_t ip = idx + (uint32_t)op, im = idx + (uint32_t)om;
+    const uint32_t ip = checked_node(Dm, idx + (uint32_t)op, idx), im = checked_node(Dm, idx + (uint32_t)om, idx);
     bool okp = !g.hi[b], okm = !g.lo[b];
     if (Dm.has_solid) {
       okp = okp && !Dm.solid[ip];
@@ -1134,7 +1156,7 @@ __global__ void __launch_bounds__(256)
         constexpr int O = Lat<L>::opp(J);
         bool b = false;
         b = g.template bounce<L, O>(Dm, idx);
-        e_out = b ? (size_t)J * Dm.ld + idx : (size_t)O * Dm.ld + (uint32_t)(idx + (uint32_t)g.template off<L, O>());
+        e_out = b ? (size_t)J * Dm.ld + idx : (size_t)O * Dm.ld + g.template nbr<L, O>(Dm, idx);
       } else {
         e_out = (size_t)J * Dm.ld + idx;
       }

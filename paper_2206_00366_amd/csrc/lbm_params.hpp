@@ -90,6 +90,11 @@ struct DomainDev {
   const void* frc;
   void* sprev;
   uint32_t src_field;
+  // checked builds (RMRT_CHECKED): the node-index bound that every neighbour
+  // index is tested against (N unless a test lowers it) and the device
+  // counter of indices found outside it; unused by the production build
+  uint32_t oob_limit;
+  uint32_t* oob;
 };
 
 // One unit of persistent-kernel work: nodes [start, start + count) of a domain.

@@ -435,6 +435,8 @@ void fill_domain(const rmrt_params* p, const Derived& v, DomainDev& D, void* fa,
   D.fa = fa;
   D.fb = fb;
   D.solid = solid;
+  D.oob_limit = D.N;
+  D.oob = nullptr;
 }
 
 bool c_zero_form(const rmrt_params* p) {
@@ -630,6 +632,7 @@ struct rmrt_ctx {
   uint32_t flags = kDefaultFlags;
   int device = 0;              // the device current at creation
   void* sprev = nullptr;       // gamma = 0 NCDE with source fields: the previous step's source (library-owned)
+  uint32_t* oob = nullptr;     // checked builds: the counter of neighbour indices out of range
 };
 
 namespace {
@@ -710,6 +713,7 @@ void ctx_release(rmrt_ctx* c) {
   if (c->links) (void)hipFree(c->links);
   if (c->hist) (void)hipFree(c->hist);
   if (c->sprev) (void)hipFree(c->sprev);
+  if (c->oob) (void)hipFree(c->oob);
   if (c->owns_ddoms && c->ddoms) (void)hipFree(c->ddoms);
 }
 
@@ -977,6 +981,16 @@ static int ctx_create(rmrt_ctx** out, const rmrt_params* p, void* f0, void* f1, 
       return fail(RMRT_EHIP, "hipMalloc(history field): %s", hipGetErrorString(e));
     }
     c->hdom.hist = c->hist;
+  }
+  if (RMRT_CHECKED != 0) {
+    hipError_t e = hipMalloc(&c->oob, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(c->oob, 0, sizeof(uint32_t));
+    if (e != hipSuccess) {
+      ctx_release(c);
+      delete c;
+      return fail(RMRT_EHIP, "hipMalloc(index-check counter): %s", hipGetErrorString(e));
+    }
+    c->hdom.oob = c->oob;
   }
   c->cus = device_cus();
   if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
@@ -1550,6 +1564,31 @@ int rmrt_preflight(const rmrt_params* p, const double* u0, int steps, double* gr
     for (size_t i = 0; i < cur.size(); ++i) cur[i] = base[i] + (cur[i] - base[i]) * scale;
   }
   *growth = std::exp(log_growth / ((double)L * (legs - legs / 2)));
+  return RMRT_OK;
+}
+
+int rmrt_checked_build(void) { return RMRT_CHECKED != 0 ? 1 : 0; }
+
+int rmrt_checked_violations(rmrt_ctx* c, unsigned* count, void* stream) {
+  if (!c || !count) return fail(RMRT_EINVAL, "ctx or count is NULL");
+  if (RMRT_CHECKED == 0 || !c->oob) return fail(RMRT_EUNSUPPORTED, "not a checked build");
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t v = 0;
+  HIP_TRY(hipMemcpyAsync(&v, c->oob, sizeof(v), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *count = v;
+  return RMRT_OK;
+}
+
+int rmrt_checked_set_limit(rmrt_ctx* c, unsigned limit, void* stream) {
+  if (!c) return fail(RMRT_EINVAL, "ctx is NULL");
+  if (RMRT_CHECKED == 0 || !c->oob) return fail(RMRT_EUNSUPPORTED, "not a checked build");
+  if (limit < 1 || limit > c->hdom.N) return fail(RMRT_EINVAL, "limit must be in [1, N]");
+  hipStream_t s = (hipStream_t)stream;
+  c->hdom.oob_limit = limit;
+  HIP_TRY(hipMemsetAsync(c->oob, 0, sizeof(uint32_t), s));
+  HIP_TRY(hipMemcpyAsync(c->ddoms + c->dom, &c->hdom, sizeof(DomainDev), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
   return RMRT_OK;
 }
 

@@ -12,7 +12,9 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librmrt.so")
+# RMRT_LIBRARY selects another build of the library (the index-checked
+# librmrt_checked.so); the default is the in-tree production build
+LIB_PATH = os.environ.get("RMRT_LIBRARY") or os.path.join(_HERE, "librmrt.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2206_00366_amd.build` first")
@@ -99,6 +101,9 @@ _sig = {
     "rmrt_batch_set_group_bytes": (C.c_int, [_vp, C.c_size_t]),
     "rmrt_batch_get_group_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_int)]),
     "rmrt_preflight": (C.c_int, [_vp, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double), _vp]),
+    "rmrt_checked_build": (C.c_int, []),
+    "rmrt_checked_violations": (C.c_int, [_vp, C.POINTER(C.c_uint), _vp]),
+    "rmrt_checked_set_limit": (C.c_int, [_vp, C.c_uint, _vp]),
     "rmrt_batch_set_xcd_chunks": (C.c_int, [_vp, C.c_int]),
     "rmrt_batch_get_xcd_chunks": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "rmrt_batch_num_configs": (C.c_int, []),
@@ -149,6 +154,11 @@ def _check(code, where):
 
 def lib():
     return _lib
+
+
+def checked_build() -> bool:
+    """True when the loaded library tests every neighbour index (librmrt_checked.so)."""
+    return bool(_lib.rmrt_checked_build())
 
 
 def version() -> str:
@@ -350,6 +360,16 @@ class Domain:
 
     def restore(self, buf):
         _check(_lib.rmrt_checkpoint_restore(self._ctx, _ptr(buf), _stream()), "rmrt_checkpoint_restore")
+
+    def checked_violations(self):
+        """Neighbour indices found out of range so far (checked builds only)."""
+        n = C.c_uint()
+        _check(_lib.rmrt_checked_violations(self._ctx, C.byref(n), _stream()), "rmrt_checked_violations")
+        return n.value
+
+    def checked_set_limit(self, limit):
+        """Lower the node bound of the index checks (a test of the checks; checked builds only)."""
+        _check(_lib.rmrt_checked_set_limit(self._ctx, int(limit), _stream()), "rmrt_checked_set_limit")
 
     def steps_taken(self):
         s = C.c_longlong()

@@ -154,6 +154,10 @@ int main(void) {
   CHECK(rmrt_preflight(&p, NULL, 100, NULL, NULL) == RMRT_EINVAL);
   CHECK(rmrt_preflight(&p, NULL, 8, &growth, NULL) == RMRT_EINVAL);
   CHECK(rmrt_preflight(&p, NULL, 2000000, &growth, NULL) == RMRT_EINVAL);
+  CHECK(rmrt_checked_build() == 0);
+  unsigned oob = 0;
+  CHECK(rmrt_checked_violations(NULL, &oob, NULL) == RMRT_EINVAL);
+  CHECK(rmrt_checked_set_limit(NULL, 1, NULL) == RMRT_EINVAL);
   CHECK(rmrt_batch_domain(NULL, 0, &ctx) == RMRT_EINVAL);
   CHECK(rmrt_batch_residual(NULL, NULL, NULL) == RMRT_EINVAL);
   CHECK(rmrt_batch_free(NULL) == RMRT_OK);

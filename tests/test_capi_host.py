@@ -32,6 +32,23 @@ def test_header_symbols_exported():
     assert set(names) == set(rmrt.EXPORTED)
 
 
+def test_checked_library_exports_the_same_symbols():
+    """librmrt_checked.so (neighbour indices tested in its FP64 kernels) has
+    the production library's entry points and reports itself as checked."""
+    path = os.path.join(os.path.dirname(rmrt.LIB_PATH), "librmrt_checked.so")
+    if not os.path.exists(path):
+        pytest.skip("librmrt_checked.so not built")
+    lib = ctypes.CDLL(path)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert lib.rmrt_checked_build() == 1
+    assert rmrt.lib().rmrt_checked_build() == (1 if rmrt.LIB_PATH == path else 0)
+    # production build: the check entry points refuse
+    if rmrt.LIB_PATH != path:
+        n = ctypes.c_uint()
+        assert rmrt.lib().rmrt_checked_violations(None, ctypes.byref(n), None) == rmrt.EINVAL
+
+
 CASES = [
     dict(lattice="Q9", n=(8, 8, 1), dx=(1.0, 0.5, 1.0), nu=0.02, nu_b=0.05),
     dict(lattice="Q9", n=(8, 8, 1), dx=(1.0, 2.0, 1.0), nu=0.1),
