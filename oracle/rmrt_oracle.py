@@ -78,6 +78,16 @@ GPU side can take the same ones; numbering as in the design notes):
       the off-diagonal second moments, s_hi above); equilibrium, auxiliary and
       source moments are N(u) times the raw ones, so the step is eq. 2-2-3 with
       Lambda = M^-1 N^-1 S N M (eq. 5-1-2).
+  A26 Hermite-moment and central-Hermite-moment collisions (option hermite,
+      NSE on rD2Q9, rD3Q19 and rD3Q27; with central on rD2Q9 / rD3Q27): the
+      moment of exponents (a, b, p) is the tensor-product Hermite polynomial
+      H_a(xi_x) H_b(xi_y) H_p(xi_z) with H_0 = 1, H_1 = xi, H_2 = xi^2 - cs2 of
+      the velocity xi = c_j (or c_j - u with central), i.e. the basis H M (or
+      H N(u) M) of eq. 5-1-1 with H the constant lower-triangular matrix that
+      subtracts cs2 times the moment two orders lower per axis; the relaxation
+      matrix in that basis has the raw model's blocks as in A25, and every
+      moment vector is transformed alike (eq. 5-1-2).  The 19 moments of
+      rD3Q19 are closed under H (it lowers exponents of 2 to 0 only).
 """
 from __future__ import annotations
 
@@ -259,7 +269,7 @@ DEFAULTS = dict(lattice="Q9", equation="NSE", n=(8, 8, 1), dx=(1.0, 1.0, 1.0), d
                 cs2=-1.0, nu=0.1, nu_b=-1.0, s_hi=-1.0, w_corner=-1.0,
                 D0=0.0, D2=0.0, adv=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0),
                 source=0.0, rho0=1.0, wall_faces=0, incompressible=False, nu_tensor=None, nu_b_axis=None,
-                gamma0=False, diffusive=False, c_zero=False, central=False)
+                gamma0=False, diffusive=False, c_zero=False, central=False, hermite=False)
 
 
 class Model:
@@ -282,6 +292,10 @@ class Model:
         self.central = bool(p["central"])
         if self.central and not (self.nse and self.lattice in ("Q9", "Q27")):
             raise ValueError("the central-moment collision is built for the NSE on rD2Q9 and rD3Q27")
+        # Hermite-moment collision (central-Hermite with central), eq. 5-1-1 / 5-1-2 (A26)
+        self.hermite = bool(p["hermite"])
+        if self.hermite and not (self.nse and self.lattice in ("Q9", "Q19", "Q27")):
+            raise ValueError("the Hermite-moment collision is built for the NSE on rD2Q9, rD3Q19 and rD3Q27")
         E = unit_offsets(self.lattice)
         self.E = E
         self.q, self.d = E.shape
@@ -377,7 +391,7 @@ class Model:
             self.P1[r, r] = 1.0
         self._build_streaming(solid)
         self.S_node = self.F_node = self.S_prev = None
-        self.S_central = None      # a relaxation matrix for the central moments other than S (tests only)
+        self.S_central = None      # a relaxation matrix for the shifted basis other than S (tests only)
 
     # ------------------------------------------------------------------ sources
     def set_sources(self, S=None, F=None):
@@ -542,6 +556,35 @@ class Model:
                     N[i, k] = v
         return N
 
+    def hermite_matrix(self):
+        """H of A26: row i (exponents a) holds prod_axis h(a, b) at column k
+        (exponents b), with h(a, a) = 1, h(2, 0) = -cs2 and 0 otherwise, so that
+        H M f = sum_j prod_axis H_a(c_j) f_j (H_0 = 1, H_1 = xi, H_2 = xi^2 - cs2)."""
+        q = self.q
+        H = np.zeros((q, q))
+        for i, ea in enumerate(self.exps):
+            for k, eb in enumerate(self.exps):
+                v = 1.0
+                for a, b in zip(ea, eb):
+                    if a == b:
+                        continue
+                    if a == 2 and b == 0:
+                        v *= -self.cs2
+                    else:
+                        v = 0.0
+                        break
+                H[i, k] = v
+        return H
+
+    def basis_matrix(self, u):
+        """The basis change N of eq. 5-1-1 per node: N(u) (central), H
+        (hermite), H N(u) (both).  u: (d, n); returns (q, q, n)."""
+        n = u.shape[1]
+        N = self.shift_matrix(u) if self.central else np.repeat(np.eye(self.q)[:, :, None], n, axis=2)
+        if self.hermite:
+            N = np.einsum("ik,kjn->ijn", self.hermite_matrix(), N)
+        return N
+
     def apply_S(self, x, s1=None):
         """S x with S the block relaxation matrix; NCDE adds s_1(phi) on the first-order rows."""
         y = self.S @ x
@@ -557,11 +600,12 @@ class Model:
         meq = self.M @ feq
         mF = self.M @ F
         mG = self.M @ G
-        if self.central:
-            # the same step in the central moments kappa = N(u) m (eq. 5-1-1), whose
-            # relaxation matrix Sbar has this model's blocks (eq. 5-1-2, A25)
+        if self.central or self.hermite:
+            # the same step in the moments kappa = N m of the central (A25),
+            # Hermite or central-Hermite (A26) basis of eq. 5-1-1, whose relaxation
+            # matrix Sbar has this model's blocks (eq. 5-1-2)
             _, u = self.macroscopic(fbar, sel)
-            N = self.shift_matrix(u)
+            N = self.basis_matrix(u)
             k, keq, kF, kG = (np.einsum("ikn,kn->in", N, v) for v in (m, meq, mF, mG))
             Sb = self.S_central if self.S_central is not None else self.S
             kstar = k - Sb @ (k - keq) + self.dt * (kG + kF - 0.5 * (Sb @ kF))
@@ -577,9 +621,9 @@ class Model:
     def collide_velocity_space(self, fbar, phi_prev=None, sel=None):
         """Same collision written in velocity space with Lambda = M^-1 S M (eq. 2-3, eq. 5-1)."""
         feq, F, G, s1 = self.distributions(fbar, phi_prev, sel)
-        if self.central:
+        if self.central or self.hermite:
             _, u = self.macroscopic(fbar, sel)
-            N = self.shift_matrix(u)
+            N = self.basis_matrix(u)
             Sb = self.S_central if self.S_central is not None else self.S
             # per node: Lambda = M^-1 N^-1 Sbar N M (eq. 5-1-2)
             Lam_n = np.stack([self.Minv @ np.linalg.solve(N[:, :, j], Sb @ N[:, :, j]) @ self.M
