@@ -137,6 +137,13 @@ enum { RMRT_OUT_F64 = 0, RMRT_OUT_F32 = 1 };                       /* macroscopi
  *             the recovered NSE is the same, the higher moments relax in the
  *             frame moving with the fluid.  RMRT_EUNSUPPORTED on the other
  *             lattices; local outputs are refused with it.
+ *   hermite   NSE on rD2Q9 / rD3Q19 / rD3Q27: 1 relaxes in the Hermite
+ *             moments H M fbar, the tensor products of H_0 = 1, H_1 = xi,
+ *             H_2 = xi^2 - cs2 of each velocity (eq. 5-1-1 with the constant
+ *             lower-triangular N = H), with the raw model's blocks and every
+ *             moment vector transformed alike (eq. 5-1-2); with central = 1
+ *             the central-Hermite moments H N(u) M fbar (xi = c - u).  Local
+ *             outputs are refused with it.
  */
 typedef struct rmrt_params {
   int lattice, equation, storage, pattern;
@@ -160,6 +167,7 @@ typedef struct rmrt_params {
   int diffusive;
   int c_zero;
   int central;
+  int hermite;
 } rmrt_params;
 
 /* Values the library derives from a parameter set (host only, no GPU). */

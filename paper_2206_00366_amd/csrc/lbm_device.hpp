@@ -304,6 +304,25 @@ __device__ __forceinline__ void central_unshift(T (&t)[NS], const T (&v)[3]) {
   });
 }
 
+// Hermite-moment transform (eq. 5-1-1) in the scaled basis: along each axis the
+// line (m0, m1, m2) becomes (m0, m1, m2 - th m0) with th = cs2 / c_a^2 (the
+// tensor-product Hermite polynomials H_0 = 1, H_1 = xi, H_2 = xi^2 - cs2), and
+// back with +th.  Lines whose second-order slot the lattice drops (rD3Q19's
+// monomials with three non-zero exponents) are left alone: no kept slot
+// depends on them.
+template <int L, int D, typename T, int NS>
+__device__ __forceinline__ void hermite_shift(T (&t)[NS], const T (&th)[3], T sign) {
+  static_for<0, D>([&](auto ax_) {
+    constexpr int ax = decltype(ax_)::value;
+    constexpr int st = axis_stride(ax);
+    const T w = sign * th[ax];
+    static_for<0, NS>([&](auto b_) {
+      constexpr int b = decltype(b_)::value;
+      if constexpr ((b / st) % 3 == 0 && !Lat<L>::dropped(b + 2 * st)) t[b + 2 * st] -= w * t[b];
+    });
+  });
+}
+
 // Scaled raw moment n of g_eq(A, B, M) (eq. 3-3): only the terms that the
 // lattice parity leaves non-zero are emitted.  Md = (Mxx, Myy, Mzz),
 // Mo = (Mxy, Mxz, Myz).
@@ -392,9 +411,10 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, const Node
                                         T phi_prev = T(0), T* phi_out = nullptr) {
   constexpr int D = Lat<L>::D;
   constexpr bool HIST = Lat<L>::linear || EQ == EQ_NCDE_C0;
-  constexpr bool NSE = EQ == EQ_NSE || EQ == EQ_NSE_CENTRAL;
-  static_assert(EQ != EQ_NSE_CENTRAL || L == LAT_Q9 || L == LAT_Q27,
-                "the central-moment collision needs a moment set closed under the shift");
+  constexpr bool NSE = EQ == EQ_NSE || EQ == EQ_NSE_BASIS;
+  // the central shift needs a moment set closed under it (rD2Q9, rD3Q27)
+  constexpr bool CENTRAL_OK = L == LAT_Q9 || L == LAT_Q27;
+  static_assert(EQ != EQ_NSE_BASIS || !Lat<L>::linear, "the basis collisions are NSE options");
   moments_fwd<D, Lat<L>::absent_mask()>(t);
 
   // slots of the first and second moments
@@ -420,7 +440,7 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, const Node
     // u = j / rho, or j / rho0 with the He-Luo equilibrium g_eq(rho, rho0 u, rho0 u u)
     const T ir = recip(C.hl ? C.rho0 : rho);
     const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
-    if constexpr (EQ == EQ_NSE_CENTRAL) {
+    if constexpr (EQ == EQ_NSE_BASIS && CENTRAL_OK) {
       vc[0] = ux * C.inv_c[0];
       vc[1] = uy * C.inv_c[1];
       vc[2] = uz * C.inv_c[2];
@@ -494,21 +514,33 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, const Node
     }
   }
 
-  if constexpr (EQ == EQ_NSE_CENTRAL) {
-    // kappa* = kappa - Sbar (kappa - kappa_eq') + kappa_s with kappa = N(u) m and
-    // the equilibrium and source moments shifted the same way (eq. 5-1-2); Sbar
-    // has the raw model's blocks.  Conserved central moments are at their
-    // equilibrium (kappa_0 = rho', kappa_1 = j - rho u = -dt F / 2), so only the
-    // source is added to them.
+  if constexpr (EQ == EQ_NSE_BASIS) {
+    // kappa* = kappa - Sbar (kappa - kappa_eq') + kappa_s with kappa = N m, N
+    // the central shift N(u), the Hermite transform H or H N(u), and the
+    // equilibrium and source moments transformed the same way (eq. 5-1-2); Sbar
+    // has the raw model's blocks.  Conserved moments of every basis are at their
+    // equilibrium (kappa_0 = rho', kappa_1 = j - rho u = -dt F / 2 centrally), so
+    // only the source is added to them.
+    const bool cen = CENTRAL_OK && (C.basis & BASIS_CENTRAL);
+    const bool her = (C.basis & BASIS_HERMITE) != 0;
     T e[NS], sv[NS];
     static_for<0, NS>([&](auto n_) {
       constexpr int n = decltype(n_)::value;
       e[n] = gmom<L, n>(C, eA, eB, eMd, eMo);
       if constexpr (FORCE) sv[n] = gmom<L, n>(C, sA, sB, sMd, sMo);
     });
-    central_shift<D>(t, vc);
-    central_shift<D>(e, vc);
-    if constexpr (FORCE) central_shift<D>(sv, vc);
+    if constexpr (CENTRAL_OK) {
+      if (cen) {
+        central_shift<D>(t, vc);
+        central_shift<D>(e, vc);
+        if constexpr (FORCE) central_shift<D>(sv, vc);
+      }
+    }
+    if (her) {
+      hermite_shift<L, D>(t, C.hth, T(1));
+      hermite_shift<L, D>(e, C.hth, T(1));
+      if constexpr (FORCE) hermite_shift<L, D>(sv, C.hth, T(1));
+    }
     T nd[3] = {t[sxx] - e[sxx], t[syy] - e[syy], D == 3 ? t[szz] - e[szz] : T(0)};
     static_for<0, NS>([&](auto n_) {
       constexpr int n = decltype(n_)::value;
@@ -531,7 +563,10 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, const Node
       t[n] -= r;
       if constexpr (FORCE) t[n] += sv[n];
     });
-    central_unshift<D>(t, vc);
+    if (her) hermite_shift<L, D>(t, C.hth, T(-1));
+    if constexpr (CENTRAL_OK) {
+      if (cen) central_unshift<D>(t, vc);
+    }
     moments_inv<D, Lat<L>::dropped_mask()>(t);
     return;
   }

@@ -382,7 +382,7 @@ struct NodeStep {
       // domain takes the same branch)
       const T Sn = Dm.src ? to_global((const T*)Dm.src)[idx] : T(0);
       T F[3] = {T(0), T(0), T(0)};
-      if constexpr (EQ == EQ_NSE || EQ == EQ_NSE_CENTRAL) {
+      if constexpr (EQ == EQ_NSE || EQ == EQ_NSE_BASIS) {
         if (Dm.frc)
           for (int a = 0; a < D; ++a) F[a] = to_global((const T*)Dm.frc)[(size_t)a * Dm.N + idx];
       }

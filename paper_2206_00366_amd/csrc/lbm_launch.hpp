@@ -5,12 +5,12 @@
 
 namespace rmrt {
 
-// Field sources, the C = 0 NCDE form and the central-moment collision have a
-// one-node-per-thread kernel only: with STEP_WIDE_TILES it walks each
-// 512-node tile in two passes.
+// Field sources, the C = 0 NCDE form and the basis collisions (central,
+// Hermite) have a one-node-per-thread kernel only: with STEP_WIDE_TILES it
+// walks each 512-node tile in two passes.
 template <int L, int ST, int EQ, int F, int BC, int PH, bool BUF>
 void do_step_npt(const StepLaunch& a) {
-  if constexpr (F == F_FIELD || EQ == EQ_NCDE_C0 || EQ == EQ_NSE_CENTRAL)
+  if constexpr (F == F_FIELD || EQ == EQ_NCDE_C0 || EQ == EQ_NSE_BASIS)
     hipLaunchKernelGGL((k_step<L, ST, EQ, F, BC, PH, 1, BUF>), dim3(a.grid), dim3(a.block), a.lds_bytes, a.stream,
                        a.doms, a.tiles, a.ntiles, a.tile_nodes, a.parity, a.flags);
   else if (a.flags & STEP_WIDE_TILES)
@@ -25,7 +25,7 @@ void do_step_npt(const StepLaunch& a) {
 template <int L, int ST, int EQ, int F, int BC, int PH>
 hipError_t do_step(const StepLaunch& a) {
   if (a.local_out) {
-    if constexpr (F == F_FIELD || EQ == EQ_NSE_CENTRAL) {
+    if constexpr (F == F_FIELD || EQ == EQ_NSE_BASIS) {
       return hipErrorInvalidValue;   // local outputs: raw-moment model, constant sources (host-checked)
     } else {
       hipLaunchKernelGGL((k_step_local<L, ST, EQ, F, BC, PH>), dim3(a.ntiles), dim3(a.block), a.lds_bytes,
@@ -76,9 +76,7 @@ hipError_t launch_step(const StepLaunch& a) {
       case EQ_NSE: return step_f<L, ST, EQ_NSE>(a);
       case EQ_NCDE: return step_f<L, ST, EQ_NCDE>(a);
       case EQ_NCDE_C0: return step_f<L, ST, EQ_NCDE_C0>(a);
-      case EQ_NSE_CENTRAL:
-        if constexpr (L == LAT_Q9 || L == LAT_Q27) return step_f<L, ST, EQ_NSE_CENTRAL>(a);
-        return hipErrorInvalidValue;
+      case EQ_NSE_BASIS: return step_f<L, ST, EQ_NSE_BASIS>(a);
     }
     return hipErrorInvalidValue;
   }

@@ -9,9 +9,11 @@ namespace rmrt {
 enum { LAT_Q9 = 0, LAT_Q19 = 1, LAT_Q27 = 2, LAT_Q5 = 3, LAT_Q7 = 4 };
 // EQ_NCDE_C0: the NCDE in the C = 0 form of eq. 4-16 on the full lattices
 // (rD2Q5 / rD3Q7 always take that form under EQ_NCDE)
-// EQ_NSE_CENTRAL: the NSE with the central-moment collision of eq. 5-1-1 /
-// 5-1-2 (rD2Q9 and rD3Q27)
-enum { EQ_NSE = 0, EQ_NCDE = 1, EQ_NCDE_C0 = 2, EQ_NSE_CENTRAL = 3 };
+// EQ_NSE_BASIS: the NSE relaxed in another moment basis of eq. 5-1-1 / 5-1-2,
+// the central (rD2Q9, rD3Q27), Hermite (rD2Q9, rD3Q19, rD3Q27) or
+// central-Hermite one (Coef::basis)
+enum { EQ_NSE = 0, EQ_NCDE = 1, EQ_NCDE_C0 = 2, EQ_NSE_BASIS = 3 };
+enum : uint32_t { BASIS_CENTRAL = 1u, BASIS_HERMITE = 2u };
 // source terms of a step: none, the parameter set's constants, or per-node
 // fields (mass or NCDE source, body force; read per node and step)
 enum { F_NONE = 0, F_CONST = 1, F_FIELD = 2 };
@@ -50,6 +52,8 @@ struct Coef {
   T half_dt, dt_cs2, half_dt_cs2, half_src_factor;
   uint32_t hl;              // He-Luo equilibrium (1) or eq. NSEfeq (0)
   uint32_t hist_g;          // NCDE: G from dB/dt with the previous step's phi (C = 0 form of eq. 4-16)
+  uint32_t basis;           // EQ_NSE_BASIS: BASIS_CENTRAL | BASIS_HERMITE
+  T hth[3];                 // Hermite basis: cs2 / c_a^2 (H_2 = e^2 - cs2 / c_a^2 in the scaled basis)
 };
 
 // Initialisation-only quantities (always FP64).

@@ -236,6 +236,8 @@ int derive(const rmrt_params* p, Derived& v) {
       return fail(RMRT_EUNSUPPORTED, "the central-moment collision is built for rD2Q9 and rD3Q27 (moment sets "
                                      "closed under the shift)");
   }
+  if (p->hermite && p->equation != RMRT_NSE)
+    return fail(RMRT_EINVAL, "the Hermite-moment collision is an NSE option");
   if (p->equation == RMRT_NSE && p->diffusive) return fail(RMRT_EINVAL, "the diffusive scaling is an NCDE option");
   if (p->equation != RMRT_NSE) {
     if (!(p->D0 > 0)) return fail(RMRT_EINVAL, "D0 must be > 0 for the NCDE");
@@ -376,6 +378,9 @@ void fill_coef(const rmrt_params* p, const Derived& v, Coef<T>& C) {
     C.adv_g[a] = diff ? (T)0 : C.adv[a];           // eq. 4-17: G = 0
   }
   C.hist_g = c0 ? 1u : 0u;
+  C.basis = (p->equation == RMRT_NSE && p->central ? BASIS_CENTRAL : 0u) |
+            (p->equation == RMRT_NSE && p->hermite ? BASIS_HERMITE : 0u);
+  for (int a = 0; a < 3; ++a) C.hth[a] = (T)(a < v.d ? v.cs2 / (v.c[a] * v.c[a]) : 0.0);
   // factors of the per-node source fields
   C.half_dt = (T)(0.5 * dt);
   C.dt_cs2 = (T)(dt * cs2);
@@ -748,7 +753,7 @@ int launch_init_fields(rmrt_ctx* c, const double* rho, const double* u, int with
 // Equation and source mode of a context's step kernel.
 int step_eq(const rmrt_ctx* c) {
   if (c->p.equation == RMRT_NCDE && c->p.c_zero && !lattice_linear(c->p.lattice)) return EQ_NCDE_C0;
-  if (c->p.equation == RMRT_NSE && c->p.central) return EQ_NSE_CENTRAL;
+  if (c->p.equation == RMRT_NSE && (c->p.central || c->p.hermite)) return EQ_NSE_BASIS;
   return c->p.equation;
 }
 int step_force(const rmrt_ctx* c) {
@@ -1142,7 +1147,8 @@ int check_local_args(const rmrt_ctx* c, int kind, const void* out, int out_dtype
   if (!c || !out) return fail(RMRT_EINVAL, "ctx or out is NULL");
   if (c->hdom.src_field)
     return fail(RMRT_EUNSUPPORTED, "local outputs take the parameter set's constant sources (fields attached)");
-  if (c->p.central) return fail(RMRT_EUNSUPPORTED, "local outputs are built for the raw-moment collision");
+  if (c->p.central || c->p.hermite)
+    return fail(RMRT_EUNSUPPORTED, "local outputs are built for the raw-moment collision");
   if (out_dtype != RMRT_OUT_F64 && out_dtype != RMRT_OUT_F32) return fail(RMRT_EINVAL, "bad out_dtype");
   const bool nse = c->p.equation == RMRT_NSE;
   if (kind == RMRT_GRAD_STRAIN || kind == RMRT_GRAD_STRESS) {
@@ -1842,8 +1848,9 @@ int rmrt_batch_create(rmrt_batch** out, int nd, const rmrt_params* params, void*
   for (int d = 1; d < nd; ++d) {
     const rmrt_params& p = params[d];
     if (p.lattice != p0.lattice || p.equation != p0.equation || p.storage != p0.storage ||
-        p.pattern != p0.pattern || (p.c_zero != 0) != (p0.c_zero != 0) || (p.central != 0) != (p0.central != 0))
-      return fail(RMRT_EINVAL, "domain %d differs in lattice/equation/storage/pattern/c_zero/central", d);
+        p.pattern != p0.pattern || (p.c_zero != 0) != (p0.c_zero != 0) || (p.central != 0) != (p0.central != 0) ||
+        (p.hermite != 0) != (p0.hermite != 0))
+      return fail(RMRT_EINVAL, "domain %d differs in lattice/equation/storage/pattern/c_zero/central/hermite", d);
   }
   hipStream_t s = (hipStream_t)stream;
   rmrt_batch* b = new (std::nothrow) rmrt_batch();
