@@ -88,6 +88,16 @@ GPU side can take the same ones; numbering as in the design notes):
       matrix in that basis has the raw model's blocks as in A25, and every
       moment vector is transformed alike (eq. 5-1-2).  The 19 moments of
       rD3Q19 are closed under H (it lowers exponents of 2 to 0 only).
+  A27 BHLL-moment collision (option bhll, NSE on rD2Q9): the moments are
+      N_BHLL M_a fbar with N_BHLL the printed matrix of Sec. V at a = c_y / c_x
+      and M_a the raw moments of the velocities measured in units of c_x (so
+      c_x = 1 gives the printed M_a); the BHLL moments of each order relax on
+      their own, with the block of that order of N S N^-1 (S the raw model's
+      relaxation matrix): the second-order block of eq. 5-8 carried into the
+      BHLL basis by similarity, s_ab on p_xy and s_hi on q_x, q_y and epsilon.
+      The couplings between orders that N S N^-1 would have are dropped, so the
+      step differs from the raw one once s_hi differs from the second-order
+      rates (through epsilon, whose definition holds second-order moments).
 """
 from __future__ import annotations
 
@@ -269,7 +279,8 @@ DEFAULTS = dict(lattice="Q9", equation="NSE", n=(8, 8, 1), dx=(1.0, 1.0, 1.0), d
                 cs2=-1.0, nu=0.1, nu_b=-1.0, s_hi=-1.0, w_corner=-1.0,
                 D0=0.0, D2=0.0, adv=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0),
                 source=0.0, rho0=1.0, wall_faces=0, incompressible=False, nu_tensor=None, nu_b_axis=None,
-                gamma0=False, diffusive=False, c_zero=False, central=False, hermite=False)
+                gamma0=False, diffusive=False, c_zero=False, central=False, hermite=False,
+                bhll=False)
 
 
 class Model:
@@ -296,6 +307,12 @@ class Model:
         self.hermite = bool(p["hermite"])
         if self.hermite and not (self.nse and self.lattice in ("Q9", "Q19", "Q27")):
             raise ValueError("the Hermite-moment collision is built for the NSE on rD2Q9, rD3Q19 and rD3Q27")
+        # BHLL-moment collision, eq. Md2q9-3 with eq. 5-1-2 (A27)
+        self.bhll = bool(p["bhll"])
+        if self.bhll and not (self.nse and self.lattice == "Q9"):
+            raise ValueError("the BHLL-moment collision is built for the NSE on rD2Q9")
+        if self.bhll and (self.central or self.hermite):
+            raise ValueError("the BHLL basis is not combined with the central or Hermite one")
         E = unit_offsets(self.lattice)
         self.E = E
         self.q, self.d = E.shape
@@ -392,6 +409,7 @@ class Model:
         self._build_streaming(solid)
         self.S_node = self.F_node = self.S_prev = None
         self.S_central = None      # a relaxation matrix for the shifted basis other than S (tests only)
+        self.S_bhll = self.bhll_relaxation() if self.bhll else None
 
     # ------------------------------------------------------------------ sources
     def set_sources(self, S=None, F=None):
@@ -576,14 +594,52 @@ class Model:
                 H[i, k] = v
         return H
 
+    def bhll_matrix(self):
+        """N of A27: the printed N_BHLL (eq. Md2q9-3) at a = c_y / c_x, times
+        diag(c_x^-order) that turns the raw moments M into M_a."""
+        a = self.c[1] / self.c[0]
+        a2 = a * a
+        Nb = np.array([
+            [1, 0, 0, 0, 0, 0, 0, 0, 0],
+            [0, 1, 0, 0, 0, 0, 0, 0, 0],
+            [0, 0, 1, 0, 0, 0, 0, 0, 0],
+            [-2 * a2 - 2, 0, 0, 3, 3, 0, 0, 0, 0],
+            [-2 * a2 + 2, 0, 0, 3 * a2, -3 / a2, 0, 0, 0, 0],
+            [0, 0, 0, 0, 0, 1, 0, 0, 0],
+            [0, -2, 0, 0, 0, 0, 3 / a2, 0, 0],
+            [0, 0, -2, 0, 0, 0, 0, 3, 0],
+            [4, 0, 0, -6, -6 / a2, 0, 0, 0, 9 / a2]], dtype=np.float64)
+        # the printed matrix acts on the rows (1, x, y, x^2, y^2, xy, xy^2, x^2y, x^2y^2)
+        assert [tuple(e) for e in self.exps] == [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (1, 1),
+                                                 (1, 2), (2, 1), (2, 2)]
+        return Nb @ np.diag(self.c[0] ** (-self.order.astype(np.float64)))
+
+    def bhll_relaxation(self):
+        """Sbar of A27 in the BHLL basis: the blocks of N S N^-1 between moments
+        of one order, nothing between orders."""
+        N = self.bhll_matrix()
+        full = N @ self.S @ np.linalg.inv(N)
+        same_order = self.order[:, None] == self.order[None, :]
+        return np.where(same_order, full, 0.0)
+
     def basis_matrix(self, u):
         """The basis change N of eq. 5-1-1 per node: N(u) (central), H
-        (hermite), H N(u) (both).  u: (d, n); returns (q, q, n)."""
+        (hermite), H N(u) (both), N_BHLL M_a M^-1 (bhll).  u: (d, n); returns
+        (q, q, n)."""
         n = u.shape[1]
+        if self.bhll:
+            return np.repeat(self.bhll_matrix()[:, :, None], n, axis=2)
         N = self.shift_matrix(u) if self.central else np.repeat(np.eye(self.q)[:, :, None], n, axis=2)
         if self.hermite:
             N = np.einsum("ik,kjn->ijn", self.hermite_matrix(), N)
         return N
+
+    def _basis_relaxation(self):
+        """Sbar of the basis collisions: a test's override, the BHLL blocks
+        (A27), or the raw model's blocks (A25, A26)."""
+        if self.S_central is not None:
+            return self.S_central
+        return self.S_bhll if self.bhll else self.S
 
     def apply_S(self, x, s1=None):
         """S x with S the block relaxation matrix; NCDE adds s_1(phi) on the first-order rows."""
@@ -600,14 +656,14 @@ class Model:
         meq = self.M @ feq
         mF = self.M @ F
         mG = self.M @ G
-        if self.central or self.hermite:
+        if self.central or self.hermite or self.bhll:
             # the same step in the moments kappa = N m of the central (A25),
-            # Hermite or central-Hermite (A26) basis of eq. 5-1-1, whose relaxation
-            # matrix Sbar has this model's blocks (eq. 5-1-2)
+            # Hermite or central-Hermite (A26) or BHLL (A27) basis of eq. 5-1-1,
+            # whose relaxation matrix Sbar has this model's blocks (eq. 5-1-2)
             _, u = self.macroscopic(fbar, sel)
             N = self.basis_matrix(u)
             k, keq, kF, kG = (np.einsum("ikn,kn->in", N, v) for v in (m, meq, mF, mG))
-            Sb = self.S_central if self.S_central is not None else self.S
+            Sb = self._basis_relaxation()
             kstar = k - Sb @ (k - keq) + self.dt * (kG + kF - 0.5 * (Sb @ kF))
             mstar = np.stack([np.linalg.solve(N[:, :, j], kstar[:, j]) for j in range(kstar.shape[1])], axis=1)
             return np.linalg.solve(self.M, mstar)
@@ -621,10 +677,10 @@ class Model:
     def collide_velocity_space(self, fbar, phi_prev=None, sel=None):
         """Same collision written in velocity space with Lambda = M^-1 S M (eq. 2-3, eq. 5-1)."""
         feq, F, G, s1 = self.distributions(fbar, phi_prev, sel)
-        if self.central or self.hermite:
+        if self.central or self.hermite or self.bhll:
             _, u = self.macroscopic(fbar, sel)
             N = self.basis_matrix(u)
-            Sb = self.S_central if self.S_central is not None else self.S
+            Sb = self._basis_relaxation()
             # per node: Lambda = M^-1 N^-1 Sbar N M (eq. 5-1-2)
             Lam_n = np.stack([self.Minv @ np.linalg.solve(N[:, :, j], Sb @ N[:, :, j]) @ self.M
                               for j in range(fbar.shape[1])], axis=2)
