@@ -144,6 +144,14 @@ enum { RMRT_OUT_F64 = 0, RMRT_OUT_F32 = 1 };                       /* macroscopi
  *             moment vector transformed alike (eq. 5-1-2); with central = 1
  *             the central-Hermite moments H N(u) M fbar (xi = c - u).  Local
  *             outputs are refused with it.
+ *   bhll      NSE on rD2Q9: 1 relaxes in the orthogonal BHLL moments
+ *             N_BHLL M_a fbar (Sec. V, eq. Md2q9-2 / Md2q9-3, a = c_y / c_x,
+ *             M_a the raw moments of the velocities in units of c_x), each
+ *             order on its own with that order's block of N S N^-1: the
+ *             second-order block of eq. 5-8 carried over by similarity, s_ab on
+ *             p_xy, s_hi on q_x, q_y and epsilon (eq. 5-1-2).  RMRT_EINVAL
+ *             with central or hermite, RMRT_EUNSUPPORTED on the other
+ *             lattices; local outputs are refused with it.
  */
 typedef struct rmrt_params {
   int lattice, equation, storage, pattern;
@@ -168,6 +176,7 @@ typedef struct rmrt_params {
   int c_zero;
   int central;
   int hermite;
+  int bhll;
 } rmrt_params;
 
 /* Values the library derives from a parameter set (host only, no GPU). */

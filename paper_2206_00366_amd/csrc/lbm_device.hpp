@@ -529,6 +529,39 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, const Node
       e[n] = gmom<L, n>(C, eA, eB, eMd, eMo);
       if constexpr (FORCE) sv[n] = gmom<L, n>(C, sA, sB, sMd, sMo);
     });
+    if constexpr (L == LAT_Q9) {
+      if (C.basis & BASIS_BHLL) {
+        // BHLL moments kappa = N m (eq. Md2q9-3) relaxed class by class: with N
+        // constant the step is m* = m - N^-1 Sbar_B N (m - eq') + src, and the
+        // host has formed N^-1 Sbar_B N in this basis.  Its rows of the
+        // conserved moments vanish and its columns there meet m - eq' = 0.
+        // non-conserved slot k: 2 (x^2), then 4 .. 8
+        T nd6[6];
+        static_for<0, 6>([&](auto k_) {
+          constexpr int k = decltype(k_)::value;
+          constexpr int sk = k == 0 ? 2 : k + 3;
+          nd6[k] = t[sk] - e[sk];
+        });
+        static_for<0, 6>([&](auto k_) {
+          constexpr int k = decltype(k_)::value;
+          constexpr int sk = k == 0 ? 2 : k + 3;
+          T r = C.rb[k][0] * nd6[0];
+          static_for<1, 6>([&](auto l_) {
+            constexpr int l = decltype(l_)::value;
+            r += C.rb[k][l] * nd6[l];
+          });
+          t[sk] -= r;
+        });
+        if constexpr (FORCE) {
+          static_for<0, NS>([&](auto n_) {
+            constexpr int n = decltype(n_)::value;
+            t[n] += sv[n];
+          });
+        }
+        moments_inv<D, Lat<L>::dropped_mask()>(t);
+        return;
+      }
+    }
     if constexpr (CENTRAL_OK) {
       if (cen) {
         central_shift<D>(t, vc);

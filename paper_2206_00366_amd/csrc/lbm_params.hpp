@@ -13,7 +13,7 @@ enum { LAT_Q9 = 0, LAT_Q19 = 1, LAT_Q27 = 2, LAT_Q5 = 3, LAT_Q7 = 4 };
 // the central (rD2Q9, rD3Q27), Hermite (rD2Q9, rD3Q19, rD3Q27) or
 // central-Hermite one (Coef::basis)
 enum { EQ_NSE = 0, EQ_NCDE = 1, EQ_NCDE_C0 = 2, EQ_NSE_BASIS = 3 };
-enum : uint32_t { BASIS_CENTRAL = 1u, BASIS_HERMITE = 2u };
+enum : uint32_t { BASIS_CENTRAL = 1u, BASIS_HERMITE = 2u, BASIS_BHLL = 4u };
 // source terms of a step: none, the parameter set's constants, or per-node
 // fields (mass or NCDE source, body force; read per node and step)
 enum { F_NONE = 0, F_CONST = 1, F_FIELD = 2 };
@@ -52,8 +52,11 @@ struct Coef {
   T half_dt, dt_cs2, half_dt_cs2, half_src_factor;
   uint32_t hl;              // He-Luo equilibrium (1) or eq. NSEfeq (0)
   uint32_t hist_g;          // NCDE: G from dB/dt with the previous step's phi (C = 0 form of eq. 4-16)
-  uint32_t basis;           // EQ_NSE_BASIS: BASIS_CENTRAL | BASIS_HERMITE
+  uint32_t basis;           // EQ_NSE_BASIS: BASIS_CENTRAL | BASIS_HERMITE, or BASIS_BHLL
   T hth[3];                 // Hermite basis: cs2 / c_a^2 (H_2 = e^2 - cs2 / c_a^2 in the scaled basis)
+  // BHLL basis (rD2Q9): the relaxation N^-1 Sbar_B N written in the scaled raw
+  // basis, over the non-conserved tensor slots 2, 4, 5, 6, 7, 8
+  T rb[6][6];
 };
 
 // Initialisation-only quantities (always FP64).

@@ -238,6 +238,13 @@ int derive(const rmrt_params* p, Derived& v) {
   }
   if (p->hermite && p->equation != RMRT_NSE)
     return fail(RMRT_EINVAL, "the Hermite-moment collision is an NSE option");
+  if (p->bhll) {
+    if (p->equation != RMRT_NSE) return fail(RMRT_EINVAL, "the BHLL-moment collision is an NSE option");
+    if (p->central || p->hermite)
+      return fail(RMRT_EINVAL, "the BHLL basis is not combined with the central or Hermite one");
+    if (p->lattice != RMRT_Q9)
+      return fail(RMRT_EUNSUPPORTED, "the BHLL-moment collision is built for rD2Q9 (the basis of eq. Md2q9-3)");
+  }
   if (p->equation == RMRT_NSE && p->diffusive) return fail(RMRT_EINVAL, "the diffusive scaling is an NCDE option");
   if (p->equation != RMRT_NSE) {
     if (!(p->D0 > 0)) return fail(RMRT_EINVAL, "D0 must be > 0 for the NCDE");
@@ -286,6 +293,104 @@ void invert3(const double A[3][3], double B[3][3], int d) {
   }
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) B[i][j] = M[i][3 + j];
+}
+
+// In-place inverse of the n x n row-major matrix A (Gauss-Jordan with partial
+// pivoting); false when a pivot vanishes.
+bool invert_small(double* A, int n) {
+  double inv[81];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) inv[i * n + j] = i == j ? 1.0 : 0.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(A[r * n + col]) > std::fabs(A[piv * n + col])) piv = r;
+    if (!(std::fabs(A[piv * n + col]) > 0)) return false;
+    for (int j = 0; j < n; ++j) {
+      std::swap(A[col * n + j], A[piv * n + j]);
+      std::swap(inv[col * n + j], inv[piv * n + j]);
+    }
+    const double d = 1.0 / A[col * n + col];
+    for (int j = 0; j < n; ++j) {
+      A[col * n + j] *= d;
+      inv[col * n + j] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double f = A[r * n + col];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        A[r * n + j] -= f * A[col * n + j];
+        inv[r * n + j] -= f * inv[col * n + j];
+      }
+    }
+  }
+  std::copy(inv, inv + n * n, A);
+  return true;
+}
+
+// The BHLL-moment relaxation (Sec. V, eq. Md2q9-2 / Md2q9-3, with eq. 5-1-2)
+// in the scaled raw basis of the kernels.  Rows and columns 0..8 below are the
+// raw moments 1, x, y, x^2, y^2, xy, xy^2, x^2y, x^2y^2 of the printed matrix.
+// N = N_BHLL(a) diag(c_x^-order) with a = c_y / c_x maps the raw moments to the
+// BHLL ones; Sbar_B keeps the blocks of N S N^-1 between moments of one order
+// (the second-order block of eq. 5-8 carried over by similarity, s_xy on p_xy,
+// s_hi on q_x, q_y and epsilon); the kernels apply D^-1 N^-1 Sbar_B N D with D =
+// diag(c_x^i c_y^j) to the non-conserved tensor slots 2, 4, 5, 6, 7, 8.
+bool bhll_relaxation(const Derived& v, double rb[6][6]) {
+  static const int ex[9][2] = {{0, 0}, {1, 0}, {0, 1}, {2, 0}, {0, 2}, {1, 1}, {1, 2}, {2, 1}, {2, 2}};
+  const double a = v.c[1] / v.c[0], a2 = a * a;
+  const double Nb[81] = {1, 0, 0, 0, 0, 0, 0, 0, 0,
+                         0, 1, 0, 0, 0, 0, 0, 0, 0,
+                         0, 0, 1, 0, 0, 0, 0, 0, 0,
+                         -2 * a2 - 2, 0, 0, 3, 3, 0, 0, 0, 0,
+                         -2 * a2 + 2, 0, 0, 3 * a2, -3 / a2, 0, 0, 0, 0,
+                         0, 0, 0, 0, 0, 1, 0, 0, 0,
+                         0, -2, 0, 0, 0, 0, 3 / a2, 0, 0,
+                         0, 0, -2, 0, 0, 0, 0, 3, 0,
+                         4, 0, 0, -6, -6 / a2, 0, 0, 0, 9 / a2};
+  int ord[9];
+  double N[81], Ni[81], S[81] = {0}, T[81], Sb[81], R[81];
+  for (int i = 0; i < 9; ++i) ord[i] = ex[i][0] + ex[i][1];
+  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j < 9; ++j) N[i * 9 + j] = Nb[i * 9 + j] * std::pow(v.c[0], -ord[j]);
+  std::copy(N, N + 81, Ni);
+  if (!invert_small(Ni, 9)) return false;
+  // the raw model's relaxation matrix (its conserved rows play no part)
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) S[(3 + i) * 9 + 3 + j] = v.Sbar[i][j];
+  S[5 * 9 + 5] = v.s_pair[0];
+  for (int i = 6; i < 9; ++i) S[i * 9 + i] = v.s_hi;
+  auto mul = [](const double* X, const double* Y, double* Z) {
+    for (int i = 0; i < 9; ++i)
+      for (int j = 0; j < 9; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < 9; ++k) acc += X[i * 9 + k] * Y[k * 9 + j];
+        Z[i * 9 + j] = acc;
+      }
+  };
+  mul(N, S, T);
+  mul(T, Ni, Sb);
+  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j < 9; ++j)
+      if (ord[i] != ord[j]) Sb[i * 9 + j] = 0.0;
+  mul(Ni, Sb, T);
+  mul(T, N, R);
+  // tensor slot (i + 3 j) of raw row r; non-conserved slot k: 2, then 4 .. 8
+  auto slot_k = [&](int r) {
+    const int sl = ex[r][0] + 3 * ex[r][1];
+    return sl == 2 ? 0 : sl - 3;
+  };
+  for (int r = 0; r < 9; ++r) {
+    if (ord[r] < 2) continue;
+    for (int s = 0; s < 9; ++s) {
+      if (ord[s] < 2) continue;
+      const double dr = std::pow(v.c[0], ex[r][0]) * std::pow(v.c[1], ex[r][1]);
+      const double ds = std::pow(v.c[0], ex[s][0]) * std::pow(v.c[1], ex[s][1]);
+      rb[slot_k(r)][slot_k(s)] = R[r * 9 + s] * ds / dr;
+    }
+  }
+  return true;
 }
 
 template <typename T>
@@ -379,7 +484,14 @@ void fill_coef(const rmrt_params* p, const Derived& v, Coef<T>& C) {
   }
   C.hist_g = c0 ? 1u : 0u;
   C.basis = (p->equation == RMRT_NSE && p->central ? BASIS_CENTRAL : 0u) |
-            (p->equation == RMRT_NSE && p->hermite ? BASIS_HERMITE : 0u);
+            (p->equation == RMRT_NSE && p->hermite ? BASIS_HERMITE : 0u) |
+            (p->equation == RMRT_NSE && p->bhll ? BASIS_BHLL : 0u);
+  if (C.basis & BASIS_BHLL) {
+    double rb[6][6];
+    bhll_relaxation(v, rb);   // N is triangular with a non-zero diagonal: always invertible
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) C.rb[i][j] = (T)rb[i][j];
+  }
   for (int a = 0; a < 3; ++a) C.hth[a] = (T)(a < v.d ? v.cs2 / (v.c[a] * v.c[a]) : 0.0);
   // factors of the per-node source fields
   C.half_dt = (T)(0.5 * dt);
@@ -753,7 +865,7 @@ int launch_init_fields(rmrt_ctx* c, const double* rho, const double* u, int with
 // Equation and source mode of a context's step kernel.
 int step_eq(const rmrt_ctx* c) {
   if (c->p.equation == RMRT_NCDE && c->p.c_zero && !lattice_linear(c->p.lattice)) return EQ_NCDE_C0;
-  if (c->p.equation == RMRT_NSE && (c->p.central || c->p.hermite)) return EQ_NSE_BASIS;
+  if (c->p.equation == RMRT_NSE && (c->p.central || c->p.hermite || c->p.bhll)) return EQ_NSE_BASIS;
   return c->p.equation;
 }
 int step_force(const rmrt_ctx* c) {
@@ -1147,7 +1259,7 @@ int check_local_args(const rmrt_ctx* c, int kind, const void* out, int out_dtype
   if (!c || !out) return fail(RMRT_EINVAL, "ctx or out is NULL");
   if (c->hdom.src_field)
     return fail(RMRT_EUNSUPPORTED, "local outputs take the parameter set's constant sources (fields attached)");
-  if (c->p.central || c->p.hermite)
+  if (c->p.central || c->p.hermite || c->p.bhll)
     return fail(RMRT_EUNSUPPORTED, "local outputs are built for the raw-moment collision");
   if (out_dtype != RMRT_OUT_F64 && out_dtype != RMRT_OUT_F32) return fail(RMRT_EINVAL, "bad out_dtype");
   const bool nse = c->p.equation == RMRT_NSE;
@@ -1849,8 +1961,8 @@ int rmrt_batch_create(rmrt_batch** out, int nd, const rmrt_params* params, void*
     const rmrt_params& p = params[d];
     if (p.lattice != p0.lattice || p.equation != p0.equation || p.storage != p0.storage ||
         p.pattern != p0.pattern || (p.c_zero != 0) != (p0.c_zero != 0) || (p.central != 0) != (p0.central != 0) ||
-        (p.hermite != 0) != (p0.hermite != 0))
-      return fail(RMRT_EINVAL, "domain %d differs in lattice/equation/storage/pattern/c_zero/central/hermite", d);
+        (p.hermite != 0) != (p0.hermite != 0) || (p.bhll != 0) != (p0.bhll != 0))
+      return fail(RMRT_EINVAL, "domain %d differs in lattice/equation/storage/pattern/c_zero/central/hermite/bhll", d);
   }
   hipStream_t s = (hipStream_t)stream;
   rmrt_batch* b = new (std::nothrow) rmrt_batch();

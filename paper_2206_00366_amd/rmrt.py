@@ -56,6 +56,7 @@ class Params(C.Structure):
         ("source", C.c_double), ("rho0", C.c_double), ("wall_faces", C.c_uint), ("check_every", C.c_int),
         ("incompressible", C.c_int), ("nu_tensor", C.c_double * 6), ("nu_b_axis", C.c_double * 3),
         ("gamma0", C.c_int), ("diffusive", C.c_int), ("c_zero", C.c_int), ("central", C.c_int), ("hermite", C.c_int),
+        ("bhll", C.c_int),
     ]
 
 
@@ -175,7 +176,7 @@ def make_params(lattice="Q9", equation="NSE", storage="f64", pattern="AB", n=(8,
                 dx=(1.0, 1.0, 1.0), dt=1.0, cs2=-1.0, nu=0.1, nu_b=-1.0, s_hi=-1.0, w_corner=-1.0,
                 D0=0.0, D2=0.0, adv=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0), source=0.0, rho0=1.0,
                 wall_faces=0, check_every=0, incompressible=False, nu_tensor=None, nu_b_axis=None,
-                gamma0=False, diffusive=False, c_zero=False, central=False, hermite=False, **_ignored) -> Params:
+                gamma0=False, diffusive=False, c_zero=False, central=False, hermite=False, bhll=False, **_ignored) -> Params:
     def pad3(v, fill):
         v = list(v) + [fill] * 3
         return v[:3]
@@ -200,6 +201,7 @@ def make_params(lattice="Q9", equation="NSE", storage="f64", pattern="AB", n=(8,
     p.c_zero = int(bool(c_zero))
     p.central = int(bool(central))
     p.hermite = int(bool(hermite))
+    p.bhll = int(bool(bhll))
     p.nu_tensor[:] = [float(v) for v in (nu_tensor if nu_tensor is not None else [-1.0] * 6)]
     p.nu_b_axis[:] = [float(v) for v in (nu_b_axis if nu_b_axis is not None else [-1.0] * 3)]
     return p

@@ -73,6 +73,9 @@ int main(void) {
     p.gamma0 = pick(4) == 0;
     p.diffusive = pick(6) == 0;
     p.c_zero = pick(4) == 0;
+    p.central = pick(6) == 0;
+    p.hermite = pick(6) == 0;
+    p.bhll = pick(6) == 0;
 
     rmrt_derived d;
     const int rc = rmrt_derive(&p, &d);
