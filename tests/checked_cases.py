@@ -80,6 +80,12 @@ def main(out_path):
                                     wall_faces=WALLS["yz"], pattern="AA"), 7)
     single("q27_central", dict(lattice="Q27", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), nu=0.05, central=True,
                                wall_faces=WALLS["z"], pattern="AA"), 5)
+    single("q19_hermite_walls", dict(lattice="Q19", n=(14, 9, 8), dx=(1.0, 2.0, 1.0), nu=0.05, s_hi=1.3,
+                                     force=(1e-5, 0.0, 2e-6), wall_faces=WALLS["yz"], hermite=True,
+                                     pattern="AA"), 5)
+    single("q9_bhll_solid", dict(lattice="Q9", n=(40, 21, 1), dx=(1.0, 0.5, 1.0), nu=0.05, s_hi=1.2,
+                                 force=(2e-5, 0.0, 0.0), wall_faces=WALLS["y"], bhll=True, pattern="AB"), 5,
+           solid=circle_mask((40, 21, 1), (12, 10), 4))
 
     # a batch: ragged tile counts, walls, force, XCD chunks, domain groups; initial
     # state set at an odd parity (swapped-layout initialisation)

@@ -3,8 +3,8 @@ tests/checked_cases.py, which take every neighbour-index path of the kernels
 (odd AA and AB streaming, walls, solid masks, link words, velocity-gradient
 initialisation, swapped-layout reads of the companion kernels, persistent,
 XCD-ordered and XCD-chunked tile orders, ragged batches with domain groups,
-the C = 0 history and the central-moment collision), find no index out of
-range and give the production library's results (bitwise for every
+the C = 0 history and the central, Hermite and BHLL collisions), find no
+index out of range and give the production library's results (bitwise for every
 single-domain case; within rounding where the inserted checks change which
 multiply-adds the compiler fuses); with the checks' bound lowered below the
 node count, they count the nodes above it."""
@@ -41,7 +41,7 @@ def test_checked_build_finds_no_index_out_of_range_and_matches(tmp_path):
     chk = _run(checked, chk_out)
     prod_cases = [ln.split() for ln in prod if ln.startswith("case ")]
     chk_cases = [ln.split() for ln in chk if ln.startswith("case ")]
-    assert [c[1] for c in prod_cases] == [c[1] for c in chk_cases] and len(chk_cases) == 11
+    assert [c[1] for c in prod_cases] == [c[1] for c in chk_cases] and len(chk_cases) == 13
     assert all(c[2] == "-1" for c in prod_cases)          # the production build has no checks
     assert all(c[2] == "0" for c in chk_cases), chk_cases  # no neighbour index out of range
     a, b = np.load(prod_out), np.load(chk_out)
