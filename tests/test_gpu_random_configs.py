@@ -2,7 +2,8 @@
 oracle: lattice (rD2Q9 / rD3Q19 / rD3Q27), equation (NSE / NCDE), ragged grid
 sizes, grid spacings, c_s^2, viscosities, higher-order rate, wall pairs, random
 solid nodes, body force and mass source, He-Luo equilibrium, viscosity tensors,
-the NCDE variants, AA or AB pattern, odd and even step counts.  FP64 storage:
+the central, Hermite, central-Hermite and BHLL moment bases, the NCDE
+variants, AA or AB pattern, odd and even step counts.  FP64 storage:
 every fluid population within 1e-12 of max |f|.  Draws that the library rejects
 as invalid (rmrt_derive) are redrawn."""
 import sys
@@ -52,6 +53,16 @@ def _draw(rng):
             prm["incompressible"] = True
         if rng.random() < 0.2:
             prm["nu_tensor"] = tuple(float(v) for v in rng.uniform(0.01, 0.1, 6))
+        # the alternative moment bases (combinations a lattice lacks are redrawn)
+        basis = rng.random()
+        if basis < 0.1:
+            prm["central"] = True
+        elif basis < 0.2:
+            prm["hermite"] = True
+        elif basis < 0.25:
+            prm["central"] = prm["hermite"] = True
+        elif basis < 0.3:
+            prm["bhll"] = True
     else:
         prm["D0"] = float(rng.uniform(0.01, 0.1))
         prm["D2"] = float(rng.choice([0.0, rng.uniform(0.0, 1.0)]))
@@ -137,16 +148,21 @@ def test_random_configuration_fp32_storage(rmrt, k):
 
 
 def _draw_batch(rng):
-    """3..7 random domains sharing lattice, equation and pattern (what a batch
-    requires); everything else per domain."""
+    """3..7 random domains sharing lattice, equation, moment basis and pattern
+    (what a batch requires); everything else per domain."""
     lat = str(rng.choice(["Q9", "Q19", "Q27"]))
     nse = rng.random() < 0.75
     pattern = str(rng.choice(["AA", "AB"]))
     doms = []
+    basis = None
     while len(doms) < int(rng.integers(3, 8)):
         prm, solid, _, _ = _draw(rng)
         if prm["lattice"] != lat or (prm["equation"] == "NSE") != nse:
             continue
+        b = tuple(bool(prm.get(k)) for k in ("central", "hermite", "bhll"))
+        if basis is not None and b != basis:
+            continue
+        basis = b
         doms.append((prm, solid))
     return doms, pattern
 
@@ -241,10 +257,13 @@ def test_random_reduced_lattice_matches_oracle(rmrt, k):
 def test_random_configuration_local_outputs(rmrt, k):
     """Local outputs (strain rate and stress for the NSE, grad phi for the NCDE) of
     the random draws after their steps, FP64 storage, against the oracle's formulas
-    on its own state: within 1e-11 of the output's magnitude; zero at solid nodes."""
+    on its own state: within 1e-11 of the output's magnitude; zero at solid nodes.
+    Local outputs belong to the raw-moment collision: the basis draws are dropped."""
     rng = np.random.default_rng(1000 + k)
     while True:
         prm, solid, pattern, steps = _draw(rng)
+        for key in ("central", "hermite", "bhll"):
+            prm.pop(key, None)
         if _valid(rmrt, prm):
             break
     print(f"[random local {k}] {prm['lattice']} {prm['equation']} {pattern} {steps} steps", flush=True)
