@@ -102,6 +102,8 @@ bool rows_straddle_lines(const rmrt_params& p) {
   return ((uint64_t)p.n[0] * elem_size(p.storage)) % 128u != 0;
 }
 
+bool bhll_relaxation(const Derived& v, double rb[6][6]);
+
 int derive(const rmrt_params* p, Derived& v) {
   if (!p) return fail(RMRT_EINVAL, "params is NULL");
   if (p->lattice < RMRT_Q9 || p->lattice > RMRT_Q7) return fail(RMRT_EINVAL, "unknown lattice %d", p->lattice);
@@ -254,6 +256,10 @@ int derive(const rmrt_params* p, Derived& v) {
     for (int k = 0; k < 3; ++k) v.s_s[k] = v.s_b[k] = 1.0;
   }
   if (!(v.s_hi > 0 && v.s_hi < 2)) return fail(RMRT_EINVAL, "s_hi = %g outside (0, 2)", v.s_hi);
+  if (p->bhll) {
+    double rb[6][6];
+    if (!bhll_relaxation(v, rb)) return fail(RMRT_EINVAL, "the BHLL basis matrix is singular");
+  }
   return RMRT_OK;
 }
 
@@ -298,6 +304,7 @@ void invert3(const double A[3][3], double B[3][3], int d) {
 // In-place inverse of the n x n row-major matrix A (Gauss-Jordan with partial
 // pivoting); false when a pivot vanishes.
 bool invert_small(double* A, int n) {
+  if (n < 1 || n > 9) return false;
   double inv[81];
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) inv[i * n + j] = i == j ? 1.0 : 0.0;
@@ -487,8 +494,8 @@ void fill_coef(const rmrt_params* p, const Derived& v, Coef<T>& C) {
             (p->equation == RMRT_NSE && p->hermite ? BASIS_HERMITE : 0u) |
             (p->equation == RMRT_NSE && p->bhll ? BASIS_BHLL : 0u);
   if (C.basis & BASIS_BHLL) {
-    double rb[6][6];
-    bhll_relaxation(v, rb);   // N is triangular with a non-zero diagonal: always invertible
+    double rb[6][6] = {};
+    bhll_relaxation(v, rb);   // derive() has checked that N is invertible
     for (int i = 0; i < 6; ++i)
       for (int j = 0; j < 6; ++j) C.rb[i][j] = (T)rb[i][j];
   }
