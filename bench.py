@@ -247,7 +247,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--only", default="all",
-                    help="comma list of: q19,q19f16,q19f64,q19local,q9ncde,q5ncde,q7ncde,q27,q27batch,q9tg,copy "
+                    help="comma list of: q19,q19f16,q19f64,q19local,q9ncde,q5ncde,q7ncde,q27,q27batch,q9tg,bases,copy "
                          "(the q19 headline always runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--warmstart", action="store_true",
@@ -278,7 +278,7 @@ def main():
         return
 
     only = set(args.only.split(",")) if args.only != "all" else {"q19f16", "q19f64", "q9ncde", "q27", "q27batch", "q9tg",
-                                                                 "q5ncde", "q7ncde", "q19local", "copy"}
+                                                                 "q5ncde", "q7ncde", "q19local", "bases", "copy"}
     K, W = args.steps, args.warmup
 
     # ---------------- headline: rD3Q19 FP32-dev 256 x 256 x 128 ----------------
@@ -394,6 +394,8 @@ def main():
         per["rD2Q9_tg_f64"] = lattice_entry("rD2Q9 NSE TG 64x32 dy=0.5 FP64 (launch-bound, MLUPS only)", 9, "f64",
                                             2048, 2000, w2, e2)
         per["rD2Q9_tg_f64"].pop("pct_hbm_peak")
+    if "bases" in only:
+        per["moment_bases"] = bench_bases(torch, R, K, W, prm_h, head)
     if "q27batch" in only:
         log("[bench] rD3Q27 batch of 64 channels f32dev")
         per["rD3Q27_batch64_f32dev"] = bench_batch(torch, R, max(K // 10, 20), W)
@@ -435,6 +437,49 @@ def main():
     print(json.dumps(out), flush=True)
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+
+
+def bench_bases(torch, R, K, W, prm_h, head):
+    """The collision in the central, Hermite, central-Hermite and BHLL moments
+    (eq. 5-1-1 / 5-1-2) at full size, FP32-dev AA, next to the raw-moment
+    collision of the same lattice and workload: the basis transforms add
+    arithmetic per node, the bytes per update stay 2 q sizeof."""
+    from inputs import taylor_green_2d
+    n3, dx3 = prm_h["n"], prm_h["dx"]
+    N3 = n3[0] * n3[1] * n3[2]
+    out = {}
+    rho, u = tg3d_fields(n3, dx3, 0.02, 1.0 / 3.0)
+    cases3 = [("rD3Q19_hermite", "Q19", dict(hermite=True)),
+              ("rD3Q27_raw", "Q27", {}),
+              ("rD3Q27_central", "Q27", dict(central=True)),
+              ("rD3Q27_hermite", "Q27", dict(hermite=True)),
+              ("rD3Q27_central_hermite", "Q27", dict(central=True, hermite=True))]
+    for key, lat, extra in cases3:
+        log(f"[bench] moment bases: {key}")
+        prm = dict(prm_h, lattice=lat, **extra)
+        w2, e2, fin = run_single(torch, R, prm, rho, u, K, W)
+        q = 19 if lat == "Q19" else 27
+        out[key] = lattice_entry(f"{lat} NSE TG 256x256x128 dz=2dx FP32-dev AA, basis {extra or 'raw'}", q,
+                                 "f32dev", N3, K, w2, e2)
+        out[key]["finite"] = fin
+    out["rD3Q19_hermite"]["vs_raw"] = round(out["rD3Q19_hermite"]["MLUPS"] / head["MLUPS"], 3)
+    for key in ("rD3Q27_central", "rD3Q27_hermite", "rD3Q27_central_hermite"):
+        out[key]["vs_raw"] = round(out[key]["MLUPS"] / out["rD3Q27_raw"]["MLUPS"], 3)
+    del rho, u
+    nx, ny = 4096, 2048
+    rho2, u2, _ = taylor_green_2d(nx, ny, 1.0, 0.5, 0.02, 0.25 / 3.0)
+    base2 = dict(lattice="Q9", n=(nx, ny, 1), dx=(1.0, 0.5, 1.0), nu=0.01, nu_b=0.03, s_hi=1.2,
+                 storage="f32dev", pattern="AA")
+    for key, extra in (("rD2Q9_raw", {}), ("rD2Q9_bhll", dict(bhll=True)), ("rD2Q9_hermite", dict(hermite=True)),
+                       ("rD2Q9_central", dict(central=True))):
+        log(f"[bench] moment bases: {key}")
+        w2, e2, fin = run_single(torch, R, dict(base2, **extra), rho2, u2, K, W)
+        out[key] = lattice_entry(f"rD2Q9 NSE TG {nx}x{ny} dy=0.5 FP32-dev AA, basis {extra or 'raw'}", 9,
+                                 "f32dev", nx * ny, K, w2, e2)
+        out[key]["finite"] = fin
+    for key in ("rD2Q9_bhll", "rD2Q9_hermite", "rD2Q9_central"):
+        out[key]["vs_raw"] = round(out[key]["MLUPS"] / out["rD2Q9_raw"]["MLUPS"], 3)
+    return out
 
 
 def bench_local(torch, R, prm, rho, u, N, reps=50):

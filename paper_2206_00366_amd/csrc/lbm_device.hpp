@@ -516,89 +516,82 @@ __device__ __forceinline__ void collide(T (&t)[NS], const Coef<T>& C, const Node
 
   if constexpr (EQ == EQ_NSE_BASIS) {
     // kappa* = kappa - Sbar (kappa - kappa_eq') + kappa_s with kappa = N m, N
-    // the central shift N(u), the Hermite transform H or H N(u), and the
-    // equilibrium and source moments transformed the same way (eq. 5-1-2); Sbar
-    // has the raw model's blocks.  Conserved moments of every basis are at their
-    // equilibrium (kappa_0 = rho', kappa_1 = j - rho u = -dt F / 2 centrally), so
-    // only the source is added to them.
+    // the central shift N(u), the Hermite transform H or H N(u), or the BHLL
+    // matrix, and the equilibrium and source moments transformed the same way
+    // (eq. 5-1-2); Sbar has the raw model's blocks.  N is linear, so
+    // m* = m - N^-1 Sbar N (m - eq') + src: only the non-equilibrium part d =
+    // m - eq' goes into the basis and its relaxation comes back.  Conserved
+    // moments of every basis are at their equilibrium (kappa_0 = rho', kappa_1 =
+    // j - rho u = -dt F / 2 centrally), so only the source changes them.
     const bool cen = CENTRAL_OK && (C.basis & BASIS_CENTRAL);
     const bool her = (C.basis & BASIS_HERMITE) != 0;
-    T e[NS], sv[NS];
+    T d[NS];
     static_for<0, NS>([&](auto n_) {
       constexpr int n = decltype(n_)::value;
-      e[n] = gmom<L, n>(C, eA, eB, eMd, eMo);
-      if constexpr (FORCE) sv[n] = gmom<L, n>(C, sA, sB, sMd, sMo);
+      d[n] = t[n] - gmom<L, n>(C, eA, eB, eMd, eMo);
     });
-    if constexpr (L == LAT_Q9) {
-      if (C.basis & BASIS_BHLL) {
-        // BHLL moments kappa = N m (eq. Md2q9-3) relaxed class by class: with N
-        // constant the step is m* = m - N^-1 Sbar_B N (m - eq') + src, and the
-        // host has formed N^-1 Sbar_B N in this basis.  Its rows of the
-        // conserved moments vanish and its columns there meet m - eq' = 0.
-        // non-conserved slot k: 2 (x^2), then 4 .. 8
+    bool bhll = false;
+    if constexpr (L == LAT_Q9) bhll = (C.basis & BASIS_BHLL) != 0;
+    if (bhll) {
+      if constexpr (L == LAT_Q9) {
+        // BHLL moments (eq. Md2q9-3) relaxed class by class: the host has formed
+        // N^-1 Sbar_B N in this basis.  Its rows of the conserved moments vanish
+        // and its columns there meet d = 0.  Non-conserved slot k: 2 (x^2), then
+        // 4 .. 8.
         T nd6[6];
         static_for<0, 6>([&](auto k_) {
           constexpr int k = decltype(k_)::value;
-          constexpr int sk = k == 0 ? 2 : k + 3;
-          nd6[k] = t[sk] - e[sk];
+          nd6[k] = d[k == 0 ? 2 : k + 3];
         });
         static_for<0, 6>([&](auto k_) {
           constexpr int k = decltype(k_)::value;
-          constexpr int sk = k == 0 ? 2 : k + 3;
           T r = C.rb[k][0] * nd6[0];
           static_for<1, 6>([&](auto l_) {
             constexpr int l = decltype(l_)::value;
             r += C.rb[k][l] * nd6[l];
           });
-          t[sk] -= r;
+          t[k == 0 ? 2 : k + 3] -= r;
         });
-        if constexpr (FORCE) {
-          static_for<0, NS>([&](auto n_) {
-            constexpr int n = decltype(n_)::value;
-            t[n] += sv[n];
-          });
+      }
+    } else {
+      if constexpr (CENTRAL_OK) {
+        if (cen) central_shift<D>(d, vc);
+      }
+      if (her) hermite_shift<L, D>(d, C.hth, T(1));
+      const T nd[3] = {d[sxx], d[syy], D == 3 ? d[szz] : T(0)};
+      static_for<0, NS>([&](auto n_) {
+        constexpr int n = decltype(n_)::value;
+        constexpr int a = n % 3, b = (n / 3) % 3, p = n / 9;
+        constexpr int ord = a + b + p;
+        constexpr bool diag2 = (n == sxx || n == syy || n == szz);
+        if constexpr (ord <= 1) {
+          d[n] = T(0);
+        } else if constexpr (diag2) {
+          constexpr int ax = (n == sxx) ? 0 : (n == syy ? 1 : 2);
+          T r = C.Sd[ax][0] * nd[0] + C.Sd[ax][1] * nd[1];
+          if constexpr (D == 3) r += C.Sd[ax][2] * nd[2];
+          d[n] = r;
+        } else if constexpr (ord == 2) {
+          constexpr int pr = (p == 0) ? 0 : ((a == 1) ? 1 : 2);
+          d[n] *= C.s_off[pr];
+        } else {
+          d[n] *= C.s_hi;
         }
-        moments_inv<D, Lat<L>::dropped_mask()>(t);
-        return;
+      });
+      if (her) hermite_shift<L, D>(d, C.hth, T(-1));
+      if constexpr (CENTRAL_OK) {
+        if (cen) central_unshift<D>(d, vc);
       }
+      static_for<0, NS>([&](auto n_) {
+        constexpr int n = decltype(n_)::value;
+        t[n] -= d[n];
+      });
     }
-    if constexpr (CENTRAL_OK) {
-      if (cen) {
-        central_shift<D>(t, vc);
-        central_shift<D>(e, vc);
-        if constexpr (FORCE) central_shift<D>(sv, vc);
-      }
-    }
-    if (her) {
-      hermite_shift<L, D>(t, C.hth, T(1));
-      hermite_shift<L, D>(e, C.hth, T(1));
-      if constexpr (FORCE) hermite_shift<L, D>(sv, C.hth, T(1));
-    }
-    T nd[3] = {t[sxx] - e[sxx], t[syy] - e[syy], D == 3 ? t[szz] - e[szz] : T(0)};
-    static_for<0, NS>([&](auto n_) {
-      constexpr int n = decltype(n_)::value;
-      constexpr int a = n % 3, b = (n / 3) % 3, p = n / 9;
-      constexpr int ord = a + b + p;
-      constexpr bool diag2 = (n == sxx || n == syy || n == szz);
-      T r;
-      if constexpr (ord <= 1) {
-        r = T(0);
-      } else if constexpr (diag2) {
-        constexpr int ax = (n == sxx) ? 0 : (n == syy ? 1 : 2);
-        r = C.Sd[ax][0] * nd[0] + C.Sd[ax][1] * nd[1];
-        if constexpr (D == 3) r += C.Sd[ax][2] * nd[2];
-      } else if constexpr (ord == 2) {
-        constexpr int pr = (p == 0) ? 0 : ((a == 1) ? 1 : 2);
-        r = C.s_off[pr] * (t[n] - e[n]);
-      } else {
-        r = C.s_hi * (t[n] - e[n]);
-      }
-      t[n] -= r;
-      if constexpr (FORCE) t[n] += sv[n];
-    });
-    if (her) hermite_shift<L, D>(t, C.hth, T(-1));
-    if constexpr (CENTRAL_OK) {
-      if (cen) central_unshift<D>(t, vc);
+    if constexpr (FORCE) {
+      static_for<0, NS>([&](auto n_) {
+        constexpr int n = decltype(n_)::value;
+        t[n] += gmom<L, n>(C, sA, sB, sMd, sMo);
+      });
     }
     moments_inv<D, Lat<L>::dropped_mask()>(t);
     return;
