@@ -2,7 +2,8 @@
 and eq. NCDE with S, Sbar, Fbar varying by node and step), of the gamma = 0
 explicit difference of dF/dt with the library-held previous-step source
 (eq. 2-1), and of the C = 0 NCDE form of eq. 4-16 on rD2Q9 / rD3Q19 / rD3Q27
-(c_zero), against the FP64 oracle.  Bars: FP64 populations within 1e-12 of
+(c_zero), also under the central, Hermite, central-Hermite and BHLL
+collisions, against the FP64 oracle.  Bars: FP64 populations within 1e-12 of
 max |f|; FP32 rho within 1e-5 of rho0, u within 1e-5 of its scale, phi within
 1e-5 of its peak."""
 import sys
@@ -37,6 +38,13 @@ CASES = {
     "q27_walls_fields": dict(lattice="Q27", n=(11, 9, 8), dx=(1.0, 2.0, 1.0), nu=0.05, wall_faces=WALLS["yz"]),
     "q9_heluo_fields": dict(lattice="Q9", n=(29, 17, 1), dx=(1.0, 0.5, 1.0), nu=0.04, incompressible=True,
                             rho0=1.05, wall_faces=WALLS["y"]),
+    "q27_central_fields": dict(lattice="Q27", n=(11, 9, 8), dx=(1.0, 0.5, 2.0), nu=0.05, nu_b=0.02, s_hi=1.3,
+                               central=True, wall_faces=WALLS["z"]),
+    "q19_hermite_fields": dict(lattice="Q19", n=(13, 11, 9), dx=(1.0, 0.5, 2.0), nu=0.03, s_hi=1.4, hermite=True),
+    "q9_central_hermite_fields": dict(lattice="Q9", n=(37, 21, 1), dx=(1.0, 0.5, 1.0), nu=0.04, nu_b=0.07,
+                                      s_hi=1.2, central=True, hermite=True, wall_faces=WALLS["y"]),
+    "q9_bhll_fields": dict(lattice="Q9", n=(37, 21, 1), dx=(1.0, 0.5, 1.0), nu=0.04, nu_b=0.07, s_hi=1.2,
+                           bhll=True, wall_faces=WALLS["y"]),
     "q9_ncde_fields": dict(lattice="Q9", equation="NCDE", n=(33, 17, 1), dx=(1.0, 0.5, 1.0), D0=0.01, D2=1.0,
                            adv=(0.05, 0.02, 0.0), rho0=0.0),
     "q9_ncde_gamma0_fields": dict(lattice="Q9", equation="NCDE", n=(33, 17, 1), dx=(1.0, 0.5, 1.0), D0=0.01,
@@ -147,7 +155,8 @@ def test_source_fields_and_c_zero_match_oracle(R, case, pattern, storage):
 
 @pytest.mark.parametrize("storage", ["f64", "f32dev"])
 @pytest.mark.parametrize("case", ["q9_channel_fields", "q27_walls_fields", "q9_ncde_fields",
-                                  "q9_ncde_gamma0_fields", "q7_gamma0_fields", "q19_czero_fields"])
+                                  "q9_ncde_gamma0_fields", "q7_gamma0_fields", "q19_czero_fields",
+                                  "q27_central_fields", "q9_bhll_fields"])
 def test_time_varying_fields_match_oracle(R, case, storage):
     """Fields rewritten in place between single steps: each step reads the
     values of its own time, and the gamma = 0 form differences them against the
