@@ -10,6 +10,8 @@ axis, so the oracle steps a (2k+1)-wide sub-box around it.
       FP64 / FP32
   rD3Q27 batch of 64 force-driven walled channels (32..256 nodes per axis), 16
       steps, on its 4 smallest domains and its largest, FP32 (autotuned) / FP64
+  the benchmark's basis-collision sizes: rD3Q27 central-Hermite 256 x 256 x 128,
+      8 steps, and rD2Q9 BHLL 4096 x 2048 (dy = dx / 2), 16 steps, FP64 / FP32
 
 The initial fields carry seeded noise so that every sampled node sees a
 non-trivial state.  Samples include domain corners (periodic wrap, wall
@@ -227,3 +229,63 @@ def test_q27_64_channel_batch_full_size_16_steps(R, batch_case, storage):
             assert ef <= 1e-12, k
         else:
             assert er <= 1e-5 and eu <= 1e-5, k
+
+
+# --------------------------------------------------------------------------
+# The alternative moment bases at the sizes of the benchmark's basis leg
+# --------------------------------------------------------------------------
+BASIS_CASES = {
+    "q27_central_hermite": (dict(lattice="Q27", n=(256, 256, 128), dx=(1.0, 1.0, 2.0), nu=0.005, cs2=1.0 / 3.0,
+                                 rho0=1.0, central=True, hermite=True), 8),
+    "q9_bhll": (dict(lattice="Q9", n=(4096, 2048, 1), dx=(1.0, 0.5, 1.0), nu=0.01, nu_b=0.03, s_hi=1.2,
+                     rho0=1.0, bhll=True), 16),
+}
+
+
+def _basis_fields(prm, seed):
+    rng = np.random.default_rng(seed)
+    if prm["lattice"] == "Q27":
+        rho, u, _ = taylor_green_3d(prm["n"], prm["dx"], 0.02, prm["cs2"])
+    else:
+        from inputs import taylor_green_2d
+        nx, ny = prm["n"][:2]
+        rho, u, _ = taylor_green_2d(nx, ny, prm["dx"][0], prm["dx"][1], 0.02, 0.25 / 3.0)
+    return rho + rng.uniform(-1e-4, 1e-4, rho.shape), u + rng.uniform(-2e-3, 2e-3, u.shape)
+
+
+@pytest.fixture(scope="module")
+def basis_cases():
+    out = {}
+    for name, (prm, k) in BASIS_CASES.items():
+        rho, u = _basis_fields(prm, 41)
+        n = prm["n"]
+        rng = np.random.default_rng(42)
+        nodes = [(0, 0, 0), tuple(s - 1 for s in n)]
+        nodes += [tuple(int(rng.integers(0, s)) for s in n) for _ in range(2)]
+        ref = np.stack([lightcone_oracle(prm, rho, u, p, k)[0] for p in nodes])
+        out[name] = (rho, u, nodes, ref)
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+@pytest.mark.parametrize("name", list(BASIS_CASES))
+def test_basis_collision_full_size(R, basis_cases, name, storage):
+    prm, k = BASIS_CASES[name]
+    rho, u, nodes, ref = basis_cases[name]
+    say(f"[full-size multistep] {name} {prm['n']} {storage}, {k} steps, {len(nodes)} light cones")
+    dom = R.Domain(R.make_params(**prm, storage=storage, pattern="AA"), rho, u)
+    dom.step(k)
+    got = _gpu_samples(dom, prm["n"], nodes)
+    dom.close()
+    del dom
+    torch.cuda.empty_cache()
+    m = O.Model(dict(prm, n=(1, 1, 1)))
+    ef = np.abs(got - ref).max() / np.abs(ref).max()
+    r_g, u_g = _macro(m, got)
+    r_o, u_o = _macro(m, ref)
+    er, eu = np.abs(r_g - r_o).max(), np.abs(u_g - u_o).max() / 0.02
+    say(f"   max|df|/max|f| {ef:.2e}, max|drho|/rho0 {er:.2e}, max|du|/U0 {eu:.2e}")
+    if storage == "f64":
+        assert ef <= 1e-12
+    else:
+        assert er <= 1e-5 and eu <= 1e-5
