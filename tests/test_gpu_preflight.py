@@ -3,9 +3,9 @@ Neumann analysis of the oracle's step (tests/vn_reference.py) on the same
 16-node periodic grid: neutral or decaying parameter sets report a growth of
 at most 1, unstable ones (s_hi = 1 on the rD3Q19 / rD3Q27 benchmark
 spacings, reading A5; a fast flow on a rectangular rD2Q9 lattice or under the
-central-moment collision; strong advection of a weakly diffusive NCDE, also in
-the C = 0 form with its previous-step phi) the oracle's largest amplification
-factor."""
+central-moment or central-Hermite collision; the BHLL collision at a low
+viscosity; strong advection of a weakly diffusive NCDE, also in the C = 0 form
+with its previous-step phi) the oracle's largest amplification factor."""
 import sys
 
 import numpy as np
@@ -53,6 +53,17 @@ CASES = {
     # the central-moment collision in a fast flow
     "q27_central_fast_flow": (dict(lattice="Q27", dx=(1.0, 2.0, 1.0), nu=0.005, central=True), 1.0,
                               (0.1, 0.05, 0.0), 2000),
+    # the other bases: Hermite (neutral in a fast flow), central-Hermite (weakly
+    # unstable), BHLL at a low viscosity with s_hi = 1.3 (unstable at rest: its
+    # epsilon moment relaxes apart from the second moments it contains)
+    "q19_hermite_fast_flow": (dict(lattice="Q19", dx=(1.0, 2.0, 1.0), nu=0.005, s_hi=1.2, hermite=True), 1.0,
+                              (0.1, 0.05, 0.0), 2000),
+    "q27_central_hermite_fast_flow": (dict(lattice="Q27", dx=(1.0, 2.0, 1.0), nu=0.005, central=True,
+                                           hermite=True), 1.0, (0.1, 0.05, 0.0), 2000),
+    "q9_bhll_low_viscosity_rest": (dict(lattice="Q9", dx=(1.0, 0.5, 1.0), nu=0.001, s_hi=1.3, bhll=True), 1.0,
+                                   (0.0, 0.0, 0.0), 200),
+    "q9_bhll_bench_rates": (dict(lattice="Q9", dx=(1.0, 0.5, 1.0), nu=0.01, nu_b=0.03, s_hi=1.2, bhll=True), 1.0,
+                            (0.02, 0.01, 0.0), 2000),
 }
 
 
