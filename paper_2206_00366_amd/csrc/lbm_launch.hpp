@@ -6,8 +6,8 @@
 namespace rmrt {
 
 // Field sources, the C = 0 NCDE form and the basis collisions (central,
-// Hermite) have a one-node-per-thread kernel only: with STEP_WIDE_TILES it
-// walks each 512-node tile in two passes.
+// Hermite, BHLL) have a one-node-per-thread kernel only: with STEP_WIDE_TILES
+// it walks each 512-node tile in two passes.
 template <int L, int ST, int EQ, int F, int BC, int PH, bool BUF>
 void do_step_npt(const StepLaunch& a) {
   if constexpr (F == F_FIELD || EQ == EQ_NCDE_C0 || EQ == EQ_NSE_BASIS)

@@ -123,6 +123,35 @@ def test_bhll_batch_matches_oracle(R):
     b.close()
 
 
+def test_basis_batches_every_tile_shape_match_oracle(R):
+    """Batches under the BHLL and the central-Hermite collision, in every tile
+    shape the autotuner chooses from (512-node tiles, which the basis kernels
+    walk in two passes, and persistent grids included) and in the autotuned
+    one, against the oracle."""
+    for extra, lat, dims in ((dict(bhll=True), "Q9", [(37, 23, 1), (19, 31, 1), (64, 9, 1)]),
+                             (dict(central=True, hermite=True), "Q27", [(11, 9, 7), (13, 6, 9)])):
+        prms = [dict(lattice=lat, n=n, dx=(1.0, 0.5, 1.0) if lat == "Q9" else (1.0, 0.5, 2.0), nu=0.04,
+                     s_hi=1.3, force=(1e-5, 0.0, 0.0), wall_faces=WALLS["y"], **extra) for n in dims]
+        fields, refs = [], []
+        for k, p in enumerate(prms):
+            m = O.Model(p)
+            rho, u = random_fields(m, 50 + k)
+            fields.append((rho, u))
+            refs.append(m.step(m.init(rho, u), 10))
+        b = R.Batch([R.make_params(**p, storage="f64", pattern="AA") for p in prms])
+        best = b.autotune(steps=2)
+        for cfg in list(range(len(R.Batch.configs()))) + [best]:
+            b.set_config(cfg)
+            for k, (rho, u) in enumerate(fields):
+                b.domains[k].set_fields(rho, u)
+            b.step(10)
+            err = max(rel_err(b.domains[k].populations().cpu().numpy(), refs[k]) for k in range(len(prms)))
+            say(f"[bhll] {lat} {extra} config {R.Batch.configs()[cfg]}{' (autotuned)' if cfg == best else ''}: "
+                f"{err:.2e}")
+            assert err < 1e-12, (lat, cfg)
+        b.close()
+
+
 def test_bhll_refused_where_not_built(R):
     with pytest.raises(R.RMRTError) as e:
         R.derive(R.make_params(lattice="Q27", n=(4, 4, 4), nu=0.05, bhll=True))
