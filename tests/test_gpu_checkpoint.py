@@ -33,6 +33,10 @@ CASES = {
     "q9_czero_gamma0_fields": (dict(lattice="Q9", equation="NCDE", n=(33, 17, 1), dx=(1.0, 0.5, 1.0), D0=0.01,
                                     D2=1.0, adv=(0.05, 0.02, 0.0), rho0=0.0, gamma0=True, c_zero=True),
                                "f64", "AA"),
+    "q27_central_hermite_f32_aa": (dict(lattice="Q27", n=(11, 9, 7), dx=(1.0, 0.5, 2.0), nu=0.05, s_hi=1.3,
+                                        central=True, hermite=True), "f32dev", "AA"),
+    "q9_bhll_f64_ab_walls": (dict(lattice="Q9", n=(37, 21, 1), dx=(1.0, 0.5, 1.0), nu=0.04, s_hi=1.2,
+                                  force=(1e-5, 0.0, 0.0), wall_faces=WALLS["y"], bhll=True), "f64", "AB"),
 }
 
 
