@@ -226,6 +226,43 @@ def test_header_is_valid_c(tmp_path):
     assert int(q) == 19 and abs(float(w0) - m.w[0]) < 1e-15
 
 
+@pytest.mark.parametrize("cname,pyname", [("rmrt_params", "Params"), ("rmrt_derived", "Derived")])
+def test_struct_layout_matches_header(tmp_path, cname, pyname):
+    """The binding's ctypes structure has the header's members in the header's
+    order, its size and its field offsets (a member added to one side only
+    would shift every later one)."""
+    import ctypes
+    import re
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    cls = getattr(rmrt, pyname)
+    fields = [f[0] for f in cls._fields_]
+    hdr = open(os.path.join(ROOT, "include", "rmrt.h")).read()
+    decl = hdr[hdr.index(f"typedef struct {cname} {{"):hdr.index(f"}} {cname};")].split("{", 1)[1]
+    decl = re.sub(r"/\*.*?\*/|//[^\n]*", "", decl, flags=re.S)
+    names = []
+    for stmt in filter(None, (t.strip() for t in decl.split(";"))):
+        declarators = re.sub(r"^(unsigned|int|double)\s+", "", stmt)
+        names += [re.match(r"\w+", d.strip()).group(0) for d in declarators.split(",")]
+    assert names == fields, (names, fields)
+    body = "".join(f'  printf("%s %zu\\n", "{f}", offsetof({cname}, {f}));\n' for f in fields)
+    src = tmp_path / "layout.c"
+    src.write_text('#include "rmrt.h"\n#include <stddef.h>\n#include <stdio.h>\nint main(void) {\n'
+                   f'  printf("sizeof %zu\\n", sizeof({cname}));\n' + body + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                        "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        timeout=60).stdout.splitlines())
+    assert int(out["sizeof"]) == ctypes.sizeof(cls)
+    for f in fields:
+        assert int(out[f]) == getattr(cls, f).offset, f
+
+
 def test_batch_rejects_mixed_lattices_without_gpu():
     ps = (rmrt.Params * 2)(rmrt.make_params(lattice="Q19", n=(4, 4, 4)), rmrt.make_params(lattice="Q27", n=(4, 4, 4)))
     f0 = (ctypes.c_void_p * 2)(16, 16)
